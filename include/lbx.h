@@ -1,0 +1,177 @@
+/*
+ * lbx — Lindblad optimal-control hot path for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library liblbx.so.  Every computation runs in HIP kernels on
+ * the current device; this header uses plain C types only.
+ *
+ * Model (Guenther, Petersson, DuBois, "Quandary", Sec. II and App. A/B):
+ *   composite system of Q subsystems with n_q levels, N = prod n_q;
+ *   rotating-frame Hamiltonian H(t) = H_sys + sum_q d_q(t) a_q + conj(d_q(t)) a_q^+,
+ *   H_sys with detuning, self-Kerr and cross-Kerr terms (diagonal);
+ *   collapse operators a_q/sqrt(T1_q) (decay) and a_q^+ a_q/sqrt(T2_q) (dephasing);
+ *   controls d_q(t) = sum_s S_s(t) sum_f alpha_q^{s,f} exp(i Omega_q^f t) with
+ *   quadratic B-splines S_s on knots of spacing T/(Ns-2), centres (s-1/2)T/(Ns-2).
+ *
+ * Units: every frequency-like input (detuning, Kerr terms, carriers, control
+ * coefficients alpha) is an ordinary frequency in GHz (the value divided by
+ * 2*pi); times (T, T1, T2, t) are in ns.  The library multiplies by 2*pi.
+ * A decay or dephasing time that is not finite and positive switches its
+ * term off.
+ *
+ * Memory layout shared by every entry point:
+ *   - a density matrix rho is complex128, row-major: rho[i][j] at i*N + j,
+ *     stored as interleaved (re, im) doubles.  Basis index i has the
+ *     subsystem digits of its levels with subsystem 0 most significant.
+ *     (The paper's column-stacked vec(rho) is a relabelling of this.)
+ *   - a batch of B states of one system is [B][N][N] contiguous;
+ *   - a multi-system plan concatenates the batches of its systems in plan
+ *     order (batch_per_sys[s] states of system s);
+ *   - alpha of one system is [Q][Ns][Nf][2] doubles (Re, Im), flattened;
+ *     a multi-system alpha concatenates the systems in plan order; gradients
+ *     use the same layout.
+ *
+ * Ownership: the caller owns every state, alpha, G, grad and workspace
+ * buffer.  Pointers documented as DEVICE must be device (or managed) memory
+ * of the current device; HOST pointers are read during the call only.
+ * A plan owns small immutable device tables (energies, digit tables) and is
+ * destroyed with lb_plan_destroy.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Kernels
+ * are enqueued on it.  lindblad_apply, imr_step and objective return without
+ * synchronising.  forward_solve and adjoint_gradient synchronise the stream
+ * once to read the per-step sweep counts (and adjoint_gradient again to check
+ * that G is finite); their results are complete when they return OK.
+ * Concurrent calls on one plan need separate workspaces.
+ *
+ * Errors: every entry point returns LB_OK (0) or a negative code; no C++
+ * exception or abort crosses the ABI.  lb_last_error() returns a message for
+ * the last failing call of the calling thread.
+ */
+#ifndef LBX_H
+#define LBX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_EINVAL (-1)        /* null pointer, bad size, bad kind, bad option */
+#define LB_ENOMEM (-2)        /* workspace too small or device allocation failed */
+#define LB_EDEVICE (-3)       /* a HIP call failed; the message has the HIP error */
+#define LB_EUNSUPPORTED (-4)  /* inputs outside what the kernels handle */
+#define LB_ENONFINITE (-5)    /* NaN or Inf in the objective */
+
+#define LB_J_FROB 0  /* J = 1/2 ||rho_tar - rho||_F^2            (Sec. III, eq. Jmeasure) */
+#define LB_J_TR 1    /* J = 1 - Re Tr(rho_tar^+ rho)              (Sec. III, eq. Jmeasure) */
+
+/* Workspace queries (lb_workspace_bytes). */
+#define LB_OP_IMR_STEP 0
+#define LB_OP_FORWARD 1
+#define LB_OP_GRADIENT 2
+
+/* Plan options (lb_plan_set_option). */
+#define LB_OPT_PATH 0      /* 0 auto, 1 LDS-resident persistent kernels, 2 streaming sweeps */
+#define LB_OPT_SOLVE_TOL 1 /* fixed-point stage-solve bound, default 2^-53 */
+
+#define LB_LIMIT_QMAX 12   /* subsystems per system */
+#define LB_LIMIT_NLEV 31   /* levels per subsystem */
+
+/* One composite system (Sec. II).  Host memory; copied by lb_plan_create. */
+typedef struct {
+  int32_t Q;                /* number of subsystems, 1..LB_LIMIT_QMAX */
+  const int32_t *nlev;      /* [Q] levels n_q, 1..LB_LIMIT_NLEV; q = 0 most significant */
+  const double *detuning;   /* [Q] (omega_q - omega_q^rot)/2pi [GHz] */
+  const double *selfkerr;   /* [Q] xi_q/2pi [GHz]; term -xi_q/2 a^+a^+aa */
+  const double *crosskerr;  /* [Q*Q] row-major, entry [p*Q+q] with p<q is xi_pq/2pi [GHz] */
+  const double *T1;         /* [Q] decay times [ns] */
+  const double *T2;         /* [Q] dephasing times [ns] */
+  int32_t Ns;               /* B-spline basis functions per control, >= 3 */
+  int32_t Nf;               /* carrier waves per control, >= 1 */
+  const double *carrier;    /* [Q*Nf] Omega_q^f/2pi [GHz] */
+  double T;                 /* horizon [ns], > 0 */
+  int32_t NT;               /* implicit-midpoint steps, >= 1; dt = T/NT */
+} lb_system_desc;
+
+typedef struct lb_plan lb_plan;
+
+/* Validates nsys descriptions and builds the device tables of a plan:
+ * per-basis-index energies of H_sys and digit tables.  All systems of one
+ * plan must share NT.  Returns LB_EINVAL for invalid descriptions. */
+int lb_plan_create(const lb_system_desc *sys, int32_t nsys, lb_plan **out);
+void lb_plan_destroy(lb_plan *plan);
+
+/* N, number of real control parameters (2*Q*Ns*Nf) and NT of system `sys`. */
+int lb_plan_info(const lb_plan *plan, int32_t sys, int32_t *N, int32_t *nalpha, int32_t *NT);
+
+/* Sets an LB_OPT_* option; options apply to later calls. */
+int lb_plan_set_option(lb_plan *plan, int32_t option, double value);
+
+/* Bytes of workspace the operation `op` (LB_OP_*) needs for the batch
+ * batch_per_sys[nsys] (HOST).  For LB_OP_IMR_STEP, batch_per_sys may name
+ * one system by giving 0 for every other.  ckpt_every (LB_OP_GRADIENT)
+ * is the forward-state checkpoint interval of streamed systems: 1 keeps
+ * every state, 0 picks ceil(sqrt(NT)). */
+int lb_workspace_bytes(const lb_plan *plan, int32_t op, const int32_t *batch_per_sys,
+                       int32_t ckpt_every, size_t *bytes);
+
+/* Control values d_q(t_{j+1/2}) at every step midpoint of system `sys`
+ * (Sec. II eq. rotctrl; App. A: M is evaluated at t_j + dt/2), in rad/ns.
+ * alpha: DEVICE [nalpha]; table: DEVICE [NT][Q] complex128. */
+int control_table(const lb_plan *plan, int32_t sys, const double *alpha, void *table,
+                  void *stream);
+
+/* y = M(t) x, or y = M(t)^+ x when adjoint != 0, for B states of system
+ * `sys` (App. A eq. mastereq_vectorized, applied matrix-free).  M^+ is the
+ * adjoint for <A, B> = Tr(A^+ B).  alpha: DEVICE [nalpha] of this system;
+ * x, y: DEVICE [B][N][N] complex128, must not overlap.  B = 0 is a no-op. */
+int lindblad_apply(const lb_plan *plan, int32_t sys, double t, const double *alpha,
+                   const void *x, void *y, int32_t B, int32_t adjoint, void *stream);
+
+/* One implicit-midpoint step j (App. A eqs. IMR, linsystem_primal):
+ * solves (I - dt/2 M) z = q_in with M = M(t_j + dt/2) and writes
+ * q_out = q_in + dt M z.  With adjoint != 0 it takes the adjoint step of
+ * App. B eq. linsystem_adjoint: (I - dt/2 M^+) zh = q_in, q_out = q_in + dt M^+ zh.
+ * q_in, q_out: DEVICE [B][N][N], distinct.  ws: DEVICE, at least
+ * lb_workspace_bytes(LB_OP_IMR_STEP) bytes.  Uses the streaming sweeps. */
+int imr_step(const lb_plan *plan, int32_t sys, int32_t j, const double *alpha, const void *q_in,
+             void *q_out, int32_t B, int32_t adjoint, void *ws, size_t ws_bytes, void *stream);
+
+/* Integrates every state of every system from t = 0 to T (App. A).
+ * alpha: DEVICE, all systems concatenated; rho0, rhoT: DEVICE batched states;
+ * batch_per_sys: HOST [nsys].  ws: DEVICE, lb_workspace_bytes(LB_OP_FORWARD). */
+int forward_solve(const lb_plan *plan, const double *alpha, const void *rho0, void *rhoT,
+                  const int32_t *batch_per_sys, void *ws, size_t ws_bytes, void *stream);
+
+/* G_s = (1/M_s) sum_i beta_i J(rho_tar_i, rho_i(T)) + gamma2/2 ||alpha_s||^2 for
+ * every system s (Sec. III eq. optimproblem with gamma1 = 0), M_s = batch_per_sys[s].
+ * rhoT, rhotar: DEVICE batched states; beta: DEVICE [total states];
+ * alpha: DEVICE; G: DEVICE [nsys]; J: DEVICE [total states] or NULL, receives
+ * each J_i (unweighted).  ws: DEVICE, lb_workspace_bytes(LB_OP_FORWARD). */
+int objective(const lb_plan *plan, int32_t kind, const void *rhoT, const void *rhotar,
+              const double *beta, const int32_t *batch_per_sys, double gamma2,
+              const double *alpha, double *G, double *J, void *ws, size_t ws_bytes,
+              void *stream);
+
+/* Objective and its exact discrete gradient (App. B eqs. linsystem_adjoint,
+ * reducedgradient): forward solve with checkpoints, terminal condition
+ * (beta_i/M) dJ/d(conj q), adjoint implicit-midpoint sweep backwards with
+ * recomputation between checkpoints, and the gradient reduction
+ * dG/dalpha = sum_j dt Re <zh^j, dM/dalpha z^j> + gamma2 alpha.
+ * G: DEVICE [nsys]; grad: DEVICE like alpha; rhoT: DEVICE batched states or
+ * NULL.  ws: DEVICE, lb_workspace_bytes(LB_OP_GRADIENT, ckpt_every) bytes.
+ * Returns LB_ENONFINITE when a G is not finite. */
+int adjoint_gradient(const lb_plan *plan, int32_t kind, const double *alpha, const void *rho0,
+                     const void *rhotar, const double *beta, const int32_t *batch_per_sys,
+                     double gamma2, int32_t ckpt_every, double *G, double *grad, void *rhoT,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Message for the last non-zero return on the calling thread ("" if none). */
+const char *lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBX_H */

@@ -409,7 +409,7 @@ def _dcontrol_dalpha(sys, t):
 
 
 @_one_blas_thread
-def value_and_gradient(sys, alpha, rho0, rhotar, beta, kind, gamma2=0.0):
+def value_and_gradient(sys, alpha, rho0, rhotar, beta, kind, gamma2=0.0, return_final=False):
     """Objective G and its exact discrete gradient, App. B.
 
     Backward for j = NT-1..0 with M = M(t_j + dt/2):
@@ -421,7 +421,7 @@ def value_and_gradient(sys, alpha, rho0, rhotar, beta, kind, gamma2=0.0):
         dM/dalpha_k = c_k Sa_q + conj(c_k) Sad_q,
     with Sa_q, Sad_q the superoperators of X -> -i[a_q, X] and
     X -> -i[a_q^+, X] and c_k = d(d_q)/d(alpha_k).  Returns (G, grad) with
-    grad shaped like alpha.
+    grad shaped like alpha, and rho(T) as a third item with return_final.
     """
     N = sys.N
     dt = sys.dt
@@ -469,4 +469,4 @@ def value_and_gradient(sys, alpha, rho0, rhotar, beta, kind, gamma2=0.0):
                     grad[q] += dt * np.real(c[q] * u + np.conj(c[q]) * v)
                 qhat[b] = qhat[b] + dt * unvec(MHv(vec(zh)), N)
     grad = grad + gamma2 * np.asarray(alpha)
-    return G, grad
+    return (G, grad, rhoT) if return_final else (G, grad)

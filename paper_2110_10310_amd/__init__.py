@@ -1,0 +1,16 @@
+"""MI355X-native hot path of open-system optimal control (Lindblad master
+equation, implicit midpoint rule, discrete adjoint) behind the C ABI of
+liblbx.so.  See include/lbx.h for the ABI; ``api`` holds the Python binding.
+"""
+from . import _native  # noqa: F401  (raises ImportError when liblbx.so is missing)
+from .api import (  # noqa: F401
+    Plan,
+    control_table,
+    lindblad_apply,
+    imr_step,
+    forward_solve,
+    objective,
+    adjoint_gradient,
+    LindbladObjective,
+    lindblad_objective,
+)

@@ -1,0 +1,804 @@
+// C ABI of liblbx: plan construction, workspace layout and the entry points
+// declared in include/lbx.h.  Host code only; all arithmetic on states runs
+// in the kernels of kernels_stream.hip and kernels_lds.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lbx_host.hpp"
+
+using namespace lbx;
+
+namespace lbx {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return LB_EDEVICE;
+}
+
+}  // namespace lbx
+
+// ----------------------------------------------------------------------------
+// Batch metadata: everything derived from batch_per_sys, cached per plan.
+// ----------------------------------------------------------------------------
+namespace {
+
+struct LdsClass {
+  int block, ept;
+  int i0, i1;  // item range
+};
+
+struct BatchMeta {
+  std::vector<int32_t> batch;
+  int64_t total_entries = 0;
+  int total_states = 0;
+  std::vector<int64_t> sys_off;     // batched entry offset of system s
+  std::vector<int32_t> sys_state0;  // first global state of system s (nsys+1)
+  std::vector<int> path;            // 1 = LDS, 2 = streaming, 0 = empty system
+  // LDS path
+  std::vector<LdsItem> items;
+  std::vector<LdsClass> classes;
+  std::vector<int32_t> lds_sys, lds_item_range;
+  int64_t lds_hist_entries = 0;  // sum over items of (NT+1) N^2
+  int64_t lds_gpart = 0;         // doubles of gradient partials
+  // streaming path
+  std::vector<StreamSeg> segs;
+  std::vector<int32_t> seg_state0;
+  int64_t st_entries = 0;  // compact streamed entries
+  int64_t st_blocks = 0;
+  // device copies (one allocation)
+  void *dmem = nullptr;
+  LdsItem *d_items = nullptr;
+  int32_t *d_lds_sys = nullptr, *d_lds_item_range = nullptr;
+  StreamSeg *d_segs = nullptr;
+  int32_t *d_seg_state0 = nullptr;
+  int32_t *d_state_sys = nullptr;
+  int64_t *d_state_off = nullptr;
+  int32_t *d_sys_state0 = nullptr;
+};
+
+struct PlanExtra {
+  std::mutex mu;
+  std::map<std::vector<int32_t>, std::unique_ptr<BatchMeta>> batches;
+};
+
+std::mutex g_extra_mu;
+std::map<const lb_plan *, std::unique_ptr<PlanExtra>> g_extra;
+
+PlanExtra *extra_of(const lb_plan *p) {
+  std::lock_guard<std::mutex> g(g_extra_mu);
+  auto &e = g_extra[p];
+  if (!e) e.reset(new PlanExtra());
+  return e.get();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int path_for(const lb_plan *p, int s, int path) {
+  int blk, ept;
+  const bool fits = lds_shape(p->sys[s].N2, &blk, &ept);
+  if (path == 1) return fits ? 1 : -1;
+  if (path == 2) return 2;
+  return fits ? 1 : 2;
+}
+
+template <class T>
+T *carve(char *&cur, size_t n) {
+  T *r = reinterpret_cast<T *>(cur);
+  cur += align256(n * sizeof(T));
+  return r;
+}
+
+// path_override: -1 uses the plan's LB_OPT_PATH.
+int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int path_override = -1) {
+  const int nsys = (int)p->sys.size();
+  const int path = path_override >= 0 ? path_override : p->path;
+  std::vector<int32_t> key(batch, batch + nsys);
+  for (int s = 0; s < nsys; ++s)
+    if (key[s] < 0) return fail(LB_EINVAL, "batch_per_sys has a negative entry");
+  key.push_back(path);
+  PlanExtra *ex = extra_of(p);
+  std::lock_guard<std::mutex> g(ex->mu);
+  auto it = ex->batches.find(key);
+  if (it != ex->batches.end()) {
+    *out = it->second.get();
+    return LB_OK;
+  }
+  std::unique_ptr<BatchMeta> m(new BatchMeta());
+  m->batch.assign(key.begin(), key.begin() + nsys);
+  m->sys_off.resize(nsys);
+  m->sys_state0.resize(nsys + 1);
+  m->path.resize(nsys);
+  int64_t off = 0;
+  int st = 0;
+  for (int s = 0; s < nsys; ++s) {
+    m->sys_off[s] = off;
+    m->sys_state0[s] = st;
+    off += (int64_t)key[s] * p->sys[s].N2;
+    st += key[s];
+    if (key[s] == 0) {
+      m->path[s] = 0;
+      continue;
+    }
+    m->path[s] = path_for(p, s, path);
+    if (m->path[s] < 0)
+      return fail(LB_EUNSUPPORTED, "system " + std::to_string(s) +
+                                       " does not fit the LDS-resident kernels (N^2 > 4096)");
+  }
+  m->sys_state0[nsys] = st;
+  m->total_entries = off;
+  m->total_states = st;
+  // LDS items grouped by kernel class, systems contiguous within a class.
+  const int NT = p->NT;
+  std::map<std::pair<int, int>, std::vector<int>> cls;
+  for (int s = 0; s < nsys; ++s)
+    if (m->path[s] == 1) {
+      int blk, ept;
+      lds_shape(p->sys[s].N2, &blk, &ept);
+      cls[{blk, ept}].push_back(s);
+    }
+  for (auto &kv : cls) {
+    LdsClass c{kv.first.first, kv.first.second, (int)m->items.size(), 0};
+    for (int s : kv.second) {
+      const SysDev &S = p->sys[s];
+      m->lds_sys.push_back(s);
+      m->lds_item_range.push_back((int)m->items.size());
+      for (int b = 0; b < key[s]; ++b) {
+        LdsItem itm{};
+        itm.sys = s;
+        itm.b = b;
+        itm.off = m->sys_off[s] + (int64_t)b * S.N2;
+        itm.st_off = m->lds_hist_entries;
+        m->lds_hist_entries += (int64_t)(NT + 1) * S.N2;
+        itm.waves = c.block / 64;
+        itm.gp_off = m->lds_gpart;
+        m->lds_gpart += (int64_t)NT * itm.waves * 2 * S.Q;
+        itm.wterm = 0.0;  // set per call (beta lives on the device); see below
+        m->items.push_back(itm);
+      }
+    }
+    c.i1 = (int)m->items.size();
+    m->classes.push_back(c);
+  }
+  m->lds_item_range.push_back((int)m->items.size());
+  // Streaming segments.
+  int64_t coff = 0, blk = 0;
+  for (int s = 0; s < nsys; ++s)
+    if (m->path[s] == 2) {
+      StreamSeg sg{};
+      sg.sys = s;
+      sg.nstates = key[s];
+      sg.off = coff;
+      sg.boff = m->sys_off[s];
+      sg.count = (int64_t)key[s] * p->sys[s].N2;
+      sg.blk0 = blk;
+      coff += sg.count;
+      blk += (sg.count + STREAM_BLOCK - 1) / STREAM_BLOCK;
+      m->segs.push_back(sg);
+      m->seg_state0.push_back(m->sys_state0[s]);
+    }
+  m->st_entries = coff;
+  m->st_blocks = blk;
+  // Per-state tables for the objective.
+  std::vector<int32_t> state_sys(std::max(1, st));
+  std::vector<int64_t> state_off(std::max(1, st));
+  for (int s = 0; s < nsys; ++s)
+    for (int b = 0; b < key[s]; ++b) {
+      state_sys[m->sys_state0[s] + b] = s;
+      state_off[m->sys_state0[s] + b] = m->sys_off[s] + (int64_t)b * p->sys[s].N2;
+    }
+  // One device allocation for every table.
+  size_t bytes = align256(std::max<size_t>(1, m->items.size()) * sizeof(LdsItem)) +
+                 align256(std::max<size_t>(1, m->lds_sys.size()) * 4) +
+                 align256(m->lds_item_range.size() * 4) +
+                 align256(std::max<size_t>(1, m->segs.size()) * sizeof(StreamSeg)) +
+                 align256(std::max<size_t>(1, m->seg_state0.size()) * 4) +
+                 align256(state_sys.size() * 4) + align256(state_off.size() * 8) +
+                 align256(m->sys_state0.size() * 4);
+  LBX_HIP(hipMalloc(&m->dmem, bytes));
+  char *cur = (char *)m->dmem;
+  m->d_items = carve<LdsItem>(cur, std::max<size_t>(1, m->items.size()));
+  m->d_lds_sys = carve<int32_t>(cur, std::max<size_t>(1, m->lds_sys.size()));
+  m->d_lds_item_range = carve<int32_t>(cur, m->lds_item_range.size());
+  m->d_segs = carve<StreamSeg>(cur, std::max<size_t>(1, m->segs.size()));
+  m->d_seg_state0 = carve<int32_t>(cur, std::max<size_t>(1, m->seg_state0.size()));
+  m->d_state_sys = carve<int32_t>(cur, state_sys.size());
+  m->d_state_off = carve<int64_t>(cur, state_off.size());
+  m->d_sys_state0 = carve<int32_t>(cur, m->sys_state0.size());
+  if (!m->items.empty())
+    LBX_HIP(hipMemcpy(m->d_items, m->items.data(), m->items.size() * sizeof(LdsItem), hipMemcpyHostToDevice));
+  if (!m->lds_sys.empty())
+    LBX_HIP(hipMemcpy(m->d_lds_sys, m->lds_sys.data(), m->lds_sys.size() * 4, hipMemcpyHostToDevice));
+  LBX_HIP(hipMemcpy(m->d_lds_item_range, m->lds_item_range.data(), m->lds_item_range.size() * 4,
+                    hipMemcpyHostToDevice));
+  if (!m->segs.empty())
+    LBX_HIP(hipMemcpy(m->d_segs, m->segs.data(), m->segs.size() * sizeof(StreamSeg), hipMemcpyHostToDevice));
+  if (!m->seg_state0.empty())
+    LBX_HIP(hipMemcpy(m->d_seg_state0, m->seg_state0.data(), m->seg_state0.size() * 4, hipMemcpyHostToDevice));
+  LBX_HIP(hipMemcpy(m->d_state_sys, state_sys.data(), state_sys.size() * 4, hipMemcpyHostToDevice));
+  LBX_HIP(hipMemcpy(m->d_state_off, state_off.data(), state_off.size() * 8, hipMemcpyHostToDevice));
+  LBX_HIP(hipMemcpy(m->d_sys_state0, m->sys_state0.data(), m->sys_state0.size() * 4, hipMemcpyHostToDevice));
+  *out = m.get();
+  ex->batches[key] = std::move(m);
+  return LB_OK;
+}
+
+// Checkpoint bookkeeping of the streaming adjoint: states kept at multiples
+// of c below NT and at NT.
+int ckpt_interval(const lb_plan *p, int ckpt_every) {
+  if (ckpt_every > 0) return std::min(ckpt_every, p->NT);
+  return std::max(1, (int)std::ceil(std::sqrt((double)p->NT)));
+}
+int ckpt_count(int NT, int c) { return (NT - 1) / c + 2; }
+
+// Workspace layout of one operation.
+struct Layout {
+  size_t ctab = 0, ktab = 0, gstep = 0, objpart = 0, hist = 0, gpart = 0, items = 0;
+  size_t st_q0 = 0, st_q1 = 0, st_z0 = 0, st_z1 = 0, st_qh0 = 0, st_qh1 = 0, ckpt = 0, seg = 0,
+         st_gpart = 0, rhoT = 0;
+  size_t total = 0;
+  int c = 1, nck = 0;
+};
+
+Layout layout(const lb_plan *p, int op, const BatchMeta &m, int ckpt_every) {
+  Layout L;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = cur;
+    cur += align256(std::max<size_t>(bytes, 1));
+    return r;
+  };
+  const int nsys = (int)p->sys.size();
+  const size_t E = (size_t)m.st_entries * sizeof(double2);
+  L.ctab = take((size_t)p->ctab_total * sizeof(double2));
+  L.ktab = take((size_t)nsys * p->NT * 2 * sizeof(int32_t));
+  L.objpart = take((size_t)std::max(1, m.total_states) * 64 * sizeof(double));
+  L.items = take(std::max<size_t>(1, m.items.size()) * sizeof(LdsItem));
+  if (op == LB_OP_IMR_STEP) {
+    L.st_z0 = take(E);
+    L.st_z1 = take(E);
+  } else if (op == LB_OP_FORWARD) {
+    L.st_q0 = take(E);
+    L.st_q1 = take(E);
+    L.st_z0 = take(E);
+    L.st_z1 = take(E);
+  } else {
+    L.gstep = take((size_t)2 * p->ctab_total * sizeof(double));
+    L.hist = take((size_t)m.lds_hist_entries * sizeof(double2));
+    L.gpart = take((size_t)m.lds_gpart * sizeof(double));
+    L.rhoT = take((size_t)m.total_entries * sizeof(double2));
+    L.c = ckpt_interval(p, ckpt_every);
+    L.nck = ckpt_count(p->NT, L.c);
+    L.st_q0 = take(E);
+    L.st_q1 = take(E);
+    L.st_z0 = take(E);
+    L.st_z1 = take(E);
+    L.st_qh0 = take(E);
+    L.st_qh1 = take(E);
+    L.ckpt = take((size_t)L.nck * E);
+    L.seg = take((size_t)std::max(0, L.c - 1) * E);
+    L.st_gpart = take((size_t)std::max<int64_t>(1, m.st_blocks) * 2 * QMAX * sizeof(double));
+  }
+  L.total = cur;
+  return L;
+}
+
+int check_plan(const lb_plan *p) {
+  if (!p) return fail(LB_EINVAL, "plan is NULL");
+  return LB_OK;
+}
+
+int fetch_ktab(const lb_plan *p, const int32_t *d_ktab, std::vector<int32_t> &k, hipStream_t st) {
+  const size_t n = p->sys.size() * (size_t)p->NT * 2;
+  k.resize(n);
+  LBX_HIP(hipMemcpyAsync(k.data(), d_ktab, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  LBX_HIP(hipStreamSynchronize(st));
+  return LB_OK;
+}
+
+int check_k(const lb_plan *p, const std::vector<int32_t> &k, const BatchMeta &m) {
+  const int nsys = (int)p->sys.size();
+  for (int s = 0; s < nsys; ++s) {
+    if (m.path[s] == 0) continue;
+    for (int j = 0; j < p->NT; ++j)
+      if (k[((size_t)s * p->NT + j) * 2] < 1)
+        return fail(LB_EUNSUPPORTED,
+                    "system " + std::to_string(s) + " step " + std::to_string(j) +
+                        ": the stage-solve contraction bound is >= 0.5 (step or control amplitude too large)");
+  }
+  return LB_OK;
+}
+
+// Weights beta_b / M_s of the LDS items live on the device (beta is a device
+// array), so the adjoint kernels read them through a per-call item copy.
+__global__ void item_weights_kernel(LdsItem *items, int n, const double *beta,
+                                    const int32_t *sys_state0) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  LdsItem &it = items[k];
+  const int M = sys_state0[it.sys + 1] - sys_state0[it.sys];
+  it.wterm = beta[sys_state0[it.sys] + it.b] / (double)M;
+}
+
+int copy_segments(const BatchMeta &m, const double2 *src, bool src_batched, double2 *dst,
+                  hipStream_t st) {
+  for (const auto &sg : m.segs) {
+    const double2 *a = src + (src_batched ? sg.boff : sg.off);
+    double2 *b = dst + (src_batched ? sg.off : sg.boff);
+    LBX_HIP(hipMemcpyAsync(b, a, sg.count * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  }
+  return LB_OK;
+}
+
+// Streaming forward steps j0..j1-1 of every segment.  slot(j) returns the
+// buffer that receives q^j (j > j0); q^{j0} is `qstart`.
+template <class Slot>
+int stream_forward(const lb_plan *p, const BatchMeta &m, const std::vector<int32_t> &k,
+                   const double2 *ctab, int j0, int j1, const double2 *qstart, Slot slot,
+                   double2 *z0, double2 *z1, hipStream_t st) {
+  const double2 *cur = qstart;
+  for (int j = j0; j < j1; ++j) {
+    int K = 1;
+    for (const auto &sg : m.segs) K = std::max(K, (int)k[((size_t)sg.sys * p->NT + j) * 2 + 1]);
+    double2 *out = slot(j + 1);
+    for (int kk = 0; kk < K; ++kk) {
+      const bool last = kk == K - 1;
+      const double2 *zin = kk == 0 ? cur : (kk & 1 ? z0 : z1);
+      double2 *dst = last ? out : (kk & 1 ? z1 : z0);
+      int rc = launch_sweep(p, m.d_segs, (int)m.segs.size(), m.st_blocks, j, false, last, ctab, zin,
+                            cur, dst, st);
+      if (rc) return rc;
+    }
+    cur = out;
+  }
+  return LB_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Plan
+// ----------------------------------------------------------------------------
+extern "C" int lb_plan_create(const lb_system_desc *desc, int32_t nsys, lb_plan **out) {
+  if (!out) return fail(LB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc || nsys <= 0) return fail(LB_EINVAL, "no systems");
+  std::unique_ptr<lb_plan> p(new lb_plan());
+  std::vector<double> E;
+  std::vector<uint64_t> dg;
+  std::vector<double> car;
+  int64_t tab = 0, aoff = 0, coff = 0, ctoff = 0;
+  for (int s = 0; s < nsys; ++s) {
+    const lb_system_desc &d = desc[s];
+    const std::string who = "system " + std::to_string(s) + ": ";
+    if (d.Q < 1 || d.Q > QMAX) return fail(LB_EINVAL, who + "Q must be in 1..12");
+    if (!d.nlev || !d.detuning || !d.selfkerr || !d.crosskerr || !d.T1 || !d.T2 || !d.carrier)
+      return fail(LB_EINVAL, who + "NULL parameter array");
+    if (d.Ns < 3) return fail(LB_EINVAL, who + "Ns must be >= 3");
+    if (d.Nf < 1) return fail(LB_EINVAL, who + "Nf must be >= 1");
+    if (!(d.T > 0.0) || !std::isfinite(d.T)) return fail(LB_EINVAL, who + "T must be finite and > 0");
+    if (d.NT < 1) return fail(LB_EINVAL, who + "NT must be >= 1");
+    if (s > 0 && d.NT != desc[0].NT) return fail(LB_EINVAL, who + "all systems of a plan must share NT");
+    SysDev S{};
+    S.Q = d.Q;
+    int64_t N = 1;
+    for (int q = 0; q < d.Q; ++q) {
+      if (d.nlev[q] < 1 || d.nlev[q] > LB_LIMIT_NLEV) return fail(LB_EINVAL, who + "nlev must be in 1..31");
+      S.nlev[q] = d.nlev[q];
+      N *= d.nlev[q];
+      if (N > (1 << 20)) return fail(LB_EUNSUPPORTED, who + "N too large");
+    }
+    for (int q = 0; q < d.Q * d.Q; ++q)
+      if (!std::isfinite(d.crosskerr[q])) return fail(LB_EINVAL, who + "non-finite cross-Kerr");
+    for (int q = 0; q < d.Q; ++q) {
+      if (!std::isfinite(d.detuning[q]) || !std::isfinite(d.selfkerr[q]))
+        return fail(LB_EINVAL, who + "non-finite detuning or self-Kerr");
+      if (std::isnan(d.T1[q]) || std::isnan(d.T2[q])) return fail(LB_EINVAL, who + "NaN T1/T2");
+      for (int f = 0; f < d.Nf; ++f)
+        if (!std::isfinite(d.carrier[q * d.Nf + f])) return fail(LB_EINVAL, who + "non-finite carrier");
+    }
+    S.N = (int32_t)N;
+    S.N2 = N * N;
+    S.NT = d.NT;
+    S.Ns = d.Ns;
+    S.Nf = d.Nf;
+    S.nalpha = 2 * d.Q * d.Ns * d.Nf;
+    int64_t stride = 1;
+    for (int q = d.Q - 1; q >= 0; --q) {
+      S.stride[q] = (int32_t)stride;
+      stride *= d.nlev[q];
+    }
+    S.T = d.T;
+    S.dt = d.T / d.NT;
+    S.h = 0.5 * S.dt;
+    S.dtau = d.T / (d.Ns - 2);
+    double theta_jump = 0.0, gmax = 0.0;
+    for (int q = 0; q < d.Q; ++q) {
+      const int nl = d.nlev[q];
+      S.g1[q] = (std::isfinite(d.T1[q]) && d.T1[q] > 0) ? 1.0 / d.T1[q] : 0.0;
+      S.g2[q] = (std::isfinite(d.T2[q]) && d.T2[q] > 0) ? 1.0 / d.T2[q] : 0.0;
+      double cs = 0.0;
+      for (int n = 0; n < nl; ++n) {
+        const double v = (n > 0 ? std::sqrt((double)n) : 0.0) + (n + 1 < nl ? std::sqrt((double)(n + 1)) : 0.0);
+        cs = std::max(cs, v);
+      }
+      S.csum[q] = cs;
+      theta_jump += S.g1[q] * (nl - 1);
+      gmax += S.g1[q] * (nl - 1) + 0.5 * S.g2[q] * (nl - 1) * (nl - 1);
+    }
+    S.theta_jump = S.h * theta_jump;
+    // Energies of H_sys (Sec. II), rad/ns, and digit tables.
+    double emin = 1e300, emax = -1e300;
+    for (int64_t i = 0; i < N; ++i) {
+      int dig[QMAX];
+      int64_t rem = i;
+      uint64_t packed = 0;
+      for (int q = d.Q - 1; q >= 0; --q) {
+        dig[q] = (int)(rem % d.nlev[q]);
+        rem /= d.nlev[q];
+      }
+      double e = 0.0;
+      for (int q = 0; q < d.Q; ++q) {
+        packed |= (uint64_t)dig[q] << (DIGIT_BITS * q);
+        const double n = dig[q];
+        e += d.detuning[q] * n - 0.5 * d.selfkerr[q] * n * (n - 1.0);
+        for (int r = q + 1; r < d.Q; ++r) e -= d.crosskerr[q * d.Q + r] * n * dig[r];
+      }
+      e *= TWO_PI;
+      E.push_back(e);
+      dg.push_back(packed);
+      emin = std::min(emin, e);
+      emax = std::max(emax, e);
+    }
+    S.hDmax = S.h * ((emax - emin) + gmax);
+    S.tab_off = tab;
+    tab += N;
+    S.carrier_off = coff;
+    for (int q = 0; q < d.Q * d.Nf; ++q) car.push_back(d.carrier[q]);
+    coff += (int64_t)d.Q * d.Nf;
+    S.alpha_off = aoff;
+    aoff += S.nalpha;
+    S.ctab_off = ctoff;
+    ctoff += (int64_t)d.NT * d.Q;
+    p->sys.push_back(S);
+  }
+  p->NT = desc[0].NT;
+  p->ctab_total = ctoff;
+  if (hipGetDevice(&p->device) != hipSuccess) return fail(LB_EDEVICE, "no HIP device");
+  auto cleanup = [&](int rc) {
+    (void)hipFree(p->d_sys);
+    (void)hipFree(p->d_E);
+    (void)hipFree(p->d_desc);
+    (void)hipFree(p->d_carrier);
+    return rc;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&p->d_sys, p->sys.size() * sizeof(SysDev))) != hipSuccess ||
+      (e = hipMalloc(&p->d_E, E.size() * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&p->d_desc, dg.size() * sizeof(uint64_t))) != hipSuccess ||
+      (e = hipMalloc(&p->d_carrier, car.size() * sizeof(double))) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMalloc(plan tables)"));
+  if ((e = hipMemcpy(p->d_sys, p->sys.data(), p->sys.size() * sizeof(SysDev), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->d_E, E.data(), E.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->d_desc, dg.data(), dg.size() * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->d_carrier, car.data(), car.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy(plan tables)"));
+  *out = p.release();
+  return LB_OK;
+}
+
+extern "C" void lb_plan_destroy(lb_plan *p) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> g(g_extra_mu);
+    auto it = g_extra.find(p);
+    if (it != g_extra.end()) {
+      for (auto &kv : it->second->batches) (void)hipFree(kv.second->dmem);
+      g_extra.erase(it);
+    }
+  }
+  (void)hipFree(p->d_sys);
+  (void)hipFree(p->d_E);
+  (void)hipFree(p->d_desc);
+  (void)hipFree(p->d_carrier);
+  delete p;
+}
+
+extern "C" int lb_plan_info(const lb_plan *p, int32_t sys, int32_t *N, int32_t *nalpha, int32_t *NT) {
+  if (int rc = check_plan(p)) return rc;
+  if (sys < 0 || sys >= (int)p->sys.size()) return fail(LB_EINVAL, "sys out of range");
+  if (N) *N = p->sys[sys].N;
+  if (nalpha) *nalpha = p->sys[sys].nalpha;
+  if (NT) *NT = p->NT;
+  return LB_OK;
+}
+
+extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
+  if (int rc = check_plan(p)) return rc;
+  if (option == LB_OPT_PATH) {
+    if (value != 0 && value != 1 && value != 2) return fail(LB_EINVAL, "LB_OPT_PATH must be 0, 1 or 2");
+    p->path = (int)value;
+    return LB_OK;
+  }
+  if (option == LB_OPT_SOLVE_TOL) {
+    if (!(value > 0.0 && value < 1.0)) return fail(LB_EINVAL, "LB_OPT_SOLVE_TOL must be in (0, 1)");
+    p->tol = value;
+    return LB_OK;
+  }
+  return fail(LB_EINVAL, "unknown option");
+}
+
+extern "C" int lb_workspace_bytes(const lb_plan *p, int32_t op, const int32_t *batch_per_sys,
+                                  int32_t ckpt_every, size_t *bytes) {
+  if (int rc = check_plan(p)) return rc;
+  if (!batch_per_sys || !bytes) return fail(LB_EINVAL, "NULL argument");
+  if (op < LB_OP_IMR_STEP || op > LB_OP_GRADIENT) return fail(LB_EINVAL, "unknown op");
+  if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
+  BatchMeta *m;
+  // imr_step always streams.
+  if (int rc = build_batch(p, batch_per_sys, &m, op == LB_OP_IMR_STEP ? 2 : -1)) return rc;
+  *bytes = layout(p, op, *m, ckpt_every).total;
+  return LB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Entry points
+// ----------------------------------------------------------------------------
+extern "C" int control_table(const lb_plan *p, int32_t sys, const double *alpha, void *table,
+                             void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (sys < 0 || sys >= (int)p->sys.size()) return fail(LB_EINVAL, "sys out of range");
+  if (!alpha || !table) return fail(LB_EINVAL, "NULL argument");
+  // alpha is this system's block; the kernel adds alpha_off, so shift it back.
+  const double *abase = alpha - p->sys[sys].alpha_off;
+  return launch_control_table(p, sys, 1, abase, (double2 *)table, p->sys[sys].ctab_off, nullptr,
+                              (hipStream_t)stream);
+}
+
+extern "C" int lindblad_apply(const lb_plan *p, int32_t sys, double t, const double *alpha,
+                              const void *x, void *y, int32_t B, int32_t adjoint, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (sys < 0 || sys >= (int)p->sys.size()) return fail(LB_EINVAL, "sys out of range");
+  if (B < 0) return fail(LB_EINVAL, "B must be >= 0");
+  if (B == 0) return LB_OK;
+  if (!alpha || !x || !y) return fail(LB_EINVAL, "NULL argument");
+  if (!std::isfinite(t)) return fail(LB_EINVAL, "t must be finite");
+  const size_t bytes = (size_t)B * p->sys[sys].N2 * sizeof(double2);
+  const char *xa = (const char *)x, *ya = (const char *)y;
+  if (xa < ya + bytes && ya < xa + bytes) return fail(LB_EINVAL, "x and y overlap");
+  return launch_apply(p, sys, t, alpha, (const double2 *)x, (double2 *)y, B, adjoint != 0,
+                      (hipStream_t)stream);
+}
+
+extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *alpha,
+                        const void *q_in, void *q_out, int32_t B, int32_t adjoint, void *ws,
+                        size_t ws_bytes, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  const int nsys = (int)p->sys.size();
+  if (sys < 0 || sys >= nsys) return fail(LB_EINVAL, "sys out of range");
+  if (j < 0 || j >= p->NT) return fail(LB_EINVAL, "step index out of range");
+  if (B < 0) return fail(LB_EINVAL, "B must be >= 0");
+  if (B == 0) return LB_OK;
+  if (!alpha || !q_in || !q_out || !ws) return fail(LB_EINVAL, "NULL argument");
+  if (q_in == q_out) return fail(LB_EINVAL, "q_in and q_out must differ");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int32_t> batch(nsys, 0);
+  batch[sys] = B;
+  BatchMeta *m;
+  int rc = build_batch(p, batch.data(), &m, 2);
+  if (rc) return rc;
+  const Layout L = layout(p, LB_OP_IMR_STEP, *m, 1);
+  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  char *w = (char *)ws;
+  double2 *ctab = (double2 *)(w + L.ctab);
+  int32_t *ktab = (int32_t *)(w + L.ktab);
+  const double *abase = alpha - p->sys[sys].alpha_off;
+  if ((rc = launch_control_table(p, sys, 1, abase, ctab, 0, ktab, st))) return rc;
+  std::vector<int32_t> k;
+  if ((rc = fetch_ktab(p, ktab, k, st))) return rc;
+  const int K = k[((size_t)sys * p->NT + j) * 2 + 1];
+  if (K < 1) return fail(LB_EUNSUPPORTED, "stage-solve contraction bound >= 0.5 at this step");
+  double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
+  const double2 *qi = (const double2 *)q_in;
+  for (int kk = 0; kk < K; ++kk) {
+    const bool last = kk == K - 1;
+    const double2 *zin = kk == 0 ? qi : (kk & 1 ? z0 : z1);
+    double2 *dst = last ? (double2 *)q_out : (kk & 1 ? z1 : z0);
+    if ((rc = launch_sweep(p, m->d_segs, (int)m->segs.size(), m->st_blocks, j, adjoint != 0, last,
+                           ctab, zin, qi, dst, st)))
+      return rc;
+  }
+  return LB_OK;
+}
+
+static int run_forward(const lb_plan *p, const BatchMeta &m, const Layout &L, char *w,
+                       const double *alpha, const double2 *rho0, double2 *rhoT, double2 *hist,
+                       std::vector<int32_t> &k, hipStream_t st, bool keep_ckpt) {
+  double2 *ctab = (double2 *)(w + L.ctab);
+  int32_t *ktab = (int32_t *)(w + L.ktab);
+  int rc;
+  if ((rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, st))) return rc;
+  if ((rc = fetch_ktab(p, ktab, k, st))) return rc;
+  if ((rc = check_k(p, k, m))) return rc;
+  // LDS-resident systems: one persistent launch per kernel class.
+  for (const auto &c : m.classes) {
+    if ((rc = launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab, rho0,
+                                 rhoT, hist, st)))
+      return rc;
+  }
+  if (m.segs.empty()) return LB_OK;
+  // Streamed systems: one launch per sweep over all of them.
+  double2 *q0 = (double2 *)(w + L.st_q0), *q1 = (double2 *)(w + L.st_q1);
+  double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
+  const size_t E = (size_t)m.st_entries;
+  double2 *ck = keep_ckpt ? (double2 *)(w + L.ckpt) : nullptr;
+  double2 *start = keep_ckpt ? ck : q0;
+  if ((rc = copy_segments(m, rho0, true, start, st))) return rc;
+  const int NT = p->NT, c = L.c;
+  const double2 *last_out = start;
+  auto slot = [&](int j) -> double2 * {
+    double2 *r;
+    if (keep_ckpt && (j % c == 0 || j == NT)) r = ck + (size_t)(j == NT ? L.nck - 1 : j / c) * E;
+    else r = (last_out == q0) ? q1 : q0;
+    last_out = r;
+    return r;
+  };
+  if ((rc = stream_forward(p, m, k, ctab, 0, NT, start, slot, z0, z1, st))) return rc;
+  return copy_segments(m, last_out, false, rhoT, st);
+}
+
+extern "C" int forward_solve(const lb_plan *p, const double *alpha, const void *rho0, void *rhoT,
+                             const int32_t *batch_per_sys, void *ws, size_t ws_bytes, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!alpha || !rho0 || !rhoT || !batch_per_sys || !ws) return fail(LB_EINVAL, "NULL argument");
+  BatchMeta *m;
+  if (int rc = build_batch(p, batch_per_sys, &m)) return rc;
+  if (m->total_entries == 0) return LB_OK;
+  const Layout L = layout(p, LB_OP_FORWARD, *m, 1);
+  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  std::vector<int32_t> k;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = run_forward(p, *m, L, (char *)ws, alpha, (const double2 *)rho0, (double2 *)rhoT, nullptr,
+                       k, st, false);
+  if (rc) return rc;
+  LBX_HIP(hipStreamSynchronize(st));
+  return LB_OK;
+}
+
+extern "C" int objective(const lb_plan *p, int32_t kind, const void *rhoT, const void *rhotar,
+                         const double *beta, const int32_t *batch_per_sys, double gamma2,
+                         const double *alpha, double *G, double *J, void *ws, size_t ws_bytes,
+                         void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (kind != LB_J_FROB && kind != LB_J_TR) return fail(LB_EINVAL, "unknown merit functional");
+  if (!rhoT || !rhotar || !beta || !batch_per_sys || !alpha || !G || !ws)
+    return fail(LB_EINVAL, "NULL argument");
+  if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
+  BatchMeta *m;
+  if (int rc = build_batch(p, batch_per_sys, &m)) return rc;
+  const Layout L = layout(p, LB_OP_FORWARD, *m, 1);
+  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  char *w = (char *)ws;
+  return launch_objective(p, kind, (const double2 *)rhoT, (const double2 *)rhotar, beta,
+                          m->d_state_sys, m->d_state_off, m->d_sys_state0, m->total_states, gamma2,
+                          alpha, (double *)(w + L.objpart), J, G, (hipStream_t)stream);
+}
+
+extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *alpha,
+                                const void *rho0, const void *rhotar, const double *beta,
+                                const int32_t *batch_per_sys, double gamma2, int32_t ckpt_every,
+                                double *G, double *grad, void *rhoT_out, void *ws, size_t ws_bytes,
+                                void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (kind != LB_J_FROB && kind != LB_J_TR) return fail(LB_EINVAL, "unknown merit functional");
+  if (!alpha || !rho0 || !rhotar || !beta || !batch_per_sys || !G || !grad || !ws)
+    return fail(LB_EINVAL, "NULL argument");
+  if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
+  if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
+  BatchMeta *m;
+  if (int rc = build_batch(p, batch_per_sys, &m)) return rc;
+  const Layout L = layout(p, LB_OP_GRADIENT, *m, ckpt_every);
+  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  int rc;
+  double2 *rhoT = rhoT_out ? (double2 *)rhoT_out : (double2 *)(w + L.rhoT);
+  double2 *hist = (double2 *)(w + L.hist);
+  double *gstep = (double *)(w + L.gstep);
+  double2 *ctab = (double2 *)(w + L.ctab);
+  int32_t *ktab = (int32_t *)(w + L.ktab);
+  LBX_HIP(hipMemsetAsync(gstep, 0, (size_t)2 * p->ctab_total * sizeof(double), st));
+  std::vector<int32_t> k;
+  if ((rc = run_forward(p, *m, L, w, alpha, (const double2 *)rho0, rhoT, hist, k, st, true))) return rc;
+  if ((rc = launch_objective(p, kind, rhoT, (const double2 *)rhotar, beta, m->d_state_sys,
+                             m->d_state_off, m->d_sys_state0, m->total_states, gamma2, alpha,
+                             (double *)(w + L.objpart), nullptr, G, st)))
+    return rc;
+  // LDS-resident adjoint.
+  if (!m->items.empty()) {
+    LdsItem *items = (LdsItem *)(w + L.items);
+    LBX_HIP(hipMemcpyAsync(items, m->d_items, m->items.size() * sizeof(LdsItem),
+                           hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(item_weights_kernel, dim3(((int)m->items.size() + 127) / 128), dim3(128), 0,
+                       st, items, (int)m->items.size(), beta, m->d_sys_state0);
+    LBX_HIP(hipGetLastError());
+    double *gpart = (double *)(w + L.gpart);
+    for (const auto &c : m->classes)
+      if ((rc = launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab, ktab,
+                                   (const double2 *)rhotar, hist, gpart, st)))
+        return rc;
+    if ((rc = launch_lds_grad_reduce(p, m->d_lds_item_range, (int)m->lds_sys.size(), m->d_lds_sys,
+                                     items, gpart, gstep, st)))
+      return rc;
+  }
+  // Streamed adjoint with checkpoint recomputation.
+  if (!m->segs.empty()) {
+    const size_t E = (size_t)m->st_entries;
+    const int NT = p->NT, c = L.c;
+    double2 *ck = (double2 *)(w + L.ckpt), *seg = (double2 *)(w + L.seg);
+    double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
+    double2 *qh[2] = {(double2 *)(w + L.st_qh0), (double2 *)(w + L.st_qh1)};
+    double *sgp = (double *)(w + L.st_gpart);
+    const int nseg = (int)m->segs.size();
+    if ((rc = launch_terminal(p, kind, m->d_segs, nseg, m->st_blocks, ck + (size_t)(L.nck - 1) * E,
+                              (const double2 *)rhotar, beta, m->d_seg_state0, qh[0], st)))
+      return rc;
+    int cur = 0;
+    const int nsegs_t = (NT + c - 1) / c;
+    for (int sgi = nsegs_t - 1; sgi >= 0; --sgi) {
+      const int j0 = sgi * c, j1 = std::min(NT, j0 + c);
+      auto slot = [&](int j) -> double2 * {
+        if (j == j0) return ck + (size_t)(j0 / c) * E;
+        if (j == j1) return ck + (size_t)(j1 == NT ? L.nck - 1 : j1 / c) * E;
+        return seg + (size_t)(j - j0 - 1) * E;
+      };
+      // Recompute q^{j0+1} .. q^{j1-1} from the checkpoint.
+      if (j1 - j0 > 1)
+        if ((rc = stream_forward(p, *m, k, ctab, j0, j1 - 1, slot(j0), slot, z0, z1, st))) return rc;
+      for (int j = j1 - 1; j >= j0; --j) {
+        int K = 1;
+        for (const auto &sg : m->segs) K = std::max(K, (int)k[((size_t)sg.sys * NT + j) * 2 + 1]);
+        const double2 *qin = qh[cur];
+        double2 *qout = qh[cur ^ 1];
+        for (int kk = 0; kk < K; ++kk) {
+          const bool last = kk == K - 1;
+          const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
+          double2 *dst = last ? qout : (kk & 1 ? z1 : z0);
+          if ((rc = launch_sweep(p, m->d_segs, nseg, m->st_blocks, j, true, last, ctab, zin, qin, dst, st)))
+            return rc;
+        }
+        if ((rc = launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, qout, qin, slot(j), slot(j + 1),
+                                     sgp, st)))
+          return rc;
+        if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, j, sgp, gstep, st))) return rc;
+        cur ^= 1;
+      }
+    }
+  }
+  if ((rc = launch_grad_contract(p, gstep, alpha, gamma2, grad, st))) return rc;
+  std::vector<double> hG(p->sys.size());
+  LBX_HIP(hipMemcpyAsync(hG.data(), G, hG.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  LBX_HIP(hipStreamSynchronize(st));
+  for (size_t s = 0; s < hG.size(); ++s)
+    if (!std::isfinite(hG[s]) && m->batch[s] > 0)
+      return fail(LB_ENONFINITE, "objective of system " + std::to_string(s) + " is not finite");
+  return LB_OK;
+}
+
+extern "C" const char *lb_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,309 @@
+// LDS-resident persistent kernels for small systems (N^2 <= 4096).
+//
+// One workgroup owns one state of one system for the whole time loop: the
+// stage iterate lives in two LDS buffers, the state q, the stage weights w
+// and the digit tables of the thread's entries live in registers, and HBM is
+// touched once per step only to store the state history that the adjoint
+// pass reads.  The forward kernel runs every implicit-midpoint step of
+// App. A; the adjoint kernel runs the discrete adjoint of App. B backwards
+// and emits the per-step gradient integrands.
+#include <hip/hip_runtime.h>
+
+#include "lbx_host.hpp"
+
+namespace lbx {
+
+template <int BLOCK, int EPT>
+__global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
+    const SysDev *__restrict__ sysv, const LdsItem *__restrict__ items,
+    const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
+    const double2 *__restrict__ ctab, const int32_t *__restrict__ ktab, int NT,
+    const double2 *__restrict__ rho0, double2 *__restrict__ rhoT, double2 *__restrict__ states) {
+  extern __shared__ double2 zbuf[];  // two stage buffers of N^2 entries
+  __shared__ double sq[SQRT_TABLE];
+  __shared__ double2 dsh[2][QMAX];
+  const LdsItem it = items[blockIdx.x];
+  const SysDev &S = sysv[it.sys];
+  const int tid = threadIdx.x;
+  const int N = S.N;
+  const int64_t N2 = S.N2;
+  const double h = S.h;
+  if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
+
+  double2 qv[EPT], wv[EPT], zn[EPT];
+  uint64_t di[EPT], dj[EPT];
+  int ee[EPT];
+  bool ok[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * BLOCK;
+    ok[k] = e < N2;
+    ee[k] = ok[k] ? e : 0;
+    const int i = ee[k] / N;
+    const int jj = ee[k] - i * N;
+    di[k] = desc[S.tab_off + i];
+    dj[k] = desc[S.tab_off + jj];
+    const double gam = diag_rate(S, di[k], dj[k]);
+    wv[k] = stage_weight(h, gam, Etab[S.tab_off + i] - Etab[S.tab_off + jj], false);
+    qv[k] = ok[k] ? rho0[it.off + e] : make_double2(0.0, 0.0);
+    zn[k] = make_double2(0.0, 0.0);
+    if (states && ok[k]) states[it.st_off + e] = qv[k];
+  }
+  double2 *buf[2] = {zbuf, zbuf + N2};
+  int cb = 0;
+  for (int j = 0; j < NT; ++j) {
+    // z0 = w q, then K sweeps z <- w (q + h O z) (App. A eq. linsystem_primal).
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+      if (ok[k]) buf[cb][ee[k]] = cmul(wv[k], qv[k]);
+    if (tid < S.Q) dsh[j & 1][tid] = ctab[S.ctab_off + (int64_t)j * S.Q + tid];
+    __syncthreads();
+    const int K = ktab[((int64_t)it.sys * NT + j) * 2 + 0];
+    for (int kk = 0; kk < K; ++kk) {
+      const double2 *src = buf[cb];
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        if (ok[k]) {
+          const double2 acc = offdiag<false>(S, di[k], dj[k], ee[k], dsh[j & 1], sq,
+                                             [&](int64_t idx) { return src[idx]; });
+          zn[k] = cmul(wv[k], cadd(qv[k], cscale(h, acc)));
+        }
+      }
+      if (kk + 1 < K) {
+        double2 *dst = buf[cb ^ 1];
+#pragma unroll
+        for (int k = 0; k < EPT; ++k)
+          if (ok[k]) dst[ee[k]] = zn[k];
+        __syncthreads();
+        cb ^= 1;
+      }
+    }
+    // q^{j+1} = q^j + dt M z = 2 z - q^j (App. A eq. IMR with h M z = z - q).
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      qv[k] = csub(cscale(2.0, zn[k]), qv[k]);
+      if (states && ok[k]) states[it.st_off + (int64_t)(j + 1) * N2 + ee[k]] = qv[k];
+    }
+    cb ^= 1;
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k)
+    if (ok[k]) rhoT[it.off + ee[k]] = qv[k];
+}
+
+template <int BLOCK, int EPT>
+__global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
+    const SysDev *__restrict__ sysv, const LdsItem *__restrict__ items,
+    const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
+    const double2 *__restrict__ ctab, const int32_t *__restrict__ ktab, int NT, int kind,
+    const double2 *__restrict__ rhotar, const double2 *__restrict__ states,
+    double *__restrict__ gpart) {
+  extern __shared__ double2 zbuf[];
+  __shared__ double sq[SQRT_TABLE];
+  __shared__ double2 dsh[2][QMAX];
+  constexpr int WAVES = BLOCK / 64;
+  const LdsItem it = items[blockIdx.x];
+  const SysDev &S = sysv[it.sys];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int N = S.N;
+  const int64_t N2 = S.N2;
+  const double h = S.h;
+  const int Q = S.Q;
+  if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
+
+  double2 qh[EPT], wv[EPT], zn[EPT], qn[EPT];
+  uint64_t di[EPT], dj[EPT];
+  int ee[EPT];
+  bool ok[EPT];
+  const double2 *hist = states + it.st_off;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * BLOCK;
+    ok[k] = e < N2;
+    ee[k] = ok[k] ? e : 0;
+    const int i = ee[k] / N;
+    const int jj = ee[k] - i * N;
+    di[k] = desc[S.tab_off + i];
+    dj[k] = desc[S.tab_off + jj];
+    const double gam = diag_rate(S, di[k], dj[k]);
+    wv[k] = stage_weight(h, gam, Etab[S.tab_off + i] - Etab[S.tab_off + jj], true);
+    // Terminal condition (App. B): qh = (beta/M) dJ/d(conj q) at q = rho(T).
+    qn[k] = ok[k] ? hist[(int64_t)NT * N2 + ee[k]] : make_double2(0.0, 0.0);
+    const double2 t = ok[k] ? rhotar[it.off + ee[k]] : make_double2(0.0, 0.0);
+    qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qn[k], t)) : cscale(-it.wterm, t);
+    zn[k] = make_double2(0.0, 0.0);
+  }
+  double2 *buf[2] = {zbuf, zbuf + N2};
+  int cb = 0;
+  for (int j = NT - 1; j >= 0; --j) {
+    // (I - h M^+) zh = qh^{j+1} (App. B eq. linsystem_adjoint).
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+      if (ok[k]) buf[cb][ee[k]] = cmul(wv[k], qh[k]);
+    if (tid < Q) dsh[j & 1][tid] = ctab[S.ctab_off + (int64_t)j * Q + tid];
+    // Forward state q^j, consumed after the sweeps so that its load overlaps them.
+    double2 qj[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) qj[k] = ok[k] ? hist[(int64_t)j * N2 + ee[k]] : make_double2(0.0, 0.0);
+    __syncthreads();
+    const int K = ktab[((int64_t)it.sys * NT + j) * 2 + 0];
+    for (int kk = 0; kk < K; ++kk) {
+      const double2 *src = buf[cb];
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        if (ok[k]) {
+          const double2 acc = offdiag<true>(S, di[k], dj[k], ee[k], dsh[j & 1], sq,
+                                            [&](int64_t idx) { return src[idx]; });
+          zn[k] = cmul(wv[k], cadd(qh[k], cscale(h, acc)));
+        }
+      }
+      if (kk + 1 < K) {
+        double2 *dst = buf[cb ^ 1];
+#pragma unroll
+        for (int k = 0; k < EPT; ++k)
+          if (ok[k]) dst[ee[k]] = zn[k];
+        __syncthreads();
+        cb ^= 1;
+      }
+    }
+    // Gradient integrands need zh at neighbours: publish it.
+    double2 *zhb = buf[cb ^ 1];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+      if (ok[k]) zhb[ee[k]] = zn[k];
+    __syncthreads();
+    for (int q = 0; q < Q; ++q) {
+      double gp = 0.0, gq = 0.0;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        if (ok[k]) {
+          const double2 z = cscale(0.5, cadd(qj[k], qn[k]));
+          grad_term(S, q, di[k], dj[k], ee[k], z, sq, [&](int64_t idx) { return zhb[idx]; }, gp,
+                    gq);
+        }
+      }
+      gp = wave_sum<64>(gp);
+      gq = wave_sum<64>(gq);
+      if (lane == 0) {
+        double *dstp = gpart + it.gp_off + ((int64_t)j * WAVES + wave) * 2 * Q + 2 * q;
+        dstp[0] = gp;
+        dstp[1] = gq;
+      }
+    }
+    // qh^j = qh^{j+1} + dt M^+ zh = 2 zh - qh^{j+1}.
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      qh[k] = csub(cscale(2.0, zn[k]), qh[k]);
+      qn[k] = qj[k];
+    }
+    // The next step writes its first iterate into buf[cb]: the last sweep's
+    // reads of it finished before the barrier above.
+  }
+}
+
+bool lds_shape(int64_t n2, int *block, int *ept) {
+  if (n2 <= 64) { *block = 64; *ept = 1; }
+  else if (n2 <= 128) { *block = 128; *ept = 1; }
+  else if (n2 <= 256) { *block = 256; *ept = 1; }
+  else if (n2 <= 512) { *block = 512; *ept = 1; }
+  else if (n2 <= 1024) { *block = 1024; *ept = 1; }
+  else if (n2 <= 2048) { *block = 1024; *ept = 2; }
+  else if (n2 <= 4096) { *block = 1024; *ept = 4; }
+  else return false;
+  return true;
+}
+
+template <int BLOCK, int EPT>
+static int launch_fwd_t(const lb_plan *p, const LdsItem *d_items, int nitems, size_t shmem,
+                        const double2 *ctab, const int32_t *ktab, const double2 *rho0,
+                        double2 *rhoT, double2 *states, hipStream_t st) {
+  auto kern = lds_forward_kernel<BLOCK, EPT>;
+  LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shmem));
+  hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E,
+                     p->d_desc, ctab, ktab, p->NT, rho0, rhoT, states);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+template <int BLOCK, int EPT>
+static int launch_adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, size_t shmem,
+                        int kind, const double2 *ctab, const int32_t *ktab,
+                        const double2 *rhotar, const double2 *states, double *gpart,
+                        hipStream_t st) {
+  auto kern = lds_adjoint_kernel<BLOCK, EPT>;
+  LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shmem));
+  hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E,
+                     p->d_desc, ctab, ktab, p->NT, kind, rhotar, states, gpart);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+static size_t lds_bytes(int block, int ept) { return (size_t)2 * block * ept * sizeof(double2); }
+
+int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
+                       const double2 *ctab, const int32_t *ktab, const double2 *rho0,
+                       double2 *rhoT, double2 *states, hipStream_t st) {
+  if (nitems == 0) return LB_OK;
+  const size_t sh = lds_bytes(block, ept);
+#define LBX_FWD(Bk, Ep) \
+  if (block == Bk && ept == Ep) return launch_fwd_t<Bk, Ep>(p, d_items, nitems, sh, ctab, ktab, rho0, rhoT, states, st);
+  LBX_FWD(64, 1) LBX_FWD(128, 1) LBX_FWD(256, 1) LBX_FWD(512, 1) LBX_FWD(1024, 1)
+  LBX_FWD(1024, 2) LBX_FWD(1024, 4)
+#undef LBX_FWD
+  return fail(LB_EUNSUPPORTED, "no LDS-resident kernel for this state size");
+}
+
+int launch_lds_adjoint(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
+                       int kind, const double2 *ctab, const int32_t *ktab, const double2 *rhotar,
+                       const double2 *states, double *gpart, hipStream_t st) {
+  if (nitems == 0) return LB_OK;
+  const size_t sh = lds_bytes(block, ept);
+#define LBX_ADJ(Bk, Ep) \
+  if (block == Bk && ept == Ep) return launch_adj_t<Bk, Ep>(p, d_items, nitems, sh, kind, ctab, ktab, rhotar, states, gpart, st);
+  LBX_ADJ(64, 1) LBX_ADJ(128, 1) LBX_ADJ(256, 1) LBX_ADJ(512, 1) LBX_ADJ(1024, 1)
+  LBX_ADJ(1024, 2) LBX_ADJ(1024, 4)
+#undef LBX_ADJ
+  return fail(LB_EUNSUPPORTED, "no LDS-resident kernel for this state size");
+}
+
+// gstep[s][j][c] = sum over the items of s and their wavefronts (fixed order).
+__global__ void lds_grad_reduce_kernel(const SysDev *__restrict__ sysv,
+                                       const int32_t *__restrict__ item_range,
+                                       const int32_t *__restrict__ sys_ids,
+                                       const LdsItem *__restrict__ items, int NT,
+                                       const double *__restrict__ gpart,
+                                       double *__restrict__ gstep) {
+  const int ls = blockIdx.y;
+  const int s = sys_ids[ls];
+  const SysDev &S = sysv[s];
+  const int twoQ = 2 * S.Q;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)NT * twoQ) return;
+  const int j = (int)(idx / twoQ);
+  const int c = (int)(idx - (int64_t)j * twoQ);
+  double v = 0.0;
+  for (int k = item_range[ls]; k < item_range[ls + 1]; ++k) {
+    const LdsItem &it = items[k];
+    const double *g = gpart + it.gp_off + (int64_t)j * it.waves * twoQ + c;
+    for (int w = 0; w < it.waves; ++w) v += g[w * twoQ];
+  }
+  gstep[2 * S.ctab_off + idx] = v;
+}
+
+int launch_lds_grad_reduce(const lb_plan *p, const int32_t *d_item_range, int nsys_lds,
+                           const int32_t *d_sys_ids, const LdsItem *d_items, const double *gpart,
+                           double *gstep, hipStream_t st) {
+  if (nsys_lds == 0) return LB_OK;
+  int qmax = 1;
+  for (const auto &s : p->sys) qmax = s.Q > qmax ? s.Q : qmax;
+  const int64_t n = (int64_t)p->NT * 2 * qmax;
+  hipLaunchKernelGGL(lds_grad_reduce_kernel, dim3((unsigned)((n + 255) / 256), nsys_lds), dim3(256),
+                     0, st, p->d_sys, d_item_range, d_sys_ids, d_items, p->NT, gpart, gstep);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+}  // namespace lbx

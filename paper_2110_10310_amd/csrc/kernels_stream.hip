@@ -1,0 +1,434 @@
+// Streaming kernels: control table, matrix-free apply of M(t), one
+// fixed-point sweep of the implicit-midpoint stage solve, the adjoint
+// gradient integrands, objective reductions and the gradient contraction.
+// Every kernel reads and writes states in HBM (or cache); the LDS-resident
+// persistent kernels for small systems live in kernels_lds.hip.
+#include <hip/hip_runtime.h>
+
+#include "lbx_host.hpp"
+
+namespace lbx {
+
+// ----------------------------------------------------------------------------
+// Control table (Sec. II eq. rotctrl, evaluated at step midpoints, App. A)
+// and the number of stage-solve sweeps per step.
+//
+// The stage system (I - h M) z = q, h = dt/2, M = D + O, is solved by the
+// fixed-point iteration z <- w (q + h O z) with w = (1 - h D)^-1.  Since
+// Re D <= 0, |w| <= 1 and the iteration contracts in the max norm with
+// factor theta <= h max_row sum|O| <= h sum_q (2 |d_q| c_q + (n_q - 1)/T1_q).
+// Started from z0 = w q the error after K sweeps is <= theta^(K+1) |z|;
+// started from z0 = q it is <= theta^K (h max|D| + theta) |z|.
+// ----------------------------------------------------------------------------
+__global__ void control_table_kernel(const SysDev *__restrict__ sysv, int s0, int NT,
+                                     const double *__restrict__ alpha,
+                                     const double *__restrict__ carrier, double2 *__restrict__ ctab,
+                                     int64_t ctab_shift, int32_t *__restrict__ ktab, double tol) {
+  const int s = s0 + (int)blockIdx.y;
+  const SysDev &S = sysv[s];
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j >= NT) return;
+  const double t = ((double)j + 0.5) * S.dt;
+  double theta = S.theta_jump;
+  for (int q = 0; q < S.Q; ++q) {
+    const double2 d = control_value(S, alpha + S.alpha_off, carrier + S.carrier_off, q, t);
+    ctab[S.ctab_off - ctab_shift + (int64_t)j * S.Q + q] = d;
+    theta += S.h * 2.0 * hypot(d.x, d.y) * S.csum[q];
+  }
+  if (ktab) {
+    int klds, kst;
+    if (!(theta < 0.5)) {
+      klds = kst = -1;
+    } else if (theta <= 0.0) {
+      klds = kst = 1;
+    } else {
+      const double lt = log(theta);
+      const double ltol = log(tol);
+      klds = (int)ceil(ltol / lt) - 1;
+      klds = klds < 1 ? 1 : klds;
+      const double e0 = S.hDmax + theta;
+      kst = e0 <= tol ? 1 : (int)ceil((ltol - log(e0)) / lt);
+      kst = kst < 1 ? 1 : kst;
+    }
+    ktab[((int64_t)s * NT + j) * 2 + 0] = klds;
+    ktab[((int64_t)s * NT + j) * 2 + 1] = kst;
+  }
+}
+
+int launch_control_table(const lb_plan *p, int s0, int nsys, const double *alpha, double2 *ctab,
+                         int64_t ctab_shift, int32_t *ktab, hipStream_t st) {
+  dim3 grid((p->NT + 255) / 256, nsys);
+  hipLaunchKernelGGL(control_table_kernel, grid, dim3(256), 0, st, p->d_sys, s0, p->NT, alpha,
+                     p->d_carrier, ctab, ctab_shift, ktab, p->tol);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// y = M(t) x or M(t)^+ x for B states of one system.
+// ----------------------------------------------------------------------------
+template <bool ADJ>
+__global__ __launch_bounds__(STREAM_BLOCK) void apply_kernel(
+    const SysDev *__restrict__ sysv, int sys, double t, const double *__restrict__ alpha,
+    const double *__restrict__ carrier, const double *__restrict__ Etab,
+    const uint64_t *__restrict__ desc, const double2 *__restrict__ x, double2 *__restrict__ y,
+    int64_t total) {
+  __shared__ double sq[SQRT_TABLE];
+  __shared__ double2 dq[QMAX];
+  const SysDev &S = sysv[sys];
+  const int tid = threadIdx.x;
+  if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
+  if (tid < S.Q) dq[tid] = control_value(S, alpha, carrier + S.carrier_off, tid, t);
+  __syncthreads();
+  const int64_t g = (int64_t)blockIdx.x * STREAM_BLOCK + tid;
+  if (g >= total) return;
+  const int64_t b = g / S.N2;
+  const int64_t r = g - b * S.N2;
+  const int i = (int)(r / S.N);
+  const int jj = (int)(r - (int64_t)i * S.N);
+  const uint64_t di = desc[S.tab_off + i], dj = desc[S.tab_off + jj];
+  const double gam = diag_rate(S, di, dj);
+  const double dE = Etab[S.tab_off + i] - Etab[S.tab_off + jj];
+  const double2 *xs = x + b * S.N2;
+  const double2 acc = offdiag<ADJ>(S, di, dj, r, dq, sq, [&](int64_t idx) { return xs[idx]; });
+  y[g] = cadd(acc, cmul(diag_coef(gam, dE, ADJ), xs[r]));
+}
+
+int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const double2 *x,
+                 double2 *y, int B, bool adj, hipStream_t st) {
+  const int64_t total = (int64_t)B * p->sys[sys].N2;
+  if (total == 0) return LB_OK;
+  const int64_t nblk = (total + STREAM_BLOCK - 1) / STREAM_BLOCK;
+  if (adj)
+    hipLaunchKernelGGL(apply_kernel<true>, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st,
+                       p->d_sys, sys, t, alpha, p->d_carrier, p->d_E, p->d_desc, x, y, total);
+  else
+    hipLaunchKernelGGL(apply_kernel<false>, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st,
+                       p->d_sys, sys, t, alpha, p->d_carrier, p->d_E, p->d_desc, x, y, total);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// One sweep of the stage solve over a list of segments (all states of some
+// systems), at step j:  out = w (q + h O zin), or on the last sweep of a step
+// the implicit-midpoint update out = 2 z - q (= q + dt M z, since
+// h M z = z - q for the converged stage vector).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int find_segment(const StreamSeg *segs, int nseg, int64_t blk) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].blk0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool ADJ, bool LAST>
+__global__ __launch_bounds__(STREAM_BLOCK) void sweep_kernel(
+    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg,
+    const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
+    const double2 *__restrict__ ctab, int j, const double2 *__restrict__ zin,
+    const double2 *__restrict__ qin, double2 *__restrict__ out) {
+  __shared__ double sq[SQRT_TABLE];
+  __shared__ double2 dq[QMAX];
+  __shared__ int sseg;
+  const int tid = threadIdx.x;
+  if (tid == 0) sseg = find_segment(segs, nseg, blockIdx.x);
+  if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
+  __syncthreads();
+  const StreamSeg &sg = segs[sseg];
+  const SysDev &S = sysv[sg.sys];
+  if (tid < S.Q) dq[tid] = ctab[S.ctab_off + (int64_t)j * S.Q + tid];
+  __syncthreads();
+  const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + tid;
+  if (local >= sg.count) return;
+  const int64_t b = local / S.N2;
+  const int64_t r = local - b * S.N2;
+  const int i = (int)(r / S.N);
+  const int jj = (int)(r - (int64_t)i * S.N);
+  const uint64_t di = desc[S.tab_off + i], dj = desc[S.tab_off + jj];
+  const double gam = diag_rate(S, di, dj);
+  const double dE = Etab[S.tab_off + i] - Etab[S.tab_off + jj];
+  const double2 w = stage_weight(S.h, gam, dE, ADJ);
+  const int64_t base = sg.off + b * S.N2;
+  const double2 acc = offdiag<ADJ>(S, di, dj, r, dq, sq, [&](int64_t idx) { return zin[base + idx]; });
+  const double2 qv = qin[base + r];
+  const double2 zn = cmul(w, cadd(qv, cscale(S.h, acc)));
+  out[base + r] = LAST ? csub(cscale(2.0, zn), qv) : zn;
+}
+
+int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
+                 bool adj, bool last, const double2 *ctab, const double2 *zin, const double2 *qin,
+                 double2 *out, hipStream_t st) {
+  if (nblk == 0) return LB_OK;
+  dim3 g((unsigned)nblk), b(STREAM_BLOCK);
+  if (adj) {
+    if (last)
+      hipLaunchKernelGGL((sweep_kernel<true, true>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E,
+                         p->d_desc, ctab, j, zin, qin, out);
+    else
+      hipLaunchKernelGGL((sweep_kernel<true, false>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E,
+                         p->d_desc, ctab, j, zin, qin, out);
+  } else {
+    if (last)
+      hipLaunchKernelGGL((sweep_kernel<false, true>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E,
+                         p->d_desc, ctab, j, zin, qin, out);
+    else
+      hipLaunchKernelGGL((sweep_kernel<false, false>), g, b, 0, st, p->d_sys, d_segs, nseg,
+                         p->d_E, p->d_desc, ctab, j, zin, qin, out);
+  }
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Gradient integrands of one step for streamed systems (App. B eq.
+// reducedgradient):  zh = (qh^j + qh^{j+1})/2 is the adjoint stage vector,
+// z = (q^j + q^{j+1})/2 the forward one.  Per-block partial sums.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
+    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg,
+    const uint64_t *__restrict__ desc, const double2 *__restrict__ qh0,
+    const double2 *__restrict__ qh1, const double2 *__restrict__ q0,
+    const double2 *__restrict__ q1, double *__restrict__ gpart) {
+  __shared__ double sq[SQRT_TABLE];
+  __shared__ int sseg;
+  __shared__ double red[STREAM_BLOCK / 64][2 * QMAX];
+  const int tid = threadIdx.x;
+  if (tid == 0) sseg = find_segment(segs, nseg, blockIdx.x);
+  if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
+  __syncthreads();
+  const StreamSeg &sg = segs[sseg];
+  const SysDev &S = sysv[sg.sys];
+  const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + tid;
+  const bool ok = local < sg.count;
+  const int64_t b = ok ? local / S.N2 : 0;
+  const int64_t r = ok ? local - b * S.N2 : 0;
+  const int i = (int)(r / S.N);
+  const int jj = (int)(r - (int64_t)i * S.N);
+  const uint64_t di = desc[S.tab_off + i], dj = desc[S.tab_off + jj];
+  const int64_t base = sg.off + b * S.N2;
+  const double2 z = ok ? cscale(0.5, cadd(q0[base + r], q1[base + r])) : make_double2(0.0, 0.0);
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int q = 0; q < S.Q; ++q) {
+    double gp = 0.0, gq = 0.0;
+    if (ok)
+      grad_term(S, q, di, dj, r, z, sq,
+                [&](int64_t idx) { return cscale(0.5, cadd(qh0[base + idx], qh1[base + idx])); },
+                gp, gq);
+    gp = wave_sum<64>(gp);
+    gq = wave_sum<64>(gq);
+    if (lane == 0) {
+      red[wv][2 * q] = gp;
+      red[wv][2 * q + 1] = gq;
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * S.Q) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < STREAM_BLOCK / 64; ++w) v += red[w][tid];
+    gpart[(int64_t)blockIdx.x * 2 * QMAX + tid] = v;
+  }
+}
+
+int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk,
+                       const double2 *qh0, const double2 *qh1, const double2 *q0,
+                       const double2 *q1, double *gpart, hipStream_t st) {
+  if (nblk == 0) return LB_OK;
+  hipLaunchKernelGGL(stream_grad_kernel, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st, p->d_sys,
+                     d_segs, nseg, p->d_desc, qh0, qh1, q0, q1, gpart);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+// Sum the block partials of each segment (fixed order) into gstep[s][j][2Q].
+__global__ __launch_bounds__(256) void stream_grad_finalize_kernel(
+    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int j,
+    const double *__restrict__ gpart, double *__restrict__ gstep) {
+  __shared__ double red[4];
+  const StreamSeg &sg = segs[blockIdx.x];
+  const SysDev &S = sysv[sg.sys];
+  const int64_t nb = (sg.count + STREAM_BLOCK - 1) / STREAM_BLOCK;
+  const int tid = threadIdx.x;
+  for (int c = 0; c < 2 * S.Q; ++c) {
+    double v = 0.0;
+    for (int64_t k = tid; k < nb; k += 256) v += gpart[(sg.blk0 + k) * 2 * QMAX + c];
+    v = wave_sum<64>(v);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) gstep[2 * S.ctab_off + (int64_t)j * 2 * S.Q + c] = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
+}
+
+int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int j,
+                                const double *gpart, double *gstep, hipStream_t st) {
+  if (nseg == 0) return LB_OK;
+  hipLaunchKernelGGL(stream_grad_finalize_kernel, dim3(nseg), dim3(256), 0, st, p->d_sys, d_segs, j,
+                     gpart, gstep);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint terminal condition (App. B): qh = (beta_i/M) dJ/d(conj q).
+//   J_Frob: rho(T) - rho_tar;   J_Tr: -rho_tar.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(STREAM_BLOCK) void terminal_kernel(
+    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg, int kind,
+    const double2 *__restrict__ rhoT, const double2 *__restrict__ rhotar,
+    const double *__restrict__ beta, const int32_t *__restrict__ seg_state0,
+    double2 *__restrict__ qh) {
+  __shared__ int sseg;
+  if (threadIdx.x == 0) sseg = find_segment(segs, nseg, blockIdx.x);
+  __syncthreads();
+  const StreamSeg &sg = segs[sseg];
+  const SysDev &S = sysv[sg.sys];
+  const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + threadIdx.x;
+  if (local >= sg.count) return;
+  const int64_t b = local / S.N2;
+  const double wgt = beta[seg_state0[sseg] + b] / (double)sg.nstates;
+  const int64_t e = sg.off + local;
+  const double2 t = rhotar[sg.boff + local];
+  qh[e] = kind == LB_J_FROB ? cscale(wgt, csub(rhoT[e], t)) : cscale(-wgt, t);
+}
+
+int launch_terminal(const lb_plan *p, int kind, const StreamSeg *d_segs, int nseg, int64_t nblk,
+                    const double2 *rhoT, const double2 *rhotar, const double *beta,
+                    const int32_t *d_seg_state0, double2 *qh, hipStream_t st) {
+  if (nblk == 0) return LB_OK;
+  hipLaunchKernelGGL(terminal_kernel, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st, p->d_sys,
+                     d_segs, nseg, kind, rhoT, rhotar, beta, d_seg_state0, qh);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Objective (Sec. III eqs. optimproblem, Jmeasure), two deterministic passes:
+// per-state block partials of sum |rho - rho_tar|^2 (Frobenius) or
+// Re sum conj(rho_tar) rho (trace), then per-system G.
+// ----------------------------------------------------------------------------
+constexpr int OBJ_PARTS = 64;
+
+__global__ __launch_bounds__(256) void objective_partial_kernel(
+    const SysDev *__restrict__ sysv, int kind, const double2 *__restrict__ rhoT,
+    const double2 *__restrict__ rhotar, const int32_t *__restrict__ state_sys,
+    const int64_t *__restrict__ state_off, double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int state = blockIdx.y;
+  const SysDev &S = sysv[state_sys[state]];
+  const int64_t off = state_off[state];
+  double v = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < S.N2; e += (int64_t)OBJ_PARTS * 256) {
+    const double2 r = rhoT[off + e], t = rhotar[off + e];
+    if (kind == LB_J_FROB) {
+      const double dx = r.x - t.x, dy = r.y - t.y;
+      v += dx * dx + dy * dy;
+    } else {
+      v += t.x * r.x + t.y * r.y;
+    }
+  }
+  v = wave_sum<64>(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[(int64_t)state * OBJ_PARTS + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void objective_final_kernel(const SysDev *__restrict__ sysv, int nsys, int kind,
+                                       const double *__restrict__ partial,
+                                       const double *__restrict__ beta,
+                                       const int32_t *__restrict__ sys_state0, double gamma2,
+                                       const double *__restrict__ alpha, double *__restrict__ J,
+                                       double *__restrict__ G) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys) return;
+  const SysDev &S = sysv[s];
+  const int st0 = sys_state0[s], st1 = sys_state0[s + 1];
+  double acc = 0.0;
+  for (int st = st0; st < st1; ++st) {
+    double v = 0.0;
+    for (int k = 0; k < OBJ_PARTS; ++k) v += partial[(int64_t)st * OBJ_PARTS + k];
+    const double Jst = kind == LB_J_FROB ? 0.5 * v : 1.0 - v;
+    if (J) J[st] = Jst;
+    acc += beta[st] * Jst;
+  }
+  double reg = 0.0;
+  for (int k = 0; k < S.nalpha; ++k) {
+    const double a = alpha[S.alpha_off + k];
+    reg += a * a;
+  }
+  const int M = st1 - st0;
+  G[s] = (M > 0 ? acc / (double)M : 0.0) + 0.5 * gamma2 * reg;
+}
+
+int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const double2 *rhotar,
+                     const double *beta, const int32_t *d_state_sys, const int64_t *d_state_off,
+                     const int32_t *d_sys_state0, int nstates, double gamma2, const double *alpha,
+                     double *partial, double *J, double *G, hipStream_t st) {
+  if (nstates > 0) {
+    hipLaunchKernelGGL(objective_partial_kernel, dim3(OBJ_PARTS, nstates), dim3(256), 0, st,
+                       p->d_sys, kind, rhoT, rhotar, d_state_sys, d_state_off, partial);
+    LBX_HIP(hipGetLastError());
+  }
+  const int nsys = (int)p->sys.size();
+  hipLaunchKernelGGL(objective_final_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, p->d_sys, nsys,
+                     kind, partial, beta, d_sys_state0, gamma2, alpha, J, G);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Gradient contraction (App. B eq. reducedgradient through the control
+// parameterisation of eq. rotctrl):
+//   dG/dRe alpha_q^{s,f} = dt sum_j 2pi S_s(t) [gp cos(W t) + gq sin(W t)] + gamma2 Re alpha
+//   dG/dIm alpha_q^{s,f} = dt sum_j 2pi S_s(t) [-gp sin(W t) + gq cos(W t)] + gamma2 Im alpha
+// with t = t_{j+1/2}, W = 2 pi Omega_q^f, gp/gq the per-step integrands.
+// ----------------------------------------------------------------------------
+__global__ void grad_contract_kernel(const SysDev *__restrict__ sysv, int nsys,
+                                     const double *__restrict__ gstep,
+                                     const double *__restrict__ alpha,
+                                     const double *__restrict__ carrier, double gamma2,
+                                     double *__restrict__ grad, int64_t total) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  int s = 0;
+  while (s + 1 < nsys && sysv[s + 1].alpha_off <= k) ++s;
+  const SysDev &S = sysv[s];
+  const int64_t loc = k - S.alpha_off;
+  const int r = (int)(loc % 2);
+  const int f = (int)((loc / 2) % S.Nf);
+  const int sp = (int)((loc / (2 * S.Nf)) % S.Ns);
+  const int q = (int)(loc / (2 * S.Nf * S.Ns));
+  const double Om = TWO_PI * carrier[S.carrier_off + q * S.Nf + f];
+  int j0 = (int)floor((sp - 2.0) * S.dtau / S.dt - 0.5) - 1;
+  int j1 = (int)ceil((sp + 1.0) * S.dtau / S.dt) + 1;
+  j0 = j0 < 0 ? 0 : j0;
+  j1 = j1 > S.NT - 1 ? S.NT - 1 : j1;
+  double acc = 0.0;
+  for (int j = j0; j <= j1; ++j) {
+    const double t = ((double)j + 0.5) * S.dt;
+    const double B = bspline2(t / S.dtau - (double)sp + 0.5);
+    if (B == 0.0) continue;
+    double sn, cs;
+    sincos(Om * t, &sn, &cs);
+    const double gp = gstep[2 * S.ctab_off + (int64_t)j * 2 * S.Q + 2 * q];
+    const double gq = gstep[2 * S.ctab_off + (int64_t)j * 2 * S.Q + 2 * q + 1];
+    acc += B * (r == 0 ? gp * cs + gq * sn : -gp * sn + gq * cs);
+  }
+  grad[k] = TWO_PI * S.dt * acc + gamma2 * alpha[k];
+}
+
+int launch_grad_contract(const lb_plan *p, const double *gstep, const double *alpha,
+                         double gamma2, double *grad, hipStream_t st) {
+  const int nsys = (int)p->sys.size();
+  const int64_t total = p->sys[nsys - 1].alpha_off + p->sys[nsys - 1].nalpha;
+  hipLaunchKernelGGL(grad_contract_kernel, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, st,
+                     p->d_sys, nsys, gstep, alpha, p->d_carrier, gamma2, grad, total);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+}  // namespace lbx

@@ -1,0 +1,206 @@
+// Device-side data structures and the matrix-free Lindbladian stencil.
+//
+// Notation (paper Sec. II, App. A): an entry (i, j) of a density matrix has
+// row digits n_q (levels of basis index i) and column digits m_q (levels of
+// j), subsystem 0 most significant.  M = D + O where
+//   D_ij = -i (E_i - E_j) - gamma_ij,
+//   gamma_ij = sum_q [ (n_q + m_q) / (2 T1_q) + (n_q - m_q)^2 / (2 T2_q) ]
+// holds H_sys (diagonal: detuning, self- and cross-Kerr), the dephasing
+// dissipator and the decay anticommutator, and O holds the control
+// commutator -i[H_c, .] (ladder shifts of one row or one column digit) and
+// the decay jump a rho a^+ / T1 (shift of both digits of one subsystem).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbx.h"
+
+namespace lbx {
+
+constexpr int QMAX = LB_LIMIT_QMAX;
+constexpr int DIGIT_BITS = 5;
+constexpr int SQRT_TABLE = 33;  // sqrt(k) for k = 0..32
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+// Per-system constants.  One array of these lives in device memory per plan.
+struct SysDev {
+  int32_t Q, N, NT, Ns, Nf, nalpha;
+  int64_t N2;
+  int32_t nlev[QMAX];
+  int32_t stride[QMAX];  // basis-index stride of subsystem q
+  double g1[QMAX];       // 1/T1_q, 0 when off
+  double g2[QMAX];       // 1/T2_q, 0 when off
+  double csum[QMAX];     // max over n of sqrt(n)[n>0] + sqrt(n+1)[n+1<nlev]
+  double T, dt, h;       // h = dt/2
+  double dtau;           // B-spline knot spacing T/(Ns-2)
+  double theta_jump;     // h * sum_q (nlev_q - 1)/T1_q
+  double hDmax;          // h * max_ij |D_ij|
+  int64_t tab_off;       // first row of this system in the energy/digit tables
+  int64_t carrier_off;   // first entry in the carrier table ([Q][Nf])
+  int64_t alpha_off;     // first entry in a concatenated alpha
+  int64_t ctab_off;      // first entry in the control table ([NT][Q] complex)
+};
+
+__device__ __forceinline__ int digit(uint64_t packed, int q) {
+  return (int)((packed >> (DIGIT_BITS * q)) & ((1u << DIGIT_BITS) - 1));
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// gamma_ij: decay anticommutator plus dephasing, both real and diagonal.
+__device__ __forceinline__ double diag_rate(const SysDev &S, uint64_t di, uint64_t dj) {
+  double g = 0.0;
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    if (q < S.Q) {
+      const int n = digit(di, q), m = digit(dj, q);
+      const double dnm = (double)(n - m);
+      g += 0.5 * (S.g1[q] * (double)(n + m) + S.g2[q] * dnm * dnm);
+    }
+  }
+  return g;
+}
+
+// D_ij (forward) or conj(D_ij) (adjoint).
+__device__ __forceinline__ double2 diag_coef(double gam, double dE, bool adj) {
+  return make_double2(-gam, adj ? dE : -dE);
+}
+
+// w_ij = 1 / (1 - h D_ij) (forward) or its conjugate (adjoint).
+// 1 - h D_ij = (1 + h gamma_ij) + i h (E_i - E_j).
+__device__ __forceinline__ double2 stage_weight(double h, double gam, double dE, bool adj) {
+  const double re = 1.0 + h * gam;
+  const double im = h * dE;
+  const double inv = 1.0 / (re * re + im * im);
+  return make_double2(re * inv, adj ? im * inv : -im * inv);
+}
+
+// The off-diagonal part O x at flat entry r = i*N + j of one state (forward)
+// or O^+ x (adjoint).  `ld(idx)` returns x at flat entry idx of the same
+// state; it is only called with in-range indices.  dq[q] = d_q(t) in rad/ns.
+//
+// Control commutator, forward:
+//   -i [ d sqrt(n+1) x_{i+e,j} + d* sqrt(n) x_{i-e,j}
+//        - d sqrt(m) x_{i,j-e} - d* sqrt(m+1) x_{i,j+e} ]
+//   = -i (d U + d* V),  U = sqrt(n+1) x_{i+e,j} - sqrt(m) x_{i,j-e},
+//                        V = sqrt(n) x_{i-e,j} - sqrt(m+1) x_{i,j+e};
+// the adjoint (+i [H_c, .]) flips the sign.  Decay jump, forward:
+// sqrt((n+1)(m+1))/T1 x_{i+e,j+e}; adjoint: sqrt(n m)/T1 x_{i-e,j-e}.
+template <bool ADJ, class Load>
+__device__ __forceinline__ double2 offdiag(const SysDev &S, uint64_t di, uint64_t dj, int64_t r,
+                                           const double2 *dq, const double *sq, Load ld) {
+  double2 acc = make_double2(0.0, 0.0);
+  const int64_t N = S.N;
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    if (q < S.Q) {
+      const int n = digit(di, q), m = digit(dj, q);
+      const int nl = S.nlev[q];
+      const int64_t s1 = S.stride[q];
+      const int64_t sN = s1 * N;
+      const bool rp = n + 1 < nl, rm = n > 0, cp = m + 1 < nl, cm = m > 0;
+      const double2 xrp = ld(rp ? r + sN : r);
+      const double2 xrm = ld(rm ? r - sN : r);
+      const double2 xcp = ld(cp ? r + s1 : r);
+      const double2 xcm = ld(cm ? r - s1 : r);
+      const double arp = rp ? sq[n + 1] : 0.0;
+      const double arm = sq[n];
+      const double acp = cp ? sq[m + 1] : 0.0;
+      const double acm = sq[m];
+      const double2 U = csub(cscale(arp, xrp), cscale(acm, xcm));
+      const double2 V = csub(cscale(arm, xrm), cscale(acp, xcp));
+      const double2 Sm = cadd(U, V);
+      const double2 Dv = csub(U, V);
+      const double a = dq[q].x, b = dq[q].y;
+      double2 ctl = make_double2(a * Sm.y + b * Dv.x, -a * Sm.x + b * Dv.y);
+      if (ADJ) ctl = make_double2(-ctl.x, -ctl.y);
+      double2 jmp;
+      if (!ADJ) {
+        const bool ok = rp && cp;
+        const double c = ok ? S.g1[q] * sq[n + 1] * sq[m + 1] : 0.0;
+        jmp = cscale(c, ld(ok ? r + sN + s1 : r));
+      } else {
+        const bool ok = rm && cm;
+        const double c = ok ? S.g1[q] * sq[n] * sq[m] : 0.0;
+        jmp = cscale(c, ld(ok ? r - sN - s1 : r));
+      }
+      acc = cadd(acc, cadd(ctl, jmp));
+    }
+  }
+  return acc;
+}
+
+// Gradient integrands of one entry for subsystem q (App. B eq.
+// reducedgradient through p_q = Re d_q and q_q = Im d_q):
+//   gp += Re <zh, X_q z>, X_q = -i[a_q + a_q^+, .] = dM/dp_q,
+//   gq += Re <zh, Y_q z>, Y_q = [a_q - a_q^+, .] = dM/dq_q,
+// evaluated as -Re <X_q zh, z> and -Re <Y_q zh, z> (X_q and Y_q are
+// skew-adjoint), so only zh needs neighbours: with U, V as in `offdiag`
+// built on zh, X_q zh = -i (U + V) and Y_q zh = U - V.
+template <class Load>
+__device__ __forceinline__ void grad_term(const SysDev &S, int q, uint64_t di, uint64_t dj,
+                                          int64_t r, double2 z, const double *sq, Load ldzh,
+                                          double &gp, double &gq) {
+  const int64_t N = S.N;
+  const int n = digit(di, q), m = digit(dj, q);
+  const int nl = S.nlev[q];
+  const int64_t s1 = S.stride[q];
+  const int64_t sN = s1 * N;
+  const bool rp = n + 1 < nl, rm = n > 0, cp = m + 1 < nl, cm = m > 0;
+  const double2 xrp = ldzh(rp ? r + sN : r);
+  const double2 xrm = ldzh(rm ? r - sN : r);
+  const double2 xcp = ldzh(cp ? r + s1 : r);
+  const double2 xcm = ldzh(cm ? r - s1 : r);
+  const double2 U = csub(cscale(rp ? sq[n + 1] : 0.0, xrp), cscale(sq[m], xcm));
+  const double2 V = csub(cscale(sq[n], xrm), cscale(cp ? sq[m + 1] : 0.0, xcp));
+  const double2 Sm = cadd(U, V);
+  const double2 Dv = csub(U, V);
+  gp += Sm.x * z.y - Sm.y * z.x;
+  gq -= Dv.x * z.x + Dv.y * z.y;
+}
+
+// Quadratic B-spline basis S_s(t) = B(t/dtau - s + 1/2), B the centred
+// quadratic B-spline (Sec. II, knot spacing dtau, centres (s - 1/2) dtau).
+__device__ __forceinline__ double bspline2(double x) {
+  const double ax = fabs(x);
+  if (ax <= 0.5) return 0.75 - ax * ax;
+  if (ax <= 1.5) {
+    const double u = ax - 1.5;
+    return 0.5 * u * u;
+  }
+  return 0.0;
+}
+
+// d_q(t) of eq. (rotctrl) in rad/ns; alpha points at this system's [Q][Ns][Nf][2].
+__device__ inline double2 control_value(const SysDev &S, const double *alpha, const double *carrier,
+                                        int q, double t) {
+  double re = 0.0, im = 0.0;
+  for (int s = 0; s < S.Ns; ++s) {
+    const double B = bspline2(t / S.dtau - (double)s + 0.5);
+    if (B == 0.0) continue;
+    for (int f = 0; f < S.Nf; ++f) {
+      const double ar = alpha[((q * S.Ns + s) * S.Nf + f) * 2 + 0];
+      const double ai = alpha[((q * S.Ns + s) * S.Nf + f) * 2 + 1];
+      double sn, cs;
+      sincos(TWO_PI * carrier[q * S.Nf + f] * t, &sn, &cs);
+      re += B * (ar * cs - ai * sn);
+      im += B * (ar * sn + ai * cs);
+    }
+  }
+  return make_double2(TWO_PI * re, TWO_PI * im);
+}
+
+template <int W>
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+  return v;
+}
+
+}  // namespace lbx

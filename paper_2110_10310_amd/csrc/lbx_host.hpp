@@ -1,0 +1,113 @@
+// Host-side plan structure and kernel launchers shared by the library's
+// translation units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lbx.h"
+#include "lbx_device.hpp"
+
+struct lb_plan {
+  std::vector<lbx::SysDev> sys;   // host copy of the per-system constants
+  lbx::SysDev *d_sys = nullptr;   // device copy
+  double *d_E = nullptr;          // energies of H_sys per basis index [rad/ns]
+  uint64_t *d_desc = nullptr;     // packed subsystem digits per basis index
+  double *d_carrier = nullptr;    // carriers [GHz], per system [Q][Nf]
+  int32_t NT = 0;                 // common number of steps
+  int64_t ctab_total = 0;         // sum over systems of NT*Q
+  int path = 0;                   // LB_OPT_PATH
+  double tol = 1.1102230246251565e-16;  // LB_OPT_SOLVE_TOL (2^-53)
+  int device = 0;
+};
+
+namespace lbx {
+
+// Work item of the LDS-resident persistent kernels: one state of one system.
+struct LdsItem {
+  int32_t sys;
+  int32_t b;          // state index within its system
+  int64_t off;        // first entry of the state in the batched buffers
+  int64_t st_off;     // first entry of this item's state history (NT+1 states)
+  int64_t gp_off;     // first double of this item's gradient partials [NT][waves][2Q]
+  double wterm;       // beta_b / M_s (terminal condition weight)
+  int32_t waves;      // wavefronts per block of this item's kernel
+  int32_t pad;
+};
+
+// Segment of the streaming kernels: all states of one system.
+struct StreamSeg {
+  int32_t sys;
+  int32_t nstates;
+  int64_t off;        // first entry in the compact work buffers of streamed states
+  int64_t boff;       // first entry in the caller's batched buffers
+  int64_t count;      // nstates * N^2
+  int64_t blk0;       // first block of the segment in a launch
+};
+
+constexpr int STREAM_BLOCK = 256;
+
+// Thread-local error message helpers.
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define LBX_HIP(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return lbx::hip_fail(_e, #call); \
+  } while (0)
+
+// ---- launchers (each returns LB_OK or an error code) ----
+
+// Control table of systems s0..s0+nsys-1; entry (s, j, q) goes to
+// ctab[ctab_off(s) - ctab_shift + j*Q + q].  ktab may be NULL.
+int launch_control_table(const lb_plan *p, int s0, int nsys, const double *alpha, double2 *ctab,
+                         int64_t ctab_shift, int32_t *ktab, hipStream_t st);
+
+int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const double2 *x,
+                 double2 *y, int B, bool adj, hipStream_t st);
+
+int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
+                 bool adj, bool last, const double2 *ctab, const double2 *zin, const double2 *qin,
+                 double2 *out, hipStream_t st);
+
+int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk,
+                       const double2 *qh0, const double2 *qh1, const double2 *q0,
+                       const double2 *q1, double *gpart, hipStream_t st);
+
+int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int j,
+                                const double *gpart, double *gstep, hipStream_t st);
+
+int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
+                       const double2 *ctab, const int32_t *ktab, const double2 *rho0,
+                       double2 *rhoT, double2 *states, hipStream_t st);
+
+int launch_lds_adjoint(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
+                       int kind, const double2 *ctab, const int32_t *ktab, const double2 *rhotar,
+                       const double2 *states, double *gpart, hipStream_t st);
+
+int launch_lds_grad_reduce(const lb_plan *p, const int32_t *d_item_range, int nsys_lds,
+                           const int32_t *d_sys_ids, const LdsItem *d_items, const double *gpart,
+                           double *gstep, hipStream_t st);
+
+int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const double2 *rhotar,
+                     const double *beta, const int32_t *d_state_sys, const int64_t *d_state_off,
+                     const int32_t *d_sys_state0, int nstates, double gamma2, const double *alpha,
+                     double *partial, double *J, double *G, hipStream_t st);
+
+int launch_terminal(const lb_plan *p, int kind, const StreamSeg *d_segs, int nseg, int64_t nblk,
+                    const double2 *rhoT, const double2 *rhotar, const double *beta,
+                    const int32_t *d_seg_state0, double2 *qh, hipStream_t st);
+
+int launch_grad_contract(const lb_plan *p, const double *gstep, const double *alpha,
+                         double gamma2, double *grad, hipStream_t st);
+
+// LDS path: block size and entries per thread for a state of n2 entries;
+// returns false when the state does not fit the LDS-resident kernels.
+bool lds_shape(int64_t n2, int *block, int *ept);
+
+}  // namespace lbx

@@ -7,7 +7,18 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+LIB = os.path.join(ROOT, "paper_2110_10310_amd", "liblbx.so")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+@pytest.fixture(scope="session")
+def built_lib():
+    """Path of liblbx.so, building it in-tree only when nothing is built."""
+    if not os.path.exists(LIB):
+        from paper_2110_10310_amd.build import build
+        build()
+    return LIB

@@ -1,0 +1,302 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (FP64 throughout): final states and single applications within
+1e-12 relative (Frobenius norm per state), objectives within 1e-12
+relative, gradients within 1e-10 relative to the max-norm of the oracle
+gradient.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from workloads import (  # noqa: E402
+    make_config, random_alpha, random_pure_states, random_system, truncate_steps,
+)
+
+from _gpu import dev, flat_alpha, flat_states, rel_state_err, say, split_states  # noqa: E402
+
+STATE_TOL = 1e-12
+GRAD_TOL = 1e-10
+
+SHAPES = [(3,), (2, 3), (4, 4), (3, 2, 2), (2, 2, 2, 2), (5, 3), (3, 3, 3), (7,)]
+
+
+@pytest.fixture(scope="module")
+def lbx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_10310_amd as lbx
+    return lbx
+
+
+def _sys(seed, nlev, NT=30, T=3.0, Ns=5, Nf=2, amp=0.02):
+    rng = np.random.default_rng(seed)
+    s = random_system(rng, nlev, NT=NT, T=T, Ns=Ns, Nf=Nf)
+    return s, random_alpha(rng, s, amp=amp), rng
+
+
+# --------------------------------------------------------------- control table
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_control_table_matches_oracle(lbx, cfg):
+    p = make_config(cfg)
+    s = p.systems[0]
+    say("control_table", cfg)
+    plan = lbx.Plan([s])
+    tab = lbx.control_table(plan, 0, dev(p.alpha[0].reshape(-1))).cpu().numpy()
+    ref = np.stack([oracle.controls(s, p.alpha[0], (j + 0.5) * s.dt) for j in range(s.NT)])
+    assert np.max(np.abs(tab - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+# --------------------------------------------------------------- apply
+
+@pytest.mark.parametrize("nlev", SHAPES)
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_lindblad_apply_matches_dense_superoperator(lbx, nlev, adjoint):
+    s, alpha, rng = _sys(hash(nlev) % 1000, nlev)
+    N = s.N
+    B = 3
+    x = rng.standard_normal((B, N, N)) + 1j * rng.standard_normal((B, N, N))
+    t = 1.234
+    say("apply", nlev, adjoint)
+    plan = lbx.Plan([s])
+    y = lbx.lindblad_apply(plan, 0, t, dev(alpha.reshape(-1)), dev(x), adjoint=adjoint).cpu().numpy()
+    if N * N <= 1024:
+        M = oracle.superoperator(s, alpha, t)
+        if adjoint:
+            M = M.conj().T
+        ref = np.stack([oracle.unvec(M @ oracle.vec(x[b]), N) for b in range(B)])
+    else:
+        f = oracle.lindbladian_adjoint if adjoint else oracle.lindbladian
+        ref = np.stack([f(s, alpha, t, x[b]) for b in range(B)])
+    assert rel_state_err(y, ref) < 1e-13
+
+
+def test_lindblad_apply_empty_batch_is_noop(lbx):
+    s, alpha, _ = _sys(1, (2, 3))
+    plan = lbx.Plan([s])
+    x = torch.zeros((0, 6, 6), dtype=torch.complex128, device="cuda")
+    y = lbx.lindblad_apply(plan, 0, 0.1, dev(alpha.reshape(-1)), x)
+    assert y.shape == (0, 6, 6)
+
+
+def test_lindblad_apply_eight_qutrits_sampled(lbx):
+    # The 8-qutrit ring at full size (N = 6561, 43M entries per state): check
+    # sampled entries, each formed by the oracle from single operator rows.
+    p = make_config(5)
+    s = p.systems[0]
+    rng = np.random.default_rng(55)
+    N = s.N
+    x = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) / np.sqrt(2)
+    t = 37.3
+    say("apply c5 full size")
+    plan = lbx.Plan([s])
+    al = dev(p.alpha[0].reshape(-1))
+    xd = dev(x[None])
+    for adjoint in (False, True):
+        y = lbx.lindblad_apply(plan, 0, t, al, xd, adjoint=adjoint)
+        rows = np.concatenate([rng.integers(0, N, 60), [0, N - 1, 0, N - 1]])
+        cols = np.concatenate([rng.integers(0, N, 60), [0, N - 1, N - 1, 0]])
+        got = y[0, torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")].cpu().numpy()
+        ref = oracle.lindbladian_entries(s, p.alpha[0], t, x, rows, cols, adjoint=adjoint)
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(got - ref)) <= 1e-13 * scale
+        del y
+
+
+# --------------------------------------------------------------- one IMR step
+
+@pytest.mark.parametrize("nlev", [(3,), (2, 3), (4, 4), (3, 2, 2)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_imr_step_matches_dense_solve(lbx, nlev, adjoint):
+    s, alpha, rng = _sys(7 + len(nlev), nlev, NT=10, T=1.0)
+    N = s.N
+    B = 2
+    q = rng.standard_normal((B, N, N)) + 1j * rng.standard_normal((B, N, N))
+    j = 4
+    say("imr_step", nlev, adjoint)
+    plan = lbx.Plan([s])
+    out = lbx.imr_step(plan, 0, j, dev(alpha.reshape(-1)), dev(q), adjoint=adjoint).cpu().numpy()
+    M = oracle.superoperator(s, alpha, (j + 0.5) * s.dt)
+    if adjoint:
+        M = M.conj().T
+    A = np.eye(N * N) - 0.5 * s.dt * M
+    ref = []
+    for b in range(B):
+        z = np.linalg.solve(A, oracle.vec(q[b]))
+        ref.append(oracle.unvec(oracle.vec(q[b]) + s.dt * (M @ z), N))
+    assert rel_state_err(out, np.stack(ref)) < STATE_TOL
+
+
+# --------------------------------------------------------------- forward solve
+
+def _multi(seeds_shapes, NT=30, B=(2, 1, 3, 2, 1, 2, 2, 1)):
+    systems, alphas, rho0, batch = [], [], [], []
+    for k, (seed, nlev) in enumerate(seeds_shapes):
+        s, a, rng = _sys(seed, nlev, NT=NT)
+        systems.append(s)
+        alphas.append(a)
+        b = B[k % len(B)]
+        batch.append(b)
+        rho0.append(random_pure_states(rng, s.N, b))
+    return systems, alphas, rho0, batch
+
+
+@pytest.mark.parametrize("path", ["auto", "lds", "stream"])
+def test_forward_solve_multi_system(lbx, path):
+    shapes = [(3,), (2, 3), (4, 4), (3, 2, 2), (2, 2, 2), (5, 3)]
+    if path == "stream":
+        shapes.append((3, 3, 3))
+    systems, alphas, rho0, batch = _multi(list(enumerate(shapes, start=20)))
+    say("forward_solve", path, batch)
+    plan = lbx.Plan(systems, path=path)
+    rhoT = lbx.forward_solve(plan, dev(flat_alpha(alphas)), dev(flat_states(rho0)), batch)
+    got = split_states(rhoT.cpu().numpy(), systems, batch)
+    ref = [oracle.imr_forward(s, a, r) for s, a, r in zip(systems, alphas, rho0)]
+    assert rel_state_err(got, ref) < STATE_TOL
+
+
+def test_forward_solve_with_empty_system_and_trivial_subsystem(lbx):
+    s1, a1, rng = _sys(31, (3, 1, 2))
+    s2, a2, _ = _sys(32, (2, 2))
+    rho1 = random_pure_states(rng, s1.N, 2)
+    batch = [2, 0]
+    say("forward_solve empty+trivial")
+    plan = lbx.Plan([s1, s2])
+    rhoT = lbx.forward_solve(plan, dev(flat_alpha([a1, a2])), dev(flat_states([rho1])), batch)
+    got = split_states(rhoT.cpu().numpy(), [s1], [2])
+    ref = [oracle.imr_forward(s1, a1, rho1)]
+    assert rel_state_err(got, ref) < STATE_TOL
+
+
+def test_config1_full_forward(lbx):
+    p = make_config(1)
+    s = p.systems[0]
+    say("c1 full forward")
+    plan = lbx.Plan([s])
+    rhoT = lbx.forward_solve(plan, dev(p.alpha[0].reshape(-1)), dev(p.rho0[0]), [1]).cpu().numpy()
+    ref = oracle.imr_forward(s, p.alpha[0], p.rho0[0])
+    assert rel_state_err([rhoT], [ref]) < STATE_TOL
+
+
+# --------------------------------------------------------------- objective
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_objective_matches_oracle(lbx, kind):
+    systems, alphas, rho0, batch = _multi([(40, (2, 3)), (41, (3, 3)), (42, (4,))])
+    rng = np.random.default_rng(43)
+    tars = [random_pure_states(rng, s.N, b) for s, b in zip(systems, batch)]
+    rhoT = [oracle.imr_forward(s, a, r) for s, a, r in zip(systems, alphas, rho0)]
+    beta = rng.uniform(0.5, 2, sum(batch))
+    say("objective", kind)
+    plan = lbx.Plan(systems)
+    G, J = lbx.objective(plan, kind, dev(flat_states(rhoT)), dev(flat_states(tars)), dev(beta),
+                         batch, 0.7, dev(flat_alpha(alphas)))
+    G = G.cpu().numpy()
+    off = 0
+    for k, s in enumerate(systems):
+        ref = oracle.objective(kind, rhoT[k], tars[k], beta[off:off + batch[k]], 0.7, alphas[k])
+        off += batch[k]
+        assert abs(G[k] - ref) <= 1e-12 * abs(ref)
+
+
+# --------------------------------------------------------------- adjoint gradient
+
+def _grad_case(lbx, systems, alphas, rho0, batch, kind, gamma2, path, ckpt, seed=50):
+    rng = np.random.default_rng(seed)
+    tars = [random_pure_states(rng, s.N, b) for s, b in zip(systems, batch)]
+    beta = rng.uniform(0.5, 2, sum(batch))
+    plan = lbx.Plan(systems, path=path)
+    G, grad, rhoT = lbx.adjoint_gradient(plan, kind, dev(flat_alpha(alphas)), dev(flat_states(rho0)),
+                                         dev(flat_states(tars)), dev(beta), batch, gamma2, ckpt,
+                                         want_rhoT=True)
+    G, grad = G.cpu().numpy(), grad.cpu().numpy()
+    got_rhoT = split_states(rhoT.cpu().numpy(), systems, batch)
+    off_b, off_a = 0, 0
+    for k, s in enumerate(systems):
+        bk = batch[k]
+        Gr, gr = oracle.value_and_gradient(s, alphas[k], rho0[k], tars[k], beta[off_b:off_b + bk], kind, gamma2)
+        rT = oracle.imr_forward(s, alphas[k], rho0[k])
+        assert rel_state_err([got_rhoT[k]], [rT]) < STATE_TOL
+        assert abs(G[k] - Gr) <= 1e-12 * abs(Gr)
+        ga = grad[off_a:off_a + alphas[k].size].reshape(alphas[k].shape)
+        assert np.max(np.abs(ga - gr)) <= GRAD_TOL * np.max(np.abs(gr)), (k, np.max(np.abs(ga - gr)), np.max(np.abs(gr)))
+        off_b += bk
+        off_a += alphas[k].size
+
+
+@pytest.mark.parametrize("path,ckpt", [("lds", 1), ("stream", 1), ("stream", 4), ("stream", 0), ("auto", 7)])
+@pytest.mark.parametrize("kind,gamma2", [(0, 0.0), (1, 0.25)])
+def test_adjoint_gradient_matches_oracle(lbx, path, ckpt, kind, gamma2):
+    shapes = [(3,), (2, 3), (3, 2, 2), (4, 4)]
+    systems, alphas, rho0, batch = _multi(list(enumerate(shapes, start=60)), NT=18)
+    say("adjoint_gradient", path, ckpt, kind, gamma2)
+    _grad_case(lbx, systems, alphas, rho0, batch, kind, gamma2, path, ckpt)
+
+
+def test_config1_full_gradient(lbx):
+    p = make_config(1)
+    s = p.systems[0]
+    say("c1 full gradient")
+    plan = lbx.Plan([s])
+    G, grad, _ = lbx.adjoint_gradient(plan, p.kind, dev(p.alpha[0].reshape(-1)), dev(p.rho0[0]),
+                                      dev(p.rhotar[0]), dev(p.beta[0]), [1])
+    Gr, gr = oracle.value_and_gradient(s, p.alpha[0], p.rho0[0], p.rhotar[0], p.beta[0], p.kind)
+    assert abs(G.item() - Gr) <= 1e-12 * abs(Gr)
+    assert np.max(np.abs(grad.cpu().numpy().reshape(gr.shape) - gr)) <= GRAD_TOL * np.max(np.abs(gr))
+
+
+def test_autograd_function_and_finite_differences(lbx):
+    s, alpha, rng = _sys(77, (2, 3), NT=20, T=2.0)
+    rho0 = random_pure_states(rng, s.N, 2)
+    tar = random_pure_states(rng, s.N, 2)
+    beta = np.array([1.0, 0.5])
+    plan = lbx.Plan([s])
+    a = dev(alpha.reshape(-1)).requires_grad_(True)
+    say("autograd")
+    G = lbx.lindblad_objective(a, plan, 0, dev(rho0), dev(tar), dev(beta), [2])
+    (3.0 * G.sum()).backward()
+    _, gr = oracle.value_and_gradient(s, alpha, rho0, tar, beta, 0)
+    assert np.max(np.abs(a.grad.cpu().numpy() - 3.0 * gr.reshape(-1))) <= GRAD_TOL * 3 * np.max(np.abs(gr))
+    # central differences of the GPU objective itself
+    h = 1e-6
+    base = alpha.reshape(-1)
+    for k in [0, 5, 11, 17]:
+        vals = []
+        for sgn in (1, -1):
+            ak = base.copy()
+            ak[k] += sgn * h
+            with torch.no_grad():
+                vals.append(lbx.lindblad_objective(dev(ak), plan, 0, dev(rho0), dev(tar), dev(beta), [2]).item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - gr.reshape(-1)[k]) <= 1e-6 * np.max(np.abs(gr))
+
+
+def test_gradient_is_bitwise_deterministic(lbx):
+    shapes = [(2, 3), (3, 3, 3)]
+    systems, alphas, rho0, batch = _multi(list(enumerate(shapes, start=90)), NT=12)
+    rng = np.random.default_rng(3)
+    tars = [random_pure_states(rng, s.N, b) for s, b in zip(systems, batch)]
+    plan = lbx.Plan(systems)
+    args = (dev(flat_alpha(alphas)), dev(flat_states(rho0)), dev(flat_states(tars)),
+            dev(np.ones(sum(batch))), batch)
+    say("determinism")
+    g1 = lbx.adjoint_gradient(plan, 0, *args)[1].cpu().numpy()
+    g2 = lbx.adjoint_gradient(plan, 0, *args)[1].cpu().numpy()
+    assert np.array_equal(g1, g2)
+
+
+def test_config3_subset_reduced_steps(lbx):
+    p = truncate_steps(make_config(3), 15)
+    # the first few systems of the uneven batch (both kernel families appear)
+    idx = [k for k, s in enumerate(p.systems) if s.N <= 100][:6]
+    systems = [p.systems[k] for k in idx]
+    alphas = [p.alpha[k] for k in idx]
+    rho0 = [p.rho0[k] for k in idx]
+    batch = [r.shape[0] for r in rho0]
+    say("c3 subset", [s.nlev for s in systems], batch)
+    _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "auto", 4)
