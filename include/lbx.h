@@ -37,10 +37,11 @@
  * destroyed with lb_plan_destroy.
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Kernels
- * are enqueued on it.  lindblad_apply, imr_step and objective return without
- * synchronising.  forward_solve and adjoint_gradient synchronise the stream
- * once to read the per-step sweep counts (and adjoint_gradient again to check
- * that G is finite); their results are complete when they return OK.
+ * are enqueued on it.  lindblad_apply, control_table and objective return
+ * without synchronising.  imr_step, forward_solve and adjoint_gradient
+ * synchronise the stream to read the per-step sweep counts (adjoint_gradient
+ * again to check that G is finite); forward_solve and adjoint_gradient have
+ * completed their work when they return OK.
  * Concurrent calls on one plan need separate workspaces.
  *
  * Errors: every entry point returns LB_OK (0) or a negative code; no C++
@@ -75,6 +76,15 @@ extern "C" {
 /* Plan options (lb_plan_set_option). */
 #define LB_OPT_PATH 0      /* 0 auto, 1 LDS-resident persistent kernels, 2 streaming sweeps */
 #define LB_OPT_SOLVE_TOL 1 /* fixed-point stage-solve bound, default 2^-53 */
+#define LB_OPT_PROFILE 2   /* 1: time kernel launches of forward_solve and adjoint_gradient
+                              with HIP events on the call's stream; 0 (default): off */
+
+/* Kernel families timed by LB_OPT_PROFILE (lb_profile_read). */
+#define LB_KERNEL_LDS_FORWARD 0  /* persistent forward time loop, LDS-resident */
+#define LB_KERNEL_LDS_ADJOINT 1  /* persistent adjoint time loop + gradient integrands */
+#define LB_KERNEL_SWEEP 2        /* one streaming stage-solve sweep */
+#define LB_KERNEL_STREAM_GRAD 3  /* streaming gradient integrands of one step */
+#define LB_KERNEL_COUNT 4
 
 #define LB_LIMIT_QMAX 12   /* subsystems per system */
 #define LB_LIMIT_NLEV 31   /* levels per subsystem */
@@ -116,6 +126,18 @@ int lb_plan_set_option(lb_plan *plan, int32_t option, double value);
  * every state, 0 picks ceil(sqrt(NT)). */
 int lb_workspace_bytes(const lb_plan *plan, int32_t op, const int32_t *batch_per_sys,
                        int32_t ckpt_every, size_t *bytes);
+
+/* Launch count and summed duration [ms] of kernel family `kernel` (LB_KERNEL_*)
+ * over the calls made while LB_OPT_PROFILE was on; reset != 0 clears them. */
+int lb_profile_read(const lb_plan *plan, int32_t kernel, int64_t *launches, double *total_ms,
+                    int32_t reset);
+
+/* Stage-solve sweep counts per step (HOST counts [nsys][NT][2]: LDS-resident
+ * kernels, streaming sweeps) for controls alpha (DEVICE, all systems).  The
+ * fixed-point stage iteration of the implicit-midpoint solve runs until its
+ * a-priori contraction bound reaches LB_OPT_SOLVE_TOL; a count of -1 marks a
+ * step whose bound is >= 0.5.  Synchronises the stream. */
+int sweep_counts(const lb_plan *plan, const double *alpha, int32_t *counts, void *stream);
 
 /* Control values d_q(t_{j+1/2}) at every step midpoint of system `sys`
  * (Sec. II eq. rotctrl; App. A: M is evaluated at t_j + dt/2), in rad/ns.

@@ -6,6 +6,7 @@ from . import _native  # noqa: F401  (raises ImportError when liblbx.so is missi
 from .api import (  # noqa: F401
     Plan,
     control_table,
+    sweep_counts,
     lindblad_apply,
     imr_step,
     forward_solve,

@@ -28,6 +28,12 @@ LB_OP_GRADIENT = 2
 
 LB_OPT_PATH = 0
 LB_OPT_SOLVE_TOL = 1
+LB_OPT_PROFILE = 2
+
+LB_KERNEL_LDS_FORWARD = 0
+LB_KERNEL_LDS_ADJOINT = 1
+LB_KERNEL_SWEEP = 2
+LB_KERNEL_STREAM_GRAD = 3
 
 # Every function the header declares, with its ctypes signature.
 _i32 = C.c_int32
@@ -58,6 +64,8 @@ SIGNATURES = {
                             C.c_size_t, _p]),
     "adjoint_gradient": (C.c_int, [_p, _i32, _p, _p, _p, _p, _ip, C.c_double, _i32, _p, _p,
                                    _p, _p, C.c_size_t, _p]),
+    "lb_profile_read": (C.c_int, [_p, _i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), _i32]),
+    "sweep_counts": (C.c_int, [_p, _p, _ip, _p]),
     "lb_last_error": (C.c_char_p, []),
 }
 

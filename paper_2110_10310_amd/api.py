@@ -100,6 +100,17 @@ class Plan:
         check(lib.lb_plan_set_option(self.handle, option, float(value)), "lb_plan_set_option")
         self._ws.clear()
 
+    def profile(self, on: bool = True) -> None:
+        """Time kernel launches of forward_solve/adjoint_gradient with HIP events."""
+        self.set_option(nat.LB_OPT_PROFILE, 1.0 if on else 0.0)
+
+    def profile_read(self, kernel: int, reset: bool = False):
+        """(launches, total milliseconds) of one LB_KERNEL_* family."""
+        n, ms = C.c_int64(), C.c_double()
+        check(lib.lb_profile_read(self.handle, kernel, C.byref(n), C.byref(ms), int(reset)),
+              "lb_profile_read")
+        return n.value, ms.value
+
     def set_path(self, path: str) -> None:
         self.set_option(nat.LB_OPT_PATH, PATHS[path])
 
@@ -133,6 +144,15 @@ class Plan:
             idx = np.repeat(np.arange(len(self.systems)), self.nalpha)
             self._alpha_sys = torch.as_tensor(idx, device="cuda")
         return self._alpha_sys
+
+
+def sweep_counts(plan: Plan, alpha: torch.Tensor) -> np.ndarray:
+    """Stage-solve sweeps per step, [nsys, NT, 2] (LDS-resident, streaming)."""
+    _need(alpha, "alpha", torch.float64, int(plan.alpha_off[-1]))
+    out = np.zeros((len(plan.systems), plan.NT, 2), dtype=np.int32)
+    check(lib.sweep_counts(plan.handle, _vp(alpha), out.ctypes.data_as(nat._ip), _stream()),
+          "sweep_counts")
+    return out
 
 
 def control_table(plan: Plan, sys: int, alpha: torch.Tensor) -> torch.Tensor:

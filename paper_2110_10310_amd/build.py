@@ -1,6 +1,6 @@
 """Build liblbx.so for gfx950 in-tree with hipcc.
 
-Usage: python -m paper_2110_10310_amd.build   (or call build()).
+Usage: python paper_2110_10310_amd/build.py   (or call build()).
 Each translation unit compiles to an object under _build/, in parallel, and
 the objects link into paper_2110_10310_amd/liblbx.so.
 """

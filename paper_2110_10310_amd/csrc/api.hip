@@ -32,6 +32,19 @@ int hip_fail(hipError_t e, const char *what) {
   return LB_EDEVICE;
 }
 
+void prof_resolve(const lb_plan *p) {
+  for (auto &e : p->prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.stop) == hipSuccess && hipEventElapsedTime(&ms, e.start, e.stop) == hipSuccess) {
+      p->prof_n[e.kernel] += 1;
+      p->prof_ms[e.kernel] += ms;
+    }
+    (void)hipEventDestroy(e.start);
+    (void)hipEventDestroy(e.stop);
+  }
+  p->prof_pending.clear();
+}
+
 }  // namespace lbx
 
 // ----------------------------------------------------------------------------
@@ -361,6 +374,7 @@ int stream_forward(const lb_plan *p, const BatchMeta &m, const std::vector<int32
       const bool last = kk == K - 1;
       const double2 *zin = kk == 0 ? cur : (kk & 1 ? z0 : z1);
       double2 *dst = last ? out : (kk & 1 ? z1 : z0);
+      ProfScope ps(p, LB_KERNEL_SWEEP, st);
       int rc = launch_sweep(p, m.d_segs, (int)m.segs.size(), m.st_blocks, j, false, last, ctab, zin,
                             cur, dst, st);
       if (rc) return rc;
@@ -536,6 +550,10 @@ extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
     p->path = (int)value;
     return LB_OK;
   }
+  if (option == LB_OPT_PROFILE) {
+    p->profile = value != 0.0;
+    return LB_OK;
+  }
   if (option == LB_OPT_SOLVE_TOL) {
     if (!(value > 0.0 && value < 1.0)) return fail(LB_EINVAL, "LB_OPT_SOLVE_TOL must be in (0, 1)");
     p->tol = value;
@@ -638,6 +656,7 @@ static int run_forward(const lb_plan *p, const BatchMeta &m, const Layout &L, ch
   if ((rc = check_k(p, k, m))) return rc;
   // LDS-resident systems: one persistent launch per kernel class.
   for (const auto &c : m.classes) {
+    ProfScope ps(p, LB_KERNEL_LDS_FORWARD, st);
     if ((rc = launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab, rho0,
                                  rhoT, hist, st)))
       return rc;
@@ -678,6 +697,7 @@ extern "C" int forward_solve(const lb_plan *p, const double *alpha, const void *
                        k, st, false);
   if (rc) return rc;
   LBX_HIP(hipStreamSynchronize(st));
+  prof_resolve(p);
   return LB_OK;
 }
 
@@ -739,10 +759,12 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
                        st, items, (int)m->items.size(), beta, m->d_sys_state0);
     LBX_HIP(hipGetLastError());
     double *gpart = (double *)(w + L.gpart);
-    for (const auto &c : m->classes)
+    for (const auto &c : m->classes) {
+      ProfScope ps(p, LB_KERNEL_LDS_ADJOINT, st);
       if ((rc = launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab, ktab,
                                    (const double2 *)rhotar, hist, gpart, st)))
         return rc;
+    }
     if ((rc = launch_lds_grad_reduce(p, m->d_lds_item_range, (int)m->lds_sys.size(), m->d_lds_sys,
                                      items, gpart, gstep, st)))
       return rc;
@@ -780,12 +802,16 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
           const bool last = kk == K - 1;
           const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
           double2 *dst = last ? qout : (kk & 1 ? z1 : z0);
+          ProfScope ps(p, LB_KERNEL_SWEEP, st);
           if ((rc = launch_sweep(p, m->d_segs, nseg, m->st_blocks, j, true, last, ctab, zin, qin, dst, st)))
             return rc;
         }
-        if ((rc = launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, qout, qin, slot(j), slot(j + 1),
-                                     sgp, st)))
-          return rc;
+        {
+          ProfScope ps(p, LB_KERNEL_STREAM_GRAD, st);
+          if ((rc = launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, qout, qin, slot(j), slot(j + 1),
+                                       sgp, st)))
+            return rc;
+        }
         if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, j, sgp, gstep, st))) return rc;
         cur ^= 1;
       }
@@ -795,10 +821,44 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
   std::vector<double> hG(p->sys.size());
   LBX_HIP(hipMemcpyAsync(hG.data(), G, hG.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   LBX_HIP(hipStreamSynchronize(st));
+  prof_resolve(p);
   for (size_t s = 0; s < hG.size(); ++s)
     if (!std::isfinite(hG[s]) && m->batch[s] > 0)
       return fail(LB_ENONFINITE, "objective of system " + std::to_string(s) + " is not finite");
   return LB_OK;
+}
+
+extern "C" int lb_profile_read(const lb_plan *p, int32_t kernel, int64_t *launches, double *total_ms,
+                               int32_t reset) {
+  if (int rc = check_plan(p)) return rc;
+  if (kernel < 0 || kernel >= LB_KERNEL_COUNT) return fail(LB_EINVAL, "unknown kernel family");
+  prof_resolve(p);
+  if (launches) *launches = p->prof_n[kernel];
+  if (total_ms) *total_ms = p->prof_ms[kernel];
+  if (reset) {
+    p->prof_n[kernel] = 0;
+    p->prof_ms[kernel] = 0.0;
+  }
+  return LB_OK;
+}
+
+extern "C" int sweep_counts(const lb_plan *p, const double *alpha, int32_t *counts, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!alpha || !counts) return fail(LB_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nk = p->sys.size() * (size_t)p->NT * 2;
+  void *tmp = nullptr;
+  LBX_HIP(hipMalloc(&tmp, align256(p->ctab_total * sizeof(double2)) + nk * sizeof(int32_t)));
+  double2 *ctab = (double2 *)tmp;
+  int32_t *ktab = (int32_t *)((char *)tmp + align256(p->ctab_total * sizeof(double2)));
+  int rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, st);
+  if (rc == LB_OK) {
+    hipError_t e = hipMemcpyAsync(counts, ktab, nk * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = hip_fail(e, "sweep_counts copy");
+  }
+  (void)hipFree(tmp);
+  return rc;
 }
 
 extern "C" const char *lb_last_error(void) { return g_err.c_str(); }

@@ -30,7 +30,13 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
   const double h = S.h;
   if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
 
-  double2 qv[EPT], wv[EPT], zn[EPT];
+  // Per entry: state q, stage weight w = (1 - h D)^-1 and h D.  The stage
+  // vector is carried as z = q + delta and only delta is iterated:
+  //   delta <- w (h D q + h O z),   q^{j+1} = q^j + 2 delta,
+  // which solves the same system as z <- w (q + h O z) but never rounds
+  // 1 + h*gamma (gamma ~ 1e-5/ns), whose rounding would repeat identically
+  // every step and accumulate linearly.
+  double2 qv[EPT], wv[EPT], hd[EPT], dn[EPT];
   uint64_t di[EPT], dj[EPT];
   int ee[EPT];
   bool ok[EPT];
@@ -44,18 +50,23 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
     di[k] = desc[S.tab_off + i];
     dj[k] = desc[S.tab_off + jj];
     const double gam = diag_rate(S, di[k], dj[k]);
-    wv[k] = stage_weight(h, gam, Etab[S.tab_off + i] - Etab[S.tab_off + jj], false);
+    const double dE = Etab[S.tab_off + i] - Etab[S.tab_off + jj];
+    wv[k] = stage_weight(h, gam, dE, false);
+    hd[k] = cscale(h, diag_coef(gam, dE, false));
     qv[k] = ok[k] ? rho0[it.off + e] : make_double2(0.0, 0.0);
-    zn[k] = make_double2(0.0, 0.0);
+    dn[k] = make_double2(0.0, 0.0);
     if (states && ok[k]) states[it.st_off + e] = qv[k];
   }
   double2 *buf[2] = {zbuf, zbuf + N2};
   int cb = 0;
   for (int j = 0; j < NT; ++j) {
-    // z0 = w q, then K sweeps z <- w (q + h O z) (App. A eq. linsystem_primal).
+    // (I - h M) z = q^j (App. A eq. linsystem_primal): z0 = w q, then K sweeps.
+    double2 hdq[EPT];
 #pragma unroll
-    for (int k = 0; k < EPT; ++k)
-      if (ok[k]) buf[cb][ee[k]] = cmul(wv[k], qv[k]);
+    for (int k = 0; k < EPT; ++k) {
+      hdq[k] = cmul(hd[k], qv[k]);
+      if (ok[k]) buf[cb][ee[k]] = cadd(qv[k], cmul(wv[k], hdq[k]));
+    }
     if (tid < S.Q) dsh[j & 1][tid] = ctab[S.ctab_off + (int64_t)j * S.Q + tid];
     __syncthreads();
     const int K = ktab[((int64_t)it.sys * NT + j) * 2 + 0];
@@ -66,22 +77,22 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
         if (ok[k]) {
           const double2 acc = offdiag<false>(S, di[k], dj[k], ee[k], dsh[j & 1], sq,
                                              [&](int64_t idx) { return src[idx]; });
-          zn[k] = cmul(wv[k], cadd(qv[k], cscale(h, acc)));
+          dn[k] = cmul(wv[k], cadd(hdq[k], cscale(h, acc)));
         }
       }
       if (kk + 1 < K) {
         double2 *dst = buf[cb ^ 1];
 #pragma unroll
         for (int k = 0; k < EPT; ++k)
-          if (ok[k]) dst[ee[k]] = zn[k];
+          if (ok[k]) dst[ee[k]] = cadd(qv[k], dn[k]);
         __syncthreads();
         cb ^= 1;
       }
     }
-    // q^{j+1} = q^j + dt M z = 2 z - q^j (App. A eq. IMR with h M z = z - q).
+    // q^{j+1} = q^j + dt M z = q^j + 2 delta (App. A eq. IMR; h M z = z - q^j = delta).
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-      qv[k] = csub(cscale(2.0, zn[k]), qv[k]);
+      qv[k] = cadd(qv[k], cscale(2.0, dn[k]));
       if (states && ok[k]) states[it.st_off + (int64_t)(j + 1) * N2 + ee[k]] = qv[k];
     }
     cb ^= 1;
@@ -112,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
   const int Q = S.Q;
   if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
 
-  double2 qh[EPT], wv[EPT], zn[EPT], qn[EPT];
+  double2 qh[EPT], wv[EPT], hd[EPT], dn[EPT], qn[EPT];
   uint64_t di[EPT], dj[EPT];
   int ee[EPT];
   bool ok[EPT];
@@ -127,20 +138,25 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
     di[k] = desc[S.tab_off + i];
     dj[k] = desc[S.tab_off + jj];
     const double gam = diag_rate(S, di[k], dj[k]);
-    wv[k] = stage_weight(h, gam, Etab[S.tab_off + i] - Etab[S.tab_off + jj], true);
+    const double dE = Etab[S.tab_off + i] - Etab[S.tab_off + jj];
+    wv[k] = stage_weight(h, gam, dE, true);
+    hd[k] = cscale(h, diag_coef(gam, dE, true));
     // Terminal condition (App. B): qh = (beta/M) dJ/d(conj q) at q = rho(T).
     qn[k] = ok[k] ? hist[(int64_t)NT * N2 + ee[k]] : make_double2(0.0, 0.0);
     const double2 t = ok[k] ? rhotar[it.off + ee[k]] : make_double2(0.0, 0.0);
     qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qn[k], t)) : cscale(-it.wterm, t);
-    zn[k] = make_double2(0.0, 0.0);
+    dn[k] = make_double2(0.0, 0.0);
   }
   double2 *buf[2] = {zbuf, zbuf + N2};
   int cb = 0;
   for (int j = NT - 1; j >= 0; --j) {
-    // (I - h M^+) zh = qh^{j+1} (App. B eq. linsystem_adjoint).
+    // (I - h M^+) zh = qh^{j+1} (App. B eq. linsystem_adjoint), zh = qh + delta.
+    double2 hdq[EPT];
 #pragma unroll
-    for (int k = 0; k < EPT; ++k)
-      if (ok[k]) buf[cb][ee[k]] = cmul(wv[k], qh[k]);
+    for (int k = 0; k < EPT; ++k) {
+      hdq[k] = cmul(hd[k], qh[k]);
+      if (ok[k]) buf[cb][ee[k]] = cadd(qh[k], cmul(wv[k], hdq[k]));
+    }
     if (tid < Q) dsh[j & 1][tid] = ctab[S.ctab_off + (int64_t)j * Q + tid];
     // Forward state q^j, consumed after the sweeps so that its load overlaps them.
     double2 qj[EPT];
@@ -155,23 +171,23 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
         if (ok[k]) {
           const double2 acc = offdiag<true>(S, di[k], dj[k], ee[k], dsh[j & 1], sq,
                                             [&](int64_t idx) { return src[idx]; });
-          zn[k] = cmul(wv[k], cadd(qh[k], cscale(h, acc)));
+          dn[k] = cmul(wv[k], cadd(hdq[k], cscale(h, acc)));
         }
       }
       if (kk + 1 < K) {
         double2 *dst = buf[cb ^ 1];
 #pragma unroll
         for (int k = 0; k < EPT; ++k)
-          if (ok[k]) dst[ee[k]] = zn[k];
+          if (ok[k]) dst[ee[k]] = cadd(qh[k], dn[k]);
         __syncthreads();
         cb ^= 1;
       }
     }
-    // Gradient integrands need zh at neighbours: publish it.
+    // Gradient integrands need zh = qh + delta at neighbours: publish it.
     double2 *zhb = buf[cb ^ 1];
 #pragma unroll
     for (int k = 0; k < EPT; ++k)
-      if (ok[k]) zhb[ee[k]] = zn[k];
+      if (ok[k]) zhb[ee[k]] = cadd(qh[k], dn[k]);
     __syncthreads();
     for (int q = 0; q < Q; ++q) {
       double gp = 0.0, gq = 0.0;
@@ -191,10 +207,10 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
         dstp[1] = gq;
       }
     }
-    // qh^j = qh^{j+1} + dt M^+ zh = 2 zh - qh^{j+1}.
+    // qh^j = qh^{j+1} + dt M^+ zh = qh^{j+1} + 2 delta.
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-      qh[k] = csub(cscale(2.0, zn[k]), qh[k]);
+      qh[k] = cadd(qh[k], cscale(2.0, dn[k]));
       qn[k] = qj[k];
     }
     // The next step writes its first iterate into buf[cb]: the last sweep's

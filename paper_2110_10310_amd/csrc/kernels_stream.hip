@@ -111,9 +111,9 @@ int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const
 
 // ----------------------------------------------------------------------------
 // One sweep of the stage solve over a list of segments (all states of some
-// systems), at step j:  out = w (q + h O zin), or on the last sweep of a step
-// the implicit-midpoint update out = 2 z - q (= q + dt M z, since
-// h M z = z - q for the converged stage vector).
+// systems), at step j:  out = q + delta with delta = w (h D q + h O zin), or
+// on the last sweep of a step the implicit-midpoint update
+// out = q + 2 delta (= q + dt M z, since h M z = z - q = delta).
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ int find_segment(const StreamSeg *segs, int nseg, int64_t blk) {
   int lo = 0, hi = nseg - 1;
@@ -155,8 +155,11 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_kernel(
   const int64_t base = sg.off + b * S.N2;
   const double2 acc = offdiag<ADJ>(S, di, dj, r, dq, sq, [&](int64_t idx) { return zin[base + idx]; });
   const double2 qv = qin[base + r];
-  const double2 zn = cmul(w, cadd(qv, cscale(S.h, acc)));
-  out[base + r] = LAST ? csub(cscale(2.0, zn), qv) : zn;
+  // z = q + delta, delta = w (h D q + h O z): the same solve as
+  // z = w (q + h O z) without rounding 1 + h*gamma (see kernels_lds.hip).
+  const double2 hdq = cscale(S.h, cmul(diag_coef(gam, dE, ADJ), qv));
+  const double2 dn = cmul(w, cadd(hdq, cscale(S.h, acc)));
+  out[base + r] = LAST ? cadd(qv, cscale(2.0, dn)) : cadd(qv, dn);
 }
 
 int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,

@@ -11,6 +11,11 @@
 #include "lbx.h"
 #include "lbx_device.hpp"
 
+struct lbx_prof_pending {
+  int kernel;
+  hipEvent_t start, stop;
+};
+
 struct lb_plan {
   std::vector<lbx::SysDev> sys;   // host copy of the per-system constants
   lbx::SysDev *d_sys = nullptr;   // device copy
@@ -22,6 +27,11 @@ struct lb_plan {
   int path = 0;                   // LB_OPT_PATH
   double tol = 1.1102230246251565e-16;  // LB_OPT_SOLVE_TOL (2^-53)
   int device = 0;
+  // LB_OPT_PROFILE: per-kernel-family launch counts and durations.
+  bool profile = false;
+  mutable int64_t prof_n[LB_KERNEL_COUNT] = {};
+  mutable double prof_ms[LB_KERNEL_COUNT] = {};
+  mutable std::vector<lbx_prof_pending> prof_pending;
 };
 
 namespace lbx {
@@ -49,6 +59,27 @@ struct StreamSeg {
 };
 
 constexpr int STREAM_BLOCK = 256;
+
+// HIP-event timing of one launch when the plan's profiling is on.
+struct ProfScope {
+  const lb_plan *p;
+  int kernel;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(const lb_plan *p_, int k, hipStream_t s) : p(p_), kernel(k), st(s) {
+    if (p->profile && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    (void)hipEventRecord(b, st);
+    p->prof_pending.push_back({kernel, a, b});
+  }
+};
+
+// Accumulates and releases the events of every finished profiled launch.
+void prof_resolve(const lb_plan *p);
 
 // Thread-local error message helpers.
 void set_error(const std::string &msg);

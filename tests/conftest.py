@@ -19,6 +19,10 @@ def pytest_configure(config):
 def built_lib():
     """Path of liblbx.so, building it in-tree only when nothing is built."""
     if not os.path.exists(LIB):
-        from paper_2110_10310_amd.build import build
-        build()
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "lbx_build", os.path.join(ROOT, "paper_2110_10310_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
     return LIB

@@ -134,10 +134,10 @@ def test_imr_step_matches_dense_solve(lbx, nlev, adjoint):
 
 # --------------------------------------------------------------- forward solve
 
-def _multi(seeds_shapes, NT=30, B=(2, 1, 3, 2, 1, 2, 2, 1)):
+def _multi(seeds_shapes, NT=30, B=(2, 1, 3, 2, 1, 2, 2, 1), T=3.0):
     systems, alphas, rho0, batch = [], [], [], []
     for k, (seed, nlev) in enumerate(seeds_shapes):
-        s, a, rng = _sys(seed, nlev, NT=NT)
+        s, a, rng = _sys(seed, nlev, NT=NT, T=T)
         systems.append(s)
         alphas.append(a)
         b = B[k % len(B)]
@@ -290,13 +290,41 @@ def test_gradient_is_bitwise_deterministic(lbx):
     assert np.array_equal(g1, g2)
 
 
+def test_lds_kernel_classes_with_several_entries_per_thread(lbx):
+    # N^2 = 1296 (two entries per thread) and N^2 = 4096 (four per thread).
+    shapes = [(6, 6), (4, 4, 4)]
+    systems, alphas, rho0, batch = _multi(list(enumerate(shapes, start=95)), NT=6, B=(2, 1), T=0.6)
+    say("lds classes ept 2/4", batch)
+    _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "lds", 1)
+
+
 def test_config3_subset_reduced_steps(lbx):
-    p = truncate_steps(make_config(3), 15)
-    # the first few systems of the uneven batch (both kernel families appear)
-    idx = [k for k, s in enumerate(p.systems) if s.N <= 100][:6]
+    p = truncate_steps(make_config(3), 12)
+    # systems of the uneven batch on both kernel families: five small ones
+    # (LDS-resident) and one with N^2 > 4096 (streamed)
+    small = [k for k, s in enumerate(p.systems) if s.N <= 32][:5]
+    big = [k for k, s in enumerate(p.systems) if 64 < s.N <= 81][:1]
+    idx = small + big
     systems = [p.systems[k] for k in idx]
     alphas = [p.alpha[k] for k in idx]
     rho0 = [p.rho0[k] for k in idx]
     batch = [r.shape[0] for r in rho0]
     say("c3 subset", [s.nlev for s in systems], batch)
     _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "auto", 4)
+
+
+def test_config2_full_length_against_stored_oracle(lbx):
+    # Two transmons, 16 basis states, 10000 steps: expected values written by
+    # tests/golden/make_golden.py from the oracle alone.
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "c2_cnot_full.npz"))
+    p = make_config(2)
+    s = p.systems[0]
+    say("c2 full gradient vs stored oracle")
+    plan = lbx.Plan([s])
+    G, grad, rhoT = lbx.adjoint_gradient(plan, p.kind, dev(p.alpha[0].reshape(-1)), dev(p.rho0[0]),
+                                         dev(p.rhotar[0]), dev(p.beta[0]), [16], want_rhoT=True)
+    assert rel_state_err([rhoT.cpu().numpy()], [gold["rhoT"]]) < STATE_TOL
+    assert abs(G.item() - float(gold["G"])) <= 1e-12 * abs(float(gold["G"]))
+    g = grad.cpu().numpy().reshape(gold["grad"].shape)
+    assert np.max(np.abs(g - gold["grad"])) <= GRAD_TOL * np.max(np.abs(gold["grad"]))
