@@ -78,6 +78,11 @@ extern "C" {
 #define LB_OPT_SOLVE_TOL 1 /* fixed-point stage-solve bound, default 2^-53 */
 #define LB_OPT_PROFILE 2   /* 1: time kernel launches of forward_solve and adjoint_gradient
                               with HIP events on the call's stream; 0 (default): off */
+#define LB_OPT_TILE 3      /* 1 (default): block-tiled kernels for large systems of
+                              equal-level subsystems; 0: generic streaming kernels */
+#define LB_OPT_TILE_KI 4   /* block shape of the block-tiled kernels, 10*KR + KC with KR
+                              (KC) row (column) digits inside a block; 0 (default): the
+                              shape listed first for the system */
 
 /* Kernel families timed by LB_OPT_PROFILE (lb_profile_read). */
 #define LB_KERNEL_LDS_FORWARD 0  /* persistent forward time loop, LDS-resident */

@@ -29,6 +29,8 @@ LB_OP_GRADIENT = 2
 LB_OPT_PATH = 0
 LB_OPT_SOLVE_TOL = 1
 LB_OPT_PROFILE = 2
+LB_OPT_TILE = 3
+LB_OPT_TILE_KI = 4
 
 LB_KERNEL_LDS_FORWARD = 0
 LB_KERNEL_LDS_ADJOINT = 1

@@ -46,7 +46,8 @@ def _need(t: torch.Tensor, name: str, dtype, numel: int | None = None) -> torch.
 class Plan:
     """Owns an lb_plan built from System-like objects (see workloads.System)."""
 
-    def __init__(self, systems: Sequence, path: str = "auto", solve_tol: float | None = None):
+    def __init__(self, systems: Sequence, path: str = "auto", solve_tol: float | None = None,
+                 tile: bool = True):
         self.systems = list(systems)
         n = len(self.systems)
         descs = (nat.SystemDesc * n)()
@@ -89,6 +90,8 @@ class Plan:
             self.set_option(nat.LB_OPT_PATH, PATHS[path])
         if solve_tol is not None:
             self.set_option(nat.LB_OPT_SOLVE_TOL, solve_tol)
+        if not tile:
+            self.set_option(nat.LB_OPT_TILE, 0)
 
     def __del__(self):
         h = getattr(self, "handle", None)

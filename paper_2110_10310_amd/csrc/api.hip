@@ -10,6 +10,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "lbx_host.hpp"
@@ -54,6 +55,7 @@ namespace {
 
 struct LdsClass {
   int block, ept;
+  int qc;      // > 0: specialised kernel for qc subsystems; 0: generic kernel
   int i0, i1;  // item range
 };
 
@@ -75,6 +77,8 @@ struct BatchMeta {
   std::vector<int32_t> seg_state0;
   int64_t st_entries = 0;  // compact streamed entries
   int64_t st_blocks = 0;
+  int tile_sys = -1;       // single streamed system run by the row-tiled kernels
+  int tile_B = 0;
   // device copies (one allocation)
   void *dmem = nullptr;
   LdsItem *d_items = nullptr;
@@ -126,6 +130,8 @@ int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int pat
   for (int s = 0; s < nsys; ++s)
     if (key[s] < 0) return fail(LB_EINVAL, "batch_per_sys has a negative entry");
   key.push_back(path);
+  key.push_back(p->tile);
+  key.push_back(p->tile_ki);
   PlanExtra *ex = extra_of(p);
   std::lock_guard<std::mutex> g(ex->mu);
   auto it = ex->batches.find(key);
@@ -159,15 +165,17 @@ int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int pat
   m->total_states = st;
   // LDS items grouped by kernel class, systems contiguous within a class.
   const int NT = p->NT;
-  std::map<std::pair<int, int>, std::vector<int>> cls;
+  std::map<std::tuple<int, int, int>, std::vector<int>> cls;
   for (int s = 0; s < nsys; ++s)
     if (m->path[s] == 1) {
       int blk, ept;
       lds_shape(p->sys[s].N2, &blk, &ept);
-      cls[{blk, ept}].push_back(s);
+      const int qc = lds_fast_ok(blk, ept, p->sys[s].Q) ? p->sys[s].Q : 0;
+      cls[std::make_tuple(blk, ept, qc)].push_back(s);
     }
   for (auto &kv : cls) {
-    LdsClass c{kv.first.first, kv.first.second, (int)m->items.size(), 0};
+    LdsClass c{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+               (int)m->items.size(), 0};
     for (int s : kv.second) {
       const SysDev &S = p->sys[s];
       m->lds_sys.push_back(s);
@@ -179,9 +187,9 @@ int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int pat
         itm.off = m->sys_off[s] + (int64_t)b * S.N2;
         itm.st_off = m->lds_hist_entries;
         m->lds_hist_entries += (int64_t)(NT + 1) * S.N2;
-        itm.waves = c.block / 64;
+        itm.parts = c.qc > 0 ? c.block / 16 : c.block / 64;
         itm.gp_off = m->lds_gpart;
-        m->lds_gpart += (int64_t)NT * itm.waves * 2 * S.Q;
+        m->lds_gpart += (int64_t)NT * itm.parts * 2 * S.Q;
         itm.wterm = 0.0;  // set per call (beta lives on the device); see below
         m->items.push_back(itm);
       }
@@ -208,6 +216,10 @@ int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int pat
     }
   m->st_entries = coff;
   m->st_blocks = blk;
+  if (m->segs.size() == 1 && p->tile && tile_nl(p, m->segs[0].sys)) {
+    m->tile_sys = m->segs[0].sys;
+    m->tile_B = m->segs[0].nstates;
+  }
   // Per-state tables for the objective.
   std::vector<int32_t> state_sys(std::max(1, st));
   std::vector<int64_t> state_off(std::max(1, st));
@@ -359,6 +371,17 @@ int copy_segments(const BatchMeta &m, const double2 *src, bool src_batched, doub
   return LB_OK;
 }
 
+// One stage-solve sweep of every streamed segment at step j.
+int sweep(const lb_plan *p, const BatchMeta &m, int j, bool adj, bool last, const double2 *ctab,
+          const double2 *zin, const double2 *qin, double2 *out, hipStream_t st) {
+  ProfScope ps(p, LB_KERNEL_SWEEP, st);
+  if (m.tile_sys >= 0)
+    return launch_tile(p, m.tile_sys, m.tile_B, last ? 2 : 1, adj, nullptr, 0.0, ctab, j, zin, qin,
+                       out, st);
+  return launch_sweep(p, m.d_segs, (int)m.segs.size(), m.st_blocks, j, adj, last, ctab, zin, qin,
+                      out, st);
+}
+
 // Streaming forward steps j0..j1-1 of every segment.  slot(j) returns the
 // buffer that receives q^j (j > j0); q^{j0} is `qstart`.
 template <class Slot>
@@ -374,10 +397,7 @@ int stream_forward(const lb_plan *p, const BatchMeta &m, const std::vector<int32
       const bool last = kk == K - 1;
       const double2 *zin = kk == 0 ? cur : (kk & 1 ? z0 : z1);
       double2 *dst = last ? out : (kk & 1 ? z1 : z0);
-      ProfScope ps(p, LB_KERNEL_SWEEP, st);
-      int rc = launch_sweep(p, m.d_segs, (int)m.segs.size(), m.st_blocks, j, false, last, ctab, zin,
-                            cur, dst, st);
-      if (rc) return rc;
+      if (int rc = sweep(p, m, j, false, last, ctab, zin, cur, dst, st)) return rc;
     }
     cur = out;
   }
@@ -550,6 +570,16 @@ extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
     p->path = (int)value;
     return LB_OK;
   }
+  if (option == LB_OPT_TILE) {
+    if (value != 0 && value != 1) return fail(LB_EINVAL, "LB_OPT_TILE must be 0 or 1");
+    p->tile = (int)value;
+    return LB_OK;
+  }
+  if (option == LB_OPT_TILE_KI) {
+    if (value < 0 || value > 99 || value != (int)value) return fail(LB_EINVAL, "LB_OPT_TILE_KI must be 0..99");
+    p->tile_ki = (int)value;
+    return LB_OK;
+  }
   if (option == LB_OPT_PROFILE) {
     p->profile = value != 0.0;
     return LB_OK;
@@ -638,9 +668,7 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
     const bool last = kk == K - 1;
     const double2 *zin = kk == 0 ? qi : (kk & 1 ? z0 : z1);
     double2 *dst = last ? (double2 *)q_out : (kk & 1 ? z1 : z0);
-    if ((rc = launch_sweep(p, m->d_segs, (int)m->segs.size(), m->st_blocks, j, adjoint != 0, last,
-                           ctab, zin, qi, dst, st)))
-      return rc;
+    if ((rc = sweep(p, *m, j, adjoint != 0, last, ctab, zin, qi, dst, st))) return rc;
   }
   return LB_OK;
 }
@@ -657,9 +685,11 @@ static int run_forward(const lb_plan *p, const BatchMeta &m, const Layout &L, ch
   // LDS-resident systems: one persistent launch per kernel class.
   for (const auto &c : m.classes) {
     ProfScope ps(p, LB_KERNEL_LDS_FORWARD, st);
-    if ((rc = launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab, rho0,
-                                 rhoT, hist, st)))
-      return rc;
+    rc = c.qc > 0 ? launch_lds_forward_fast(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc,
+                                            ctab, ktab, rho0, rhoT, hist, st)
+                  : launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab,
+                                       rho0, rhoT, hist, st);
+    if (rc) return rc;
   }
   if (m.segs.empty()) return LB_OK;
   // Streamed systems: one launch per sweep over all of them.
@@ -761,9 +791,11 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
     double *gpart = (double *)(w + L.gpart);
     for (const auto &c : m->classes) {
       ProfScope ps(p, LB_KERNEL_LDS_ADJOINT, st);
-      if ((rc = launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab, ktab,
-                                   (const double2 *)rhotar, hist, gpart, st)))
-        return rc;
+      rc = c.qc > 0 ? launch_lds_adjoint_fast(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, kind,
+                                              ctab, ktab, (const double2 *)rhotar, hist, gpart, st)
+                    : launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab,
+                                         ktab, (const double2 *)rhotar, hist, gpart, st);
+      if (rc) return rc;
     }
     if ((rc = launch_lds_grad_reduce(p, m->d_lds_item_range, (int)m->lds_sys.size(), m->d_lds_sys,
                                      items, gpart, gstep, st)))
@@ -802,9 +834,7 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
           const bool last = kk == K - 1;
           const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
           double2 *dst = last ? qout : (kk & 1 ? z1 : z0);
-          ProfScope ps(p, LB_KERNEL_SWEEP, st);
-          if ((rc = launch_sweep(p, m->d_segs, nseg, m->st_blocks, j, true, last, ctab, zin, qin, dst, st)))
-            return rc;
+          if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, st))) return rc;
         }
         {
           ProfScope ps(p, LB_KERNEL_STREAM_GRAD, st);

@@ -57,7 +57,9 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
     dn[k] = make_double2(0.0, 0.0);
     if (states && ok[k]) states[it.st_off + e] = qv[k];
   }
-  double2 *buf[2] = {zbuf, zbuf + N2};
+  // Two LDS stage buffers; selected by value (not through a pointer array)
+  // so that every access stays an LDS instruction.
+  double2 *const zb0 = zbuf, *const zb1 = zbuf + N2;
   int cb = 0;
   for (int j = 0; j < NT; ++j) {
     // (I - h M) z = q^j (App. A eq. linsystem_primal): z0 = w q, then K sweeps.
@@ -65,13 +67,13 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       hdq[k] = cmul(hd[k], qv[k]);
-      if (ok[k]) buf[cb][ee[k]] = cadd(qv[k], cmul(wv[k], hdq[k]));
+      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qv[k], cmul(wv[k], hdq[k]));
     }
     if (tid < S.Q) dsh[j & 1][tid] = ctab[S.ctab_off + (int64_t)j * S.Q + tid];
     __syncthreads();
     const int K = ktab[((int64_t)it.sys * NT + j) * 2 + 0];
     for (int kk = 0; kk < K; ++kk) {
-      const double2 *src = buf[cb];
+      const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         if (ok[k]) {
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
         }
       }
       if (kk + 1 < K) {
-        double2 *dst = buf[cb ^ 1];
+        double2 *dst = (cb ? zb0 : zb1);
 #pragma unroll
         for (int k = 0; k < EPT; ++k)
           if (ok[k]) dst[ee[k]] = cadd(qv[k], dn[k]);
@@ -147,7 +149,9 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
     qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qn[k], t)) : cscale(-it.wterm, t);
     dn[k] = make_double2(0.0, 0.0);
   }
-  double2 *buf[2] = {zbuf, zbuf + N2};
+  // Two LDS stage buffers; selected by value (not through a pointer array)
+  // so that every access stays an LDS instruction.
+  double2 *const zb0 = zbuf, *const zb1 = zbuf + N2;
   int cb = 0;
   for (int j = NT - 1; j >= 0; --j) {
     // (I - h M^+) zh = qh^{j+1} (App. B eq. linsystem_adjoint), zh = qh + delta.
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       hdq[k] = cmul(hd[k], qh[k]);
-      if (ok[k]) buf[cb][ee[k]] = cadd(qh[k], cmul(wv[k], hdq[k]));
+      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qh[k], cmul(wv[k], hdq[k]));
     }
     if (tid < Q) dsh[j & 1][tid] = ctab[S.ctab_off + (int64_t)j * Q + tid];
     // Forward state q^j, consumed after the sweeps so that its load overlaps them.
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
     __syncthreads();
     const int K = ktab[((int64_t)it.sys * NT + j) * 2 + 0];
     for (int kk = 0; kk < K; ++kk) {
-      const double2 *src = buf[cb];
+      const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         if (ok[k]) {
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
         }
       }
       if (kk + 1 < K) {
-        double2 *dst = buf[cb ^ 1];
+        double2 *dst = (cb ? zb0 : zb1);
 #pragma unroll
         for (int k = 0; k < EPT; ++k)
           if (ok[k]) dst[ee[k]] = cadd(qh[k], dn[k]);
@@ -184,7 +188,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
       }
     }
     // Gradient integrands need zh = qh + delta at neighbours: publish it.
-    double2 *zhb = buf[cb ^ 1];
+    double2 *zhb = (cb ? zb0 : zb1);
 #pragma unroll
     for (int k = 0; k < EPT; ++k)
       if (ok[k]) zhb[ee[k]] = cadd(qh[k], dn[k]);
@@ -213,7 +217,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
       qh[k] = cadd(qh[k], cscale(2.0, dn[k]));
       qn[k] = qj[k];
     }
-    // The next step writes its first iterate into buf[cb]: the last sweep's
+    // The next step writes its first iterate into (cb ? zb1 : zb0): the last sweep's
     // reads of it finished before the barrier above.
   }
 }
@@ -285,7 +289,7 @@ int launch_lds_adjoint(const lb_plan *p, const LdsItem *d_items, int nitems, int
   return fail(LB_EUNSUPPORTED, "no LDS-resident kernel for this state size");
 }
 
-// gstep[s][j][c] = sum over the items of s and their wavefronts (fixed order).
+// gstep[s][j][c] = sum over the items of s and their partial sums (fixed order).
 __global__ void lds_grad_reduce_kernel(const SysDev *__restrict__ sysv,
                                        const int32_t *__restrict__ item_range,
                                        const int32_t *__restrict__ sys_ids,
@@ -303,8 +307,8 @@ __global__ void lds_grad_reduce_kernel(const SysDev *__restrict__ sysv,
   double v = 0.0;
   for (int k = item_range[ls]; k < item_range[ls + 1]; ++k) {
     const LdsItem &it = items[k];
-    const double *g = gpart + it.gp_off + (int64_t)j * it.waves * twoQ + c;
-    for (int w = 0; w < it.waves; ++w) v += g[w * twoQ];
+    const double *g = gpart + it.gp_off + (int64_t)j * it.parts * twoQ + c;
+    for (int w = 0; w < it.parts; ++w) v += g[w * twoQ];
   }
   gstep[2 * S.ctab_off + idx] = v;
 }

@@ -98,6 +98,8 @@ int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const
                  double2 *y, int B, bool adj, hipStream_t st) {
   const int64_t total = (int64_t)B * p->sys[sys].N2;
   if (total == 0) return LB_OK;
+  if (p->tile && tile_nl(p, sys))
+    return launch_tile(p, sys, B, 0, adj, alpha, t, nullptr, 0, x, nullptr, y, st);
   const int64_t nblk = (total + STREAM_BLOCK - 1) / STREAM_BLOCK;
   if (adj)
     hipLaunchKernelGGL(apply_kernel<true>, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st,

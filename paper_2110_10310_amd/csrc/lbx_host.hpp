@@ -25,6 +25,8 @@ struct lb_plan {
   int32_t NT = 0;                 // common number of steps
   int64_t ctab_total = 0;         // sum over systems of NT*Q
   int path = 0;                   // LB_OPT_PATH
+  int tile = 1;                   // LB_OPT_TILE
+  int tile_ki = 0;                // LB_OPT_TILE_KI (0: default block)
   double tol = 1.1102230246251565e-16;  // LB_OPT_SOLVE_TOL (2^-53)
   int device = 0;
   // LB_OPT_PROFILE: per-kernel-family launch counts and durations.
@@ -42,9 +44,9 @@ struct LdsItem {
   int32_t b;          // state index within its system
   int64_t off;        // first entry of the state in the batched buffers
   int64_t st_off;     // first entry of this item's state history (NT+1 states)
-  int64_t gp_off;     // first double of this item's gradient partials [NT][waves][2Q]
+  int64_t gp_off;     // first double of this item's gradient partials [NT][parts][2Q]
   double wterm;       // beta_b / M_s (terminal condition weight)
-  int32_t waves;      // wavefronts per block of this item's kernel
+  int32_t parts;      // gradient partial sums per step written by this item's block
   int32_t pad;
 };
 
@@ -140,5 +142,26 @@ int launch_grad_contract(const lb_plan *p, const double *gstep, const double *al
 // LDS path: block size and entries per thread for a state of n2 entries;
 // returns false when the state does not fit the LDS-resident kernels.
 bool lds_shape(int64_t n2, int *block, int *ept);
+
+// Row-tiled streaming kernels (kernels_tile.hip).  tile_nl returns the common
+// level count of an eligible system (equal-level subsystems, N = NL^Q of
+// 512..8192) or 0.
+int tile_nl(const lb_plan *p, int sys);
+int tile_ki(const lb_plan *p, int sys);  // internal digits of the block, 0 if not eligible
+// mode 0: y = M x (alpha, t); mode 1: sweep (q + delta); mode 2: last sweep (q + 2 delta),
+// with the controls of step j from ctab.
+int launch_tile(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
+                const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
+                hipStream_t st);
+
+// Specialised LDS-resident kernels (kernels_lds_fast.hip) for Q subsystems.
+bool lds_fast_ok(int block, int ept, int Q);
+int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
+                            int Q, const double2 *ctab, const int32_t *ktab, const double2 *rho0,
+                            double2 *rhoT, double2 *states, hipStream_t st);
+int launch_lds_adjoint_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
+                            int Q, int kind, const double2 *ctab, const int32_t *ktab,
+                            const double2 *rhotar, const double2 *states, double *gpart,
+                            hipStream_t st);
 
 }  // namespace lbx

@@ -328,3 +328,52 @@ def test_config2_full_length_against_stored_oracle(lbx):
     assert abs(G.item() - float(gold["G"])) <= 1e-12 * abs(float(gold["G"]))
     g = grad.cpu().numpy().reshape(gold["grad"].shape)
     assert np.max(np.abs(g - gold["grad"])) <= GRAD_TOL * np.max(np.abs(gold["grad"]))
+
+
+# --------------------------------------------------------------- row-tiled kernels
+
+TILE_SHAPES = [(2,) * 9, (3,) * 6, (4,) * 5]
+
+
+@pytest.mark.parametrize("nlev", TILE_SHAPES)
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_row_tiled_apply_matches_operator_form(lbx, nlev, adjoint):
+    s, alpha, rng = _sys(200 + len(nlev), nlev, Nf=1)
+    N = s.N
+    x = rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))
+    t = 0.77
+    say("tile apply", nlev, adjoint)
+    plan = lbx.Plan([s])
+    y = lbx.lindblad_apply(plan, 0, t, dev(alpha.reshape(-1)), dev(x), adjoint=adjoint).cpu().numpy()
+    f = oracle.lindbladian_adjoint if adjoint else oracle.lindbladian
+    ref = np.stack([f(s, alpha, t, x[b]) for b in range(2)])
+    assert rel_state_err(y, ref) < 1e-13
+    plan_g = lbx.Plan([s], tile=False)
+    yg = lbx.lindblad_apply(plan_g, 0, t, dev(alpha.reshape(-1)), dev(x), adjoint=adjoint).cpu().numpy()
+    assert rel_state_err(y, yg) < 1e-14
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_row_tiled_imr_step_matches_oracle(lbx, adjoint):
+    s, alpha, rng = _sys(211, (3,) * 6, NT=8, T=0.4, Nf=1)
+    N = s.N
+    q = random_pure_states(rng, N, 1)
+    j = 3
+    say("tile imr_step", adjoint)
+    plan = lbx.Plan([s])
+    out = lbx.imr_step(plan, 0, j, dev(alpha.reshape(-1)), dev(q), adjoint=adjoint).cpu().numpy()
+    t = (j + 0.5) * s.dt
+    f = oracle.lindbladian_adjoint if adjoint else oracle.lindbladian
+    import scipy.sparse.linalg as spla
+    v0 = oracle.vec(q[0])
+    A = spla.LinearOperator((N * N, N * N), dtype=complex,
+                            matvec=lambda v: v - 0.5 * s.dt * oracle.vec(f(s, alpha, t, oracle.unvec(v, N))))
+    z, info = spla.gmres(A, v0, rtol=1e-14, atol=0.0, restart=60, maxiter=40)
+    ref = oracle.unvec(v0 + s.dt * oracle.vec(f(s, alpha, t, oracle.unvec(z, N))), N)
+    assert rel_state_err(out, ref[None]) < STATE_TOL
+
+
+def test_row_tiled_gradient_matches_oracle(lbx):
+    systems, alphas, rho0, batch = _multi([(220, (3,) * 6)], NT=3, B=(1,), T=0.15)
+    say("tile gradient")
+    _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "stream", 2)
