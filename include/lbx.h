@@ -83,6 +83,9 @@ extern "C" {
 #define LB_OPT_TILE_KI 4   /* block shape of the block-tiled kernels, 10*KR + KC with KR
                               (KC) row (column) digits inside a block; 0 (default): the
                               shape listed first for the system */
+#define LB_OPT_GRAPH 5     /* > 0: streamed time loops are captured as HIP graphs of this
+                              many steps and replayed (one graph launch per chunk);
+                              0 (default): kernels are launched directly */
 
 /* Kernel families timed by LB_OPT_PROFILE (lb_profile_read). */
 #define LB_KERNEL_LDS_FORWARD 0  /* persistent forward time loop, LDS-resident */
@@ -194,6 +197,17 @@ int adjoint_gradient(const lb_plan *plan, int32_t kind, const double *alpha, con
                      const void *rhotar, const double *beta, const int32_t *batch_per_sys,
                      double gamma2, int32_t ckpt_every, double *G, double *grad, void *rhoT,
                      void *ws, size_t ws_bytes, void *stream);
+
+/* Autotuner for the streamed systems of batch_per_sys (HOST): times one stage
+ * sweep of the generic kernel and of every instantiated block shape of the
+ * block-tiled kernels, then a short streamed forward run with and without
+ * graph capture, on the workspace (DEVICE, lb_workspace_bytes(LB_OP_FORWARD)
+ * bytes; its contents are overwritten), and sets LB_OPT_TILE, LB_OPT_TILE_KI and
+ * LB_OPT_GRAPH of the plan to the fastest.  result: HOST [3], the chosen
+ * values.  alpha: DEVICE.  Synchronises the stream.  A plan without streamed
+ * systems in this batch is left unchanged. */
+int lb_autotune(lb_plan *plan, const double *alpha, const int32_t *batch_per_sys, void *ws,
+                size_t ws_bytes, void *stream, int32_t *result);
 
 /* Message for the last non-zero return on the calling thread ("" if none). */
 const char *lb_last_error(void);

@@ -31,6 +31,7 @@ LB_OPT_SOLVE_TOL = 1
 LB_OPT_PROFILE = 2
 LB_OPT_TILE = 3
 LB_OPT_TILE_KI = 4
+LB_OPT_GRAPH = 5
 
 LB_KERNEL_LDS_FORWARD = 0
 LB_KERNEL_LDS_ADJOINT = 1
@@ -68,6 +69,7 @@ SIGNATURES = {
                                    _p, _p, C.c_size_t, _p]),
     "lb_profile_read": (C.c_int, [_p, _i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), _i32]),
     "sweep_counts": (C.c_int, [_p, _p, _ip, _p]),
+    "lb_autotune": (C.c_int, [_p, _p, _ip, _p, C.c_size_t, _p, _ip]),
     "lb_last_error": (C.c_char_p, []),
 }
 

@@ -114,6 +114,39 @@ class Plan:
               "lb_profile_read")
         return n.value, ms.value
 
+    def autotune(self, alpha: torch.Tensor, batch: Sequence[int], cache: str | None = None) -> dict:
+        """Pick the fastest kernel configuration of the streamed systems.
+
+        Runs lb_autotune, or reuses the choice stored in the JSON file `cache`
+        under a key made of the system shapes and the batch.
+        """
+        import json
+        import os
+        key = json.dumps([[list(s.nlev) for s in self.systems], [int(b) for b in batch], self.NT])
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+        if key in table:
+            ch = table[key]
+            self.set_option(nat.LB_OPT_TILE, ch["tile"])
+            self.set_option(nat.LB_OPT_TILE_KI, ch["tile_ki"])
+            self.set_option(nat.LB_OPT_GRAPH, ch["graph_steps"])
+            return ch
+        b = self.batch_array(batch)
+        _need(alpha, "alpha", torch.float64, int(self.alpha_off[-1]))
+        ws = self.workspace(nat.LB_OP_FORWARD, batch)
+        res = np.zeros(3, dtype=np.int32)
+        check(lib.lb_autotune(self.handle, _vp(alpha), b.ctypes.data_as(nat._ip), _vp(ws), ws.numel(),
+                              _stream(), res.ctypes.data_as(nat._ip)), "lb_autotune")
+        self._ws.clear()
+        ch = {"tile": int(res[0]), "tile_ki": int(res[1]), "graph_steps": int(res[2])}
+        if cache:
+            table[key] = ch
+            with open(cache, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+        return ch
+
     def set_path(self, path: str) -> None:
         self.set_option(nat.LB_OPT_PATH, PATHS[path])
 

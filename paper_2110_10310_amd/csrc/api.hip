@@ -371,6 +371,83 @@ int copy_segments(const BatchMeta &m, const double2 *src, bool src_batched, doub
   return LB_OK;
 }
 
+// LB_OPT_GRAPH: the streamed time loop is recorded in chunks of steps with
+// stream capture on a private stream and replayed as one graph launch per
+// chunk.  Chunks of equal shape reuse the executable graph through
+// hipGraphExecUpdate.  Only kernel launches are captured.
+struct GraphRun {
+  const lb_plan *p;
+  hipStream_t user;
+  hipStream_t cap = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool on;
+  bool active = false;  // a capture is open
+  GraphRun(const lb_plan *p_, hipStream_t s) : p(p_), user(s), on(p_->graph_steps > 0) {}
+  int init() {
+    if (!on) return LB_OK;
+    LBX_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    LBX_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    return LB_OK;
+  }
+  hipStream_t stream() const { return on ? cap : user; }
+  int begin() {
+    if (!on) return LB_OK;
+    LBX_HIP(hipEventRecord(ev, user));
+    LBX_HIP(hipStreamWaitEvent(cap, ev, 0));
+    LBX_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    active = true;
+    p->capturing = true;
+    return LB_OK;
+  }
+  int end() {
+    if (!on) return LB_OK;
+    p->capturing = false;
+    active = false;
+    hipGraph_t g = nullptr;
+    LBX_HIP(hipStreamEndCapture(cap, &g));
+    bool ok = false;
+    if (exec) {
+      hipGraphExecUpdateResult res;
+      hipGraphNode_t err_node = nullptr;
+      ok = hipGraphExecUpdate(exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+      if (!ok) {
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+      }
+    }
+    if (!exec) {
+      const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+    }
+    (void)hipGraphDestroy(g);
+    LBX_HIP(hipGraphLaunch(exec, cap));
+    LBX_HIP(hipEventRecord(ev, cap));
+    LBX_HIP(hipStreamWaitEvent(user, ev, 0));
+    return LB_OK;
+  }
+  ~GraphRun() {
+    if (!on) return;
+    p->capturing = false;
+    if (active) {  // an error left the capture open: close and drop it
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (cap) {
+      (void)hipStreamSynchronize(cap);
+      (void)hipStreamDestroy(cap);
+    }
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
 // One stage-solve sweep of every streamed segment at step j.
 int sweep(const lb_plan *p, const BatchMeta &m, int j, bool adj, bool last, const double2 *ctab,
           const double2 *zin, const double2 *qin, double2 *out, hipStream_t st) {
@@ -387,19 +464,28 @@ int sweep(const lb_plan *p, const BatchMeta &m, int j, bool adj, bool last, cons
 template <class Slot>
 int stream_forward(const lb_plan *p, const BatchMeta &m, const std::vector<int32_t> &k,
                    const double2 *ctab, int j0, int j1, const double2 *qstart, Slot slot,
-                   double2 *z0, double2 *z1, hipStream_t st) {
+                   double2 *z0, double2 *z1, hipStream_t user) {
+  GraphRun gr(p, user);
+  if (int rc = gr.init()) return rc;
+  const hipStream_t st = gr.stream();
+  const int chunk = gr.on ? p->graph_steps : (j1 - j0);
   const double2 *cur = qstart;
-  for (int j = j0; j < j1; ++j) {
-    int K = 1;
-    for (const auto &sg : m.segs) K = std::max(K, (int)k[((size_t)sg.sys * p->NT + j) * 2 + 1]);
-    double2 *out = slot(j + 1);
-    for (int kk = 0; kk < K; ++kk) {
-      const bool last = kk == K - 1;
-      const double2 *zin = kk == 0 ? cur : (kk & 1 ? z0 : z1);
-      double2 *dst = last ? out : (kk & 1 ? z1 : z0);
-      if (int rc = sweep(p, m, j, false, last, ctab, zin, cur, dst, st)) return rc;
+  for (int c0 = j0; c0 < j1; c0 += chunk) {
+    const int c1 = std::min(j1, c0 + chunk);
+    if (int rc = gr.begin()) return rc;
+    for (int j = c0; j < c1; ++j) {
+      int K = 1;
+      for (const auto &sg : m.segs) K = std::max(K, (int)k[((size_t)sg.sys * p->NT + j) * 2 + 1]);
+      double2 *out = slot(j + 1);
+      for (int kk = 0; kk < K; ++kk) {
+        const bool last = kk == K - 1;
+        const double2 *zin = kk == 0 ? cur : (kk & 1 ? z0 : z1);
+        double2 *dst = last ? out : (kk & 1 ? z1 : z0);
+        if (int rc = sweep(p, m, j, false, last, ctab, zin, cur, dst, st)) return rc;
+      }
+      cur = out;
     }
-    cur = out;
+    if (int rc = gr.end()) return rc;
   }
   return LB_OK;
 }
@@ -578,6 +664,11 @@ extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
   if (option == LB_OPT_TILE_KI) {
     if (value < 0 || value > 99 || value != (int)value) return fail(LB_EINVAL, "LB_OPT_TILE_KI must be 0..99");
     p->tile_ki = (int)value;
+    return LB_OK;
+  }
+  if (option == LB_OPT_GRAPH) {
+    if (value < 0 || value > 100000 || value != (int)value) return fail(LB_EINVAL, "LB_OPT_GRAPH must be 0..100000");
+    p->graph_steps = (int)value;
     return LB_OK;
   }
   if (option == LB_OPT_PROFILE) {
@@ -825,25 +916,34 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
       // Recompute q^{j0+1} .. q^{j1-1} from the checkpoint.
       if (j1 - j0 > 1)
         if ((rc = stream_forward(p, *m, k, ctab, j0, j1 - 1, slot(j0), slot, z0, z1, st))) return rc;
-      for (int j = j1 - 1; j >= j0; --j) {
-        int K = 1;
-        for (const auto &sg : m->segs) K = std::max(K, (int)k[((size_t)sg.sys * NT + j) * 2 + 1]);
-        const double2 *qin = qh[cur];
-        double2 *qout = qh[cur ^ 1];
-        for (int kk = 0; kk < K; ++kk) {
-          const bool last = kk == K - 1;
-          const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
-          double2 *dst = last ? qout : (kk & 1 ? z1 : z0);
-          if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, st))) return rc;
+      GraphRun gr(p, st);
+      if ((rc = gr.init())) return rc;
+      const hipStream_t ast = gr.stream();
+      const int chunk = gr.on ? p->graph_steps : c;
+      for (int ce = j1; ce > j0; ce -= chunk) {
+        const int cb = std::max(j0, ce - chunk);
+        if ((rc = gr.begin())) return rc;
+        for (int j = ce - 1; j >= cb; --j) {
+          int K = 1;
+          for (const auto &sg : m->segs) K = std::max(K, (int)k[((size_t)sg.sys * NT + j) * 2 + 1]);
+          const double2 *qin = qh[cur];
+          double2 *qout = qh[cur ^ 1];
+          for (int kk = 0; kk < K; ++kk) {
+            const bool last = kk == K - 1;
+            const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
+            double2 *dst = last ? qout : (kk & 1 ? z1 : z0);
+            if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, ast))) return rc;
+          }
+          {
+            ProfScope ps(p, LB_KERNEL_STREAM_GRAD, ast);
+            if ((rc = launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, qout, qin, slot(j),
+                                         slot(j + 1), sgp, ast)))
+              return rc;
+          }
+          if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, j, sgp, gstep, ast))) return rc;
+          cur ^= 1;
         }
-        {
-          ProfScope ps(p, LB_KERNEL_STREAM_GRAD, st);
-          if ((rc = launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, qout, qin, slot(j), slot(j + 1),
-                                       sgp, st)))
-            return rc;
-        }
-        if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, j, sgp, gstep, st))) return rc;
-        cur ^= 1;
+        if ((rc = gr.end())) return rc;
       }
     }
   }
@@ -889,6 +989,141 @@ extern "C" int sweep_counts(const lb_plan *p, const double *alpha, int32_t *coun
   }
   (void)hipFree(tmp);
   return rc;
+}
+
+// ----------------------------------------------------------------------------
+// Autotuner: times the kernel configurations of the streamed systems of a
+// batch on the caller's workspace and keeps the fastest in the plan.
+// ----------------------------------------------------------------------------
+namespace {
+
+int time_sweeps(const lb_plan *p, const BatchMeta &m, const Layout &L, char *w, int reps,
+                hipStream_t st, float *ms) {
+  double2 *ctab = (double2 *)(w + L.ctab);
+  double2 *q0 = (double2 *)(w + L.st_q0), *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
+  hipEvent_t a, b;
+  LBX_HIP(hipEventCreate(&a));
+  LBX_HIP(hipEventCreate(&b));
+  int rc = LB_OK;
+  for (int r = 0; r < 2 && !rc; ++r) rc = sweep(p, m, 0, false, false, ctab, z0, q0, z1, st);
+  if (!rc) (void)hipEventRecord(a, st);
+  for (int r = 0; r < reps && !rc; ++r)
+    rc = sweep(p, m, 0, false, false, ctab, (r & 1) ? z1 : z0, q0, (r & 1) ? z0 : z1, st);
+  if (!rc) {
+    (void)hipEventRecord(b, st);
+    const hipError_t e = hipEventSynchronize(b);
+    if (e != hipSuccess) rc = hip_fail(e, "autotune timing");
+    else (void)hipEventElapsedTime(ms, a, b);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch_per_sys, void *ws,
+                           size_t ws_bytes, void *stream, int32_t *result) {
+  if (int rc = check_plan(p)) return rc;
+  if (!alpha || !batch_per_sys || !ws || !result) return fail(LB_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  BatchMeta *m;
+  if (int rc = build_batch(p, batch_per_sys, &m)) return rc;
+  result[0] = p->tile;
+  result[1] = p->tile_ki;
+  result[2] = p->graph_steps;
+  if (m->segs.empty()) return LB_OK;
+  // Workspace must hold the forward layout of every candidate (the generic
+  // and tiled layouts are the same size).
+  const Layout L = layout(p, LB_OP_FORWARD, *m, 1);
+  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  int rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, (double2 *)(w + L.ctab), 0,
+                                (int32_t *)(w + L.ktab), st);
+  if (rc) return rc;
+  std::vector<int32_t> k;
+  if ((rc = fetch_ktab(p, (int32_t *)(w + L.ktab), k, st))) return rc;
+  if ((rc = check_k(p, k, *m))) return rc;
+  const size_t E = (size_t)m->st_entries * sizeof(double2);
+  LBX_HIP(hipMemsetAsync(w + L.st_q0, 0, E, st));
+  LBX_HIP(hipMemsetAsync(w + L.st_z0, 0, E, st));
+  LBX_HIP(hipMemsetAsync(w + L.st_z1, 0, E, st));
+  // Kernel family and block shape.
+  std::vector<std::pair<int, int>> cand = {{0, 0}};
+  const int saved_tile = p->tile, saved_ki = p->tile_ki, saved_graph = p->graph_steps;
+  if (m->segs.size() == 1) {
+    const int sys = m->segs[0].sys;
+    for (int ki : {44, 43, 34, 42, 33, 66, 55, 32, 23}) {
+      p->tile = 1;
+      p->tile_ki = ki;
+      if (tile_ki(p, sys) == ki) cand.push_back({1, ki});
+    }
+  }
+  const int reps = m->st_entries > (1 << 22) ? 4 : 20;
+  float best = 1e30f;
+  int bt = 0, bk = 0;
+  p->graph_steps = 0;
+  for (const auto &c : cand) {
+    p->tile = c.first;
+    p->tile_ki = c.second;
+    BatchMeta *mc;
+    if ((rc = build_batch(p, batch_per_sys, &mc))) break;
+    float ms = 0.f;
+    if ((rc = time_sweeps(p, *mc, L, w, reps, st, &ms))) break;
+    if (ms < best) {
+      best = ms;
+      bt = c.first;
+      bk = c.second;
+    }
+  }
+  if (rc) {
+    p->tile = saved_tile;
+    p->tile_ki = saved_ki;
+    p->graph_steps = saved_graph;
+    return rc;
+  }
+  p->tile = bt;
+  p->tile_ki = bk;
+  // Direct launches against graph-captured chunks of the time loop.
+  BatchMeta *mb;
+  if ((rc = build_batch(p, batch_per_sys, &mb))) return rc;
+  const int steps = std::min(p->NT, 32);
+  double2 *q0 = (double2 *)(w + L.st_q0), *q1 = (double2 *)(w + L.st_q1);
+  double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
+  float tg[2] = {0.f, 0.f};
+  for (int g = 0; g < 2 && !rc; ++g) {
+    p->graph_steps = g ? steps : 0;
+    for (int rep = 0; rep < 2 && !rc; ++rep) {  // first repetition warms up
+      hipEvent_t a, b;
+      LBX_HIP(hipEventCreate(&a));
+      LBX_HIP(hipEventCreate(&b));
+      (void)hipEventRecord(a, st);
+      const double2 *last = q0;
+      auto slot = [&](int) -> double2 * {
+        double2 *r = last == q0 ? q1 : q0;
+        last = r;
+        return r;
+      };
+      rc = stream_forward(p, *mb, k, (double2 *)(w + L.ctab), 0, steps, q0, slot, z0, z1, st);
+      (void)hipEventRecord(b, st);
+      if (!rc) {
+        const hipError_t e = hipEventSynchronize(b);
+        if (e != hipSuccess) rc = hip_fail(e, "autotune timing");
+        else (void)hipEventElapsedTime(&tg[g], a, b);
+      }
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  }
+  if (rc) {
+    p->graph_steps = saved_graph;
+    return rc;
+  }
+  p->graph_steps = tg[1] < 0.95f * tg[0] ? steps : 0;
+  result[0] = p->tile;
+  result[1] = p->tile_ki;
+  result[2] = p->graph_steps;
+  return LB_OK;
 }
 
 extern "C" const char *lb_last_error(void) { return g_err.c_str(); }

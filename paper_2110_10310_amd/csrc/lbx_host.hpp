@@ -27,6 +27,8 @@ struct lb_plan {
   int path = 0;                   // LB_OPT_PATH
   int tile = 1;                   // LB_OPT_TILE
   int tile_ki = 0;                // LB_OPT_TILE_KI (0: default block)
+  int graph_steps = 0;            // LB_OPT_GRAPH (0: launch directly)
+  mutable bool capturing = false; // inside a stream capture: no profiling events
   double tol = 1.1102230246251565e-16;  // LB_OPT_SOLVE_TOL (2^-53)
   int device = 0;
   // LB_OPT_PROFILE: per-kernel-family launch counts and durations.
@@ -69,7 +71,7 @@ struct ProfScope {
   hipStream_t st;
   hipEvent_t a = nullptr;
   ProfScope(const lb_plan *p_, int k, hipStream_t s) : p(p_), kernel(k), st(s) {
-    if (p->profile && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
+    if (p->profile && !p->capturing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
   }
   ~ProfScope() {
     if (!a) return;

@@ -377,3 +377,44 @@ def test_row_tiled_gradient_matches_oracle(lbx):
     systems, alphas, rho0, batch = _multi([(220, (3,) * 6)], NT=3, B=(1,), T=0.15)
     say("tile gradient")
     _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "stream", 2)
+
+
+# --------------------------------------------------------------- graphs and autotuning
+
+def test_graph_captured_time_loop_matches_direct_launches(lbx):
+    from paper_2110_10310_amd import _native as nat
+    systems, alphas, rho0, batch = _multi([(300, (3, 3, 3)), (301, (2, 3, 4))], NT=23, B=(3, 2))
+    rng = np.random.default_rng(302)
+    tars = [random_pure_states(rng, s.N, b) for s, b in zip(systems, batch)]
+    args = (dev(flat_alpha(alphas)), dev(flat_states(rho0)), dev(flat_states(tars)),
+            dev(np.ones(sum(batch))), batch)
+    say("graph capture")
+    direct = lbx.Plan(systems, path="stream")
+    graph = lbx.Plan(systems, path="stream")
+    graph.set_option(nat.LB_OPT_GRAPH, 5)  # chunks of 5 steps: several replays, ragged last chunk
+    rd = lbx.forward_solve(direct, args[0], args[1], batch).cpu().numpy()
+    for _ in range(3):  # replays interleaved with eager work and synchronisation
+        rg = lbx.forward_solve(graph, args[0], args[1], batch).cpu().numpy()
+        assert np.array_equal(rg, rd)
+        torch.cuda.synchronize()
+    Gd, gd, _ = lbx.adjoint_gradient(direct, 0, *args, ckpt_every=7)
+    Gg, gg, _ = lbx.adjoint_gradient(graph, 0, *args, ckpt_every=7)
+    assert np.array_equal(gd.cpu().numpy(), gg.cpu().numpy())
+    assert np.array_equal(Gd.cpu().numpy(), Gg.cpu().numpy())
+    ref = [oracle.imr_forward(s, a, r) for s, a, r in zip(systems, alphas, rho0)]
+    assert rel_state_err(split_states(rg, systems, batch), ref) < STATE_TOL
+
+
+def test_autotuner_choice_and_cache(lbx, tmp_path):
+    systems, alphas, rho0, batch = _multi([(310, (3,) * 6)], NT=4, B=(1,), T=0.2)
+    plan = lbx.Plan(systems)
+    al = dev(flat_alpha(alphas))
+    say("autotune")
+    cache = str(tmp_path / "tune.json")
+    ch = plan.autotune(al, batch, cache=cache)
+    assert ch["tile"] in (0, 1) and ch["graph_steps"] >= 0
+    plan2 = lbx.Plan(systems)
+    assert plan2.autotune(al, batch, cache=cache) == ch  # served from the cache
+    rT = lbx.forward_solve(plan, al, dev(flat_states(rho0)), batch).cpu().numpy()
+    ref = [oracle.imr_forward(systems[0], alphas[0], rho0[0])]
+    assert rel_state_err(split_states(rT, systems, batch), ref) < STATE_TOL
