@@ -40,9 +40,20 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, dense
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 APPLY_SOURCES = ["paper_2110_10310_amd/csrc/kernels_stream.hip",
+                 "paper_2110_10310_amd/csrc/kernels_tile.hip",
                  "paper_2110_10310_amd/csrc/lbx_device.hpp"]
 LDS_SOURCES = ["paper_2110_10310_amd/csrc/kernels_lds.hip",
+               "paper_2110_10310_amd/csrc/kernels_lds_fast.hip",
                "paper_2110_10310_amd/csrc/lbx_device.hpp"]
+# traffic keys: (substring of the kernel name in the counter CSV, sources it is built from)
+TRAFFIC_KEYS = {
+    "apply_kernel_forward": (["tile_kernel<3, 8, 4, 4, false, 0>"], APPLY_SOURCES),
+    "apply_kernel_adjoint": (["tile_kernel<3, 8, 4, 4, true, 0>"], APPLY_SOURCES),
+    "stage_sweep_kernel_c5": (["tile_kernel<3, 8, 4, 4, false, 1>", "tile_kernel<3, 8, 4, 4, false, 2>"],
+                              APPLY_SOURCES),
+    "lds_forward_kernel": (["lds_forward_fast_kernel"], LDS_SOURCES),
+    "lds_adjoint_kernel": (["lds_adjoint_fast_kernel"], LDS_SOURCES),
+}
 
 
 def source_sha(files):
@@ -87,56 +98,96 @@ def flops_per_entry(nlev):
     return sweep, grad
 
 
-def run_gradient_bench(lbx, torch, steps, warmup):
-    from workloads import make_config
-    p = make_config(2)
-    s = p.systems[0]
+WORKLOADS = {
+    1: "c1_qutrit: 1 qutrit (N=3), 1 state, 2000 IMR steps, 20 controls, J_Frob",
+    2: "c2_cnot_2x4: 2 transmons x 4 levels (N=16), 16 basis states, 10000 IMR steps, "
+       "160 controls, J_Frob, forward+adjoint gradient",
+    3: "c3_uneven_96: 96 systems of 2-4 qudits with 3-5 levels (N 9..500), 1-8 states each, "
+       "5000 IMR steps, J_Frob",
+    4: "c4_5qutrit_chain: 5 qutrits (N=243), 10 states, 20000 IMR steps, 300 controls, J_Tr, "
+       "checkpoints every 200 steps",
+    5: "c5_8qutrit_ring: 8 qutrits (N=6561, 43M entries), 1 state, 5000 IMR steps, 320 controls, "
+       "J_Frob, checkpoints every ceil(sqrt(NT)) steps",
+}
+
+
+def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
+    from workloads import make_config, truncate_steps
+    p = make_config(workload)
+    nt_full = p.systems[0].NT
+    if sample_steps and sample_steps < nt_full:
+        p = truncate_steps(p, sample_steps)
+    nat = lbx._native
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda")
-    alpha = dev(p.alpha[0].reshape(-1))
-    rho0, tar, beta = dev(p.rho0[0]), dev(p.rhotar[0]), dev(p.beta[0])
-    plan = lbx.Plan([s])
-    B = rho0.shape[0]
-    batch = [B]
+    alpha = dev(np.concatenate([a.reshape(-1) for a in p.alpha]))
+    rho0 = dev(np.concatenate([r.reshape(-1) for r in p.rho0]))
+    tar = dev(np.concatenate([r.reshape(-1) for r in p.rhotar]))
+    beta = dev(np.concatenate(p.beta))
+    batch = p.batch
+    plan = lbx.Plan(p.systems)
+    tuned = plan.autotune(alpha, batch)
+    ckpt = p.ckpt_every
     for _ in range(warmup):
-        lbx.adjoint_gradient(plan, p.kind, alpha, rho0, tar, beta, batch)
+        lbx.adjoint_gradient(plan, p.kind, alpha, rho0, tar, beta, batch, p.gamma2, ckpt)
     plan.profile(True)
     for k in range(4):
         plan.profile_read(k, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        G, grad, _ = lbx.adjoint_gradient(plan, p.kind, alpha, rho0, tar, beta, batch)
+        G, grad, _ = lbx.adjoint_gradient(plan, p.kind, alpha, rho0, tar, beta, batch, p.gamma2, ckpt)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    nat = lbx._native
-    n_f, ms_f = plan.profile_read(nat.LB_KERNEL_LDS_FORWARD)
-    n_a, ms_a = plan.profile_read(nat.LB_KERNEL_LDS_ADJOINT)
+    prof = {k: plan.profile_read(k) for k in range(4)}
     plan.profile(False)
-    counts = lbx.sweep_counts(plan, alpha)[0, :, 0].astype(np.int64)
-    entries = B * s.N * s.N
-    f_sweep, f_grad = flops_per_entry(s.nlev)
-    fl_fwd = float(counts.sum()) * entries * f_sweep
-    fl_adj = fl_fwd + s.NT * entries * f_grad
-    if ms_a >= ms_f:
-        name, n, ms, fl = "lds_adjoint_kernel", n_a, ms_a, fl_adj
+    counts = lbx.sweep_counts(plan, alpha)  # [nsys, NT, 2]
+    # algorithmic cost of each kernel family per launch
+    lds_fwd = lds_adj = 0.0
+    st_entries = 0
+    for k, s in enumerate(p.systems):
+        entries = batch[k] * s.N * s.N
+        if s.N * s.N <= 4096:
+            f_sweep, f_grad = flops_per_entry(s.nlev)
+            fl = float(counts[k, :, 0].sum()) * entries * f_sweep
+            lds_fwd += fl
+            lds_adj += fl + s.NT * entries * f_grad
+        else:
+            st_entries += entries
+    n = {k: max(v[0], 1) for k, v in prof.items()}
+    ms = {k: v[1] for k, v in prof.items()}
+    name_of = {nat.LB_KERNEL_LDS_FORWARD: "lds_forward_kernel", nat.LB_KERNEL_LDS_ADJOINT: "lds_adjoint_kernel",
+               nat.LB_KERNEL_SWEEP: "stage_sweep_kernel", nat.LB_KERNEL_STREAM_GRAD: "stream_grad_kernel"}
+    dom = max(ms, key=lambda k: ms[k])
+    avg_s = ms[dom] / n[dom] / 1e3
+    if dom in (nat.LB_KERNEL_LDS_FORWARD, nat.LB_KERNEL_LDS_ADJOINT):
+        fl = (lds_fwd if dom == nat.LB_KERNEL_LDS_FORWARD else lds_adj) / (n[dom] / steps)
+        achieved = fl / avg_s / 1e12
+        roof = {"kernel": name_of[dom], "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": measured_traffic(name_of[dom], LDS_SOURCES),
+                "avg_launch_ms": 1e3 * avg_s, "launches": prof[dom][0], "flops_per_launch": fl,
+                "workgroups": sum(b for k, b in enumerate(batch) if p.systems[k].N ** 2 <= 4096)}
     else:
-        name, n, ms, fl = "lds_forward_kernel", n_f, ms_f, fl_fwd
-    avg_s = ms / max(n, 1) / 1e3
-    achieved = fl / avg_s / 1e12
-    traffic = measured_traffic(name, LDS_SOURCES)
+        per_entry = 48.0 if dom == nat.LB_KERNEL_SWEEP else 64.0
+        by = per_entry * st_entries
+        achieved = by / avg_s / 1e9
+        roof = {"kernel": name_of[dom], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(name_of[dom] + f"_c{workload}", APPLY_SOURCES),
+                "avg_launch_ms": 1e3 * avg_s, "launches": prof[dom][0], "bytes_per_launch": by}
+    scale = nt_full / p.systems[0].NT
     return {
-        "value": steps / elapsed,
-        "ms_per_step": 1e3 * elapsed / steps,
-        "G": float(G.item()),
+        "value": steps / (elapsed * scale),
+        "ms_per_step": 1e3 * elapsed * scale / steps,
+        "sample": None if scale == 1 else f"{p.systems[0].NT} of {nt_full} steps timed, scaled x{scale:g}",
+        "G": [float(v) for v in G.cpu().numpy()[:4]],
         "grad_norm": float(grad.abs().max().item()),
-        "sweeps_per_step_mean": float(counts.mean()),
-        "roofline": {
-            "kernel": name, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-            "avg_launch_ms": 1e3 * avg_s, "launches": n, "flops_per_launch": fl,
-            "workgroups": B, "note": "one workgroup per state: 16 of 256 CUs busy",
-        },
-        "kernel_ms": {"lds_forward_kernel": ms_f / max(n_f, 1), "lds_adjoint_kernel": ms_a / max(n_a, 1)},
+        "sweeps_per_step_mean": float(counts[:, :, 0].mean()),
+        "roofline": roof,
+        "kernel_ms": {name_of[k]: ms[k] / n[k] for k in ms if prof[k][0] > 0},
+        "kernel_total_ms": {name_of[k]: ms[k] / steps for k in ms if prof[k][0] > 0},
+        "autotune": tuned,
+        "states": sum(batch),
     }
 
 
@@ -174,6 +225,92 @@ def run_apply_bench(lbx, torch, reps):
         "adjoint_achieved": algo / (out["adjoint"] / 1e3) / 1e9,
         "bytes_per_launch": algo, "workload": "8 qutrits ring, N=6561, 1 state",
     }
+
+
+def run_traffic_probe(lbx, torch):
+    """Launches whose HBM counters are read by rocprofv3 --pmc: a plain device
+    copy of one eight-qutrit state (the calibration of the counters), two
+    forward and two adjoint applies and one IMR step on that state, and one
+    two-transmon gradient evaluation."""
+    from workloads import make_config
+    p = make_config(5)
+    s = p.systems[0]
+    N = s.N
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    x = torch.randn((1, N, N), dtype=torch.complex128, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    plan = lbx.Plan([s])
+    alpha = torch.as_tensor(p.alpha[0].reshape(-1)).to("cuda")
+    for adj in (False, True):
+        for _ in range(2):
+            lbx.lindblad_apply(plan, 0, 41.0, alpha, x, adjoint=adj, out=y)
+    lbx.imr_step(plan, 0, 2000, alpha, x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    print("[probe] eight-qutrit launches done", file=sys.stderr, flush=True)
+    p = make_config(2)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda")
+    plan = lbx.Plan(p.systems)
+    lbx.adjoint_gradient(plan, p.kind, dev(p.alpha[0].reshape(-1)), dev(p.rho0[0]), dev(p.rhotar[0]),
+                         dev(p.beta[0]), p.batch, p.gamma2, p.ckpt_every)
+    torch.cuda.synchronize()
+    print("[probe] two-transmon gradient done", file=sys.stderr, flush=True)
+    return {"copy_bytes": 16 * N * N}
+
+
+def traffic_summary(fetch_csv, write_csv, copy_bytes):
+    """Per-launch HBM bytes from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
+    for the plain device copy of copy_bytes bytes.  Writes profiles/traffic.json
+    and prints a markdown table."""
+    import csv
+
+    def per_kernel(path):
+        out = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
+    cal_f = copy_bytes / 1024 / max(fetch.get("__amd_rocclr_copyBuffer", [0]))
+    cal_w = copy_bytes / 1024 / max(write.get("__amd_rocclr_copyBuffer", [0]))
+    table = {"calibration": {"copy_bytes": copy_bytes, "fetch_factor": cal_f, "write_factor": cal_w}}
+    rows = []
+    for key, (pats, files) in TRAFFIC_KEYS.items():
+        fv = [v for k, vs in fetch.items() if any(pt in k for pt in pats) for v in vs]
+        wv = [v for k, vs in write.items() if any(pt in k for pt in pats) for v in vs]
+        if not fv or not wv:
+            continue
+        fb = 1024 * cal_f * float(np.mean(fv))
+        wb = 1024 * cal_w * float(np.mean(wv))
+        table[key] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                      "fetch_kib_raw": float(np.mean(fv)), "write_kib_raw": float(np.mean(wv)),
+                      "dispatches": [len(fv), len(wv)], "source_sha": source_sha(files)}
+        rows.append(f"| {key} | {len(fv)} | {np.mean(fv):.1f} | {np.mean(wv):.1f} | {fb / 1e9:.4f} | "
+                    f"{wb / 1e9:.4f} |")
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    print(f"calibration: copy of {copy_bytes} B; FETCH_SIZE x{cal_f:.3f}, WRITE_SIZE x{cal_w:.3f}")
+    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | fetch GB (scaled) | write GB (scaled) |")
+    print("|---|---|---|---|---|---|")
+    print("\n".join(rows))
+
+
+def kernel_stats(db):
+    """Markdown table of the per-kernel summary in a rocprofv3 --stats database."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    # durations in the summary view are in microseconds
+    print("| kernel | calls | total ms | average ms | % |")
+    print("|---|---|---|---|---|")
+    for name, calls, total, avg, pct in con.execute(
+            "select name, total_calls, total_duration, average, percentage from top_kernels limit 12"):
+        short = name.split("(")[0].replace("void ", "")
+        print(f"| `{short}` | {calls} | {total / 1e3:.3f} | {avg / 1e3:.4f} | {pct:.1f} |")
 
 
 def run_loop_baseline(lbx, torch, nsteps):
@@ -223,7 +360,26 @@ def main():
     ap.add_argument("--no-apply", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                    help="workload: 2 (default, two-transmon CNOT) or 1, 3, 4, 5")
+    ap.add_argument("--sample-steps", type=int, default=0,
+                    help="time only the first S time steps of the workload and scale to the full "
+                         "horizon (for workloads whose single evaluation runs for minutes)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run only the launches whose HBM counters profiles/traffic.json records")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs")
+    ap.add_argument("--kernel-stats", metavar="DB",
+                    help="print the per-kernel table of a rocprofv3 --stats results database")
     args = ap.parse_args()
+    if args.kernel_stats:
+        kernel_stats(args.kernel_stats)
+        return
+    if args.traffic_summary:
+        from workloads import make_config
+        n = make_config(5).systems[0].N
+        traffic_summary(*args.traffic_summary, 16 * n * n)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the batch of states would shard over GPUs with one all-reduce of G and dG/dalpha).",
@@ -234,21 +390,29 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.traffic_probe:
+        print(json.dumps(run_traffic_probe(lbx, torch)), flush=True)
+        return
     print("[bench] gradient evaluations", file=sys.stderr, flush=True)
-    res = run_gradient_bench(lbx, torch, args.steps, args.warmup)
+    res = run_gradient_bench(lbx, torch, args.steps, args.warmup, args.workload, args.sample_steps)
     line = {
         "metric": "forward+adjoint gradient evals/sec; lindblad_apply HBM GB/s vs peak",
         "value": res["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "c2_cnot_2x4: 2 transmons x 4 levels (N=16), 16 basis states, "
-                               "10000 IMR steps, 160 controls, J_Frob, forward+adjoint gradient",
-                   "global_batch": 16, "parallelism": "single GPU"},
+        "config": {"workload": WORKLOADS[args.workload], "global_batch": res["states"],
+                   "parallelism": "single GPU"},
+        "sample": res["sample"],
         "roofline": res["roofline"],
         "detail": {"G": res["G"], "grad_max": res["grad_norm"],
                    "sweeps_per_step_mean": res["sweeps_per_step_mean"],
-                   "kernel_avg_ms": res["kernel_ms"]},
+                   "kernel_avg_ms": res["kernel_ms"], "kernel_ms_per_eval": res["kernel_total_ms"],
+                   "autotune": res["autotune"]},
     }
+    if args.workload != 2:
+        args.no_apply = args.no_apply or args.workload != 5
+        args.no_loop = True
+        args.no_cpu = True
     if not args.no_apply:
         print("[bench] lindblad_apply 8 qutrits", file=sys.stderr, flush=True)
         line["apply_roofline"] = run_apply_bench(lbx, torch, args.apply_reps)

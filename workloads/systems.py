@@ -277,7 +277,8 @@ def _config3(rng, nsys=96):
         rho0s.append(random_pure_states(rng, N, B))
         tars.append(np.repeat(_basis_state(N, 0)[None], B, axis=0))
         betas.append(np.ones(B))
-    return Problem("c3_uneven_96", systems, alphas, rho0s, tars, betas, kind=KIND_FROB)
+    # the full state history of the streamed systems would take ~0.9 TB: checkpoint every ~sqrt(NT)
+    return Problem("c3_uneven_96", systems, alphas, rho0s, tars, betas, kind=KIND_FROB, ckpt_every=0)
 
 
 def _config4(rng):
