@@ -139,20 +139,28 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = {k: plan.profile_read(k) for k in range(4)}
+    work = {k: plan.profile_work(k) for k in range(4)}
     plan.profile(False)
-    counts = lbx.sweep_counts(plan, alpha)  # [nsys, NT, 2]
-    # algorithmic cost of each kernel family per launch
-    lds_fwd = lds_adj = 0.0
-    st_entries = 0
+    counts = lbx.sweep_counts(plan, alpha)  # [nsys, NT, 2], a-priori
+    # Algorithmic flops of the LDS-resident kernels: entry-sweeps done (read
+    # back from the kernels) times flops per entry and sweep, averaged over
+    # the systems with their a-priori sweep counts as weights.
+    wsum = fsum = grad_fl = 0.0
+    lds_entries = st_entries = 0
     for k, s in enumerate(p.systems):
         entries = batch[k] * s.N * s.N
         if s.N * s.N <= 4096:
             f_sweep, f_grad = flops_per_entry(s.nlev)
-            fl = float(counts[k, :, 0].sum()) * entries * f_sweep
-            lds_fwd += fl
-            lds_adj += fl + s.NT * entries * f_grad
+            wk = float(counts[k, :, 0].sum()) * entries
+            wsum += wk
+            fsum += wk * f_sweep
+            grad_fl += s.NT * entries * f_grad
+            lds_entries += entries
         else:
             st_entries += entries
+    f_avg = fsum / wsum if wsum else 0.0
+    lds_fwd = work[nat.LB_KERNEL_LDS_FORWARD] * f_avg / steps
+    lds_adj = work[nat.LB_KERNEL_LDS_ADJOINT] * f_avg / steps + grad_fl
     n = {k: max(v[0], 1) for k, v in prof.items()}
     ms = {k: v[1] for k, v in prof.items()}
     name_of = {nat.LB_KERNEL_LDS_FORWARD: "lds_forward_kernel", nat.LB_KERNEL_LDS_ADJOINT: "lds_adjoint_kernel",
@@ -169,12 +177,20 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
                 "workgroups": sum(b for k, b in enumerate(batch) if p.systems[k].N ** 2 <= 4096)}
     else:
         per_entry = 48.0 if dom == nat.LB_KERNEL_SWEEP else 64.0
-        by = per_entry * st_entries
+        by = per_entry * work[dom] / n[dom]
         achieved = by / avg_s / 1e9
         roof = {"kernel": name_of[dom], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(name_of[dom] + f"_c{workload}", APPLY_SOURCES),
                 "avg_launch_ms": 1e3 * avg_s, "launches": prof[dom][0], "bytes_per_launch": by}
+    nt = p.systems[0].NT
+    sweeps = {}
+    if lds_entries:
+        sweeps["lds_forward"] = work[nat.LB_KERNEL_LDS_FORWARD] / (steps * nt * lds_entries)
+        sweeps["lds_adjoint"] = work[nat.LB_KERNEL_LDS_ADJOINT] / (steps * nt * lds_entries)
+        sweeps["lds_a_priori"] = wsum / (nt * lds_entries)
+    if st_entries:
+        sweeps["stream_all_passes"] = work[nat.LB_KERNEL_SWEEP] / (steps * st_entries) / nt
     scale = nt_full / p.systems[0].NT
     return {
         "value": steps / (elapsed * scale),
@@ -182,7 +198,7 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
         "sample": None if scale == 1 else f"{p.systems[0].NT} of {nt_full} steps timed, scaled x{scale:g}",
         "G": [float(v) for v in G.cpu().numpy()[:4]],
         "grad_norm": float(grad.abs().max().item()),
-        "sweeps_per_step_mean": float(counts[:, :, 0].mean()),
+        "sweeps_per_step_mean": sweeps,
         "roofline": roof,
         "kernel_ms": {name_of[k]: ms[k] / n[k] for k in ms if prof[k][0] > 0},
         "kernel_total_ms": {name_of[k]: ms[k] / steps for k in ms if prof[k][0] > 0},

@@ -140,11 +140,24 @@ int lb_workspace_bytes(const lb_plan *plan, int32_t op, const int32_t *batch_per
 int lb_profile_read(const lb_plan *plan, int32_t kernel, int64_t *launches, double *total_ms,
                     int32_t reset);
 
-/* Stage-solve sweep counts per step (HOST counts [nsys][NT][2]: LDS-resident
- * kernels, streaming sweeps) for controls alpha (DEVICE, all systems).  The
- * fixed-point stage iteration of the implicit-midpoint solve runs until its
- * a-priori contraction bound reaches LB_OPT_SOLVE_TOL; a count of -1 marks a
- * step whose bound is >= 0.5.  Synchronises the stream. */
+/* Work done by kernel family `kernel` over the calls made while
+ * LB_OPT_PROFILE was on: state entries times stage-solve sweeps (entries
+ * times steps for LB_KERNEL_STREAM_GRAD).  Cleared with lb_profile_read's
+ * reset.  Profiling reads the per-state sweep totals of the LDS-resident
+ * kernels back after each launch (a synchronisation of the stream). */
+int lb_profile_work(const lb_plan *plan, int32_t kernel, int64_t *entry_sweeps);
+
+/* A-priori stage-solve sweep counts per step (HOST counts [nsys][NT][2]:
+ * LDS-resident kernels started from w h D q, streaming sweeps started from
+ * q) for controls alpha (DEVICE, all systems): the fixed-point stage
+ * iteration of the implicit-midpoint solve (App. A) contracts with a factor
+ * theta_j that is known before the step, and the count is the number of
+ * sweeps after which the contraction bound reaches LB_OPT_SOLVE_TOL.  A count
+ * of -1 marks a step with theta_j >= 0.5, which every entry point rejects.
+ * The streaming kernels and the generic LDS-resident kernels run exactly
+ * these counts; the specialised LDS-resident kernels start from an
+ * extrapolation of the previous stage increments and stop on an
+ * a-posteriori bound of the same tolerance.  Synchronises the stream. */
 int sweep_counts(const lb_plan *plan, const double *alpha, int32_t *counts, void *stream);
 
 /* Control values d_q(t_{j+1/2}) at every step midpoint of system `sys`

@@ -68,6 +68,7 @@ SIGNATURES = {
     "adjoint_gradient": (C.c_int, [_p, _i32, _p, _p, _p, _p, _ip, C.c_double, _i32, _p, _p,
                                    _p, _p, C.c_size_t, _p]),
     "lb_profile_read": (C.c_int, [_p, _i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), _i32]),
+    "lb_profile_work": (C.c_int, [_p, _i32, C.POINTER(C.c_int64)]),
     "sweep_counts": (C.c_int, [_p, _p, _ip, _p]),
     "lb_autotune": (C.c_int, [_p, _p, _ip, _p, C.c_size_t, _p, _ip]),
     "lb_last_error": (C.c_char_p, []),

@@ -114,6 +114,13 @@ class Plan:
               "lb_profile_read")
         return n.value, ms.value
 
+    def profile_work(self, kernel: int) -> int:
+        """Entries x stage sweeps (entries x steps for the gradient kernel) done
+        by one LB_KERNEL_* family while profiling; reset by profile_read."""
+        w = C.c_int64()
+        check(lib.lb_profile_work(self.handle, kernel, C.byref(w)), "lb_profile_work")
+        return w.value
+
     def autotune(self, alpha: torch.Tensor, batch: Sequence[int], cache: str | None = None) -> dict:
         """Pick the fastest kernel configuration of the streamed systems.
 

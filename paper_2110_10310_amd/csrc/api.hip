@@ -274,9 +274,9 @@ int ckpt_count(int NT, int c) { return (NT - 1) / c + 2; }
 
 // Workspace layout of one operation.
 struct Layout {
-  size_t ctab = 0, ktab = 0, gstep = 0, objpart = 0, hist = 0, gpart = 0, items = 0;
+  size_t ctab = 0, ktab = 0, ttab = 0, gstep = 0, objpart = 0, hist = 0, gpart = 0, items = 0;
   size_t st_q0 = 0, st_q1 = 0, st_z0 = 0, st_z1 = 0, st_qh0 = 0, st_qh1 = 0, ckpt = 0, seg = 0,
-         st_gpart = 0, rhoT = 0;
+         st_gpart = 0, st_gfin = 0, rhoT = 0;
   size_t total = 0;
   int c = 1, nck = 0;
 };
@@ -293,6 +293,7 @@ Layout layout(const lb_plan *p, int op, const BatchMeta &m, int ckpt_every) {
   const size_t E = (size_t)m.st_entries * sizeof(double2);
   L.ctab = take((size_t)p->ctab_total * sizeof(double2));
   L.ktab = take((size_t)nsys * p->NT * 2 * sizeof(int32_t));
+  L.ttab = take((size_t)nsys * p->NT * sizeof(double2));
   L.objpart = take((size_t)std::max(1, m.total_states) * 64 * sizeof(double));
   L.items = take(std::max<size_t>(1, m.items.size()) * sizeof(LdsItem));
   if (op == LB_OP_IMR_STEP) {
@@ -319,6 +320,7 @@ Layout layout(const lb_plan *p, int op, const BatchMeta &m, int ckpt_every) {
     L.ckpt = take((size_t)L.nck * E);
     L.seg = take((size_t)std::max(0, L.c - 1) * E);
     L.st_gpart = take((size_t)std::max<int64_t>(1, m.st_blocks) * 2 * QMAX * sizeof(double));
+    L.st_gfin = take(stream_grad_fin_doubles((int)m.segs.size()) * sizeof(double));
   }
   L.total = cur;
   return L;
@@ -451,7 +453,7 @@ struct GraphRun {
 // One stage-solve sweep of every streamed segment at step j.
 int sweep(const lb_plan *p, const BatchMeta &m, int j, bool adj, bool last, const double2 *ctab,
           const double2 *zin, const double2 *qin, double2 *out, hipStream_t st) {
-  ProfScope ps(p, LB_KERNEL_SWEEP, st);
+  ProfScope ps(p, LB_KERNEL_SWEEP, st, m.st_entries);
   if (m.tile_sys >= 0)
     return launch_tile(p, m.tile_sys, m.tile_B, last ? 2 : 1, adj, nullptr, 0.0, ctab, j, zin, qin,
                        out, st);
@@ -637,6 +639,7 @@ extern "C" void lb_plan_destroy(lb_plan *p) {
   (void)hipFree(p->d_E);
   (void)hipFree(p->d_desc);
   (void)hipFree(p->d_carrier);
+  if (p->d_sweeps) (void)hipFree(p->d_sweeps);
   delete p;
 }
 
@@ -706,7 +709,7 @@ extern "C" int control_table(const lb_plan *p, int32_t sys, const double *alpha,
   if (!alpha || !table) return fail(LB_EINVAL, "NULL argument");
   // alpha is this system's block; the kernel adds alpha_off, so shift it back.
   const double *abase = alpha - p->sys[sys].alpha_off;
-  return launch_control_table(p, sys, 1, abase, (double2 *)table, p->sys[sys].ctab_off, nullptr,
+  return launch_control_table(p, sys, 1, abase, (double2 *)table, p->sys[sys].ctab_off, nullptr, nullptr,
                               (hipStream_t)stream);
 }
 
@@ -748,7 +751,7 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
   double2 *ctab = (double2 *)(w + L.ctab);
   int32_t *ktab = (int32_t *)(w + L.ktab);
   const double *abase = alpha - p->sys[sys].alpha_off;
-  if ((rc = launch_control_table(p, sys, 1, abase, ctab, 0, ktab, st))) return rc;
+  if ((rc = launch_control_table(p, sys, 1, abase, ctab, 0, ktab, nullptr, st))) return rc;
   std::vector<int32_t> k;
   if ((rc = fetch_ktab(p, ktab, k, st))) return rc;
   const int K = k[((size_t)sys * p->NT + j) * 2 + 1];
@@ -764,24 +767,64 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
   return LB_OK;
 }
 
+// Per-item sweep totals of the LDS-resident kernels, kept only while profiling.
+static int64_t *lds_sweep_slots(const lb_plan *p, const BatchMeta &m) {
+  if (!p->profile || p->capturing || m.items.empty()) return nullptr;
+  if (p->sweeps_cap < m.items.size()) {
+    if (p->d_sweeps) (void)hipFree(p->d_sweeps);
+    p->d_sweeps = nullptr;
+    p->sweeps_cap = 0;
+    if (hipMalloc((void **)&p->d_sweeps, m.items.size() * sizeof(int64_t)) != hipSuccess) return nullptr;
+    p->sweeps_cap = m.items.size();
+  }
+  return p->d_sweeps;
+}
+
+// Adds the entry-sweeps of one LDS-resident pass to the profile: read back
+// for the specialised kernels, from the a-priori counts for the generic ones.
+static int lds_profile_work(const lb_plan *p, const BatchMeta &m, const std::vector<int32_t> &k,
+                            int kernel, const int64_t *slots, hipStream_t st) {
+  if (!slots) return LB_OK;
+  std::vector<int64_t> sw(m.items.size());
+  LBX_HIP(hipMemcpyAsync(sw.data(), slots, sw.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  LBX_HIP(hipStreamSynchronize(st));
+  int64_t work = 0;
+  for (const auto &c : m.classes)
+    for (int i = c.i0; i < c.i1; ++i) {
+      const int s = m.items[i].sys;
+      const int64_t n2 = p->sys[s].N2;
+      if (c.qc > 0) {
+        work += sw[i] * n2;
+      } else {
+        for (int j = 0; j < p->NT; ++j) work += (int64_t)k[((size_t)s * p->NT + j) * 2] * n2;
+      }
+    }
+  p->prof_work[kernel] += work;
+  return LB_OK;
+}
+
 static int run_forward(const lb_plan *p, const BatchMeta &m, const Layout &L, char *w,
                        const double *alpha, const double2 *rho0, double2 *rhoT, double2 *hist,
                        std::vector<int32_t> &k, hipStream_t st, bool keep_ckpt) {
   double2 *ctab = (double2 *)(w + L.ctab);
   int32_t *ktab = (int32_t *)(w + L.ktab);
   int rc;
-  if ((rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, st))) return rc;
+  double2 *ttab = (double2 *)(w + L.ttab);
+  if ((rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, ttab, st))) return rc;
   if ((rc = fetch_ktab(p, ktab, k, st))) return rc;
   if ((rc = check_k(p, k, m))) return rc;
   // LDS-resident systems: one persistent launch per kernel class.
+  int64_t *slots = lds_sweep_slots(p, m);
   for (const auto &c : m.classes) {
     ProfScope ps(p, LB_KERNEL_LDS_FORWARD, st);
     rc = c.qc > 0 ? launch_lds_forward_fast(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc,
-                                            ctab, ktab, rho0, rhoT, hist, st)
+                                            ctab, ttab, rho0, rhoT, hist, slots ? slots + c.i0 : nullptr,
+                                            st)
                   : launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab,
                                        rho0, rhoT, hist, st);
     if (rc) return rc;
   }
+  if ((rc = lds_profile_work(p, m, k, LB_KERNEL_LDS_FORWARD, slots, st))) return rc;
   if (m.segs.empty()) return LB_OK;
   // Streamed systems: one launch per sweep over all of them.
   double2 *q0 = (double2 *)(w + L.st_q0), *q1 = (double2 *)(w + L.st_q1);
@@ -880,14 +923,18 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
                        st, items, (int)m->items.size(), beta, m->d_sys_state0);
     LBX_HIP(hipGetLastError());
     double *gpart = (double *)(w + L.gpart);
+    int64_t *slots = lds_sweep_slots(p, *m);
     for (const auto &c : m->classes) {
       ProfScope ps(p, LB_KERNEL_LDS_ADJOINT, st);
       rc = c.qc > 0 ? launch_lds_adjoint_fast(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, kind,
-                                              ctab, ktab, (const double2 *)rhotar, hist, gpart, st)
+                                              ctab, (const double2 *)(w + L.ttab),
+                                              (const double2 *)rhotar, hist, gpart,
+                                              slots ? slots + c.i0 : nullptr, st)
                     : launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab,
                                          ktab, (const double2 *)rhotar, hist, gpart, st);
       if (rc) return rc;
     }
+    if ((rc = lds_profile_work(p, *m, k, LB_KERNEL_LDS_ADJOINT, slots, st))) return rc;
     if ((rc = launch_lds_grad_reduce(p, m->d_lds_item_range, (int)m->lds_sys.size(), m->d_lds_sys,
                                      items, gpart, gstep, st)))
       return rc;
@@ -899,7 +946,7 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
     double2 *ck = (double2 *)(w + L.ckpt), *seg = (double2 *)(w + L.seg);
     double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
     double2 *qh[2] = {(double2 *)(w + L.st_qh0), (double2 *)(w + L.st_qh1)};
-    double *sgp = (double *)(w + L.st_gpart);
+    double *sgp = (double *)(w + L.st_gpart), *sgf = (double *)(w + L.st_gfin);
     const int nseg = (int)m->segs.size();
     if ((rc = launch_terminal(p, kind, m->d_segs, nseg, m->st_blocks, ck + (size_t)(L.nck - 1) * E,
                               (const double2 *)rhotar, beta, m->d_seg_state0, qh[0], st)))
@@ -935,12 +982,12 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
             if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, ast))) return rc;
           }
           {
-            ProfScope ps(p, LB_KERNEL_STREAM_GRAD, ast);
+            ProfScope ps(p, LB_KERNEL_STREAM_GRAD, ast, m->st_entries);
             if ((rc = launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, qout, qin, slot(j),
                                          slot(j + 1), sgp, ast)))
               return rc;
           }
-          if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, j, sgp, gstep, ast))) return rc;
+          if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, j, sgp, sgf, gstep, ast))) return rc;
           cur ^= 1;
         }
         if ((rc = gr.end())) return rc;
@@ -968,7 +1015,16 @@ extern "C" int lb_profile_read(const lb_plan *p, int32_t kernel, int64_t *launch
   if (reset) {
     p->prof_n[kernel] = 0;
     p->prof_ms[kernel] = 0.0;
+    p->prof_work[kernel] = 0;
   }
+  return LB_OK;
+}
+
+extern "C" int lb_profile_work(const lb_plan *p, int32_t kernel, int64_t *entry_sweeps) {
+  if (int rc = check_plan(p)) return rc;
+  if (kernel < 0 || kernel >= LB_KERNEL_COUNT) return fail(LB_EINVAL, "unknown kernel family");
+  if (!entry_sweeps) return fail(LB_EINVAL, "NULL argument");
+  *entry_sweeps = p->prof_work[kernel];
   return LB_OK;
 }
 
@@ -981,7 +1037,7 @@ extern "C" int sweep_counts(const lb_plan *p, const double *alpha, int32_t *coun
   LBX_HIP(hipMalloc(&tmp, align256(p->ctab_total * sizeof(double2)) + nk * sizeof(int32_t)));
   double2 *ctab = (double2 *)tmp;
   int32_t *ktab = (int32_t *)((char *)tmp + align256(p->ctab_total * sizeof(double2)));
-  int rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, st);
+  int rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, nullptr, st);
   if (rc == LB_OK) {
     hipError_t e = hipMemcpyAsync(counts, ktab, nk * sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1039,7 +1095,7 @@ extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch
   const Layout L = layout(p, LB_OP_FORWARD, *m, 1);
   if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
   int rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, (double2 *)(w + L.ctab), 0,
-                                (int32_t *)(w + L.ktab), st);
+                                (int32_t *)(w + L.ktab), nullptr, st);
   if (rc) return rc;
   std::vector<int32_t> k;
   if ((rc = fetch_ktab(p, (int32_t *)(w + L.ktab), k, st))) return rc;

@@ -104,23 +104,115 @@ __device__ __forceinline__ double2 offdiag_nb(const Nb (&nb)[QC], const double2 
 
 }  // namespace
 
+// Stage solve with an extrapolated start and an a-posteriori sweep count.
+//
+// The fixed-point map delta -> w (h D q + h O (q + delta)) contracts in the
+// max norm with factor theta (see control_table_kernel), so after a first
+// sweep delta0 -> delta1 the error obeys |delta1 - delta*| <= theta/(1 - theta)
+// |delta1 - delta0|, and every further sweep multiplies that bound by theta.
+// The kernels start from the quadratic extrapolation of the last three
+// converged deltas (the stage increment varies smoothly with t), measure
+// |delta1 - delta0| and max|q| once per step over the workgroup, and run at
+// least two sweeps and otherwise the smallest number that brings the bound
+// below tol max|q|.  Every thread reads the same two maxima from LDS, so the
+// count is uniform.
+__device__ __forceinline__ int extra_sweeps(double theta, double ratio, double e1, double qmax,
+                                            double tol) {
+  double r = ratio * e1;  // ratio = theta / (1 - theta), from the control table
+  const double lim = tol * qmax;
+  int k = 0;
+  while (r > lim && k < 64) {
+    r *= theta;
+    ++k;
+  }
+  return k;
+}
+
+// Start of the stage iteration at step number `n` of the sweep direction:
+// w h D q at the first step, then the constant, linear and quadratic
+// extrapolations of the previous converged deltas d1 (latest), d2, d3.
+__device__ __forceinline__ double2 extrapolated_start(int n, double2 w, double2 hdq, double2 d1,
+                                                      double2 d2, double2 d3) {
+  if (n == 0) return cmul(w, hdq);
+  if (n == 1) return d1;
+  if (n == 2) return make_double2(2.0 * d1.x - d2.x, 2.0 * d1.y - d2.y);
+  return make_double2(3.0 * (d1.x - d2.x) + d3.x, 3.0 * (d1.y - d2.y) + d3.y);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Maximum over the wavefront of 32-bit unsigned values: prefix maxima within
+// rows of 16 lanes, then the four row maxima.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_row_shift_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, dpp_row_shift_u<0x111>(v));
+  v = max(v, dpp_row_shift_u<0x112>(v));
+  v = max(v, dpp_row_shift_u<0x114>(v));
+  v = max(v, dpp_row_shift_u<0x118>(v));
+  const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+  const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+  const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+  return max(max(a, b), max(c, d));
+}
+
+// The block maxima of the first-sweep change and of |q| are reduced on the
+// high words of the (non-negative) doubles, which order like the values:
+// the change is then bounded from above (low word all ones) and max|q| from
+// below (low word zero), both within a relative 2^-20.
+__device__ __forceinline__ double hi_upper(uint32_t hi) { return __hiloint2double((int)hi, -1); }
+__device__ __forceinline__ double hi_lower(uint32_t hi) { return __hiloint2double((int)hi, 0); }
+
+// Per-step constants of step j, one double per lane: the controls d_q in
+// lanes 0 .. 2 QC - 1, then theta and theta / (1 - theta).  A vector load, so
+// that the load for the next step is in flight during this one.
+struct StepConst {
+  double theta, ratio;
+};
+
+template <int QC>
+__device__ __forceinline__ double load_controls(const double2 *cq, const double2 *tq, int j, int NT,
+                                                int lane) {
+  const int jj = j < NT ? j : NT - 1;
+  const double *c = (const double *)(cq + (int64_t)jj * QC);
+  const double *t = (const double *)(tq + jj);
+  return lane < 2 * QC ? c[lane] : t[lane == 2 * QC ? 0 : 1];
+}
+
+template <int QC>
+__device__ __forceinline__ StepConst unpack_controls(double v, double2 (&dq)[QC]) {
+#pragma unroll
+  for (int q = 0; q < QC; ++q) dq[q] = make_double2(readlane_d(v, 2 * q), readlane_d(v, 2 * q + 1));
+  return {readlane_d(v, 2 * QC), readlane_d(v, 2 * QC + 1)};
+}
+
 template <int BLOCK, int EPT, int QC>
 __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
     const SysDev *__restrict__ sysv, const LdsItem *__restrict__ items,
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
-    const double2 *__restrict__ ctab, const int32_t *__restrict__ ktab, int NT,
-    const double2 *__restrict__ rho0, double2 *__restrict__ rhoT, double2 *__restrict__ states) {
+    const double2 *__restrict__ ctab, const double2 *__restrict__ ttab, double tol, int NT,
+    const double2 *__restrict__ rho0, double2 *__restrict__ rhoT, double2 *__restrict__ states,
+    int64_t *__restrict__ sweeps) {
   extern __shared__ double2 zbuf[];
+  constexpr int WAVES = BLOCK / 64;
+  __shared__ uint32_t wmax[2][WAVES];
   const LdsItem it = items[blockIdx.x];
   const SysDev &S = sysv[it.sys];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int N = S.N;
   const int N2 = (int)S.N2;
   const double h = S.h;
   const double2 *cq = ctab + S.ctab_off;
-  const int32_t *kt = ktab + (int64_t)it.sys * NT * 2;
 
-  double2 qv[EPT], wv[EPT], hd[EPT], dn[EPT];
+  double2 qv[EPT], wv[EPT], hd[EPT], dn[EPT], d1[EPT], d2[EPT], d3[EPT];
   Nb nb[EPT][QC];
   int ee[EPT];
   bool ok[EPT];
@@ -138,44 +230,97 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
 #pragma unroll
     for (int q = 0; q < QC; ++q) nb[k][q] = make_nb<false>(S, q, di, dj, ee[k]);
     qv[k] = ok[k] ? rho0[it.off + e] : make_double2(0.0, 0.0);
-    dn[k] = make_double2(0.0, 0.0);
+    dn[k] = d1[k] = d2[k] = d3[k] = make_double2(0.0, 0.0);
     if (states && ok[k]) states[it.st_off + e] = qv[k];
   }
   // Two LDS stage buffers; selected by value (not through a pointer array)
   // so that every access stays an LDS instruction.
   double2 *const zb0 = zbuf, *const zb1 = zbuf + N2;
   int cb = 0;
+  int64_t nsw = 0;
+  // Controls of step j + 1 are loaded during step j and unpacked before
+  // the state store of step j, so that waiting for them never waits for a
+  // store just issued.
+  const double2 *tq = ttab + (int64_t)it.sys * NT;
+  double2 dq[QC];
+  StepConst sc = unpack_controls<QC>(load_controls<QC>(cq, tq, 0, NT, lane), dq);
+  double cnext = load_controls<QC>(cq, tq, 1, NT, lane);
   for (int j = 0; j < NT; ++j) {
-    double2 dq[QC];
-#pragma unroll
-    for (int q = 0; q < QC; ++q) dq[q] = cq[(int64_t)j * QC + q];
-    const int K = kt[2 * j];
-    double2 hdq[EPT];
+    double2 hdq[EPT], d0[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       hdq[k] = cmul(hd[k], qv[k]);
-      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qv[k], cmul(wv[k], hdq[k]));
+      d0[k] = extrapolated_start(j, wv[k], hdq[k], d1[k], d2[k], d3[k]);
+      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qv[k], d0[k]);
     }
     __syncthreads();
-    for (int kk = 0; kk < K; ++kk) {
+    // first sweep, with the change it makes and max|q|
+    double e1 = 0.0, qm = 0.0;
+    {
+      const double2 *src = (cb ? zb1 : zb0);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const double2 acc = offdiag_nb<false, QC>(nb[k], dq, src);
+        dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
+        if (ok[k]) {
+          e1 = fmax(e1, fabs(dn[k].x - d0[k].x) + fabs(dn[k].y - d0[k].y));
+          qm = fmax(qm, fmax(fabs(qv[k].x), fabs(qv[k].y)));
+        }
+      }
+      const uint32_t he = wave_max_u32((uint32_t)__double2hiint(e1));
+      const uint32_t hq = wave_max_u32((uint32_t)__double2hiint(qm));
+      if (lane == 0) {
+        wmax[0][tid >> 6] = he;
+        wmax[1][tid >> 6] = hq;
+      }
+      double2 *dst = (cb ? zb0 : zb1);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k)
+        if (ok[k]) dst[ee[k]] = cadd(qv[k], dn[k]);
+      __syncthreads();
+      cb ^= 1;
+    }
+    // The second sweep runs in any case; the count of further ones is
+    // settled while its LDS reads are in flight.
+    {
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const double2 acc = offdiag_nb<false, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
       }
-      if (kk + 1 < K) {
-        double2 *dst = (cb ? zb0 : zb1);
+    }
+    uint32_t he = wmax[0][0], hq = wmax[1][0];
 #pragma unroll
-        for (int k = 0; k < EPT; ++k)
-          if (ok[k]) dst[ee[k]] = cadd(qv[k], dn[k]);
-        __syncthreads();
-        cb ^= 1;
+    for (int w = 1; w < WAVES; ++w) {
+      he = max(he, wmax[0][w]);
+      hq = max(hq, wmax[1][w]);
+    }
+    const int K = extra_sweeps(sc.theta, sc.ratio, hi_upper(he), hi_lower(hq), tol);
+    const int rest = K > 1 ? K - 1 : 0;
+    nsw += 2 + rest;
+    for (int kk = 0; kk < rest; ++kk) {
+      double2 *dst = (cb ? zb0 : zb1);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k)
+        if (ok[k]) dst[ee[k]] = cadd(qv[k], dn[k]);
+      __syncthreads();
+      cb ^= 1;
+      const double2 *src = (cb ? zb1 : zb0);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const double2 acc = offdiag_nb<false, QC>(nb[k], dq, src);
+        dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
       }
     }
+    sc = unpack_controls<QC>(cnext, dq);
+    cnext = load_controls<QC>(cq, tq, j + 2, NT, lane);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       qv[k] = make_double2(qv[k].x + 2.0 * dn[k].x, qv[k].y + 2.0 * dn[k].y);
+      d3[k] = d2[k];
+      d2[k] = d1[k];
+      d1[k] = dn[k];
       if (states && ok[k]) states[it.st_off + (int64_t)(j + 1) * N2 + ee[k]] = qv[k];
     }
     cb ^= 1;
@@ -183,28 +328,30 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
 #pragma unroll
   for (int k = 0; k < EPT; ++k)
     if (ok[k]) rhoT[it.off + ee[k]] = qv[k];
+  if (sweeps && tid == 0) sweeps[blockIdx.x] = nsw;
 }
 
 template <int BLOCK, int EPT, int QC>
 __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     const SysDev *__restrict__ sysv, const LdsItem *__restrict__ items,
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
-    const double2 *__restrict__ ctab, const int32_t *__restrict__ ktab, int NT, int kind,
-    const double2 *__restrict__ rhotar, const double2 *__restrict__ states,
-    double *__restrict__ gpart) {
+    const double2 *__restrict__ ctab, const double2 *__restrict__ ttab, double tol, int NT,
+    int kind, const double2 *__restrict__ rhotar, const double2 *__restrict__ states,
+    double *__restrict__ gpart, int64_t *__restrict__ sweeps) {
   extern __shared__ double2 zbuf[];
   constexpr int ROWS = BLOCK / 16;
+  constexpr int WAVES = BLOCK / 64;
+  __shared__ uint32_t wmax[2][WAVES];
   const LdsItem it = items[blockIdx.x];
   const SysDev &S = sysv[it.sys];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int N = S.N;
   const int N2 = (int)S.N2;
   const double h = S.h;
   const double2 *cq = ctab + S.ctab_off;
-  const int32_t *kt = ktab + (int64_t)it.sys * NT * 2;
   const double2 *hist = states + it.st_off;
 
-  double2 qh[EPT], wv[EPT], hd[EPT], dn[EPT], qn[EPT];
+  double2 qh[EPT], wv[EPT], hd[EPT], dn[EPT], qn[EPT], d1[EPT], d2[EPT], d3[EPT];
   Nb nb[EPT][QC];
   int ee[EPT];
   bool ok[EPT];
@@ -225,43 +372,87 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     qn[k] = ok[k] ? hist[(int64_t)NT * N2 + ee[k]] : make_double2(0.0, 0.0);
     const double2 t = ok[k] ? rhotar[it.off + ee[k]] : make_double2(0.0, 0.0);
     qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qn[k], t)) : cscale(-it.wterm, t);
-    dn[k] = make_double2(0.0, 0.0);
+    dn[k] = d1[k] = d2[k] = d3[k] = make_double2(0.0, 0.0);
   }
-  // Two LDS stage buffers; selected by value (not through a pointer array)
-  // so that every access stays an LDS instruction.
   double2 *const zb0 = zbuf, *const zb1 = zbuf + N2;
   int cb = 0;
+  int64_t nsw = 0;
+  // Controls of step j - 1 are loaded before the history load of step j and
+  // unpacked after the sweeps, where that history value is awaited anyway.
+  const double2 *tq = ttab + (int64_t)it.sys * NT;
+  double2 dq[QC];
+  StepConst sc = unpack_controls<QC>(load_controls<QC>(cq, tq, NT - 1, NT, lane), dq);
   for (int j = NT - 1; j >= 0; --j) {
-    double2 dq[QC];
-#pragma unroll
-    for (int q = 0; q < QC; ++q) dq[q] = cq[(int64_t)j * QC + q];
-    const int K = kt[2 * j];
+    const double cnext = load_controls<QC>(cq, tq, j > 0 ? j - 1 : 0, NT, lane);
     // (I - h M^+) zh = qh^{j+1} (App. B eq. linsystem_adjoint), zh = qh + delta.
-    double2 hdq[EPT];
+    double2 hdq[EPT], d0[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       hdq[k] = cmul(hd[k], qh[k]);
-      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qh[k], cmul(wv[k], hdq[k]));
+      d0[k] = extrapolated_start(NT - 1 - j, wv[k], hdq[k], d1[k], d2[k], d3[k]);
+      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qh[k], d0[k]);
     }
     // Forward state q^j, consumed after the sweeps so that its load overlaps them.
     double2 qj[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) qj[k] = ok[k] ? hist[(int64_t)j * N2 + ee[k]] : make_double2(0.0, 0.0);
     __syncthreads();
-    for (int kk = 0; kk < K; ++kk) {
+    double e1 = 0.0, qm = 0.0;
+    {
+      const double2 *src = (cb ? zb1 : zb0);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const double2 acc = offdiag_nb<true, QC>(nb[k], dq, src);
+        dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
+        if (ok[k]) {
+          e1 = fmax(e1, fabs(dn[k].x - d0[k].x) + fabs(dn[k].y - d0[k].y));
+          qm = fmax(qm, fmax(fabs(qh[k].x), fabs(qh[k].y)));
+        }
+      }
+      const uint32_t he = wave_max_u32((uint32_t)__double2hiint(e1));
+      const uint32_t hq = wave_max_u32((uint32_t)__double2hiint(qm));
+      if (lane == 0) {
+        wmax[0][tid >> 6] = he;
+        wmax[1][tid >> 6] = hq;
+      }
+      double2 *dst = (cb ? zb0 : zb1);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k)
+        if (ok[k]) dst[ee[k]] = cadd(qh[k], dn[k]);
+      __syncthreads();
+      cb ^= 1;
+    }
+    // The second sweep runs in any case; the count of further ones is
+    // settled while its LDS reads are in flight.
+    {
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const double2 acc = offdiag_nb<true, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
       }
-      if (kk + 1 < K) {
-        double2 *dst = (cb ? zb0 : zb1);
+    }
+    uint32_t he = wmax[0][0], hq = wmax[1][0];
 #pragma unroll
-        for (int k = 0; k < EPT; ++k)
-          if (ok[k]) dst[ee[k]] = cadd(qh[k], dn[k]);
-        __syncthreads();
-        cb ^= 1;
+    for (int w = 1; w < WAVES; ++w) {
+      he = max(he, wmax[0][w]);
+      hq = max(hq, wmax[1][w]);
+    }
+    const int K = extra_sweeps(sc.theta, sc.ratio, hi_upper(he), hi_lower(hq), tol);
+    const int rest = K > 1 ? K - 1 : 0;
+    nsw += 2 + rest;
+    for (int kk = 0; kk < rest; ++kk) {
+      double2 *dst = (cb ? zb0 : zb1);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k)
+        if (ok[k]) dst[ee[k]] = cadd(qh[k], dn[k]);
+      __syncthreads();
+      cb ^= 1;
+      const double2 *src = (cb ? zb1 : zb0);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const double2 acc = offdiag_nb<true, QC>(nb[k], dq, src);
+        dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
       }
     }
     // Gradient integrands (see grad_term in lbx_device.hpp) need zh at neighbours.
@@ -270,6 +461,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     for (int k = 0; k < EPT; ++k)
       if (ok[k]) zhb[ee[k]] = cadd(qh[k], dn[k]);
     __syncthreads();
+    sc = unpack_controls<QC>(cnext, dq);  // next step's; the integrands do not use them
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
       double gp = 0.0, gq = 0.0;
@@ -297,40 +489,44 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     for (int k = 0; k < EPT; ++k) {
       qh[k] = make_double2(qh[k].x + 2.0 * dn[k].x, qh[k].y + 2.0 * dn[k].y);
       qn[k] = qj[k];
+      d3[k] = d2[k];
+      d2[k] = d1[k];
+      d1[k] = dn[k];
     }
   }
+  if (sweeps && tid == 0) sweeps[blockIdx.x] = nsw;
 }
 
-// Shapes with a specialised kernel.  Workgroups of 1024 threads leave 128
-// VGPRs per thread, which bounds the register-resident stencil data there.
+// Shapes with a specialised kernel: one entry per thread.  Workgroups of
+// 1024 threads leave 128 VGPRs per thread, which bounds the register-resident
+// stencil data there.
 bool lds_fast_ok(int block, int ept, int Q) {
-  if (Q < 1 || Q > 4) return false;
-  if (ept == 1) return block <= 512 || Q <= 3;
-  return block == 1024 && ept == 2 && Q == 1;
+  if (Q < 1 || Q > 4 || ept != 1) return false;
+  return block <= 512 || Q <= 3;
 }
 
 template <int BLOCK, int EPT, int QC>
 static int fwd_t(const lb_plan *p, const LdsItem *d_items, int nitems, const double2 *ctab,
-                 const int32_t *ktab, const double2 *rho0, double2 *rhoT, double2 *states,
-                 hipStream_t st) {
+                 const double2 *ttab, const double2 *rho0, double2 *rhoT, double2 *states,
+                 int64_t *sweeps, hipStream_t st) {
   const size_t shmem = (size_t)2 * BLOCK * EPT * sizeof(double2);
   auto kern = lds_forward_fast_kernel<BLOCK, EPT, QC>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E, p->d_desc,
-                     ctab, ktab, p->NT, rho0, rhoT, states);
+                     ctab, ttab, p->tol, p->NT, rho0, rhoT, states, sweeps);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
 
 template <int BLOCK, int EPT, int QC>
 static int adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, int kind, const double2 *ctab,
-                 const int32_t *ktab, const double2 *rhotar, const double2 *states, double *gpart,
-                 hipStream_t st) {
+                 const double2 *ttab, const double2 *rhotar, const double2 *states, double *gpart,
+                 int64_t *sweeps, hipStream_t st) {
   const size_t shmem = (size_t)2 * BLOCK * EPT * sizeof(double2);
   auto kern = lds_adjoint_fast_kernel<BLOCK, EPT, QC>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E, p->d_desc,
-                     ctab, ktab, p->NT, kind, rhotar, states, gpart);
+                     ctab, ttab, p->tol, p->NT, kind, rhotar, states, gpart, sweeps);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -338,26 +534,26 @@ static int adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, int kind,
 #define LBX_FAST_SHAPES(X)                                                                  \
   X(64, 1, 1) X(64, 1, 2) X(64, 1, 3) X(64, 1, 4) X(128, 1, 1) X(128, 1, 2) X(128, 1, 3)    \
   X(128, 1, 4) X(256, 1, 1) X(256, 1, 2) X(256, 1, 3) X(256, 1, 4) X(512, 1, 1) X(512, 1, 2) \
-  X(512, 1, 3) X(512, 1, 4) X(1024, 1, 1) X(1024, 1, 2) X(1024, 1, 3) X(1024, 2, 1)
+  X(512, 1, 3) X(512, 1, 4) X(1024, 1, 1) X(1024, 1, 2) X(1024, 1, 3)
 
 int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, const double2 *ctab, const int32_t *ktab, const double2 *rho0,
-                            double2 *rhoT, double2 *states, hipStream_t st) {
+                            int Q, const double2 *ctab, const double2 *ttab, const double2 *rho0,
+                            double2 *rhoT, double2 *states, int64_t *sweeps, hipStream_t st) {
   if (nitems == 0) return LB_OK;
 #define X(B, E, C) \
-  if (block == B && ept == E && Q == C) return fwd_t<B, E, C>(p, d_items, nitems, ctab, ktab, rho0, rhoT, states, st);
+  if (block == B && ept == E && Q == C) return fwd_t<B, E, C>(p, d_items, nitems, ctab, ttab, rho0, rhoT, states, sweeps, st);
   LBX_FAST_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "no specialised LDS-resident kernel for this shape");
 }
 
 int launch_lds_adjoint_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, int kind, const double2 *ctab, const int32_t *ktab,
+                            int Q, int kind, const double2 *ctab, const double2 *ttab,
                             const double2 *rhotar, const double2 *states, double *gpart,
-                            hipStream_t st) {
+                            int64_t *sweeps, hipStream_t st) {
   if (nitems == 0) return LB_OK;
 #define X(B, E, C) \
-  if (block == B && ept == E && Q == C) return adj_t<B, E, C>(p, d_items, nitems, kind, ctab, ktab, rhotar, states, gpart, st);
+  if (block == B && ept == E && Q == C) return adj_t<B, E, C>(p, d_items, nitems, kind, ctab, ttab, rhotar, states, gpart, sweeps, st);
   LBX_FAST_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "no specialised LDS-resident kernel for this shape");

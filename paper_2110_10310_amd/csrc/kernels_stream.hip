@@ -5,6 +5,8 @@
 // persistent kernels for small systems live in kernels_lds.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lbx_host.hpp"
 
 namespace lbx {
@@ -23,7 +25,8 @@ namespace lbx {
 __global__ void control_table_kernel(const SysDev *__restrict__ sysv, int s0, int NT,
                                      const double *__restrict__ alpha,
                                      const double *__restrict__ carrier, double2 *__restrict__ ctab,
-                                     int64_t ctab_shift, int32_t *__restrict__ ktab, double tol) {
+                                     int64_t ctab_shift, int32_t *__restrict__ ktab,
+                                     double2 *__restrict__ ttab, double tol) {
   const int s = s0 + (int)blockIdx.y;
   const SysDev &S = sysv[s];
   const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -35,6 +38,9 @@ __global__ void control_table_kernel(const SysDev *__restrict__ sysv, int s0, in
     ctab[S.ctab_off - ctab_shift + (int64_t)j * S.Q + q] = d;
     theta += S.h * 2.0 * hypot(d.x, d.y) * S.csum[q];
   }
+  // (theta, theta / (1 - theta)) for the a-posteriori sweep counts of the
+  // specialised LDS-resident kernels.
+  if (ttab) ttab[(int64_t)s * NT + j] = make_double2(theta, theta < 1.0 ? theta / (1.0 - theta) : 0.0);
   if (ktab) {
     int klds, kst;
     if (!(theta < 0.5)) {
@@ -56,10 +62,10 @@ __global__ void control_table_kernel(const SysDev *__restrict__ sysv, int s0, in
 }
 
 int launch_control_table(const lb_plan *p, int s0, int nsys, const double *alpha, double2 *ctab,
-                         int64_t ctab_shift, int32_t *ktab, hipStream_t st) {
+                         int64_t ctab_shift, int32_t *ktab, double2 *ttab, hipStream_t st) {
   dim3 grid((p->NT + 255) / 256, nsys);
   hipLaunchKernelGGL(control_table_kernel, grid, dim3(256), 0, st, p->d_sys, s0, p->NT, alpha,
-                     p->d_carrier, ctab, ctab_shift, ktab, p->tol);
+                     p->d_carrier, ctab, ctab_shift, ktab, ttab, p->tol);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -249,31 +255,67 @@ int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int6
   return LB_OK;
 }
 
-// Sum the block partials of each segment (fixed order) into gstep[s][j][2Q].
-__global__ __launch_bounds__(256) void stream_grad_finalize_kernel(
-    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int j,
-    const double *__restrict__ gpart, double *__restrict__ gstep) {
-  __shared__ double red[4];
+// Sum the block partials of each segment into gstep[s][j][2Q] in two fixed-
+// order passes: FIN_SPLIT workgroups per segment each reduce a contiguous
+// range of partial rows (one row of 2 QMAX doubles per thread and pass, so
+// that a wavefront reads consecutive rows), then one workgroup per segment
+// adds the FIN_SPLIT results.
+constexpr int FIN_SPLIT = 64;
+
+__global__ __launch_bounds__(256) void stream_grad_partial_kernel(
+    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs,
+    const double *__restrict__ gpart, double *__restrict__ gfin) {
+  __shared__ double red[4][2 * QMAX];
   const StreamSeg &sg = segs[blockIdx.x];
-  const SysDev &S = sysv[sg.sys];
+  const int Q2 = 2 * sysv[sg.sys].Q;
   const int64_t nb = (sg.count + STREAM_BLOCK - 1) / STREAM_BLOCK;
+  const int64_t per = (nb + FIN_SPLIT - 1) / FIN_SPLIT;
+  const int64_t k0 = (int64_t)blockIdx.y * per;
+  const int64_t k1 = k0 + per < nb ? k0 + per : nb;
   const int tid = threadIdx.x;
-  for (int c = 0; c < 2 * S.Q; ++c) {
-    double v = 0.0;
-    for (int64_t k = tid; k < nb; k += 256) v += gpart[(sg.blk0 + k) * 2 * QMAX + c];
-    v = wave_sum<64>(v);
-    if ((tid & 63) == 0) red[tid >> 6] = v;
-    __syncthreads();
-    if (tid == 0) gstep[2 * S.ctab_off + (int64_t)j * 2 * S.Q + c] = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
+  double v[2 * QMAX];
+#pragma unroll
+  for (int c = 0; c < 2 * QMAX; ++c) v[c] = 0.0;
+  for (int64_t k = k0 + tid; k < k1; k += 256) {
+    const double *row = gpart + (sg.blk0 + k) * 2 * QMAX;
+#pragma unroll
+    for (int c = 0; c < 2 * QMAX; ++c)
+      if (c < Q2) v[c] += row[c];
   }
+#pragma unroll
+  for (int c = 0; c < 2 * QMAX; ++c) {
+    if (c >= Q2) break;
+    const double w = wave_sum<64>(v[c]);
+    if ((tid & 63) == 0) red[tid >> 6][c] = w;
+  }
+  __syncthreads();
+  if (tid < Q2)
+    gfin[((int64_t)blockIdx.x * FIN_SPLIT + blockIdx.y) * 2 * QMAX + tid] =
+        red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
+__global__ __launch_bounds__(64) void stream_grad_finalize_kernel(
+    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int j,
+    const double *__restrict__ gfin, double *__restrict__ gstep) {
+  const StreamSeg &sg = segs[blockIdx.x];
+  const SysDev &S = sysv[sg.sys];
+  const int c = threadIdx.x;
+  if (c >= 2 * S.Q) return;
+  double v = 0.0;
+  for (int g = 0; g < FIN_SPLIT; ++g) v += gfin[((int64_t)blockIdx.x * FIN_SPLIT + g) * 2 * QMAX + c];
+  gstep[2 * S.ctab_off + (int64_t)j * 2 * S.Q + c] = v;
+}
+
+size_t stream_grad_fin_doubles(int nseg) { return (size_t)std::max(nseg, 1) * FIN_SPLIT * 2 * QMAX; }
+
 int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int j,
-                                const double *gpart, double *gstep, hipStream_t st) {
+                                const double *gpart, double *gfin, double *gstep, hipStream_t st) {
   if (nseg == 0) return LB_OK;
-  hipLaunchKernelGGL(stream_grad_finalize_kernel, dim3(nseg), dim3(256), 0, st, p->d_sys, d_segs, j,
-                     gpart, gstep);
+  hipLaunchKernelGGL(stream_grad_partial_kernel, dim3(nseg, FIN_SPLIT), dim3(256), 0, st, p->d_sys,
+                     d_segs, gpart, gfin);
+  LBX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(stream_grad_finalize_kernel, dim3(nseg), dim3(64), 0, st, p->d_sys, d_segs, j,
+                     gfin, gstep);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }

@@ -35,7 +35,10 @@ struct lb_plan {
   bool profile = false;
   mutable int64_t prof_n[LB_KERNEL_COUNT] = {};
   mutable double prof_ms[LB_KERNEL_COUNT] = {};
+  mutable int64_t prof_work[LB_KERNEL_COUNT] = {};  // entries x sweeps (x steps for STREAM_GRAD)
   mutable std::vector<lbx_prof_pending> prof_pending;
+  mutable int64_t *d_sweeps = nullptr;  // per-item sweep totals of the LDS kernels (profiling)
+  mutable size_t sweeps_cap = 0;
 };
 
 namespace lbx {
@@ -70,8 +73,10 @@ struct ProfScope {
   int kernel;
   hipStream_t st;
   hipEvent_t a = nullptr;
-  ProfScope(const lb_plan *p_, int k, hipStream_t s) : p(p_), kernel(k), st(s) {
-    if (p->profile && !p->capturing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
+  ProfScope(const lb_plan *p_, int k, hipStream_t s, int64_t work = 0) : p(p_), kernel(k), st(s) {
+    if (!p->profile || p->capturing) return;
+    p->prof_work[k] += work;
+    if (hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
   }
   ~ProfScope() {
     if (!a) return;
@@ -99,9 +104,10 @@ int hip_fail(hipError_t e, const char *what);
 // ---- launchers (each returns LB_OK or an error code) ----
 
 // Control table of systems s0..s0+nsys-1; entry (s, j, q) goes to
-// ctab[ctab_off(s) - ctab_shift + j*Q + q].  ktab may be NULL.
+// ctab[ctab_off(s) - ctab_shift + j*Q + q].  ktab ([s][j][2] a-priori sweep
+// counts) and ttab ([s][j] = (theta, theta / (1 - theta))) may be NULL.
 int launch_control_table(const lb_plan *p, int s0, int nsys, const double *alpha, double2 *ctab,
-                         int64_t ctab_shift, int32_t *ktab, hipStream_t st);
+                         int64_t ctab_shift, int32_t *ktab, double2 *ttab, hipStream_t st);
 
 int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const double2 *x,
                  double2 *y, int B, bool adj, hipStream_t st);
@@ -114,8 +120,11 @@ int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int6
                        const double2 *qh0, const double2 *qh1, const double2 *q0,
                        const double2 *q1, double *gpart, hipStream_t st);
 
+// Two-pass fixed-order sum of the stream_grad partials into gstep; gfin is
+// scratch of stream_grad_fin_doubles(nseg) doubles.
+size_t stream_grad_fin_doubles(int nseg);
 int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int j,
-                                const double *gpart, double *gstep, hipStream_t st);
+                                const double *gpart, double *gfin, double *gstep, hipStream_t st);
 
 int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                        const double2 *ctab, const int32_t *ktab, const double2 *rho0,
@@ -158,12 +167,14 @@ int launch_tile(const lb_plan *p, int sys, int B, int mode, bool adj, const doub
 
 // Specialised LDS-resident kernels (kernels_lds_fast.hip) for Q subsystems.
 bool lds_fast_ok(int block, int ept, int Q);
+// They pick the number of sweeps of every step a posteriori (see
+// extra_sweeps) and, when `sweeps` is not NULL, write each item's total.
 int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, const double2 *ctab, const int32_t *ktab, const double2 *rho0,
-                            double2 *rhoT, double2 *states, hipStream_t st);
+                            int Q, const double2 *ctab, const double2 *ttab, const double2 *rho0,
+                            double2 *rhoT, double2 *states, int64_t *sweeps, hipStream_t st);
 int launch_lds_adjoint_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, int kind, const double2 *ctab, const int32_t *ktab,
+                            int Q, int kind, const double2 *ctab, const double2 *ttab,
                             const double2 *rhotar, const double2 *states, double *gpart,
-                            hipStream_t st);
+                            int64_t *sweeps, hipStream_t st);
 
 }  // namespace lbx

@@ -290,6 +290,42 @@ def test_gradient_is_bitwise_deterministic(lbx):
     assert np.array_equal(g1, g2)
 
 
+@pytest.mark.parametrize("NT", [1, 2, 3, 4, 9])
+def test_lds_extrapolated_start_on_short_horizons(lbx, NT):
+    # The specialised LDS kernels start each stage iteration from the
+    # constant, linear or quadratic extrapolation of the previous increments
+    # (first, second, third step onward); every start must converge.
+    shapes = [(3, 3), (2, 2, 2)]
+    systems, alphas, rho0, batch = _multi(list(enumerate(shapes, start=120)), NT=NT, T=0.2 * NT)
+    say("lds extrapolated start", NT)
+    _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "lds", 1)
+
+
+def test_profile_work_counts_sweeps(lbx):
+    p = truncate_steps(make_config(2), 200)
+    s = p.systems[0]
+    args = (dev(p.alpha[0].reshape(-1)), dev(p.rho0[0]), dev(p.rhotar[0]), dev(p.beta[0]), [16])
+    entries = 16 * s.N * s.N
+    say("profile work")
+    nat = lbx._native
+    plan = lbx.Plan([s], path="lds")
+    plan.profile(True)
+    lbx.adjoint_gradient(plan, p.kind, *args)
+    apriori = int(lbx.sweep_counts(plan, args[0])[0, :, 0].sum()) * entries
+    for k in (nat.LB_KERNEL_LDS_FORWARD, nat.LB_KERNEL_LDS_ADJOINT):
+        w = plan.profile_work(k)
+        assert w % (s.N * s.N) == 0 and s.NT * entries <= w <= 2 * apriori, (k, w, apriori)
+        assert plan.profile_read(k, reset=True)[0] == 1
+        assert plan.profile_work(k) == 0
+    splan = lbx.Plan([s], path="stream")
+    splan.profile(True)
+    lbx.adjoint_gradient(splan, p.kind, *args)
+    n_sweeps, _ = splan.profile_read(nat.LB_KERNEL_SWEEP)
+    assert splan.profile_work(nat.LB_KERNEL_SWEEP) == n_sweeps * entries
+    n_grad, _ = splan.profile_read(nat.LB_KERNEL_STREAM_GRAD)
+    assert n_grad == s.NT and splan.profile_work(nat.LB_KERNEL_STREAM_GRAD) == s.NT * entries
+
+
 def test_lds_kernel_classes_with_several_entries_per_thread(lbx):
     # N^2 = 1296 (two entries per thread) and N^2 = 4096 (four per thread).
     shapes = [(6, 6), (4, 4, 4)]
