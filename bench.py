@@ -46,14 +46,18 @@ LDS_SOURCES = ["paper_2110_10310_amd/csrc/kernels_lds.hip",
                "paper_2110_10310_amd/csrc/kernels_lds_fast.hip",
                "paper_2110_10310_amd/csrc/lbx_device.hpp"]
 # traffic keys: (substring of the kernel name in the counter CSV, sources it is built from)
+# traffic keys: (substrings of the kernel name in the counter CSV, sources it is built from)
+TILE_KIS = {44: 512, 43: 256, 33: 256, 32: 256, 23: 256}  # eight-qutrit block shapes, threads
 TRAFFIC_KEYS = {
-    "apply_kernel_forward": (["tile_kernel<3, 8, 4, 4, false, 0>"], APPLY_SOURCES),
-    "apply_kernel_adjoint": (["tile_kernel<3, 8, 4, 4, true, 0>"], APPLY_SOURCES),
-    "stage_sweep_kernel_c5": (["tile_kernel<3, 8, 4, 4, false, 1>", "tile_kernel<3, 8, 4, 4, false, 2>"],
-                              APPLY_SOURCES),
     "lds_forward_kernel": (["lds_forward_fast_kernel"], LDS_SOURCES),
     "lds_adjoint_kernel": (["lds_adjoint_fast_kernel"], LDS_SOURCES),
 }
+for _ki, _thr in TILE_KIS.items():
+    _sh = f"tile_kernel<3, 8, {_ki // 10}, {_ki % 10}"
+    TRAFFIC_KEYS[f"apply_kernel_forward_ki{_ki}"] = ([f"{_sh}, false, 0, {_thr}>"], APPLY_SOURCES)
+    TRAFFIC_KEYS[f"apply_kernel_adjoint_ki{_ki}"] = ([f"{_sh}, true, 0, {_thr}>"], APPLY_SOURCES)
+    TRAFFIC_KEYS[f"stage_sweep_kernel_c5_ki{_ki}"] = ([f"{_sh}, false, 1, {_thr}>", f"{_sh}, false, 2, {_thr}>"],
+                                                      APPLY_SOURCES)
 
 
 def source_sha(files):
@@ -181,7 +185,8 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
         achieved = by / avg_s / 1e9
         roof = {"kernel": name_of[dom], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(name_of[dom] + f"_c{workload}", APPLY_SOURCES),
+                "traffic": measured_traffic(name_of[dom] + f"_c{workload}_ki{tuned.get('tile_ki', 0)}",
+                                            APPLY_SOURCES),
                 "avg_launch_ms": 1e3 * avg_s, "launches": prof[dom][0], "bytes_per_launch": by}
     nt = p.systems[0].NT
     sweeps = {}
@@ -208,46 +213,54 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
 
 
 def run_apply_bench(lbx, torch, reps):
+    """lindblad_apply on the eight-qutrit ring with the one-pass block-tiled
+    kernel (LB_OPT_TILE 1) and the two-pass split kernels (2); the faster
+    forward apply is the reported roofline."""
     from workloads import make_config
     p = make_config(5)
     s = p.systems[0]
-    plan = lbx.Plan([s])
     N = s.N
     g = torch.Generator(device="cuda")
     g.manual_seed(5)
     x = torch.randn((1, N, N), dtype=torch.complex128, device="cuda", generator=g)
     y = torch.empty_like(x)
     alpha = torch.as_tensor(p.alpha[0].reshape(-1)).to("cuda")
-    out = {}
-    for adj in (False, True):
-        for _ in range(3):
-            lbx.lindblad_apply(plan, 0, 41.0, alpha, x, adjoint=adj, out=y)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-        for k in range(reps):
-            ev[k][0].record()
-            lbx.lindblad_apply(plan, 0, 41.0 + 0.01 * k, alpha, x, adjoint=adj, out=y)
-            ev[k][1].record()
-        torch.cuda.synchronize()
-        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-        out["adjoint" if adj else "forward"] = ms
+    times = {}
+    for tile, ki in ((1, 44), (1, 43), (1, 33), (1, 32), (1, 23), (2, 0)):
+        plan = lbx.Plan([s], tile=tile)
+        plan.set_option(lbx._native.LB_OPT_TILE_KI, ki)
+        for adj in (False, True):
+            for _ in range(3):
+                lbx.lindblad_apply(plan, 0, 41.0, alpha, x, adjoint=adj, out=y)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for k in range(reps):
+                ev[k][0].record()
+                lbx.lindblad_apply(plan, 0, 41.0 + 0.01 * k, alpha, x, adjoint=adj, out=y)
+                ev[k][1].record()
+            torch.cuda.synchronize()
+            times[(tile, ki, adj)] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    tile, ki = min({(t, k) for t, k, _ in times}, key=lambda c: times[(c[0], c[1], False)])
     algo = 32.0 * N * N
-    ms = out["forward"]
+    ms = times[(tile, ki, False)]
     achieved = algo / (ms / 1e3) / 1e9
-    traffic = measured_traffic("apply_kernel_forward", APPLY_SOURCES)
+    key = f"apply_kernel_forward_ki{ki}" if tile == 1 else "multipass_apply_forward"
     return {
-        "kernel": "apply_kernel<forward>", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-        "avg_launch_ms": ms, "adjoint_avg_launch_ms": out["adjoint"],
-        "adjoint_achieved": algo / (out["adjoint"] / 1e3) / 1e9,
+        "kernel": f"tile_kernel<3, 8, {ki // 10}, {ki % 10}, forward>" if tile == 1
+                  else "pass_kernel<forward> (three passes)",
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(key, APPLY_SOURCES),
+        "avg_launch_ms": ms, "adjoint_avg_launch_ms": times[(tile, ki, True)],
+        "adjoint_achieved": algo / (times[(tile, ki, True)] / 1e3) / 1e9,
         "bytes_per_launch": algo, "workload": "8 qutrits ring, N=6561, 1 state",
+        "ms_by_kernel": {f"tile{t}_ki{k}_{'adjoint' if a else 'forward'}": v for (t, k, a), v in times.items()},
     }
 
 
 def run_traffic_probe(lbx, torch):
     """Launches whose HBM counters are read by rocprofv3 --pmc: a plain device
-    copy of one eight-qutrit state (the calibration of the counters), two
-    forward and two adjoint applies and one IMR step on that state, and one
-    two-transmon gradient evaluation."""
+    copy of one eight-qutrit state (the calibration of the counters), for each
+    block shape two forward and two adjoint applies and one IMR step on that
+    state, and one two-transmon gradient evaluation."""
     from workloads import make_config
     p = make_config(5)
     s = p.systems[0]
@@ -258,12 +271,14 @@ def run_traffic_probe(lbx, torch):
     y = torch.empty_like(x)
     for _ in range(2):
         y.copy_(x)
-    plan = lbx.Plan([s])
     alpha = torch.as_tensor(p.alpha[0].reshape(-1)).to("cuda")
-    for adj in (False, True):
-        for _ in range(2):
-            lbx.lindblad_apply(plan, 0, 41.0, alpha, x, adjoint=adj, out=y)
-    lbx.imr_step(plan, 0, 2000, alpha, x, out=y)
+    for ki in TILE_KIS:
+        plan = lbx.Plan([s])
+        plan.set_option(lbx._native.LB_OPT_TILE_KI, ki)
+        for adj in (False, True):
+            for _ in range(2):
+                lbx.lindblad_apply(plan, 0, 41.0, alpha, x, adjoint=adj, out=y)
+        lbx.imr_step(plan, 0, 2000, alpha, x, out=y)
     torch.cuda.synchronize()
     del x, y
     print("[probe] eight-qutrit launches done", file=sys.stderr, flush=True)

@@ -79,7 +79,9 @@ extern "C" {
 #define LB_OPT_PROFILE 2   /* 1: time kernel launches of forward_solve and adjoint_gradient
                               with HIP events on the call's stream; 0 (default): off */
 #define LB_OPT_TILE 3      /* 1 (default): block-tiled kernels for large systems of
-                              equal-level subsystems; 0: generic streaming kernels */
+                              equal-level subsystems; 2: the two-pass split kernels
+                              where the system is eligible (else as 1); 0: generic
+                              streaming kernels */
 #define LB_OPT_TILE_KI 4   /* block shape of the block-tiled kernels, 10*KR + KC with KR
                               (KC) row (column) digits inside a block; 0 (default): the
                               shape listed first for the system */

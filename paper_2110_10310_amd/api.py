@@ -47,7 +47,7 @@ class Plan:
     """Owns an lb_plan built from System-like objects (see workloads.System)."""
 
     def __init__(self, systems: Sequence, path: str = "auto", solve_tol: float | None = None,
-                 tile: bool = True):
+                 tile: int = 1):
         self.systems = list(systems)
         n = len(self.systems)
         descs = (nat.SystemDesc * n)()
@@ -90,8 +90,8 @@ class Plan:
             self.set_option(nat.LB_OPT_PATH, PATHS[path])
         if solve_tol is not None:
             self.set_option(nat.LB_OPT_SOLVE_TOL, solve_tol)
-        if not tile:
-            self.set_option(nat.LB_OPT_TILE, 0)
+        if int(tile) != 1:  # 0: generic streaming kernels, 2: two-pass split kernels
+            self.set_option(nat.LB_OPT_TILE, int(tile))
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -660,7 +660,7 @@ extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
     return LB_OK;
   }
   if (option == LB_OPT_TILE) {
-    if (value != 0 && value != 1) return fail(LB_EINVAL, "LB_OPT_TILE must be 0 or 1");
+    if (value != 0 && value != 1 && value != 2) return fail(LB_EINVAL, "LB_OPT_TILE must be 0, 1 or 2");
     p->tile = (int)value;
     return LB_OK;
   }
@@ -738,7 +738,11 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
   if (B < 0) return fail(LB_EINVAL, "B must be >= 0");
   if (B == 0) return LB_OK;
   if (!alpha || !q_in || !q_out || !ws) return fail(LB_EINVAL, "NULL argument");
-  if (q_in == q_out) return fail(LB_EINVAL, "q_in and q_out must differ");
+  {
+    const uintptr_t a = (uintptr_t)q_in, c = (uintptr_t)q_out;
+    const size_t bytes = (size_t)B * p->sys[sys].N2 * sizeof(double2);
+    if (a < c + bytes && c < a + bytes) return fail(LB_EINVAL, "q_in and q_out overlap");
+  }
   hipStream_t st = (hipStream_t)stream;
   std::vector<int32_t> batch(nsys, 0);
   batch[sys] = B;
@@ -1109,6 +1113,7 @@ extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch
   const int saved_tile = p->tile, saved_ki = p->tile_ki, saved_graph = p->graph_steps;
   if (m->segs.size() == 1) {
     const int sys = m->segs[0].sys;
+    if (split_kl(p, sys)) cand.push_back({2, 0});
     for (int ki : {44, 43, 34, 42, 33, 66, 55, 32, 23}) {
       p->tile = 1;
       p->tile_ki = ki;

@@ -26,41 +26,38 @@ __device__ __forceinline__ double sqrt_small(int k) {
   return r;
 }
 
-// Contribution of one subsystem with row digit n, column digit m, control
-// (a, b) = (Re d, Im d) and the five neighbour values; see `offdiag`.
-template <int NL, bool ADJ>
-__device__ __forceinline__ void tile_term(int n, int m, double g1, double g2, double a, double b,
-                                          double2 vrp, double2 vrm, double2 vcp, double2 vcm,
-                                          double2 vj, double2 &acc, double &gam) {
-  const bool rp = n + 1 < NL, rm = n > 0, cp = m + 1 < NL, cm = m > 0;
-  const double dnm = (double)(n - m);
-  gam += 0.5 * (g1 * (double)(n + m) + g2 * dnm * dnm);
-  const double arp = rp ? sqrt_small<NL>(n + 1) : 0.0;
-  const double arm = sqrt_small<NL>(n);
-  const double acp = cp ? sqrt_small<NL>(m + 1) : 0.0;
-  const double acm = sqrt_small<NL>(m);
-  const double2 U = make_double2(arp * vrp.x - acm * vcm.x, arp * vrp.y - acm * vcm.y);
-  const double2 V = make_double2(arm * vrm.x - acp * vcp.x, arm * vrm.y - acp * vcp.y);
-  const double2 Sm = cadd(U, V), Dv = csub(U, V);
-  const double cr = a * Sm.y + b * Dv.x;
-  const double ci = -a * Sm.x + b * Dv.y;
-  const double cj = !ADJ ? ((rp && cp) ? g1 * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1) : 0.0)
-                         : ((rm && cm) ? g1 * sqrt_small<NL>(n) * sqrt_small<NL>(m) : 0.0);
-  if (!ADJ) {
-    acc.x += cr + cj * vj.x;
-    acc.y += ci + cj * vj.y;
-  } else {
-    acc.x += -cr + cj * vj.x;
-    acc.y += -ci + cj * vj.y;
-  }
-}
-
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 __device__ __forceinline__ double uniform(double v) {
   const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
   return __hiloint2double(hi, lo);
+}
+
+// Every off-diagonal term is a complex multiple of one neighbour value.  With
+// d = a + i b the control of subsystem q, the forward control commutator
+// contributes
+//   row shift +e (weight sqrt(n+1)):  (b, -a) x_{i+e,j}
+//   row shift -e (weight sqrt(n)):    (-b, -a) x_{i-e,j}
+//   column shift +e (sqrt(m+1)):      (b, a) x_{i,j+e}
+//   column shift -e (sqrt(m)):        (-b, a) x_{i,j-e}
+// times the weight, and the adjoint the negatives; the decay jump
+// contributes g1 sqrt((n+1)(m+1)) x_{i+e,j+e} (adjoint: g1 sqrt(nm) x_{i-e,j-e}).
+// These are the terms of `offdiag` in lbx_device.hpp regrouped by neighbour.
+enum { DIR_RP = 0, DIR_RM = 1, DIR_CP = 2, DIR_CM = 3 };
+
+template <int DIR, bool ADJ>
+__device__ __forceinline__ double2 ctl_coef(double a, double b, double wgt) {
+  const double s = ADJ ? -wgt : wgt;
+  if (DIR == DIR_RP) return make_double2(s * b, -s * a);
+  if (DIR == DIR_RM) return make_double2(-s * b, -s * a);
+  if (DIR == DIR_CP) return make_double2(s * b, s * a);
+  return make_double2(-s * b, s * a);
+}
+
+__device__ __forceinline__ void cmac(double2 &acc, double2 c, double2 v) {
+  acc.x += c.x * v.x - c.y * v.y;
+  acc.y += c.x * v.y + c.y * v.x;
 }
 
 }  // namespace
@@ -72,14 +69,18 @@ __device__ __forceinline__ double uniform(double v) {
 // TC = NL^KC columns: the KR (KC) least significant digits of the row
 // (column) index vary and the others are fixed.  The block is staged in LDS,
 // so every neighbour along an internal digit (row or column ladder shift, or
-// decay jump of a subsystem internal in both) is an LDS read.  Neighbours
-// along the external digits are global loads, all issued before any is used;
-// their weights depend only on the fixed digits (uniform over the
-// workgroup), and a missing one reads the entry itself with a zero weight.
-// Blocks are remapped so that each XCD (blocks are dealt to the 8 XCDs
-// round-robin) walks a contiguous band of block rows.
-template <int NL, int QC, int KR, int KC, bool ADJ, int MODE>
-__global__ __launch_bounds__(TILE_BLOCK) void tile_kernel(
+// decay jump of a subsystem internal in both) is an LDS read.  Along the
+// external digits every neighbour of the block is the block shifted by a
+// constant offset, with a coefficient that depends only on the fixed digits:
+// those terms are applied one direction at a time for all entries of a
+// thread (a direction whose neighbour does not exist for this block is
+// skipped), so that a thread has one coalesced load per entry in flight per
+// direction and the neighbour values need no per-entry weights.  Jumps of a
+// subsystem with one internal and one external digit are per-entry global
+// loads.  Blocks are remapped so that each XCD (blocks are dealt to the 8
+// XCDs round-robin) walks a contiguous band of block rows.
+template <int NL, int QC, int KR, int KC, bool ADJ, int MODE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tile_kernel(
     const SysDev *__restrict__ sysv, int sys, int64_t nblocks, const double *__restrict__ Etab,
     const double *__restrict__ alpha, const double *__restrict__ carrier, double t,
     const double2 *__restrict__ ctab, int jstep, const double2 *__restrict__ zin,
@@ -88,6 +89,8 @@ __global__ __launch_bounds__(TILE_BLOCK) void tile_kernel(
   __shared__ double2 dqs[QC];
   constexpr int ER = QC - KR, EC = QC - KC;  // external row / column digits
   constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
+  constexpr int TT = TR * TC;
+  constexpr int EPT = (TT + BLOCK - 1) / BLOCK;
   const SysDev &S = sysv[sys];
   const int N = S.N;
   const int NBR = N / TR, NBC = N / TC;
@@ -104,9 +107,17 @@ __global__ __launch_bounds__(TILE_BLOCK) void tile_kernel(
   const int bi = rem / NBC, bj = rem - (rem / NBC) * NBC;
   const double2 *X = zin + b * N2;
   const int64_t base = (int64_t)bi * TR * N + (int64_t)bj * TC;
-  for (int f = tid; f < TR * TC; f += TILE_BLOCK) {
-    const int a = f / TC, c = f - (f / TC) * TC;
-    tile[f] = X[base + (int64_t)a * N + c];
+  // flat offset (within the state) of this thread's k-th entry
+  auto off_of = [&](int k) -> int64_t {
+    const int f = tid + k * BLOCK;
+    const int ff = f < TT ? f : 0;
+    const int a = ff / TC, c = ff - (ff / TC) * TC;
+    return base + (int64_t)a * N + c;
+  };
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int f = tid + k * BLOCK;
+    if (f < TT) tile[f] = X[off_of(k)];
   }
   // fixed (external) digits of the row and column index
   int ne[ER > 0 ? ER : 1], me[EC > 0 ? EC : 1];
@@ -133,10 +144,49 @@ __global__ __launch_bounds__(TILE_BLOCK) void tile_kernel(
     da[q] = uniform(dqs[q].x);
     db[q] = uniform(dqs[q].y);
   }
-  for (int f = tid; f < TR * TC; f += TILE_BLOCK) {
+  // External directions first: existence and coefficient are uniform per
+  // block; each direction is one coalesced load per entry of the thread.
+  double2 acc[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) acc[k] = make_double2(0.0, 0.0);
+  auto direction = [&](double2 cf, int64_t shift) {
+    double2 v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) v[k] = X[off_of(k) + shift];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) cmac(acc[k], cf, v[k]);
+  };
+#pragma unroll
+  for (int q = 0; q < ER; ++q) {
+    const int n = ne[q];
+    const int64_t sN = (int64_t)S.stride[q] * N;
+    if (n + 1 < NL) direction(ctl_coef<DIR_RP, ADJ>(da[q], db[q], sqrt_small<NL>(n + 1)), sN);
+    if (n > 0) direction(ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), -sN);
+  }
+#pragma unroll
+  for (int q = 0; q < EC; ++q) {
+    const int m = me[q];
+    const int64_t s1 = S.stride[q];
+    if (m + 1 < NL) direction(ctl_coef<DIR_CP, ADJ>(da[q], db[q], sqrt_small<NL>(m + 1)), s1);
+    if (m > 0) direction(ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), -s1);
+  }
+#pragma unroll
+  for (int q = 0; q < (ER < EC ? ER : EC); ++q) {
+    const int n = ne[q], m = me[q];
+    const bool jr = !ADJ ? (n + 1 < NL && m + 1 < NL) : (n > 0 && m > 0);
+    if (jr) {
+      const double cj = !ADJ ? S.g1[q] * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
+                             : S.g1[q] * sqrt_small<NL>(n) * sqrt_small<NL>(m);
+      const int64_t sj = (int64_t)S.stride[q] * N + S.stride[q];
+      direction(make_double2(cj, 0.0), !ADJ ? sj : -sj);
+    }
+  }
+  // Internal terms (LDS), the diagonal part and the output, entry by entry.
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int f = tid + k * BLOCK;
+    if (f >= TT) continue;
     const int a = f / TC, c = f - (f / TC) * TC;
-    const int64_t e0 = base + (int64_t)a * N + c;
-    // all digits of this entry
     int nd[QC], md[QC];
     {
       int ra = a;
@@ -156,89 +206,249 @@ __global__ __launch_bounds__(TILE_BLOCK) void tile_kernel(
 #pragma unroll
       for (int q = 0; q < EC; ++q) md[q] = me[q];
     }
-    // global neighbour loads first
-    double2 gr[ER > 0 ? 2 * ER : 1], gc[EC > 0 ? 2 * EC : 1], gj[QC];
-#pragma unroll
-    for (int q = 0; q < QC; ++q) {
-      const int n = nd[q], m = md[q];
-      const int64_t s1 = S.stride[q];
-      const int64_t sN = s1 * N;
-      const bool rp = n + 1 < NL, rm = n > 0, cp = m + 1 < NL, cm = m > 0;
-      if (q < ER) {
-        gr[2 * q] = X[e0 + (rp ? sN : 0)];
-        gr[2 * q + 1] = X[e0 - (rm ? sN : 0)];
-      }
-      if (q < EC) {
-        gc[2 * q] = X[e0 + (cp ? s1 : 0)];
-        gc[2 * q + 1] = X[e0 - (cm ? s1 : 0)];
-      }
-      if (q < ER || q < EC) {
-        if (!ADJ) gj[q] = X[e0 + ((rp && cp) ? sN + s1 : 0)];
-        else gj[q] = X[e0 - ((rm && cm) ? sN + s1 : 0)];
-      }
-    }
-    double2 acc = make_double2(0.0, 0.0);
     double gam = 0.0;
+    double2 ac = acc[k];
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
       const int n = nd[q], m = md[q];
-      const bool rp = n + 1 < NL, rm = n > 0, cp = m + 1 < NL, cm = m > 0;
+      const double dnm = (double)(n - m);
+      gam += 0.5 * (S.g1[q] * (double)(n + m) + S.g2[q] * dnm * dnm);
       const int st = S.stride[q];
-      double2 vrp, vrm, vcp, vcm, vj;
-      if (q < ER) {
-        vrp = gr[2 * q];
-        vrm = gr[2 * q + 1];
-      } else {  // internal row digit: a row shift of st is st*TC entries in the block
-        vrp = tile[f + (rp ? st * TC : 0)];
-        vrm = tile[f - (rm ? st * TC : 0)];
+      // Internal neighbours are LDS reads; a missing one reads the entry
+      // itself with a zero weight (no divergent branches).
+      const bool rp = n + 1 < NL, rm = n > 0, cp = m + 1 < NL, cm = m > 0;
+      if (q >= ER) {  // internal row digit: a row shift of st is st*TC entries in the block
+        cmac(ac, ctl_coef<DIR_RP, ADJ>(da[q], db[q], rp ? sqrt_small<NL>(n + 1) : 0.0),
+             tile[f + (rp ? st * TC : 0)]);
+        cmac(ac, ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), tile[f - (rm ? st * TC : 0)]);
       }
-      if (q < EC) {
-        vcp = gc[2 * q];
-        vcm = gc[2 * q + 1];
-      } else {
-        vcp = tile[f + (cp ? st : 0)];
-        vcm = tile[f - (cm ? st : 0)];
+      if (q >= EC) {
+        cmac(ac, ctl_coef<DIR_CP, ADJ>(da[q], db[q], cp ? sqrt_small<NL>(m + 1) : 0.0),
+             tile[f + (cp ? st : 0)]);
+        cmac(ac, ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), tile[f - (cm ? st : 0)]);
       }
-      if (q < ER || q < EC) {
-        vj = gj[q];
-      } else if (!ADJ) {
-        vj = tile[f + ((rp && cp) ? st * TC + st : 0)];
-      } else {
-        vj = tile[f - ((rm && cm) ? st * TC + st : 0)];
+      const bool jr = !ADJ ? (rp && cp) : (rm && cm);
+      const double cj = !jr ? 0.0
+                            : !ADJ ? S.g1[q] * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
+                                   : S.g1[q] * sqrt_small<NL>(n) * sqrt_small<NL>(m);
+      if (q >= ER && q >= EC) {
+        const double2 v = tile[f + (!jr ? 0 : !ADJ ? st * TC + st : -(st * TC + st))];
+        ac.x += cj * v.x;
+        ac.y += cj * v.y;
+      } else if (q >= ER || q >= EC) {  // one digit internal: a per-entry global load
+        const int64_t sj = (int64_t)st * N + st;
+        const double2 v = X[off_of(k) + (!jr ? 0 : !ADJ ? sj : -sj)];
+        ac.x += cj * v.x;
+        ac.y += cj * v.y;
       }
-      tile_term<NL, ADJ>(n, m, S.g1[q], S.g2[q], da[q], db[q], vrp, vrm, vcp, vcm, vj, acc, gam);
     }
     const int i = bi * TR + a, j = bj * TC + c;
     const double dE = Es[i] - Es[j];
     const double2 D = diag_coef(gam, dE, ADJ);
-    const int64_t e = b * N2 + e0;
+    const int64_t e = b * N2 + off_of(k);
     if (MODE == 0) {
-      out[e] = cadd(acc, cmul(D, tile[f]));
+      out[e] = cadd(ac, cmul(D, tile[f]));
     } else {
       const double2 qv = qin[e];
       const double2 w = stage_weight(h, gam, dE, ADJ);
       const double2 hdq = cscale(h, cmul(D, qv));
-      const double2 dn = cmul(w, make_double2(hdq.x + h * acc.x, hdq.y + h * acc.y));
+      const double2 dn = cmul(w, make_double2(hdq.x + h * ac.x, hdq.y + h * ac.y));
       out[e] = MODE == 2 ? make_double2(qv.x + 2.0 * dn.x, qv.y + 2.0 * dn.y) : cadd(qv, dn);
     }
   }
 }
 
-// Block shapes: KR row digits and KC column digits inside a block.  The
-// default is the square block with the most entries up to 6561; the plan's
-// LB_OPT_TILE_KI selects another instantiated shape (encoded 10*KR + KC).
-constexpr int TILE_MAX = 6561;
+// Multi-pass application for large systems of equal-level subsystems.  The
+// subsystems are split into groups; pass g applies the terms of group g
+// (row and column ladder shifts and decay jumps, all of which move only
+// digits of the group's subsystems) to every entry, so that a block holding
+// every row digit of the group in its rows (mask RM) and every column digit
+// in its columns (mask CM) finds all neighbours in LDS and reads nothing
+// outside itself.  Both masks may hold further, passive digits: the lowest
+// column digits are always in CM, so that a block row is a contiguous run
+// of at least 16 entries.  The first pass writes its terms to `out`, later
+// passes add theirs to what `out` holds (each entry is read and written by
+// one thread), and the last adds the diagonal part (MODE 0) or takes the
+// stage update (MODE 1, 2); out must therefore not overlap zin or qin.
+// Bit q of a mask stands for subsystem q (q = 0 most significant).
+constexpr int popc(unsigned m) { return m ? (int)(m & 1u) + popc(m >> 1) : 0; }
 
-template <int NL, int QC, int KR, int KC, bool ADJ, int MODE>
-static int tile_launch(const lb_plan *p, int sys, int B, const double *alpha, double t,
+template <int NL, int QC, unsigned IM, unsigned RM, unsigned CM, int STAGE, bool ADJ, int MODE>
+__global__ __launch_bounds__(TILE_BLOCK) void pass_kernel(
+    const SysDev *__restrict__ sysv, int sys, int64_t nblocks, const double *__restrict__ Etab,
+    const double *__restrict__ alpha, const double *__restrict__ carrier, double t,
+    const double2 *__restrict__ ctab, int jstep, const double2 *__restrict__ zin,
+    const double2 *__restrict__ qin, double2 *__restrict__ out) {
+  extern __shared__ double2 tile[];
+  __shared__ double2 dqs[QC];
+  constexpr int NR = popc(RM), NC = popc(CM);
+  constexpr int TRn = ipow(NL, NR), TCn = ipow(NL, NC), TT = TRn * TCn;
+  constexpr int FC = ipow(NL, QC - NC), FR = ipow(NL, QC - NR);
+  constexpr int EPT = (TT + TILE_BLOCK - 1) / TILE_BLOCK;
+  const SysDev &S = sysv[sys];
+  const int N = S.N;
+  const int64_t N2 = S.N2;
+  const int tid = threadIdx.x;
+  const int64_t per = (nblocks + 7) / 8;
+  const int64_t lb = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (lb >= nblocks) return;
+  if (tid < QC)
+    dqs[tid] = ctab ? ctab[S.ctab_off + (int64_t)jstep * QC + tid]
+                    : control_value(S, alpha, carrier + S.carrier_off, tid, t);
+  const int64_t b = lb / ((int64_t)FR * FC);
+  const int rem = (int)(lb - b * FR * FC);
+  // fixed digits: the row digits outside RM from u, the column digits outside CM from v
+  int nf[QC], mf[QC];
+  int ibase = 0, jbase = 0;
+  {
+    int u = rem / FC, v = rem - (rem / FC) * FC;
+#pragma unroll
+    for (int q = QC - 1; q >= 0; --q) {
+        const int sq = ipow(NL, QC - 1 - q);
+      if (!((RM >> q) & 1u)) {
+        nf[q] = u % NL;
+        u /= NL;
+        ibase += nf[q] * sq;
+      } else {
+        nf[q] = 0;
+      }
+      if (!((CM >> q) & 1u)) {
+        mf[q] = v % NL;
+        v /= NL;
+        jbase += mf[q] * sq;
+      } else {
+        mf[q] = 0;
+      }
+    }
+  }
+  const double2 *X = zin + b * N2;
+  // row / column offset of block row a / block column c, and all digits
+  auto rowoff = [&](int a) {
+    int r = 0;
+#pragma unroll
+    for (int q = QC - 1; q >= 0; --q)
+      if ((RM >> q) & 1u) {
+        r += (a % NL) * ipow(NL, QC - 1 - q);
+        a /= NL;
+      }
+    return r;
+  };
+  auto coloff = [&](int c) {
+    int r = 0;
+#pragma unroll
+    for (int q = QC - 1; q >= 0; --q)
+      if ((CM >> q) & 1u) {
+        r += (c % NL) * ipow(NL, QC - 1 - q);
+        c /= NL;
+      }
+    return r;
+  };
+  auto off_of = [&](int k) -> int64_t {
+    const int f = tid + k * TILE_BLOCK;
+    const int ff = f < TT ? f : 0;
+    const int a = ff / TCn, c = ff - (ff / TCn) * TCn;
+    return (int64_t)(ibase + rowoff(a)) * N + jbase + coloff(c);
+  };
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int f = tid + k * TILE_BLOCK;
+    if (f < TT) tile[f] = X[off_of(k)];
+  }
+  const double h = S.h;
+  const double *Es = Etab + S.tab_off;
+  __syncthreads();
+  double da[QC], db[QC];
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    da[q] = uniform(dqs[q].x);
+    db[q] = uniform(dqs[q].y);
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int f = tid + k * TILE_BLOCK;
+    if (f >= TT) continue;
+    const int a = f / TCn, c = f - (f / TCn) * TCn;
+    int nd[QC], md[QC];
+    {
+      int ra = a, rc = c;
+#pragma unroll
+      for (int q = QC - 1; q >= 0; --q) {
+        if ((RM >> q) & 1u) {
+          nd[q] = ra % NL;
+          ra /= NL;
+        } else {
+          nd[q] = nf[q];
+        }
+        if ((CM >> q) & 1u) {
+          md[q] = rc % NL;
+          rc /= NL;
+        } else {
+          md[q] = mf[q];
+        }
+      }
+    }
+    double2 ac = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      if (!((IM >> q) & 1u)) continue;
+      const int n = nd[q], m = md[q];
+      // strides of digit q inside the block's row and column index
+      const int sr = ipow(NL, popc(RM & (~0u << (q + 1)))) * TCn;
+      const int sc = ipow(NL, popc(CM & (~0u << (q + 1))));
+      const bool rp = n + 1 < NL, rm = n > 0, cp = m + 1 < NL, cm = m > 0;
+      cmac(ac, ctl_coef<DIR_RP, ADJ>(da[q], db[q], rp ? sqrt_small<NL>(n + 1) : 0.0), tile[f + (rp ? sr : 0)]);
+      cmac(ac, ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), tile[f - (rm ? sr : 0)]);
+      cmac(ac, ctl_coef<DIR_CP, ADJ>(da[q], db[q], cp ? sqrt_small<NL>(m + 1) : 0.0), tile[f + (cp ? sc : 0)]);
+      cmac(ac, ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), tile[f - (cm ? sc : 0)]);
+      const bool jr = !ADJ ? (rp && cp) : (rm && cm);
+      const double cj = !jr ? 0.0
+                            : !ADJ ? S.g1[q] * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
+                                   : S.g1[q] * sqrt_small<NL>(n) * sqrt_small<NL>(m);
+      const double2 vj = tile[f + (!jr ? 0 : !ADJ ? sr + sc : -(sr + sc))];
+      ac.x += cj * vj.x;
+      ac.y += cj * vj.y;
+    }
+    const int i = ibase + rowoff(a), j = jbase + coloff(c);
+    const int64_t e = b * N2 + (int64_t)i * N + j;
+    if (STAGE == 0) {
+      out[e] = ac;
+      continue;
+    }
+    ac = cadd(ac, out[e]);
+    if (STAGE == 1) {
+      out[e] = ac;
+      continue;
+    }
+    double gam = 0.0;
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      const double dnm = (double)(nd[q] - md[q]);
+      gam += 0.5 * (S.g1[q] * (double)(nd[q] + md[q]) + S.g2[q] * dnm * dnm);
+    }
+    const double dE = Es[i] - Es[j];
+    const double2 D = diag_coef(gam, dE, ADJ);
+    if (MODE == 0) {
+      out[e] = cadd(ac, cmul(D, tile[f]));
+    } else {
+      const double2 qv = qin[e];
+      const double2 w = stage_weight(h, gam, dE, ADJ);
+      const double2 hdq = cscale(h, cmul(D, qv));
+      const double2 dn = cmul(w, make_double2(hdq.x + h * ac.x, hdq.y + h * ac.y));
+      out[e] = MODE == 2 ? make_double2(qv.x + 2.0 * dn.x, qv.y + 2.0 * dn.y) : cadd(qv, dn);
+    }
+  }
+}
+
+template <int NL, int QC, unsigned IM, unsigned RM, unsigned CM, int STAGE, bool ADJ, int MODE>
+static int pass_launch(const lb_plan *p, int sys, int B, const double *alpha, double t,
                        const double2 *ctab, int j, const double2 *zin, const double2 *qin,
                        double2 *out, hipStream_t st) {
-  constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
-  const int N = p->sys[sys].N;
-  const size_t shmem = (size_t)TR * TC * sizeof(double2);
-  auto kern = tile_kernel<NL, QC, KR, KC, ADJ, MODE>;
+  constexpr int NR = popc(RM), NC = popc(CM);
+  static_assert(ipow(NL, NR + NC) <= 6561, "block does not fit in LDS");
+  const size_t shmem = (size_t)ipow(NL, NR + NC) * sizeof(double2);
+  auto kern = pass_kernel<NL, QC, IM, RM, CM, STAGE, ADJ, MODE>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  const int64_t nblocks = (int64_t)B * (N / TR) * (N / TC);
+  const int64_t nblocks = (int64_t)B * ipow(NL, QC - NR) * ipow(NL, QC - NC);
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TILE_BLOCK), shmem, st, p->d_sys, sys, nblocks,
                      p->d_E, alpha, p->d_carrier, t, ctab, j, zin, qin, out);
@@ -246,25 +456,111 @@ static int tile_launch(const lb_plan *p, int sys, int B, const double *alpha, do
   return LB_OK;
 }
 
-template <int NL, int QC, int KR, int KC>
+// One pass of a plan: STAGE 0 first, 1 middle, 2 last (which takes MODE).
+template <int NL, int QC, unsigned IM, unsigned RM, unsigned CM, int STAGE>
+static int pass_run(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha,
+                    double t, const double2 *ctab, int j, const double2 *zin, const double2 *qin,
+                    double2 *out, hipStream_t st) {
+  if constexpr (STAGE < 2) {
+    return adj ? pass_launch<NL, QC, IM, RM, CM, STAGE, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st)
+               : pass_launch<NL, QC, IM, RM, CM, STAGE, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+  }
+  if (adj) {
+    if (mode == 0) return pass_launch<NL, QC, IM, RM, CM, 2, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+    if (mode == 1) return pass_launch<NL, QC, IM, RM, CM, 2, true, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+    return pass_launch<NL, QC, IM, RM, CM, 2, true, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+  }
+  if (mode == 0) return pass_launch<NL, QC, IM, RM, CM, 2, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+  if (mode == 1) return pass_launch<NL, QC, IM, RM, CM, 2, false, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+  return pass_launch<NL, QC, IM, RM, CM, 2, false, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+}
+
+// Pass plans (NL, Q, then per pass: subsystems applied, row mask, column
+// mask).  Every subsystem is applied by exactly one pass.
+#define LBX_PASS_PLANS(P3)                                                    \
+  P3(3, 8, 0xF0u, 0xF0u, 0xF0u, 0x03u, 0x03u, 0xF3u, 0x0Cu, 0x0Cu, 0xFCu)     \
+  P3(3, 7, 0x78u, 0x78u, 0x78u, 0x03u, 0x03u, 0x7Bu, 0x04u, 0x1Cu, 0x7Cu)     \
+  P3(2, 12, 0xFC0u, 0xFC0u, 0xFC0u, 0x007u, 0x007u, 0xFC7u, 0x038u, 0x038u, 0xFF8u) \
+  P3(2, 11, 0x7E0u, 0x7E0u, 0x7E0u, 0x007u, 0x007u, 0x7E7u, 0x018u, 0x078u, 0x7F8u) \
+  P3(4, 6, 0x38u, 0x38u, 0x38u, 0x03u, 0x03u, 0x33u, 0x04u, 0x0Cu, 0x3Cu)
+
+int split_kl(const lb_plan *p, int sys) {
+  const SysDev &S = p->sys[sys];
+  const int nl = S.nlev[0];
+  for (int q = 1; q < S.Q; ++q)
+    if (S.nlev[q] != nl) return 0;
+#define P3(A, B, I0, R0, C0, I1, R1, C1, I2, R2, C2) \
+  if (nl == A && S.Q == B) return 3;
+  LBX_PASS_PLANS(P3)
+#undef P3
+  return 0;
+}
+
+int launch_split(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
+                 const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
+                 hipStream_t st) {
+  if (B == 0) return LB_OK;
+  const SysDev &S = p->sys[sys];
+  const int nl = S.nlev[0];
+  if (!split_kl(p, sys)) return fail(LB_EUNSUPPORTED, "system not eligible for the multi-pass kernels");
+#define P3(A, Bq, I0, R0, C0, I1, R1, C1, I2, R2, C2)                                                    \
+  if (nl == A && S.Q == Bq) {                                                                           \
+    int rc = pass_run<A, Bq, I0, R0, C0, 0>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st); \
+    if (!rc) rc = pass_run<A, Bq, I1, R1, C1, 1>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st); \
+    if (!rc) rc = pass_run<A, Bq, I2, R2, C2, 2>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st); \
+    return rc;                                                                                          \
+  }
+  LBX_PASS_PLANS(P3)
+#undef P3
+  return fail(LB_EUNSUPPORTED, "system not eligible for the multi-pass kernels");
+}
+
+// Block shapes: KR row digits and KC column digits inside a block.  The
+// default is the square block with the most entries up to 6561; the plan's
+// LB_OPT_TILE_KI selects another instantiated shape (encoded 10*KR + KC).
+constexpr int TILE_MAX = 6561;
+
+template <int NL, int QC, int KR, int KC, int BLOCK, bool ADJ, int MODE>
+static int tile_launch(const lb_plan *p, int sys, int B, const double *alpha, double t,
+                       const double2 *ctab, int j, const double2 *zin, const double2 *qin,
+                       double2 *out, hipStream_t st) {
+  constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
+  const int N = p->sys[sys].N;
+  const size_t shmem = (size_t)TR * TC * sizeof(double2);
+  auto kern = tile_kernel<NL, QC, KR, KC, ADJ, MODE, BLOCK>;
+  LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  const int64_t nblocks = (int64_t)B * (N / TR) * (N / TC);
+  const int64_t grid = ((nblocks + 7) / 8) * 8;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(BLOCK), shmem, st, p->d_sys, sys, nblocks,
+                     p->d_E, alpha, p->d_carrier, t, ctab, j, zin, qin, out);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+template <int NL, int QC, int KR, int KC, int BLOCK>
 static int tile_modes(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha,
                       double t, const double2 *ctab, int j, const double2 *zin, const double2 *qin,
                       double2 *out, hipStream_t st) {
   if (adj) {
-    if (mode == 0) return tile_launch<NL, QC, KR, KC, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-    if (mode == 1) return tile_launch<NL, QC, KR, KC, true, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-    return tile_launch<NL, QC, KR, KC, true, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+    if (mode == 0) return tile_launch<NL, QC, KR, KC, BLOCK, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+    if (mode == 1) return tile_launch<NL, QC, KR, KC, BLOCK, true, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+    return tile_launch<NL, QC, KR, KC, BLOCK, true, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
   }
-  if (mode == 0) return tile_launch<NL, QC, KR, KC, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-  if (mode == 1) return tile_launch<NL, QC, KR, KC, false, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-  return tile_launch<NL, QC, KR, KC, false, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+  if (mode == 0) return tile_launch<NL, QC, KR, KC, BLOCK, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+  if (mode == 1) return tile_launch<NL, QC, KR, KC, BLOCK, false, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+  return tile_launch<NL, QC, KR, KC, BLOCK, false, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
 }
 
-// Instantiated shapes (NL, Q, KR, KC); the first listed for a (NL, Q) is the default.
+// Instantiated shapes (NL, Q, KR, KC, threads per block); the first listed
+// for a (NL, Q) is the default.  Blocks of up to 2187 entries run 256
+// threads, so that several fit on one compute unit.
 #define LBX_TILE_SHAPES(X)                                                                    \
-  X(3, 8, 4, 4) X(3, 8, 4, 3) X(3, 8, 3, 4) X(3, 8, 4, 2) X(3, 8, 3, 3)                          \
-  X(3, 7, 4, 4) X(3, 7, 4, 3) X(3, 6, 4, 4) X(3, 6, 4, 3)                                       \
-  X(2, 9, 6, 6) X(2, 10, 6, 6) X(2, 11, 6, 6) X(2, 12, 6, 6) X(4, 5, 3, 3) X(4, 6, 3, 3)
+  X(3, 8, 4, 4, 512) X(3, 8, 4, 3, 256) X(3, 8, 3, 4, 256) X(3, 8, 4, 2, 256)                  \
+  X(3, 8, 3, 3, 256) X(3, 8, 3, 2, 256) X(3, 8, 2, 3, 256)                                     \
+  X(3, 7, 4, 4, 512) X(3, 7, 4, 3, 256) X(3, 7, 3, 3, 256) X(3, 6, 4, 4, 512)                  \
+  X(3, 6, 4, 3, 256) X(3, 5, 3, 3, 256) X(3, 5, 3, 2, 256) X(3, 5, 2, 3, 256)                  \
+  X(2, 9, 6, 6, 512) X(2, 10, 6, 6, 512) X(2, 11, 6, 6, 512) X(2, 12, 6, 6, 512)               \
+  X(4, 5, 3, 3, 512) X(4, 6, 3, 3, 512)
 
 int tile_ki(const lb_plan *p, int sys) {
   const SysDev &S = p->sys[sys];
@@ -272,7 +568,7 @@ int tile_ki(const lb_plan *p, int sys) {
   for (int q = 1; q < S.Q; ++q)
     if (S.nlev[q] != nl) return 0;
   int first = 0;
-#define X(A, B, R, C)                                              \
+#define X(A, B, R, C, T)                                           \
   if (nl == A && S.Q == B) {                                       \
     if (!first) first = 10 * R + C;                                \
     if (p->tile_ki == 10 * R + C) return 10 * R + C;               \
@@ -282,16 +578,20 @@ int tile_ki(const lb_plan *p, int sys) {
   return first;
 }
 
-int tile_nl(const lb_plan *p, int sys) { return tile_ki(p, sys) > 0 ? p->sys[sys].nlev[0] : 0; }
+int tile_nl(const lb_plan *p, int sys) {
+  return (tile_ki(p, sys) > 0 || (p->tile == 2 && split_kl(p, sys) > 0)) ? p->sys[sys].nlev[0] : 0;
+}
 
 int launch_tile(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
                 const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
                 hipStream_t st) {
   if (B == 0) return LB_OK;
+  if (p->tile == 2 && split_kl(p, sys))
+    return launch_split(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st);
   const SysDev &S = p->sys[sys];
   const int nl = tile_nl(p, sys), k = tile_ki(p, sys);
-#define X(A, Bq, R, C) \
-  if (nl == A && S.Q == Bq && k == 10 * R + C) return tile_modes<A, Bq, R, C>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st);
+#define X(A, Bq, R, C, T) \
+  if (nl == A && S.Q == Bq && k == 10 * R + C) return tile_modes<A, Bq, R, C, T>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st);
   LBX_TILE_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "system not eligible for the tiled kernels");

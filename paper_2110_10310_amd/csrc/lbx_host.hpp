@@ -161,6 +161,13 @@ int tile_nl(const lb_plan *p, int sys);
 int tile_ki(const lb_plan *p, int sys);  // internal digits of the block, 0 if not eligible
 // mode 0: y = M x (alpha, t); mode 1: sweep (q + delta); mode 2: last sweep (q + 2 delta),
 // with the controls of step j from ctab.
+// Two-pass split kernels (kernels_tile.hip): number of low subsystems of the
+// split of system sys, 0 if not eligible; launch_split runs both passes.
+// launch_tile uses them when LB_OPT_TILE is 2 and the system is eligible.
+int split_kl(const lb_plan *p, int sys);
+int launch_split(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
+                 const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
+                 hipStream_t st);
 int launch_tile(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
                 const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
                 hipStream_t st);

@@ -84,17 +84,20 @@ def test_lindblad_apply_empty_batch_is_noop(lbx):
     assert y.shape == (0, 6, 6)
 
 
-def test_lindblad_apply_eight_qutrits_sampled(lbx):
+@pytest.mark.parametrize("tile,ki", [(1, 44), (1, 33), (1, 32), (1, 23), (2, 0)])
+def test_lindblad_apply_eight_qutrits_sampled(lbx, tile, ki):
     # The 8-qutrit ring at full size (N = 6561, 43M entries per state): check
-    # sampled entries, each formed by the oracle from single operator rows.
+    # sampled entries, each formed by the oracle from single operator rows,
+    # for the one-pass block-tiled and the two-pass split kernels.
     p = make_config(5)
     s = p.systems[0]
     rng = np.random.default_rng(55)
     N = s.N
     x = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) / np.sqrt(2)
     t = 37.3
-    say("apply c5 full size")
-    plan = lbx.Plan([s])
+    say("apply c5 full size, tile", tile, ki)
+    plan = lbx.Plan([s], tile=tile)
+    plan.set_option(lbx._native.LB_OPT_TILE_KI, ki)
     al = dev(p.alpha[0].reshape(-1))
     xd = dev(x[None])
     for adjoint in (False, True):
@@ -389,6 +392,28 @@ def test_row_tiled_apply_matches_operator_form(lbx, nlev, adjoint):
     assert rel_state_err(y, yg) < 1e-14
 
 
+@pytest.mark.parametrize("nlev,ki", [((3,) * 7, 43), ((3,) * 6, 43), ((3,) * 5, 33), ((3,) * 5, 32),
+                                     ((3,) * 5, 23)])
+def test_block_shapes_match_generic_kernel(lbx, nlev, ki):
+    # Every instantiated block shape (some with 256-thread blocks) against
+    # the generic streaming kernel and the operator form.
+    s, alpha, rng = _sys(260 + ki, nlev, Nf=1)
+    N = s.N
+    x = rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))
+    t = 0.52
+    say("block shape", nlev, ki)
+    plan = lbx.Plan([s])
+    plan.set_option(lbx._native.LB_OPT_TILE_KI, ki)
+    al = dev(alpha.reshape(-1))
+    for adjoint in (False, True):
+        y = lbx.lindblad_apply(plan, 0, t, al, dev(x), adjoint=adjoint).cpu().numpy()
+        yg = lbx.lindblad_apply(lbx.Plan([s], tile=0), 0, t, al, dev(x), adjoint=adjoint).cpu().numpy()
+        assert rel_state_err(y, yg) < 1e-14
+        if N <= 729:
+            f = oracle.lindbladian_adjoint if adjoint else oracle.lindbladian
+            assert rel_state_err(y[:1], f(s, alpha, t, x[0])[None]) < 1e-13
+
+
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_row_tiled_imr_step_matches_oracle(lbx, adjoint):
     s, alpha, rng = _sys(211, (3,) * 6, NT=8, T=0.4, Nf=1)
@@ -413,6 +438,67 @@ def test_row_tiled_gradient_matches_oracle(lbx):
     systems, alphas, rho0, batch = _multi([(220, (3,) * 6)], NT=3, B=(1,), T=0.15)
     say("tile gradient")
     _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "stream", 2)
+
+
+# --------------------------------------------------------------- two-pass split kernels
+
+@pytest.mark.parametrize("nlev", [(3,) * 7, (2,) * 11])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_split_apply_matches_operator_form(lbx, nlev, adjoint):
+    s, alpha, rng = _sys(230 + len(nlev), nlev, Nf=1)
+    N = s.N
+    x = rng.standard_normal((1, N, N)) + 1j * rng.standard_normal((1, N, N))
+    t = 0.61
+    say("split apply", nlev, adjoint)
+    plan = lbx.Plan([s], tile=2)
+    y = lbx.lindblad_apply(plan, 0, t, dev(alpha.reshape(-1)), dev(x), adjoint=adjoint).cpu().numpy()
+    f = oracle.lindbladian_adjoint if adjoint else oracle.lindbladian
+    assert rel_state_err(y, f(s, alpha, t, x[0])[None]) < 1e-13
+    yg = lbx.lindblad_apply(lbx.Plan([s], tile=0), 0, t, dev(alpha.reshape(-1)), dev(x),
+                            adjoint=adjoint).cpu().numpy()
+    assert rel_state_err(y, yg) < 1e-14
+
+
+def test_split_apply_four_level_sampled(lbx):
+    # Six 4-level subsystems (N = 4096): sampled entries against the oracle,
+    # every entry against the generic streaming kernel.
+    s, alpha, rng = _sys(240, (4,) * 6, Nf=1)
+    N = s.N
+    x = rng.standard_normal((1, N, N)) + 1j * rng.standard_normal((1, N, N))
+    t = 0.33
+    say("split apply 4^6")
+    al = dev(alpha.reshape(-1))
+    for adjoint in (False, True):
+        y = lbx.lindblad_apply(lbx.Plan([s], tile=2), 0, t, al, dev(x), adjoint=adjoint)
+        rows = np.concatenate([rng.integers(0, N, 40), [0, N - 1]])
+        cols = np.concatenate([rng.integers(0, N, 40), [N - 1, 0]])
+        got = y[0, torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")].cpu().numpy()
+        ref = oracle.lindbladian_entries(s, alpha, t, x[0], rows, cols, adjoint=adjoint)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+        yg = lbx.lindblad_apply(lbx.Plan([s], tile=0), 0, t, al, dev(x), adjoint=adjoint)
+        assert rel_state_err(y.cpu().numpy(), yg.cpu().numpy()) < 1e-14
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_split_imr_step_and_gradient_match_generic(lbx, adjoint):
+    # The split and the generic kernels run the same sweeps (the generic ones
+    # are checked against the oracle above): results agree to rounding.
+    systems, alphas, rho0, batch = _multi([(250, (3,) * 7)], NT=3, B=(1,), T=0.15)
+    s, alpha = systems[0], alphas[0]
+    say("split imr_step/gradient", adjoint)
+    al = dev(alpha.reshape(-1))
+    q = dev(rho0[0])
+    outs = [lbx.imr_step(lbx.Plan([s], tile=tile), 0, 1, al, q, adjoint=adjoint).cpu().numpy()
+            for tile in (2, 0)]
+    assert rel_state_err(outs[0], outs[1]) < 1e-14
+    if adjoint:
+        rng = np.random.default_rng(7)
+        tar = dev(random_pure_states(rng, s.N, 1))
+        res = [lbx.adjoint_gradient(lbx.Plan([s], tile=tile), 0, al, q, tar, dev(np.ones(1)), [1], 0.0, 2)
+               for tile in (2, 0)]
+        assert abs(res[0][0].item() - res[1][0].item()) <= 1e-13 * abs(res[1][0].item())
+        g0, g1 = res[0][1].cpu().numpy(), res[1][1].cpu().numpy()
+        assert np.max(np.abs(g0 - g1)) <= 1e-12 * np.max(np.abs(g1))
 
 
 # --------------------------------------------------------------- graphs and autotuning
