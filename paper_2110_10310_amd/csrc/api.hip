@@ -33,17 +33,47 @@ int hip_fail(hipError_t e, const char *what) {
   return LB_EDEVICE;
 }
 
+static void prof_account(const lb_plan *p, const lbx_prof_pending &e) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, e.start, e.stop) == hipSuccess) {
+    p->prof_n[e.kernel] += 1;
+    p->prof_ms[e.kernel] += ms;
+  }
+  p->ev_pool.push_back(e.start);
+  p->ev_pool.push_back(e.stop);
+}
+
 void prof_resolve(const lb_plan *p) {
   for (auto &e : p->prof_pending) {
-    float ms = 0.f;
-    if (hipEventSynchronize(e.stop) == hipSuccess && hipEventElapsedTime(&ms, e.start, e.stop) == hipSuccess) {
-      p->prof_n[e.kernel] += 1;
-      p->prof_ms[e.kernel] += ms;
+    if (hipEventSynchronize(e.stop) == hipSuccess) {
+      prof_account(p, e);
+    } else {
+      (void)hipEventDestroy(e.start);
+      (void)hipEventDestroy(e.stop);
     }
-    (void)hipEventDestroy(e.start);
-    (void)hipEventDestroy(e.stop);
   }
   p->prof_pending.clear();
+}
+
+hipEvent_t ProfScope::prof_event(const lb_plan *p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+// Accounts the launches that have already finished (oldest first, without
+// waiting), so that a long profiled time loop keeps few events alive.
+void ProfScope::prof_drain(const lb_plan *p) {
+  size_t n = 0;
+  while (n < p->prof_pending.size() && hipEventQuery(p->prof_pending[n].stop) == hipSuccess) {
+    prof_account(p, p->prof_pending[n]);
+    ++n;
+  }
+  p->prof_pending.erase(p->prof_pending.begin(), p->prof_pending.begin() + n);
 }
 
 }  // namespace lbx
@@ -319,7 +349,9 @@ Layout layout(const lb_plan *p, int op, const BatchMeta &m, int ckpt_every) {
     L.st_qh1 = take(E);
     L.ckpt = take((size_t)L.nck * E);
     L.seg = take((size_t)std::max(0, L.c - 1) * E);
-    L.st_gpart = take((size_t)std::max<int64_t>(1, m.st_blocks) * 2 * QMAX * sizeof(double));
+    const int64_t grows =
+        std::max<int64_t>(m.st_blocks, m.tile_sys >= 0 ? tile_grad_rows(p, m.tile_sys, m.tile_B) : 0);
+    L.st_gpart = take((size_t)std::max<int64_t>(1, grows) * 2 * QMAX * sizeof(double));
     L.st_gfin = take(stream_grad_fin_doubles((int)m.segs.size()) * sizeof(double));
   }
   L.total = cur;
@@ -451,14 +483,16 @@ struct GraphRun {
 };
 
 // One stage-solve sweep of every streamed segment at step j.
+// zout (last sweep only, may be NULL) receives the converged stage vector.
 int sweep(const lb_plan *p, const BatchMeta &m, int j, bool adj, bool last, const double2 *ctab,
-          const double2 *zin, const double2 *qin, double2 *out, hipStream_t st) {
+          const double2 *zin, const double2 *qin, double2 *out, hipStream_t st,
+          double2 *zout = nullptr) {
   ProfScope ps(p, LB_KERNEL_SWEEP, st, m.st_entries);
   if (m.tile_sys >= 0)
     return launch_tile(p, m.tile_sys, m.tile_B, last ? 2 : 1, adj, nullptr, 0.0, ctab, j, zin, qin,
-                       out, st);
+                       out, last ? zout : nullptr, st);
   return launch_sweep(p, m.d_segs, (int)m.segs.size(), m.st_blocks, j, adj, last, ctab, zin, qin,
-                      out, st);
+                      out, last ? zout : nullptr, st);
 }
 
 // Streaming forward steps j0..j1-1 of every segment.  slot(j) returns the
@@ -640,6 +674,12 @@ extern "C" void lb_plan_destroy(lb_plan *p) {
   (void)hipFree(p->d_desc);
   (void)hipFree(p->d_carrier);
   if (p->d_sweeps) (void)hipFree(p->d_sweeps);
+  for (auto &e : p->prof_pending) {
+    (void)hipEventSynchronize(e.stop);
+    (void)hipEventDestroy(e.start);
+    (void)hipEventDestroy(e.stop);
+  }
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -979,19 +1019,27 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
           for (const auto &sg : m->segs) K = std::max(K, (int)k[((size_t)sg.sys * NT + j) * 2 + 1]);
           const double2 *qin = qh[cur];
           double2 *qout = qh[cur ^ 1];
+          // The last sweep also writes the stage vector zh = qh^{j+1} + delta =
+          // (qh^j + qh^{j+1})/2 into the z buffer it does not read.
+          double2 *zh = nullptr;
           for (int kk = 0; kk < K; ++kk) {
             const bool last = kk == K - 1;
             const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
             double2 *dst = last ? qout : (kk & 1 ? z1 : z0);
-            if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, ast))) return rc;
+            if (last) zh = kk == 0 ? z0 : (kk & 1 ? z1 : z0);
+            if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, ast, zh))) return rc;
           }
+          int64_t rows = 0;
           {
             ProfScope ps(p, LB_KERNEL_STREAM_GRAD, ast, m->st_entries);
-            if ((rc = launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, qout, qin, slot(j),
-                                         slot(j + 1), sgp, ast)))
-              return rc;
+            rc = m->tile_sys >= 0
+                     ? launch_tile_grad(p, m->tile_sys, m->tile_B, zh, slot(j), slot(j + 1), sgp, &rows, ast)
+                     : launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, zh, slot(j), slot(j + 1), sgp,
+                                          ast);
+            if (rc) return rc;
           }
-          if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, j, sgp, sgf, gstep, ast))) return rc;
+          if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, j, sgp, sgf, gstep, rows, ast)))
+            return rc;
           cur ^= 1;
         }
         if ((rc = gr.end())) return rc;

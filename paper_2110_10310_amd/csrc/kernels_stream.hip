@@ -105,7 +105,7 @@ int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const
   const int64_t total = (int64_t)B * p->sys[sys].N2;
   if (total == 0) return LB_OK;
   if (p->tile && tile_nl(p, sys))
-    return launch_tile(p, sys, B, 0, adj, alpha, t, nullptr, 0, x, nullptr, y, st);
+    return launch_tile(p, sys, B, 0, adj, alpha, t, nullptr, 0, x, nullptr, y, nullptr, st);
   const int64_t nblk = (total + STREAM_BLOCK - 1) / STREAM_BLOCK;
   if (adj)
     hipLaunchKernelGGL(apply_kernel<true>, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st,
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_kernel(
     const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg,
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
     const double2 *__restrict__ ctab, int j, const double2 *__restrict__ zin,
-    const double2 *__restrict__ qin, double2 *__restrict__ out) {
+    const double2 *__restrict__ qin, double2 *__restrict__ out, double2 *__restrict__ zout) {
   __shared__ double sq[SQRT_TABLE];
   __shared__ double2 dq[QMAX];
   __shared__ int sseg;
@@ -168,27 +168,28 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_kernel(
   const double2 hdq = cscale(S.h, cmul(diag_coef(gam, dE, ADJ), qv));
   const double2 dn = cmul(w, cadd(hdq, cscale(S.h, acc)));
   out[base + r] = LAST ? cadd(qv, cscale(2.0, dn)) : cadd(qv, dn);
+  if (LAST && zout) zout[base + r] = cadd(qv, dn);  // the converged stage vector
 }
 
 int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
                  bool adj, bool last, const double2 *ctab, const double2 *zin, const double2 *qin,
-                 double2 *out, hipStream_t st) {
+                 double2 *out, double2 *zout, hipStream_t st) {
   if (nblk == 0) return LB_OK;
   dim3 g((unsigned)nblk), b(STREAM_BLOCK);
   if (adj) {
     if (last)
       hipLaunchKernelGGL((sweep_kernel<true, true>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E,
-                         p->d_desc, ctab, j, zin, qin, out);
+                         p->d_desc, ctab, j, zin, qin, out, zout);
     else
       hipLaunchKernelGGL((sweep_kernel<true, false>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E,
-                         p->d_desc, ctab, j, zin, qin, out);
+                         p->d_desc, ctab, j, zin, qin, out, zout);
   } else {
     if (last)
       hipLaunchKernelGGL((sweep_kernel<false, true>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E,
-                         p->d_desc, ctab, j, zin, qin, out);
+                         p->d_desc, ctab, j, zin, qin, out, zout);
     else
       hipLaunchKernelGGL((sweep_kernel<false, false>), g, b, 0, st, p->d_sys, d_segs, nseg,
-                         p->d_E, p->d_desc, ctab, j, zin, qin, out);
+                         p->d_E, p->d_desc, ctab, j, zin, qin, out, zout);
   }
   LBX_HIP(hipGetLastError());
   return LB_OK;
@@ -196,14 +197,14 @@ int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nb
 
 // ----------------------------------------------------------------------------
 // Gradient integrands of one step for streamed systems (App. B eq.
-// reducedgradient):  zh = (qh^j + qh^{j+1})/2 is the adjoint stage vector,
-// z = (q^j + q^{j+1})/2 the forward one.  Per-block partial sums.
+// reducedgradient):  zh = (qh^j + qh^{j+1})/2 is the adjoint stage vector
+// (written by the last adjoint sweep of the step), z = (q^j + q^{j+1})/2 the
+// forward one.  Per-block partial sums.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
     const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg,
-    const uint64_t *__restrict__ desc, const double2 *__restrict__ qh0,
-    const double2 *__restrict__ qh1, const double2 *__restrict__ q0,
-    const double2 *__restrict__ q1, double *__restrict__ gpart) {
+    const uint64_t *__restrict__ desc, const double2 *__restrict__ zh,
+    const double2 *__restrict__ q0, const double2 *__restrict__ q1, double *__restrict__ gpart) {
   __shared__ double sq[SQRT_TABLE];
   __shared__ int sseg;
   __shared__ double red[STREAM_BLOCK / 64][2 * QMAX];
@@ -226,9 +227,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
   for (int q = 0; q < S.Q; ++q) {
     double gp = 0.0, gq = 0.0;
     if (ok)
-      grad_term(S, q, di, dj, r, z, sq,
-                [&](int64_t idx) { return cscale(0.5, cadd(qh0[base + idx], qh1[base + idx])); },
-                gp, gq);
+      grad_term(S, q, di, dj, r, z, sq, [&](int64_t idx) { return zh[base + idx]; }, gp, gq);
     gp = wave_sum<64>(gp);
     gq = wave_sum<64>(gq);
     if (lane == 0) {
@@ -246,11 +245,11 @@ __global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
 }
 
 int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk,
-                       const double2 *qh0, const double2 *qh1, const double2 *q0,
-                       const double2 *q1, double *gpart, hipStream_t st) {
+                       const double2 *zh, const double2 *q0, const double2 *q1, double *gpart,
+                       hipStream_t st) {
   if (nblk == 0) return LB_OK;
   hipLaunchKernelGGL(stream_grad_kernel, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st, p->d_sys,
-                     d_segs, nseg, p->d_desc, qh0, qh1, q0, q1, gpart);
+                     d_segs, nseg, p->d_desc, zh, q0, q1, gpart);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -264,11 +263,13 @@ constexpr int FIN_SPLIT = 64;
 
 __global__ __launch_bounds__(256) void stream_grad_partial_kernel(
     const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs,
-    const double *__restrict__ gpart, double *__restrict__ gfin) {
+    const double *__restrict__ gpart, double *__restrict__ gfin, int64_t rows) {
   __shared__ double red[4][2 * QMAX];
   const StreamSeg &sg = segs[blockIdx.x];
   const int Q2 = 2 * sysv[sg.sys].Q;
-  const int64_t nb = (sg.count + STREAM_BLOCK - 1) / STREAM_BLOCK;
+  // rows > 0: one segment whose partial rows start at 0 (block-tiled kernel)
+  const int64_t nb = rows > 0 ? rows : (sg.count + STREAM_BLOCK - 1) / STREAM_BLOCK;
+  const int64_t row0 = rows > 0 ? 0 : sg.blk0;
   const int64_t per = (nb + FIN_SPLIT - 1) / FIN_SPLIT;
   const int64_t k0 = (int64_t)blockIdx.y * per;
   const int64_t k1 = k0 + per < nb ? k0 + per : nb;
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(256) void stream_grad_partial_kernel(
 #pragma unroll
   for (int c = 0; c < 2 * QMAX; ++c) v[c] = 0.0;
   for (int64_t k = k0 + tid; k < k1; k += 256) {
-    const double *row = gpart + (sg.blk0 + k) * 2 * QMAX;
+    const double *row = gpart + (row0 + k) * 2 * QMAX;
 #pragma unroll
     for (int c = 0; c < 2 * QMAX; ++c)
       if (c < Q2) v[c] += row[c];
@@ -309,10 +310,11 @@ __global__ __launch_bounds__(64) void stream_grad_finalize_kernel(
 size_t stream_grad_fin_doubles(int nseg) { return (size_t)std::max(nseg, 1) * FIN_SPLIT * 2 * QMAX; }
 
 int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int j,
-                                const double *gpart, double *gfin, double *gstep, hipStream_t st) {
+                                const double *gpart, double *gfin, double *gstep, int64_t rows,
+                                hipStream_t st) {
   if (nseg == 0) return LB_OK;
   hipLaunchKernelGGL(stream_grad_partial_kernel, dim3(nseg, FIN_SPLIT), dim3(256), 0, st, p->d_sys,
-                     d_segs, gpart, gfin);
+                     d_segs, gpart, gfin, rows);
   LBX_HIP(hipGetLastError());
   hipLaunchKernelGGL(stream_grad_finalize_kernel, dim3(nseg), dim3(64), 0, st, p->d_sys, d_segs, j,
                      gfin, gstep);

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(
     const SysDev *__restrict__ sysv, int sys, int64_t nblocks, const double *__restrict__ Etab,
     const double *__restrict__ alpha, const double *__restrict__ carrier, double t,
     const double2 *__restrict__ ctab, int jstep, const double2 *__restrict__ zin,
-    const double2 *__restrict__ qin, double2 *__restrict__ out) {
+    const double2 *__restrict__ qin, double2 *__restrict__ out, double2 *__restrict__ zout) {
   extern __shared__ double2 tile[];
   __shared__ double2 dqs[QC];
   constexpr int ER = QC - KR, EC = QC - KC;  // external row / column digits
@@ -254,7 +254,155 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(
       const double2 hdq = cscale(h, cmul(D, qv));
       const double2 dn = cmul(w, make_double2(hdq.x + h * ac.x, hdq.y + h * ac.y));
       out[e] = MODE == 2 ? make_double2(qv.x + 2.0 * dn.x, qv.y + 2.0 * dn.y) : cadd(qv, dn);
+      if (MODE == 2 && zout) zout[e] = cadd(qv, dn);  // the converged stage vector
     }
+  }
+}
+
+// Gradient integrands of one step (App. B eq. reducedgradient) with the same
+// blocking as tile_kernel: zh (the adjoint stage vector) is staged in LDS,
+// the forward stage vector z = (q0 + q1)/2 is read per entry, and for every
+// subsystem q the block sums
+//   gp_q = sum Re<X_q zh, z>-type terms  and  gq_q likewise
+// as in grad_term (lbx_device.hpp), regrouped by neighbour: with U and V
+// built from the ladder neighbours of zh, gp += cross(U + V, z) and
+// gq -= dot(U - V, z), cross(a, z) = a.x z.y - a.y z.x.  Neighbours along
+// external digits are applied one direction at a time.  One row of 2 QMAX
+// partial sums per block.
+__device__ __forceinline__ double cross2(double2 a, double2 z) { return a.x * z.y - a.y * z.x; }
+__device__ __forceinline__ double dot2(double2 a, double2 z) { return a.x * z.x + a.y * z.y; }
+
+template <int NL, int QC, int KR, int KC, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tile_grad_kernel(
+    const SysDev *__restrict__ sysv, int sys, int64_t nblocks, const double2 *__restrict__ zh,
+    const double2 *__restrict__ q0, const double2 *__restrict__ q1, double *__restrict__ gpart) {
+  extern __shared__ double2 tile[];
+  __shared__ double red[BLOCK / 64][2 * QC];
+  constexpr int ER = QC - KR, EC = QC - KC;
+  constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
+  constexpr int TT = TR * TC;
+  constexpr int EPT = (TT + BLOCK - 1) / BLOCK;
+  const SysDev &S = sysv[sys];
+  const int N = S.N;
+  const int NBR = N / TR, NBC = N / TC;
+  const int64_t N2 = S.N2;
+  const int tid = threadIdx.x;
+  const int64_t per = (nblocks + 7) / 8;
+  const int64_t lb = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (lb >= nblocks) return;
+  const int64_t b = lb / ((int64_t)NBR * NBC);
+  const int rem = (int)(lb - b * NBR * NBC);
+  const int bi = rem / NBC, bj = rem - (rem / NBC) * NBC;
+  const double2 *Z = zh + b * N2;
+  const int64_t base = (int64_t)bi * TR * N + (int64_t)bj * TC;
+  auto off_of = [&](int k) -> int64_t {
+    const int f = tid + k * BLOCK;
+    const int ff = f < TT ? f : 0;
+    const int a = ff / TC, c = ff - (ff / TC) * TC;
+    return base + (int64_t)a * N + c;
+  };
+  double2 z[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int f = tid + k * BLOCK;
+    const int64_t e = off_of(k);
+    if (f < TT) tile[f] = Z[e];
+    const double2 a = q0[b * N2 + e], c = q1[b * N2 + e];
+    z[k] = f < TT ? make_double2(0.5 * (a.x + c.x), 0.5 * (a.y + c.y)) : make_double2(0.0, 0.0);
+  }
+  int ne[ER > 0 ? ER : 1], me[EC > 0 ? EC : 1];
+  {
+    int ri = bi;
+#pragma unroll
+    for (int q = ER - 1; q >= 0; --q) {
+      ne[q] = ri % NL;
+      ri /= NL;
+    }
+    int rj = bj;
+#pragma unroll
+    for (int q = EC - 1; q >= 0; --q) {
+      me[q] = rj % NL;
+      rj /= NL;
+    }
+  }
+  __syncthreads();
+  double gp[QC], gq[QC];
+#pragma unroll
+  for (int q = 0; q < QC; ++q) gp[q] = gq[q] = 0.0;
+  // external directions; sp, sq: signs of the cross and dot terms
+  auto direction = [&](int q, double w, double sp, double sg, int64_t shift) {
+    double2 v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) v[k] = Z[off_of(k) + shift];
+    double cp = 0.0, dp = 0.0;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      cp += cross2(v[k], z[k]);
+      dp += dot2(v[k], z[k]);
+    }
+    gp[q] += sp * w * cp;
+    gq[q] += sg * w * dp;
+  };
+#pragma unroll
+  for (int q = 0; q < ER; ++q) {
+    const int n = ne[q];
+    const int64_t sN = (int64_t)S.stride[q] * N;
+    if (n + 1 < NL) direction(q, sqrt_small<NL>(n + 1), 1.0, -1.0, sN);   // U += sqrt(n+1) x_{i+e}
+    if (n > 0) direction(q, sqrt_small<NL>(n), 1.0, 1.0, -sN);            // V += sqrt(n) x_{i-e}
+  }
+#pragma unroll
+  for (int q = 0; q < EC; ++q) {
+    const int m = me[q];
+    const int64_t s1 = S.stride[q];
+    if (m + 1 < NL) direction(q, sqrt_small<NL>(m + 1), -1.0, -1.0, s1);  // V -= sqrt(m+1) x_{j+e}
+    if (m > 0) direction(q, sqrt_small<NL>(m), -1.0, 1.0, -s1);           // U -= sqrt(m) x_{j-e}
+  }
+  // internal neighbours from LDS
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int f = tid + k * BLOCK;
+    if (f >= TT) continue;
+    const int a = f / TC, c = f - (f / TC) * TC;
+    int ra = a, rc = c;
+#pragma unroll
+    for (int q = QC - 1; q >= 0; --q) {
+      const int st = S.stride[q];
+      if (q >= ER) {
+        const int n = ra % NL;
+        ra /= NL;
+        const bool rp = n + 1 < NL, rm = n > 0;
+        const double2 vp = tile[f + (rp ? st * TC : 0)], vm = tile[f - (rm ? st * TC : 0)];
+        const double wp = rp ? sqrt_small<NL>(n + 1) : 0.0, wm = sqrt_small<NL>(n);
+        gp[q] += wp * cross2(vp, z[k]) + wm * cross2(vm, z[k]);
+        gq[q] += -wp * dot2(vp, z[k]) + wm * dot2(vm, z[k]);
+      }
+      if (q >= EC) {
+        const int m = rc % NL;
+        rc /= NL;
+        const bool cp = m + 1 < NL, cm = m > 0;
+        const double2 vp = tile[f + (cp ? st : 0)], vm = tile[f - (cm ? st : 0)];
+        const double wp = cp ? sqrt_small<NL>(m + 1) : 0.0, wm = sqrt_small<NL>(m);
+        gp[q] += -wp * cross2(vp, z[k]) - wm * cross2(vm, z[k]);
+        gq[q] += -wp * dot2(vp, z[k]) + wm * dot2(vm, z[k]);
+      }
+    }
+  }
+  // block sums in a fixed order
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    const double a = wave_sum<64>(gp[q]), c = wave_sum<64>(gq[q]);
+    if (lane == 0) {
+      red[wv][2 * q] = a;
+      red[wv][2 * q + 1] = c;
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * QC) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) v += red[w][tid];
+    gpart[lb * 2 * QMAX + tid] = v;
   }
 }
 
@@ -278,7 +426,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void pass_kernel(
     const SysDev *__restrict__ sysv, int sys, int64_t nblocks, const double *__restrict__ Etab,
     const double *__restrict__ alpha, const double *__restrict__ carrier, double t,
     const double2 *__restrict__ ctab, int jstep, const double2 *__restrict__ zin,
-    const double2 *__restrict__ qin, double2 *__restrict__ out) {
+    const double2 *__restrict__ qin, double2 *__restrict__ out, double2 *__restrict__ zout) {
   extern __shared__ double2 tile[];
   __shared__ double2 dqs[QC];
   constexpr int NR = popc(RM), NC = popc(CM);
@@ -435,6 +583,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void pass_kernel(
       const double2 hdq = cscale(h, cmul(D, qv));
       const double2 dn = cmul(w, make_double2(hdq.x + h * ac.x, hdq.y + h * ac.y));
       out[e] = MODE == 2 ? make_double2(qv.x + 2.0 * dn.x, qv.y + 2.0 * dn.y) : cadd(qv, dn);
+      if (MODE == 2 && zout) zout[e] = cadd(qv, dn);  // the converged stage vector
     }
   }
 }
@@ -442,7 +591,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void pass_kernel(
 template <int NL, int QC, unsigned IM, unsigned RM, unsigned CM, int STAGE, bool ADJ, int MODE>
 static int pass_launch(const lb_plan *p, int sys, int B, const double *alpha, double t,
                        const double2 *ctab, int j, const double2 *zin, const double2 *qin,
-                       double2 *out, hipStream_t st) {
+                       double2 *out, double2 *zout, hipStream_t st) {
   constexpr int NR = popc(RM), NC = popc(CM);
   static_assert(ipow(NL, NR + NC) <= 6561, "block does not fit in LDS");
   const size_t shmem = (size_t)ipow(NL, NR + NC) * sizeof(double2);
@@ -451,7 +600,7 @@ static int pass_launch(const lb_plan *p, int sys, int B, const double *alpha, do
   const int64_t nblocks = (int64_t)B * ipow(NL, QC - NR) * ipow(NL, QC - NC);
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TILE_BLOCK), shmem, st, p->d_sys, sys, nblocks,
-                     p->d_E, alpha, p->d_carrier, t, ctab, j, zin, qin, out);
+                     p->d_E, alpha, p->d_carrier, t, ctab, j, zin, qin, out, zout);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -460,19 +609,19 @@ static int pass_launch(const lb_plan *p, int sys, int B, const double *alpha, do
 template <int NL, int QC, unsigned IM, unsigned RM, unsigned CM, int STAGE>
 static int pass_run(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha,
                     double t, const double2 *ctab, int j, const double2 *zin, const double2 *qin,
-                    double2 *out, hipStream_t st) {
+                    double2 *out, double2 *zout, hipStream_t st) {
   if constexpr (STAGE < 2) {
-    return adj ? pass_launch<NL, QC, IM, RM, CM, STAGE, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st)
-               : pass_launch<NL, QC, IM, RM, CM, STAGE, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+    return adj ? pass_launch<NL, QC, IM, RM, CM, STAGE, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st)
+               : pass_launch<NL, QC, IM, RM, CM, STAGE, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
   }
   if (adj) {
-    if (mode == 0) return pass_launch<NL, QC, IM, RM, CM, 2, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-    if (mode == 1) return pass_launch<NL, QC, IM, RM, CM, 2, true, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-    return pass_launch<NL, QC, IM, RM, CM, 2, true, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+    if (mode == 0) return pass_launch<NL, QC, IM, RM, CM, 2, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
+    if (mode == 1) return pass_launch<NL, QC, IM, RM, CM, 2, true, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
+    return pass_launch<NL, QC, IM, RM, CM, 2, true, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
   }
-  if (mode == 0) return pass_launch<NL, QC, IM, RM, CM, 2, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-  if (mode == 1) return pass_launch<NL, QC, IM, RM, CM, 2, false, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-  return pass_launch<NL, QC, IM, RM, CM, 2, false, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+  if (mode == 0) return pass_launch<NL, QC, IM, RM, CM, 2, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
+  if (mode == 1) return pass_launch<NL, QC, IM, RM, CM, 2, false, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
+  return pass_launch<NL, QC, IM, RM, CM, 2, false, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
 }
 
 // Pass plans (NL, Q, then per pass: subsystems applied, row mask, column
@@ -498,16 +647,16 @@ int split_kl(const lb_plan *p, int sys) {
 
 int launch_split(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
                  const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
-                 hipStream_t st) {
+                 double2 *zout, hipStream_t st) {
   if (B == 0) return LB_OK;
   const SysDev &S = p->sys[sys];
   const int nl = S.nlev[0];
   if (!split_kl(p, sys)) return fail(LB_EUNSUPPORTED, "system not eligible for the multi-pass kernels");
 #define P3(A, Bq, I0, R0, C0, I1, R1, C1, I2, R2, C2)                                                    \
   if (nl == A && S.Q == Bq) {                                                                           \
-    int rc = pass_run<A, Bq, I0, R0, C0, 0>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st); \
-    if (!rc) rc = pass_run<A, Bq, I1, R1, C1, 1>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st); \
-    if (!rc) rc = pass_run<A, Bq, I2, R2, C2, 2>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st); \
+    int rc = pass_run<A, Bq, I0, R0, C0, 0>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, zout, st); \
+    if (!rc) rc = pass_run<A, Bq, I1, R1, C1, 1>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, zout, st); \
+    if (!rc) rc = pass_run<A, Bq, I2, R2, C2, 2>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, zout, st); \
     return rc;                                                                                          \
   }
   LBX_PASS_PLANS(P3)
@@ -523,7 +672,7 @@ constexpr int TILE_MAX = 6561;
 template <int NL, int QC, int KR, int KC, int BLOCK, bool ADJ, int MODE>
 static int tile_launch(const lb_plan *p, int sys, int B, const double *alpha, double t,
                        const double2 *ctab, int j, const double2 *zin, const double2 *qin,
-                       double2 *out, hipStream_t st) {
+                       double2 *out, double2 *zout, hipStream_t st) {
   constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
   const int N = p->sys[sys].N;
   const size_t shmem = (size_t)TR * TC * sizeof(double2);
@@ -532,7 +681,7 @@ static int tile_launch(const lb_plan *p, int sys, int B, const double *alpha, do
   const int64_t nblocks = (int64_t)B * (N / TR) * (N / TC);
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(BLOCK), shmem, st, p->d_sys, sys, nblocks,
-                     p->d_E, alpha, p->d_carrier, t, ctab, j, zin, qin, out);
+                     p->d_E, alpha, p->d_carrier, t, ctab, j, zin, qin, out, zout);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -540,15 +689,15 @@ static int tile_launch(const lb_plan *p, int sys, int B, const double *alpha, do
 template <int NL, int QC, int KR, int KC, int BLOCK>
 static int tile_modes(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha,
                       double t, const double2 *ctab, int j, const double2 *zin, const double2 *qin,
-                      double2 *out, hipStream_t st) {
+                      double2 *out, double2 *zout, hipStream_t st) {
   if (adj) {
-    if (mode == 0) return tile_launch<NL, QC, KR, KC, BLOCK, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-    if (mode == 1) return tile_launch<NL, QC, KR, KC, BLOCK, true, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-    return tile_launch<NL, QC, KR, KC, BLOCK, true, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+    if (mode == 0) return tile_launch<NL, QC, KR, KC, BLOCK, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
+    if (mode == 1) return tile_launch<NL, QC, KR, KC, BLOCK, true, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
+    return tile_launch<NL, QC, KR, KC, BLOCK, true, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
   }
-  if (mode == 0) return tile_launch<NL, QC, KR, KC, BLOCK, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-  if (mode == 1) return tile_launch<NL, QC, KR, KC, BLOCK, false, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
-  return tile_launch<NL, QC, KR, KC, BLOCK, false, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, st);
+  if (mode == 0) return tile_launch<NL, QC, KR, KC, BLOCK, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
+  if (mode == 1) return tile_launch<NL, QC, KR, KC, BLOCK, false, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
+  return tile_launch<NL, QC, KR, KC, BLOCK, false, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
 }
 
 // Instantiated shapes (NL, Q, KR, KC, threads per block); the first listed
@@ -578,20 +727,63 @@ int tile_ki(const lb_plan *p, int sys) {
   return first;
 }
 
+template <int NL, int QC, int KR, int KC, int BLOCK>
+static int tile_grad_launch(const lb_plan *p, int sys, int B, const double2 *zh, const double2 *q0,
+                            const double2 *q1, double *gpart, int64_t *rows, hipStream_t st) {
+  constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
+  const int N = p->sys[sys].N;
+  const size_t shmem = (size_t)TR * TC * sizeof(double2);
+  auto kern = tile_grad_kernel<NL, QC, KR, KC, BLOCK>;
+  LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  const int64_t nblocks = (int64_t)B * (N / TR) * (N / TC);
+  const int64_t grid = ((nblocks + 7) / 8) * 8;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(BLOCK), shmem, st, p->d_sys, sys, nblocks, zh, q0,
+                     q1, gpart);
+  LBX_HIP(hipGetLastError());
+  *rows = nblocks;
+  return LB_OK;
+}
+
+// Gradient integrands of one step for a system on the block-tiled path, in
+// the block shape of its sweeps (the single-pass shape even when the sweeps
+// use the multi-pass kernels).  *rows receives the number of partial rows.
+int launch_tile_grad(const lb_plan *p, int sys, int B, const double2 *zh, const double2 *q0,
+                     const double2 *q1, double *gpart, int64_t *rows, hipStream_t st) {
+  *rows = 0;
+  if (B == 0) return LB_OK;
+  const SysDev &S = p->sys[sys];
+  const int nl = S.nlev[0], k = tile_ki(p, sys);
+#define X(A, Bq, R, C, T) \
+  if (nl == A && S.Q == Bq && k == 10 * R + C) return tile_grad_launch<A, Bq, R, C, T>(p, sys, B, zh, q0, q1, gpart, rows, st);
+  LBX_TILE_SHAPES(X)
+#undef X
+  return fail(LB_EUNSUPPORTED, "system not eligible for the tiled gradient kernel");
+}
+
+int64_t tile_grad_rows(const lb_plan *p, int sys, int B) {
+  const SysDev &S = p->sys[sys];
+  const int k = tile_ki(p, sys);
+  if (!k) return 0;
+  int tr = 1, tc = 1;
+  for (int i = 0; i < k / 10; ++i) tr *= S.nlev[0];
+  for (int i = 0; i < k % 10; ++i) tc *= S.nlev[0];
+  return (int64_t)B * (S.N / tr) * (S.N / tc);
+}
+
 int tile_nl(const lb_plan *p, int sys) {
   return (tile_ki(p, sys) > 0 || (p->tile == 2 && split_kl(p, sys) > 0)) ? p->sys[sys].nlev[0] : 0;
 }
 
 int launch_tile(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
                 const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
-                hipStream_t st) {
+                double2 *zout, hipStream_t st) {
   if (B == 0) return LB_OK;
   if (p->tile == 2 && split_kl(p, sys))
-    return launch_split(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st);
+    return launch_split(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, zout, st);
   const SysDev &S = p->sys[sys];
   const int nl = tile_nl(p, sys), k = tile_ki(p, sys);
 #define X(A, Bq, R, C, T) \
-  if (nl == A && S.Q == Bq && k == 10 * R + C) return tile_modes<A, Bq, R, C, T>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, st);
+  if (nl == A && S.Q == Bq && k == 10 * R + C) return tile_modes<A, Bq, R, C, T>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, zout, st);
   LBX_TILE_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "system not eligible for the tiled kernels");

@@ -37,6 +37,7 @@ struct lb_plan {
   mutable double prof_ms[LB_KERNEL_COUNT] = {};
   mutable int64_t prof_work[LB_KERNEL_COUNT] = {};  // entries x sweeps (x steps for STREAM_GRAD)
   mutable std::vector<lbx_prof_pending> prof_pending;
+  mutable std::vector<hipEvent_t> ev_pool;  // recycled profiling events
   mutable int64_t *d_sweeps = nullptr;  // per-item sweep totals of the LDS kernels (profiling)
   mutable size_t sweeps_cap = 0;
 };
@@ -76,18 +77,22 @@ struct ProfScope {
   ProfScope(const lb_plan *p_, int k, hipStream_t s, int64_t work = 0) : p(p_), kernel(k), st(s) {
     if (!p->profile || p->capturing) return;
     p->prof_work[k] += work;
-    if (hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
+    a = prof_event(p);
+    if (a) (void)hipEventRecord(a, st);
   }
   ~ProfScope() {
     if (!a) return;
-    hipEvent_t b;
-    if (hipEventCreate(&b) != hipSuccess) return;
+    hipEvent_t b = prof_event(p);
+    if (!b) return;
     (void)hipEventRecord(b, st);
     p->prof_pending.push_back({kernel, a, b});
+    if (p->prof_pending.size() >= 2048) prof_drain(p);
   }
+  static hipEvent_t prof_event(const lb_plan *p);
+  static void prof_drain(const lb_plan *p);
 };
 
-// Accumulates and releases the events of every finished profiled launch.
+// Waits for every profiled launch, accumulates its time and recycles its events.
 void prof_resolve(const lb_plan *p);
 
 // Thread-local error message helpers.
@@ -112,19 +117,22 @@ int launch_control_table(const lb_plan *p, int s0, int nsys, const double *alpha
 int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const double2 *x,
                  double2 *y, int B, bool adj, hipStream_t st);
 
+// zout (may be NULL): the last sweep of a step also writes the converged
+// stage vector z = q + delta there.
 int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
                  bool adj, bool last, const double2 *ctab, const double2 *zin, const double2 *qin,
-                 double2 *out, hipStream_t st);
+                 double2 *out, double2 *zout, hipStream_t st);
 
 int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk,
-                       const double2 *qh0, const double2 *qh1, const double2 *q0,
-                       const double2 *q1, double *gpart, hipStream_t st);
+                       const double2 *zh, const double2 *q0, const double2 *q1, double *gpart,
+                       hipStream_t st);
 
 // Two-pass fixed-order sum of the stream_grad partials into gstep; gfin is
 // scratch of stream_grad_fin_doubles(nseg) doubles.
 size_t stream_grad_fin_doubles(int nseg);
 int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int j,
-                                const double *gpart, double *gfin, double *gstep, hipStream_t st);
+                                const double *gpart, double *gfin, double *gstep, int64_t rows,
+                                hipStream_t st);
 
 int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                        const double2 *ctab, const int32_t *ktab, const double2 *rho0,
@@ -167,10 +175,14 @@ int tile_ki(const lb_plan *p, int sys);  // internal digits of the block, 0 if n
 int split_kl(const lb_plan *p, int sys);
 int launch_split(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
                  const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
-                 hipStream_t st);
+                 double2 *zout, hipStream_t st);
 int launch_tile(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
                 const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
-                hipStream_t st);
+                double2 *zout, hipStream_t st);
+// Block-tiled gradient integrands of one step (partial rows: tile_grad_rows).
+int64_t tile_grad_rows(const lb_plan *p, int sys, int B);
+int launch_tile_grad(const lb_plan *p, int sys, int B, const double2 *zh, const double2 *q0,
+                     const double2 *q1, double *gpart, int64_t *rows, hipStream_t st);
 
 // Specialised LDS-resident kernels (kernels_lds_fast.hip) for Q subsystems.
 bool lds_fast_ok(int block, int ept, int Q);

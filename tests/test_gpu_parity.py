@@ -440,6 +440,25 @@ def test_row_tiled_gradient_matches_oracle(lbx):
     _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "stream", 2)
 
 
+@pytest.mark.parametrize("ki", [33, 23, 32])
+def test_tiled_gradient_block_shapes_match_oracle(lbx, ki):
+    # Five qutrits, two states: sweeps and gradient integrands in 256-thread
+    # block shapes, against the oracle's discrete adjoint.
+    systems, alphas, rho0, batch = _multi([(270 + ki, (3,) * 5)], NT=4, B=(2,), T=0.2)
+    say("tile gradient shape", ki)
+    rng = np.random.default_rng(ki)
+    tars = [random_pure_states(rng, systems[0].N, 2)]
+    beta = np.array([1.0, 0.7])
+    plan = lbx.Plan(systems, path="stream")
+    plan.set_option(lbx._native.LB_OPT_TILE_KI, ki)
+    G, grad, rhoT = lbx.adjoint_gradient(plan, 1, dev(flat_alpha(alphas)), dev(flat_states(rho0)),
+                                         dev(flat_states(tars)), dev(beta), batch, 0.0, 2, want_rhoT=True)
+    Gr, gr = oracle.value_and_gradient(systems[0], alphas[0], rho0[0], tars[0], beta, 1)
+    assert abs(G.item() - Gr) <= 1e-12 * abs(Gr)
+    g = grad.cpu().numpy().reshape(gr.shape)
+    assert np.max(np.abs(g - gr)) <= GRAD_TOL * np.max(np.abs(gr))
+
+
 # --------------------------------------------------------------- two-pass split kernels
 
 @pytest.mark.parametrize("nlev", [(3,) * 7, (2,) * 11])
