@@ -121,6 +121,14 @@ __device__ __forceinline__ int extra_sweeps(double theta, double ratio, double e
   double r = ratio * e1;  // ratio = theta / (1 - theta), from the control table
   const double lim = tol * qmax;
   int k = 0;
+  // The usual counts without branches (so the compiler can interleave them
+  // with the second sweep), then a loop for the rare remainder.
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const bool more = r > lim;
+    k += more ? 1 : 0;
+    r = more ? r * theta : r;
+  }
   while (r > lim && k < 64) {
     r *= theta;
     ++k;
