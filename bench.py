@@ -68,11 +68,11 @@ def source_sha(files):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key, files, launches_per_unit=1):
+def measured_traffic(key, files, traffic_file=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file or TRAFFIC_FILE) as fh:
             rec = json.load(fh).get(key)
     except (OSError, ValueError):
         return None
@@ -292,7 +292,7 @@ def run_traffic_probe(lbx, torch):
     return {"copy_bytes": 16 * N * N}
 
 
-def traffic_summary(fetch_csv, write_csv, copy_bytes):
+def traffic_summary(fetch_csv, write_csv, copy_bytes, out_path=None):
     """Per-launch HBM bytes from two rocprofv3 --pmc runs (FETCH_SIZE, then
     WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
     for the plain device copy of copy_bytes bytes.  Writes profiles/traffic.json
@@ -323,7 +323,7 @@ def traffic_summary(fetch_csv, write_csv, copy_bytes):
                       "dispatches": [len(fv), len(wv)], "source_sha": source_sha(files)}
         rows.append(f"| {key} | {len(fv)} | {np.mean(fv):.1f} | {np.mean(wv):.1f} | {fb / 1e9:.4f} | "
                     f"{wb / 1e9:.4f} |")
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(out_path or TRAFFIC_FILE, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     print(f"calibration: copy of {copy_bytes} B; FETCH_SIZE x{cal_f:.3f}, WRITE_SIZE x{cal_w:.3f}")
     print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | fetch GB (scaled) | write GB (scaled) |")
