@@ -198,6 +198,7 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
         sweeps["stream_all_passes"] = work[nat.LB_KERNEL_SWEEP] / (steps * st_entries) / nt
     scale = nt_full / p.systems[0].NT
     return {
+        "scale": scale,
         "value": steps / (elapsed * scale),
         "ms_per_step": 1e3 * elapsed * scale / steps,
         "sample": None if scale == 1 else f"{p.systems[0].NT} of {nt_full} steps timed, scaled x{scale:g}",
@@ -209,6 +210,9 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
         "kernel_total_ms": {name_of[k]: ms[k] / steps for k in ms if prof[k][0] > 0},
         "autotune": tuned,
         "states": sum(batch),
+        # applications of M per evaluation on the streamed path: every sweep of
+        # every pass, plus the gradient integrands of every step
+        "apply_equivalents": (work[nat.LB_KERNEL_SWEEP] / steps / st_entries + nt) if st_entries else None,
     }
 
 
@@ -366,6 +370,28 @@ def run_loop_baseline(lbx, torch, nsteps):
             "sample": f"16 states one by one, streaming path, {nsteps} of 10000 steps, time x{scale:g}"}
 
 
+def run_cpu_apply_baseline(workload, apply_equivalents, scale):
+    """The oracle's operator-form apply of M(t) on one state of a large
+    workload, timed once on one core and extrapolated to a whole gradient
+    evaluation (applications of M per evaluation on the GPU path)."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    from workloads import make_config
+    p = make_config(workload)
+    s = p.systems[0]
+    N = s.N
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.lindbladian(s, p.alpha[0], 41.0, x)
+        el = time.perf_counter() - t0
+    per_eval = el * apply_equivalents * scale * p.rho0[0].shape[0]
+    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"one operator-form apply of M on one state ({el:.1f} s), extrapolated x"
+                      f"{apply_equivalents * scale:.0f} applies per state and evaluation"}
+
+
 def run_cpu_baseline(nsteps):
     import oracle
     from workloads import make_config, truncate_steps
@@ -443,6 +469,9 @@ def main():
     if args.workload != 2:
         args.no_apply = args.no_apply or args.workload != 5
         args.no_loop = True
+        if args.workload == 5 and not args.no_cpu and res["apply_equivalents"]:
+            print("[bench] cpu baseline (oracle apply, extrapolated)", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = run_cpu_apply_baseline(5, res["apply_equivalents"], res["scale"])
         args.no_cpu = True
     if not args.no_apply:
         print("[bench] lindblad_apply 8 qutrits", file=sys.stderr, flush=True)

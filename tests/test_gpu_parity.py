@@ -279,6 +279,47 @@ def test_autograd_function_and_finite_differences(lbx):
         assert abs(fd - gr.reshape(-1)[k]) <= 1e-6 * np.max(np.abs(gr))
 
 
+def _fd_check(lbx, p, idx, h=1e-6, rel=1e-6):
+    """Central differences of the GPU objective (forward solve + objective) on
+    coefficients idx against the autograd/adjoint gradient of the same call."""
+    s = p.systems[0]
+    batch = [p.rho0[0].shape[0]]
+    plan = lbx.Plan([s])
+    a0 = p.alpha[0].reshape(-1)
+    args = (dev(p.rho0[0]), dev(p.rhotar[0]), dev(p.beta[0]), batch, p.gamma2, p.ckpt_every or 0)
+    a = dev(a0).requires_grad_(True)
+    lbx.lindblad_objective(a, plan, p.kind, *args).sum().backward()
+    g = a.grad.cpu().numpy()
+    gmax = np.max(np.abs(g))
+    for k in idx:
+        vals = []
+        for sgn in (1, -1):
+            ak = a0.copy()
+            ak[k] += sgn * h
+            with torch.no_grad():
+                vals.append(lbx.lindblad_objective(dev(ak), plan, p.kind, *args).item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[k]) <= rel * gmax, (k, fd, g[k], gmax)
+
+
+def test_config2_full_length_finite_differences(lbx):
+    # Two transmons, 16 basis states, 10000 steps: central differences with
+    # h = 1e-6 on a seeded subset of 16 of the 160 coefficients.
+    p = make_config(2)
+    idx = np.random.default_rng(2).choice(p.alpha[0].size, 16, replace=False)
+    say("c2 finite differences", list(idx))
+    _fd_check(lbx, p, idx)
+
+
+def test_config4_full_length_finite_differences(lbx):
+    # Five-qutrit chain, 10 states, 20000 steps, checkpoints every 200 steps
+    # recomputed in the adjoint: spot check on 8 coefficients.
+    p = make_config(4)
+    idx = np.random.default_rng(4).choice(p.alpha[0].size, 8, replace=False)
+    say("c4 finite differences", list(idx))
+    _fd_check(lbx, p, idx)
+
+
 def test_gradient_is_bitwise_deterministic(lbx):
     shapes = [(2, 3), (3, 3, 3)]
     systems, alphas, rho0, batch = _multi(list(enumerate(shapes, start=90)), NT=12)
