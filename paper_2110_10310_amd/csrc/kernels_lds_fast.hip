@@ -110,8 +110,8 @@ __device__ __forceinline__ double2 offdiag_nb(const Nb (&nb)[QC], const double2 
 // max norm with factor theta (see control_table_kernel), so after a first
 // sweep delta0 -> delta1 the error obeys |delta1 - delta*| <= theta/(1 - theta)
 // |delta1 - delta0|, and every further sweep multiplies that bound by theta.
-// The kernels start from the quadratic extrapolation of the last three
-// converged deltas (the stage increment varies smoothly with t), measure
+// The kernels start from the polynomial extrapolation of the last converged
+// deltas (the stage increment varies smoothly with t), measure
 // |delta1 - delta0| and max|q| once per step over the workgroup, and run at
 // least two sweeps and otherwise the smallest number that brings the bound
 // below tol max|q|.  Every thread reads the same two maxima from LDS, so the
@@ -137,15 +137,42 @@ __device__ __forceinline__ int extra_sweeps(double theta, double ratio, double e
 }
 
 // Start of the stage iteration at step number `n` of the sweep direction:
-// w h D q at the first step, then the constant, linear and quadratic
-// extrapolations of the previous converged deltas d1 (latest), d2, d3.
-__device__ __forceinline__ double2 extrapolated_start(int n, double2 w, double2 hdq, double2 d1,
-                                                      double2 d2, double2 d3) {
+// w h D q at the first step, then the polynomial extrapolation of the
+// previous converged deltas d[0] (latest) .. d[4] of the highest order they
+// allow, up to 4 (the controls are piecewise quadratic in t, so delta is
+// smooth between B-spline knots).
+template <int H>
+__device__ __forceinline__ double2 extrapolated_start(int n, double2 w, double2 hdq,
+                                                      const double2 (&d)[H]) {
+  static_assert(H >= 2 && H <= 5, "history of 2 to 5 deltas");
   if (n == 0) return cmul(w, hdq);
-  if (n == 1) return d1;
-  if (n == 2) return make_double2(2.0 * d1.x - d2.x, 2.0 * d1.y - d2.y);
-  return make_double2(3.0 * (d1.x - d2.x) + d3.x, 3.0 * (d1.y - d2.y) + d3.y);
+  // coefficients (-1)^i C(m, i+1) of the order-(m-1) extrapolation, m = min(n, H)
+  const int m = n < H ? n : H;
+  const double c0 = (double)m;
+  const double c1 = m >= 2 ? -(double)(m * (m - 1) / 2) : 0.0;
+  double2 r = make_double2(c0 * d[0].x + c1 * d[1].x, c0 * d[0].y + c1 * d[1].y);
+  if constexpr (H >= 3) {
+    const double c2 = m >= 3 ? (double)(m * (m - 1) * (m - 2) / 6) : 0.0;
+    r.x += c2 * d[2].x;
+    r.y += c2 * d[2].y;
+  }
+  if constexpr (H >= 4) {
+    const double c3 = m >= 4 ? -(double)(m * (m - 1) * (m - 2) * (m - 3) / 24) : 0.0;
+    r.x += c3 * d[3].x;
+    r.y += c3 * d[3].y;
+  }
+  if constexpr (H >= 5) {
+    const double c4 = m >= 5 ? 1.0 : 0.0;
+    r.x += c4 * d[4].x;
+    r.y += c4 * d[4].y;
+  }
+  return r;
 }
+
+// Deltas kept for the extrapolation: five (order 4) except on 1024-thread
+// workgroups (one subsystem only, see lds_fast_ok), order 2.
+template <int BLOCK>
+constexpr int hist_len() { return BLOCK >= 1024 ? 3 : 5; }
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -220,7 +247,8 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
   const double h = S.h;
   const double2 *cq = ctab + S.ctab_off;
 
-  double2 qv[EPT], wv[EPT], hd[EPT], dn[EPT], d1[EPT], d2[EPT], d3[EPT];
+  constexpr int HL = hist_len<BLOCK>();
+  double2 qv[EPT], wv[EPT], hd[EPT], dn[EPT], dh[EPT][HL];
   Nb nb[EPT][QC];
   int ee[EPT];
   bool ok[EPT];
@@ -238,7 +266,9 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
 #pragma unroll
     for (int q = 0; q < QC; ++q) nb[k][q] = make_nb<false>(S, q, di, dj, ee[k]);
     qv[k] = ok[k] ? rho0[it.off + e] : make_double2(0.0, 0.0);
-    dn[k] = d1[k] = d2[k] = d3[k] = make_double2(0.0, 0.0);
+    dn[k] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < HL; ++i) dh[k][i] = make_double2(0.0, 0.0);
     if (states && ok[k]) states[it.st_off + e] = qv[k];
   }
   // Two LDS stage buffers; selected by value (not through a pointer array)
@@ -258,7 +288,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       hdq[k] = cmul(hd[k], qv[k]);
-      d0[k] = extrapolated_start(j, wv[k], hdq[k], d1[k], d2[k], d3[k]);
+      d0[k] = extrapolated_start(j, wv[k], hdq[k], dh[k]);
       if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qv[k], d0[k]);
     }
     __syncthreads();
@@ -326,9 +356,9 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       qv[k] = make_double2(qv[k].x + 2.0 * dn[k].x, qv[k].y + 2.0 * dn[k].y);
-      d3[k] = d2[k];
-      d2[k] = d1[k];
-      d1[k] = dn[k];
+#pragma unroll
+      for (int i = HL - 1; i > 0; --i) dh[k][i] = dh[k][i - 1];
+      dh[k][0] = dn[k];
       if (states && ok[k]) states[it.st_off + (int64_t)(j + 1) * N2 + ee[k]] = qv[k];
     }
     cb ^= 1;
@@ -359,7 +389,8 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
   const double2 *cq = ctab + S.ctab_off;
   const double2 *hist = states + it.st_off;
 
-  double2 qh[EPT], wv[EPT], hd[EPT], dn[EPT], qn[EPT], d1[EPT], d2[EPT], d3[EPT];
+  constexpr int HL = hist_len<BLOCK>();
+  double2 qh[EPT], wv[EPT], hd[EPT], dn[EPT], qn[EPT], dh[EPT][HL];
   Nb nb[EPT][QC];
   int ee[EPT];
   bool ok[EPT];
@@ -380,7 +411,9 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     qn[k] = ok[k] ? hist[(int64_t)NT * N2 + ee[k]] : make_double2(0.0, 0.0);
     const double2 t = ok[k] ? rhotar[it.off + ee[k]] : make_double2(0.0, 0.0);
     qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qn[k], t)) : cscale(-it.wterm, t);
-    dn[k] = d1[k] = d2[k] = d3[k] = make_double2(0.0, 0.0);
+    dn[k] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < HL; ++i) dh[k][i] = make_double2(0.0, 0.0);
   }
   double2 *const zb0 = zbuf, *const zb1 = zbuf + N2;
   int cb = 0;
@@ -397,7 +430,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       hdq[k] = cmul(hd[k], qh[k]);
-      d0[k] = extrapolated_start(NT - 1 - j, wv[k], hdq[k], d1[k], d2[k], d3[k]);
+      d0[k] = extrapolated_start(NT - 1 - j, wv[k], hdq[k], dh[k]);
       if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qh[k], d0[k]);
     }
     // Forward state q^j, consumed after the sweeps so that its load overlaps them.
@@ -497,20 +530,20 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     for (int k = 0; k < EPT; ++k) {
       qh[k] = make_double2(qh[k].x + 2.0 * dn[k].x, qh[k].y + 2.0 * dn[k].y);
       qn[k] = qj[k];
-      d3[k] = d2[k];
-      d2[k] = d1[k];
-      d1[k] = dn[k];
+#pragma unroll
+      for (int i = HL - 1; i > 0; --i) dh[k][i] = dh[k][i - 1];
+      dh[k][0] = dn[k];
     }
   }
   if (sweeps && tid == 0) sweeps[blockIdx.x] = nsw;
 }
 
 // Shapes with a specialised kernel: one entry per thread.  Workgroups of
-// 1024 threads leave 128 VGPRs per thread, which bounds the register-resident
-// stencil data there.
+// 1024 threads leave 128 VGPRs per thread, which holds the register-resident
+// stencil data of one subsystem only; larger ones use the generic kernels.
 bool lds_fast_ok(int block, int ept, int Q) {
   if (Q < 1 || Q > 4 || ept != 1) return false;
-  return block <= 512 || Q <= 3;
+  return block <= 512 || Q == 1;
 }
 
 template <int BLOCK, int EPT, int QC>
@@ -542,7 +575,7 @@ static int adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, int kind,
 #define LBX_FAST_SHAPES(X)                                                                  \
   X(64, 1, 1) X(64, 1, 2) X(64, 1, 3) X(64, 1, 4) X(128, 1, 1) X(128, 1, 2) X(128, 1, 3)    \
   X(128, 1, 4) X(256, 1, 1) X(256, 1, 2) X(256, 1, 3) X(256, 1, 4) X(512, 1, 1) X(512, 1, 2) \
-  X(512, 1, 3) X(512, 1, 4) X(1024, 1, 1) X(1024, 1, 2) X(1024, 1, 3)
+  X(512, 1, 3) X(512, 1, 4) X(1024, 1, 1)
 
 int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                             int Q, const double2 *ctab, const double2 *ttab, const double2 *rho0,

@@ -334,11 +334,11 @@ def test_gradient_is_bitwise_deterministic(lbx):
     assert np.array_equal(g1, g2)
 
 
-@pytest.mark.parametrize("NT", [1, 2, 3, 4, 9])
+@pytest.mark.parametrize("NT", [1, 2, 3, 4, 5, 6, 12])
 def test_lds_extrapolated_start_on_short_horizons(lbx, NT):
     # The specialised LDS kernels start each stage iteration from the
-    # constant, linear or quadratic extrapolation of the previous increments
-    # (first, second, third step onward); every start must converge.
+    # polynomial extrapolation of the previous increments, of order 0 to 4
+    # (second to sixth step onward); every start must converge.
     shapes = [(3, 3), (2, 2, 2)]
     systems, alphas, rho0, batch = _multi(list(enumerate(shapes, start=120)), NT=NT, T=0.2 * NT)
     say("lds extrapolated start", NT)
