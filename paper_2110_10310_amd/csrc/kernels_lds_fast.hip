@@ -138,13 +138,13 @@ __device__ __forceinline__ int extra_sweeps(double theta, double ratio, double e
 
 // Start of the stage iteration at step number `n` of the sweep direction:
 // w h D q at the first step, then the polynomial extrapolation of the
-// previous converged deltas d[0] (latest) .. d[4] of the highest order they
-// allow, up to 4 (the controls are piecewise quadratic in t, so delta is
-// smooth between B-spline knots).
+// previous converged deltas d[0] (latest) .. d[H-1] of the highest order
+// they allow, up to H - 1 (the controls are piecewise quadratic in t, so
+// delta is smooth between B-spline knots).
 template <int H>
 __device__ __forceinline__ double2 extrapolated_start(int n, double2 w, double2 hdq,
                                                       const double2 (&d)[H]) {
-  static_assert(H >= 2 && H <= 5, "history of 2 to 5 deltas");
+  static_assert(H >= 2 && H <= 6, "history of 2 to 6 deltas");
   if (n == 0) return cmul(w, hdq);
   // coefficients (-1)^i C(m, i+1) of the order-(m-1) extrapolation, m = min(n, H)
   const int m = n < H ? n : H;
@@ -162,17 +162,22 @@ __device__ __forceinline__ double2 extrapolated_start(int n, double2 w, double2 
     r.y += c3 * d[3].y;
   }
   if constexpr (H >= 5) {
-    const double c4 = m >= 5 ? 1.0 : 0.0;
+    const double c4 = m >= 5 ? (double)(m * (m - 1) * (m - 2) * (m - 3) * (m - 4) / 120) : 0.0;
     r.x += c4 * d[4].x;
     r.y += c4 * d[4].y;
+  }
+  if constexpr (H >= 6) {
+    const double c5 = m >= 6 ? -1.0 : 0.0;
+    r.x += c5 * d[5].x;
+    r.y += c5 * d[5].y;
   }
   return r;
 }
 
-// Deltas kept for the extrapolation: five (order 4) except on 1024-thread
+// Deltas kept for the extrapolation: six (order 5) except on 1024-thread
 // workgroups (one subsystem only, see lds_fast_ok), order 2.
 template <int BLOCK>
-constexpr int hist_len() { return BLOCK >= 1024 ? 3 : 5; }
+constexpr int hist_len() { return BLOCK >= 1024 ? 3 : 6; }
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
