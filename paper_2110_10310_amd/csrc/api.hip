@@ -107,7 +107,7 @@ struct BatchMeta {
   std::vector<int32_t> seg_state0;
   int64_t st_entries = 0;  // compact streamed entries
   int64_t st_blocks = 0;
-  int tile_sys = -1;       // single streamed system run by the row-tiled kernels
+  int tile_sys = -1;       // single streamed system run by the block-tiled kernels
   int tile_B = 0;
   // device copies (one allocation)
   void *dmem = nullptr;

@@ -1,16 +1,18 @@
 // LDS-resident persistent kernels specialised on the number of subsystems.
 //
-// Same algorithm and memory layout as the generic kernels of
-// kernels_lds.hip (one workgroup per state, stage iterate in two LDS
-// buffers, delta-form fixed-point sweeps), for systems with few subsystems
-// and at most four (entry, subsystem) pairs per thread.  Everything that does
-// not change over the time loop is computed once per entry and kept in
-// registers: the ladder weights sqrt(n), sqrt(n+1), sqrt(m), sqrt(m+1) with
-// the boundary cases folded in as zeros, the decay-jump weight, and the LDS
-// offsets of every neighbour (the entry itself where a neighbour does not
-// exist, with a zero weight).  A sweep is then LDS reads and FP64 FMAs only;
-// the per-step control values come through scalar loads.  The adjoint
-// reduces its per-step gradient integrands over 16-lane DPP rows.
+// Same memory layout as the generic kernels of kernels_lds.hip (one
+// workgroup per state, stage iterate in two LDS buffers, delta-form
+// fixed-point sweeps), for systems of one to four subsystems with one entry
+// per thread.  Everything that does not change over the time loop is
+// computed once per entry and kept in registers: the ladder weights sqrt(n),
+// sqrt(n+1), sqrt(m), sqrt(m+1) with the boundary cases folded in as zeros,
+// the decay-jump weight, and the LDS offsets of every neighbour (the entry
+// itself where a neighbour does not exist, with a zero weight).  A sweep is
+// then LDS reads and FP64 FMAs only.  Unlike the generic kernels they start
+// each stage solve from an extrapolation of earlier steps and stop on an
+// a-posteriori bound (see extra_sweeps); the per-step controls come through a
+// vector load one step ahead.  The adjoint reduces its per-step gradient
+// integrands over 16-lane DPP rows.
 #include <hip/hip_runtime.h>
 
 #include "lbx_host.hpp"

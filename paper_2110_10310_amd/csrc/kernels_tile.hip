@@ -1,17 +1,15 @@
-// Row-tiled streaming kernels for large systems of equal-level subsystems.
-//
 // Block-tiled streaming kernels for large systems of equal-level subsystems
-// (the eight-qutrit ring is the design case).  Used for lindblad_apply and
-// for the stage-solve sweeps of a single streamed system when every
-// subsystem has the same number of levels NL and the shape is one of
-// LBX_TILE_SHAPES.  See tile_kernel for the tiling.
+// (the eight-qutrit ring is the design case): lindblad_apply, the stage-solve
+// sweeps and the gradient integrands of a single streamed system whose
+// subsystems all have NL levels, in one of the LBX_TILE_SHAPES (tile_kernel,
+// tile_grad_kernel), and the multi-pass variant (pass_kernel, LB_OPT_TILE 2).
 #include <hip/hip_runtime.h>
 
 #include "lbx_host.hpp"
 
 namespace lbx {
 
-constexpr int TILE_BLOCK = 512;
+constexpr int TILE_BLOCK = 512;  // threads of the multi-pass kernels
 
 namespace {
 

@@ -162,11 +162,12 @@ int launch_grad_contract(const lb_plan *p, const double *gstep, const double *al
 // returns false when the state does not fit the LDS-resident kernels.
 bool lds_shape(int64_t n2, int *block, int *ept);
 
-// Row-tiled streaming kernels (kernels_tile.hip).  tile_nl returns the common
-// level count of an eligible system (equal-level subsystems, N = NL^Q of
-// 512..8192) or 0.
+// Block-tiled streaming kernels (kernels_tile.hip).  tile_nl returns the
+// common level count of an eligible system (equal-level subsystems whose
+// (NL, Q) has an instantiated block shape or, with LB_OPT_TILE 2, a pass
+// plan) or 0.
 int tile_nl(const lb_plan *p, int sys);
-int tile_ki(const lb_plan *p, int sys);  // internal digits of the block, 0 if not eligible
+int tile_ki(const lb_plan *p, int sys);  // block shape 10*KR + KC, 0 if not eligible
 // mode 0: y = M x (alpha, t); mode 1: sweep (q + delta); mode 2: last sweep (q + 2 delta),
 // with the controls of step j from ctab.
 // Two-pass split kernels (kernels_tile.hip): number of low subsystems of the

@@ -410,7 +410,7 @@ def test_config2_full_length_against_stored_oracle(lbx):
     assert np.max(np.abs(g - gold["grad"])) <= GRAD_TOL * np.max(np.abs(gold["grad"]))
 
 
-# --------------------------------------------------------------- row-tiled kernels
+# --------------------------------------------------------------- block-tiled kernels
 
 TILE_SHAPES = [(2,) * 9, (3,) * 6, (4,) * 5]
 
