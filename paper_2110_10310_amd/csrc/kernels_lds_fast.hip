@@ -344,18 +344,36 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
     const int K = extra_sweeps(sc.theta, sc.ratio, hi_upper(he), hi_lower(hq), tol);
     const int rest = K > 1 ? K - 1 : 0;
     nsw += 2 + rest;
-    for (int kk = 0; kk < rest; ++kk) {
+    // Further sweeps: the iterate for the third is written (and the barrier
+    // taken) before the count is known, so that the count's latency is
+    // hidden; it is unused when two sweeps suffice.  The usual counts are
+    // straight-line code.
+    auto sweep_more = [&]() {
       double2 *dst = (cb ? zb0 : zb1);
 #pragma unroll
       for (int k = 0; k < EPT; ++k)
         if (ok[k]) dst[ee[k]] = cadd(qv[k], dn[k]);
       __syncthreads();
       cb ^= 1;
+    };
+    auto sweep_math = [&]() {
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const double2 acc = offdiag_nb<false, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
+      }
+    };
+    sweep_more();
+    if (rest >= 1) {
+      sweep_math();
+      if (rest >= 2) {
+        sweep_more();
+        sweep_math();
+        for (int kk = 2; kk < rest; ++kk) {
+          sweep_more();
+          sweep_math();
+        }
       }
     }
     sc = unpack_controls<QC>(cnext, dq);
@@ -489,18 +507,36 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     const int K = extra_sweeps(sc.theta, sc.ratio, hi_upper(he), hi_lower(hq), tol);
     const int rest = K > 1 ? K - 1 : 0;
     nsw += 2 + rest;
-    for (int kk = 0; kk < rest; ++kk) {
+    // Further sweeps: the iterate for the third is written (and the barrier
+    // taken) before the count is known, so that the count's latency is
+    // hidden; it is unused when two sweeps suffice.  The usual counts are
+    // straight-line code.
+    auto sweep_more = [&]() {
       double2 *dst = (cb ? zb0 : zb1);
 #pragma unroll
       for (int k = 0; k < EPT; ++k)
         if (ok[k]) dst[ee[k]] = cadd(qh[k], dn[k]);
       __syncthreads();
       cb ^= 1;
+    };
+    auto sweep_math = [&]() {
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const double2 acc = offdiag_nb<true, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
+      }
+    };
+    sweep_more();
+    if (rest >= 1) {
+      sweep_math();
+      if (rest >= 2) {
+        sweep_more();
+        sweep_math();
+        for (int kk = 2; kk < rest; ++kk) {
+          sweep_more();
+          sweep_math();
+        }
       }
     }
     // Gradient integrands (see grad_term in lbx_device.hpp) need zh at neighbours.
