@@ -26,6 +26,19 @@ __device__ __forceinline__ double sqrt_small(int k) {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
+// Value of lane l (uniform l) of a double / int64.
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int64_t lane_i64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double uniform(double v) {
   const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
@@ -69,11 +82,13 @@ __device__ __forceinline__ void cmac(double2 &acc, double2 c, double2 v) {
 // so every neighbour along an internal digit (row or column ladder shift, or
 // decay jump of a subsystem internal in both) is an LDS read.  Along the
 // external digits every neighbour of the block is the block shifted by a
-// constant offset, with a coefficient that depends only on the fixed digits:
-// those terms are applied one direction at a time for all entries of a
-// thread (a direction whose neighbour does not exist for this block is
-// skipped), so that a thread has one coalesced load per entry in flight per
-// direction and the neighbour values need no per-entry weights.  Jumps of a
+// constant offset, with a coefficient that depends only on the fixed digits.
+// Each wavefront tabulates those directions, one per lane (existence,
+// coefficient, shift), and walks the existing ones from the ballot mask with
+// readlane, G directions at a time: G coalesced loads per entry of a thread
+// are in flight together, the neighbour values need no per-entry weights,
+// and no direction that does not exist for the block is loaded.  The
+// block's own loads are all issued before its LDS stores.  Jumps of a
 // subsystem with one internal and one external digit are per-entry global
 // loads.  Blocks are remapped so that each XCD (blocks are dealt to the 8
 // XCDs round-robin) walks a contiguous band of block rows.
@@ -84,11 +99,17 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(
     const double2 *__restrict__ ctab, int jstep, const double2 *__restrict__ zin,
     const double2 *__restrict__ qin, double2 *__restrict__ out, double2 *__restrict__ zout) {
   extern __shared__ double2 tile[];
-  __shared__ double2 dqs[QC];
   constexpr int ER = QC - KR, EC = QC - KC;  // external row / column digits
   constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
   constexpr int TT = TR * TC;
   constexpr int EPT = (TT + BLOCK - 1) / BLOCK;
+  // External direction slots: two ladder shifts per external digit and one
+  // jump per subsystem external in both (at most 40 for 8 subsystems), one
+  // per lane; the existing ones are applied G at a time.
+  constexpr int ND = 2 * ER + 2 * EC + (ER < EC ? ER : EC);
+  static_assert(ND < 64, "one lane per direction slot, and a lane without one");
+  constexpr int G = EPT >= 8 ? 1 : EPT >= 4 ? 2 : 4;
+  constexpr bool TABLE = EPT > 1 && EPT < 12;
   const SysDev &S = sysv[sys];
   const int N = S.N;
   const int NBR = N / TR, NBC = N / TC;
@@ -97,9 +118,6 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(
   const int64_t per = (nblocks + 7) / 8;
   const int64_t lb = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (lb >= nblocks) return;
-  if (tid < QC)
-    dqs[tid] = ctab ? ctab[S.ctab_off + (int64_t)jstep * QC + tid]
-                    : control_value(S, alpha, carrier + S.carrier_off, tid, t);
   const int64_t b = lb / ((int64_t)NBR * NBC);
   const int rem = (int)(lb - b * NBR * NBC);
   const int bi = rem / NBC, bj = rem - (rem / NBC) * NBC;
@@ -112,11 +130,6 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(
     const int a = ff / TC, c = ff - (ff / TC) * TC;
     return base + (int64_t)a * N + c;
   };
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int f = tid + k * BLOCK;
-    if (f < TT) tile[f] = X[off_of(k)];
-  }
   // fixed (external) digits of the row and column index
   int ne[ER > 0 ? ER : 1], me[EC > 0 ? EC : 1];
   {
@@ -133,52 +146,147 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(
       rj /= NL;
     }
   }
-  const double h = S.h;
-  const double *Es = Etab + S.tab_off;
-  __syncthreads();
+  // Every wavefront forms the controls, lane q holding d_q: the apply (MODE
+  // 0) evaluates them before the block's loads, so that no loaded value is
+  // live across the evaluation; the sweeps read them from the control table.
+  const int lane = tid & 63;
+  double2 dv = make_double2(0.0, 0.0);
+  if (MODE == 0 && lane < QC) dv = control_value(S, alpha, carrier + S.carrier_off, lane, t);
+  int64_t offs[EPT];
+  double2 tv[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {  // (past the block's end: entry 0, unused)
+    offs[k] = off_of(k);
+    tv[k] = X[offs[k]];
+  }
+  if (MODE != 0 && lane < QC) dv = ctab[S.ctab_off + (int64_t)jstep * QC + lane];
   double da[QC], db[QC];
 #pragma unroll
   for (int q = 0; q < QC; ++q) {
-    da[q] = uniform(dqs[q].x);
-    db[q] = uniform(dqs[q].y);
+    da[q] = lane_d(dv.x, q);
+    db[q] = lane_d(dv.y, q);
   }
-  // External directions first: existence and coefficient are uniform per
-  // block; each direction is one coalesced load per entry of the thread.
+  // While the block loads, every wavefront builds its table of external
+  // directions (blocks of 2 to 11 entries per thread): lane d takes slot
+  // d (row digit d / 2, column digit (d - 2 ER) / 2, then jumps) and decides
+  // whether its neighbour exists for this block, with its coefficient and
+  // shift.
+  bool ex = false;
+  double2 cf = make_double2(0.0, 0.0);
+  int64_t sh = 0;
+  if constexpr (TABLE) {
+    if (lane < ND) {
+      const int d = lane;
+      const int kind = d < 2 * ER ? 0 : d < 2 * ER + 2 * EC ? 1 : 2;
+      const int q = kind == 0 ? d >> 1 : kind == 1 ? (d - 2 * ER) >> 1 : d - 2 * ER - 2 * EC;
+      const bool plus = kind == 2 || !(d & 1);
+      int n = 0, m = 0;
+      int64_t st = 0;
+      double g1 = 0.0, a = 0.0, bq = 0.0;
+#pragma unroll
+      for (int qq = 0; qq < QC; ++qq)
+        if (q == qq) {
+          st = S.stride[qq];
+          g1 = S.g1[qq];
+          a = da[qq];
+          bq = db[qq];
+        }
+#pragma unroll
+      for (int qq = 0; qq < ER; ++qq)
+        if (q == qq) n = ne[qq];
+#pragma unroll
+      for (int qq = 0; qq < EC; ++qq)
+        if (q == qq) m = me[qq];
+      if (kind == 0) {
+        ex = plus ? n + 1 < NL : n > 0;
+        cf = plus ? ctl_coef<DIR_RP, ADJ>(a, bq, sqrt_small<NL>(n + 1))
+                  : ctl_coef<DIR_RM, ADJ>(a, bq, sqrt_small<NL>(n));
+        sh = plus ? st * N : -st * N;
+      } else if (kind == 1) {
+        ex = plus ? m + 1 < NL : m > 0;
+        cf = plus ? ctl_coef<DIR_CP, ADJ>(a, bq, sqrt_small<NL>(m + 1))
+                  : ctl_coef<DIR_CM, ADJ>(a, bq, sqrt_small<NL>(m));
+        sh = plus ? st : -st;
+      } else {
+        ex = !ADJ ? (n + 1 < NL && m + 1 < NL) : (n > 0 && m > 0);
+        cf = make_double2(!ADJ ? g1 * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
+                               : g1 * sqrt_small<NL>(n) * sqrt_small<NL>(m),
+                          0.0);
+        sh = !ADJ ? st * N + st : -(st * N + st);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int f = tid + k * BLOCK;
+    if (f < TT) tile[f] = tv[k];
+  }
+  const double h = S.h;
+  const double *Es = Etab + S.tab_off;
+  // External directions first (they do not read the LDS block), G at a time:
+  // the existing slots are taken in order from the ballot mask, a missing
+  // G-th one is the last lane (no slot: weight zero, shift zero); one
+  // coalesced load per entry of the thread and direction, G x EPT in flight.
   double2 acc[EPT];
 #pragma unroll
   for (int k = 0; k < EPT; ++k) acc[k] = make_double2(0.0, 0.0);
-  auto direction = [&](double2 cf, int64_t shift) {
-    double2 v[EPT];
+  if constexpr (TABLE) {
+    uint64_t emask = __ballot(ex);
+    while (emask) {
+      int dl[G];
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) v[k] = X[off_of(k) + shift];
+      for (int g = 0; g < G; ++g) {
+        dl[g] = emask ? (int)__builtin_ctzll(emask) : 63;
+        emask &= emask - 1;
+      }
+      double2 cg[G], v[G][EPT];
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) cmac(acc[k], cf, v[k]);
-  };
+      for (int g = 0; g < G; ++g) {
+        const int64_t s = lane_i64(sh, dl[g]);
 #pragma unroll
-  for (int q = 0; q < ER; ++q) {
-    const int n = ne[q];
-    const int64_t sN = (int64_t)S.stride[q] * N;
-    if (n + 1 < NL) direction(ctl_coef<DIR_RP, ADJ>(da[q], db[q], sqrt_small<NL>(n + 1)), sN);
-    if (n > 0) direction(ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), -sN);
-  }
+        for (int k = 0; k < EPT; ++k) v[g][k] = X[offs[k] + s];
+      }
 #pragma unroll
-  for (int q = 0; q < EC; ++q) {
-    const int m = me[q];
-    const int64_t s1 = S.stride[q];
-    if (m + 1 < NL) direction(ctl_coef<DIR_CP, ADJ>(da[q], db[q], sqrt_small<NL>(m + 1)), s1);
-    if (m > 0) direction(ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), -s1);
-  }
+      for (int g = 0; g < G; ++g) cg[g] = make_double2(lane_d(cf.x, dl[g]), lane_d(cf.y, dl[g]));
 #pragma unroll
-  for (int q = 0; q < (ER < EC ? ER : EC); ++q) {
-    const int n = ne[q], m = me[q];
-    const bool jr = !ADJ ? (n + 1 < NL && m + 1 < NL) : (n > 0 && m > 0);
-    if (jr) {
-      const double cj = !ADJ ? S.g1[q] * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
-                             : S.g1[q] * sqrt_small<NL>(n) * sqrt_small<NL>(m);
-      const int64_t sj = (int64_t)S.stride[q] * N + S.stride[q];
-      direction(make_double2(cj, 0.0), !ADJ ? sj : -sj);
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) cmac(acc[k], cg[g], v[g][k]);
+    }
+  } else {
+    // One entry per thread, or the largest blocks: the directions one at a
+    // time under uniform branches (measured faster there than the table).
+    auto direction = [&](double2 c, int64_t shift) {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) cmac(acc[k], c, X[offs[k] + shift]);
+    };
+#pragma unroll
+    for (int q = 0; q < ER; ++q) {
+      const int n = ne[q];
+      const int64_t sN = (int64_t)S.stride[q] * N;
+      if (n + 1 < NL) direction(ctl_coef<DIR_RP, ADJ>(da[q], db[q], sqrt_small<NL>(n + 1)), sN);
+      if (n > 0) direction(ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), -sN);
+    }
+#pragma unroll
+    for (int q = 0; q < EC; ++q) {
+      const int m = me[q];
+      const int64_t s1 = S.stride[q];
+      if (m + 1 < NL) direction(ctl_coef<DIR_CP, ADJ>(da[q], db[q], sqrt_small<NL>(m + 1)), s1);
+      if (m > 0) direction(ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), -s1);
+    }
+#pragma unroll
+    for (int q = 0; q < (ER < EC ? ER : EC); ++q) {
+      const int n = ne[q], m = me[q];
+      const bool jr = !ADJ ? (n + 1 < NL && m + 1 < NL) : (n > 0 && m > 0);
+      if (jr) {
+        const double cj = !ADJ ? S.g1[q] * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
+                               : S.g1[q] * sqrt_small<NL>(n) * sqrt_small<NL>(m);
+        const int64_t sj = (int64_t)S.stride[q] * N + S.stride[q];
+        direction(make_double2(cj, 0.0), !ADJ ? sj : -sj);
+      }
     }
   }
+  __syncthreads();
   // Internal terms (LDS), the diagonal part and the output, entry by entry.
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
@@ -235,7 +343,7 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(
         ac.y += cj * v.y;
       } else if (q >= ER || q >= EC) {  // one digit internal: a per-entry global load
         const int64_t sj = (int64_t)st * N + st;
-        const double2 v = X[off_of(k) + (!jr ? 0 : !ADJ ? sj : -sj)];
+        const double2 v = X[offs[k] + (!jr ? 0 : !ADJ ? sj : -sj)];
         ac.x += cj * v.x;
         ac.y += cj * v.y;
       }
@@ -243,7 +351,7 @@ __global__ __launch_bounds__(BLOCK) void tile_kernel(
     const int i = bi * TR + a, j = bj * TC + c;
     const double dE = Es[i] - Es[j];
     const double2 D = diag_coef(gam, dE, ADJ);
-    const int64_t e = b * N2 + off_of(k);
+    const int64_t e = b * N2 + offs[k];
     if (MODE == 0) {
       out[e] = cadd(ac, cmul(D, tile[f]));
     } else {
@@ -303,9 +411,10 @@ __global__ __launch_bounds__(BLOCK) void tile_grad_kernel(
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int f = tid + k * BLOCK;
-    const int64_t e = off_of(k);
-    if (f < TT) tile[f] = Z[e];
+    const int64_t e = off_of(k);  // (past the block's end: entry 0, unused)
+    const double2 v = Z[e];
     const double2 a = q0[b * N2 + e], c = q1[b * N2 + e];
+    if (f < TT) tile[f] = v;
     z[k] = f < TT ? make_double2(0.5 * (a.x + c.x), 0.5 * (a.y + c.y)) : make_double2(0.0, 0.0);
   }
   int ne[ER > 0 ? ER : 1], me[EC > 0 ? EC : 1];
@@ -495,10 +604,15 @@ __global__ __launch_bounds__(TILE_BLOCK) void pass_kernel(
     const int a = ff / TCn, c = ff - (ff / TCn) * TCn;
     return (int64_t)(ibase + rowoff(a)) * N + jbase + coloff(c);
   };
+  {
+    double2 tv[EPT];  // all loads in flight before the first LDS store
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int f = tid + k * TILE_BLOCK;
-    if (f < TT) tile[f] = X[off_of(k)];
+    for (int k = 0; k < EPT; ++k) tv[k] = X[off_of(k)];  // (past the end: entry 0, unused)
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int f = tid + k * TILE_BLOCK;
+      if (f < TT) tile[f] = tv[k];
+    }
   }
   const double h = S.h;
   const double *Es = Etab + S.tab_off;
@@ -778,6 +892,7 @@ int launch_tile(const lb_plan *p, int sys, int B, int mode, bool adj, const doub
   if (B == 0) return LB_OK;
   if (p->tile == 2 && split_kl(p, sys))
     return launch_split(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, zout, st);
+  if (mode != 0 && !ctab) return fail(LB_EINVAL, "stage sweeps need the control table");
   const SysDev &S = p->sys[sys];
   const int nl = tile_nl(p, sys), k = tile_ki(p, sys);
 #define X(A, Bq, R, C, T) \

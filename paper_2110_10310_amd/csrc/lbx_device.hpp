@@ -178,20 +178,26 @@ __device__ __forceinline__ double bspline2(double x) {
 }
 
 // d_q(t) of eq. (rotctrl) in rad/ns; alpha points at this system's [Q][Ns][Nf][2].
+// Only splines whose support holds t contribute (at most three, found from
+// t / dtau with one spline of margin on each side); each carrier's phase
+// factor multiplies the spline sum of its coefficients.
 __device__ inline double2 control_value(const SysDev &S, const double *alpha, const double *carrier,
                                         int q, double t) {
+  const double u = t / S.dtau;
+  const int fu = (int)floor(u);
+  const int s0 = max(fu - 1, 0), s1 = min(fu + 3, S.Ns - 1);
   double re = 0.0, im = 0.0;
-  for (int s = 0; s < S.Ns; ++s) {
-    const double B = bspline2(t / S.dtau - (double)s + 0.5);
-    if (B == 0.0) continue;
-    for (int f = 0; f < S.Nf; ++f) {
-      const double ar = alpha[((q * S.Ns + s) * S.Nf + f) * 2 + 0];
-      const double ai = alpha[((q * S.Ns + s) * S.Nf + f) * 2 + 1];
-      double sn, cs;
-      sincos(TWO_PI * carrier[q * S.Nf + f] * t, &sn, &cs);
-      re += B * (ar * cs - ai * sn);
-      im += B * (ar * sn + ai * cs);
+  for (int f = 0; f < S.Nf; ++f) {
+    double ar = 0.0, ai = 0.0;
+    for (int s = s0; s <= s1; ++s) {
+      const double B = bspline2(u - (double)s + 0.5);
+      ar += B * alpha[((q * S.Ns + s) * S.Nf + f) * 2 + 0];
+      ai += B * alpha[((q * S.Ns + s) * S.Nf + f) * 2 + 1];
     }
+    double sn, cs;
+    sincos(TWO_PI * carrier[q * S.Nf + f] * t, &sn, &cs);
+    re += ar * cs - ai * sn;
+    im += ar * sn + ai * cs;
   }
   return make_double2(TWO_PI * re, TWO_PI * im);
 }
