@@ -88,10 +88,6 @@ extern "C" {
 #define LB_OPT_GRAPH 5     /* > 0: streamed time loops are captured as HIP graphs of this
                               many steps and replayed (one graph launch per chunk);
                               0 (default): kernels are launched directly */
-#define LB_OPT_LDS_DPP 6   /* 1 (default): LDS-resident kernels of systems with N = 16 take
-                              column neighbours from neighbouring lanes (DPP) where a
-                              kernel for the system's strides exists; 0: from LDS.
-                              Results are identical bit for bit. */
 
 /* Kernel families timed by LB_OPT_PROFILE (lb_profile_read). */
 #define LB_KERNEL_LDS_FORWARD 0  /* persistent forward time loop, LDS-resident */

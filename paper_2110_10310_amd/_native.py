@@ -32,7 +32,6 @@ LB_OPT_PROFILE = 2
 LB_OPT_TILE = 3
 LB_OPT_TILE_KI = 4
 LB_OPT_GRAPH = 5
-LB_OPT_LDS_DPP = 6
 
 LB_KERNEL_LDS_FORWARD = 0
 LB_KERNEL_LDS_ADJOINT = 1

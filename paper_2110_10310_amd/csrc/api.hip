@@ -85,9 +85,8 @@ namespace {
 
 struct LdsClass {
   int block, ept;
-  int qc;       // > 0: specialised kernel for qc subsystems; 0: generic kernel
-  uint32_t cs;  // column-stride code of the DPP variant (lds_col_code), or 0
-  int i0, i1;   // item range
+  int qc;      // > 0: specialised kernel for qc subsystems; 0: generic kernel
+  int i0, i1;  // item range
 };
 
 struct BatchMeta {
@@ -196,18 +195,17 @@ int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int pat
   m->total_states = st;
   // LDS items grouped by kernel class, systems contiguous within a class.
   const int NT = p->NT;
-  std::map<std::tuple<int, int, int, uint32_t>, std::vector<int>> cls;
+  std::map<std::tuple<int, int, int>, std::vector<int>> cls;
   for (int s = 0; s < nsys; ++s)
     if (m->path[s] == 1) {
       int blk, ept;
       lds_shape(p->sys[s].N2, &blk, &ept);
       const int qc = lds_fast_ok(blk, ept, p->sys[s].Q) ? p->sys[s].Q : 0;
-      const uint32_t cs = qc > 0 ? lds_col_code(p->sys[s], blk, ept) : 0;
-      cls[std::make_tuple(blk, ept, qc, cs)].push_back(s);
+      cls[std::make_tuple(blk, ept, qc)].push_back(s);
     }
   for (auto &kv : cls) {
     LdsClass c{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-               std::get<3>(kv.first), (int)m->items.size(), 0};
+               (int)m->items.size(), 0};
     for (int s : kv.second) {
       const SysDev &S = p->sys[s];
       m->lds_sys.push_back(s);
@@ -720,11 +718,6 @@ extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
     p->profile = value != 0.0;
     return LB_OK;
   }
-  if (option == LB_OPT_LDS_DPP) {
-    if (value != 0 && value != 1) return fail(LB_EINVAL, "LB_OPT_LDS_DPP must be 0 or 1");
-    p->lds_dpp = (int)value;
-    return LB_OK;
-  }
   if (option == LB_OPT_SOLVE_TOL) {
     if (!(value > 0.0 && value < 1.0)) return fail(LB_EINVAL, "LB_OPT_SOLVE_TOL must be in (0, 1)");
     p->tol = value;
@@ -869,8 +862,8 @@ static int run_forward(const lb_plan *p, const BatchMeta &m, const Layout &L, ch
   for (const auto &c : m.classes) {
     ProfScope ps(p, LB_KERNEL_LDS_FORWARD, st);
     rc = c.qc > 0 ? launch_lds_forward_fast(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc,
-                                            p->lds_dpp ? c.cs : 0u, ctab, ttab, rho0, rhoT, hist,
-                                            slots ? slots + c.i0 : nullptr, st)
+                                            ctab, ttab, rho0, rhoT, hist, slots ? slots + c.i0 : nullptr,
+                                            st)
                   : launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab,
                                        rho0, rhoT, hist, st);
     if (rc) return rc;
@@ -977,8 +970,7 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
     int64_t *slots = lds_sweep_slots(p, *m);
     for (const auto &c : m->classes) {
       ProfScope ps(p, LB_KERNEL_LDS_ADJOINT, st);
-      rc = c.qc > 0 ? launch_lds_adjoint_fast(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc,
-                                              p->lds_dpp ? c.cs : 0u, kind,
+      rc = c.qc > 0 ? launch_lds_adjoint_fast(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, kind,
                                               ctab, (const double2 *)(w + L.ttab),
                                               (const double2 *)rhotar, hist, gpart,
                                               slots ? slots + c.i0 : nullptr, st)

@@ -104,62 +104,6 @@ __device__ __forceinline__ double2 offdiag_nb(const Nb (&nb)[QC], const double2 
   return acc;
 }
 
-// Column neighbours through DPP.  When N = 16 a matrix row is one row of 16
-// lanes (entry (i, j) in lane j of its row), so the column neighbour j +/- s
-// of subsystem q (column stride s) is lane j +/- s of the same row: a DPP row
-// shift of the thread's own current iterate, with no LDS read.  Lanes whose
-// source falls outside the row read zero, and their weight is zero anyway.
-// The jump neighbour (i + e, j + e) is the row neighbour (i + e, j) of lane
-// j + s (forward; the adjoint's (i - e, j - e) likewise), so it is a DPP
-// shift of the row neighbour read from LDS.  CS packs the column strides,
-// four bits per subsystem (subsystem q in bits 4q .. 4q + 3).
-template <int CTRL>
-__device__ __forceinline__ double2 dpp_move(double2 v) {
-  return make_double2(dpp_row_shift<CTRL>(v.x), dpp_row_shift<CTRL>(v.y));
-}
-
-template <bool ADJ, int QC, uint32_t CS, int Q = 0>
-__device__ __forceinline__ void offdiag_dpp_acc(double2 &acc, const Nb (&nb)[QC],
-                                                const double2 (&dq)[QC], const double2 *x,
-                                                double2 z) {
-  if constexpr (Q < QC) {
-    constexpr int st = (CS >> (4 * Q)) & 15;
-    static_assert(st >= 1 && st <= 15, "column stride within a row of 16 lanes");
-    const Nb &b = nb[Q];
-    const double2 xrp = x[b.orp], xrm = x[b.orm];
-    const double2 xcp = dpp_move<0x100 + st>(z);  // lane j + st
-    const double2 xcm = dpp_move<0x110 + st>(z);  // lane j - st
-    const double2 U = make_double2(b.crp * xrp.x - b.ccm * xcm.x, b.crp * xrp.y - b.ccm * xcm.y);
-    const double2 V = make_double2(b.crm * xrm.x - b.ccp * xcp.x, b.crm * xrm.y - b.ccp * xcp.y);
-    const double2 Sm = cadd(U, V), Dv = csub(U, V);
-    const double a = dq[Q].x, bb = dq[Q].y;
-    const double cr = a * Sm.y + bb * Dv.x;
-    const double ci = -a * Sm.x + bb * Dv.y;
-    const double2 xj = !ADJ ? dpp_move<0x100 + st>(xrp) : dpp_move<0x110 + st>(xrm);
-    if (!ADJ) {
-      acc.x += cr + b.cj * xj.x;
-      acc.y += ci + b.cj * xj.y;
-    } else {
-      acc.x += -cr + b.cj * xj.x;
-      acc.y += -ci + b.cj * xj.y;
-    }
-    offdiag_dpp_acc<ADJ, QC, CS, Q + 1>(acc, nb, dq, x, z);
-  }
-}
-
-// O x at one entry, x the LDS iterate and z this thread's own entry of it.
-template <bool ADJ, int QC, uint32_t CS>
-__device__ __forceinline__ double2 offdiag_sel(const Nb (&nb)[QC], const double2 (&dq)[QC],
-                                               const double2 *x, double2 z) {
-  if constexpr (CS == 0) {
-    return offdiag_nb<ADJ, QC>(nb, dq, x);
-  } else {
-    double2 acc = make_double2(0.0, 0.0);
-    offdiag_dpp_acc<ADJ, QC, CS>(acc, nb, dq, x, z);
-    return acc;
-  }
-}
-
 }  // namespace
 
 // Stage solve with an extrapolated start and an a-posteriori sweep count.
@@ -292,7 +236,7 @@ __device__ __forceinline__ StepConst unpack_controls(double v, double2 (&dq)[QC]
   return {readlane_d(v, 2 * QC), readlane_d(v, 2 * QC + 1)};
 }
 
-template <int BLOCK, int EPT, int QC, uint32_t CS>
+template <int BLOCK, int EPT, int QC>
 __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
     const SysDev *__restrict__ sysv, const LdsItem *__restrict__ items,
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
@@ -347,13 +291,12 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
   StepConst sc = unpack_controls<QC>(load_controls<QC>(cq, tq, 0, NT, lane), dq);
   double cnext = load_controls<QC>(cq, tq, 1, NT, lane);
   for (int j = 0; j < NT; ++j) {
-    double2 hdq[EPT], d0[EPT], zr[EPT];  // zr: this thread's entries of the iterate
+    double2 hdq[EPT], d0[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       hdq[k] = cmul(hd[k], qv[k]);
       d0[k] = extrapolated_start(j, wv[k], hdq[k], dh[k]);
-      zr[k] = cadd(qv[k], d0[k]);
-      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = zr[k];
+      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qv[k], d0[k]);
     }
     __syncthreads();
     // first sweep, with the change it makes and max|q|
@@ -362,7 +305,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
-        const double2 acc = offdiag_sel<false, QC, CS>(nb[k], dq, src, zr[k]);
+        const double2 acc = offdiag_nb<false, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
         if (ok[k]) {
           e1 = fmax(e1, fabs(dn[k].x - d0[k].x) + fabs(dn[k].y - d0[k].y));
@@ -377,10 +320,8 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
       }
       double2 *dst = (cb ? zb0 : zb1);
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        zr[k] = cadd(qv[k], dn[k]);
-        if (ok[k]) dst[ee[k]] = zr[k];
-      }
+      for (int k = 0; k < EPT; ++k)
+        if (ok[k]) dst[ee[k]] = cadd(qv[k], dn[k]);
       __syncthreads();
       cb ^= 1;
     }
@@ -390,7 +331,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
-        const double2 acc = offdiag_sel<false, QC, CS>(nb[k], dq, src, zr[k]);
+        const double2 acc = offdiag_nb<false, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
       }
     }
@@ -410,10 +351,8 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
     auto sweep_more = [&]() {
       double2 *dst = (cb ? zb0 : zb1);
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        zr[k] = cadd(qv[k], dn[k]);
-        if (ok[k]) dst[ee[k]] = zr[k];
-      }
+      for (int k = 0; k < EPT; ++k)
+        if (ok[k]) dst[ee[k]] = cadd(qv[k], dn[k]);
       __syncthreads();
       cb ^= 1;
     };
@@ -421,7 +360,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
-        const double2 acc = offdiag_sel<false, QC, CS>(nb[k], dq, src, zr[k]);
+        const double2 acc = offdiag_nb<false, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
       }
     };
@@ -455,7 +394,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
   if (sweeps && tid == 0) sweeps[blockIdx.x] = nsw;
 }
 
-template <int BLOCK, int EPT, int QC, uint32_t CS>
+template <int BLOCK, int EPT, int QC>
 __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     const SysDev *__restrict__ sysv, const LdsItem *__restrict__ items,
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
@@ -512,13 +451,12 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
   for (int j = NT - 1; j >= 0; --j) {
     const double cnext = load_controls<QC>(cq, tq, j > 0 ? j - 1 : 0, NT, lane);
     // (I - h M^+) zh = qh^{j+1} (App. B eq. linsystem_adjoint), zh = qh + delta.
-    double2 hdq[EPT], d0[EPT], zr[EPT];  // zr: this thread's entries of the iterate
+    double2 hdq[EPT], d0[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       hdq[k] = cmul(hd[k], qh[k]);
       d0[k] = extrapolated_start(NT - 1 - j, wv[k], hdq[k], dh[k]);
-      zr[k] = cadd(qh[k], d0[k]);
-      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = zr[k];
+      if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qh[k], d0[k]);
     }
     // Forward state q^j, consumed after the sweeps so that its load overlaps them.
     double2 qj[EPT];
@@ -530,7 +468,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
-        const double2 acc = offdiag_sel<true, QC, CS>(nb[k], dq, src, zr[k]);
+        const double2 acc = offdiag_nb<true, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
         if (ok[k]) {
           e1 = fmax(e1, fabs(dn[k].x - d0[k].x) + fabs(dn[k].y - d0[k].y));
@@ -545,10 +483,8 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
       }
       double2 *dst = (cb ? zb0 : zb1);
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        zr[k] = cadd(qh[k], dn[k]);
-        if (ok[k]) dst[ee[k]] = zr[k];
-      }
+      for (int k = 0; k < EPT; ++k)
+        if (ok[k]) dst[ee[k]] = cadd(qh[k], dn[k]);
       __syncthreads();
       cb ^= 1;
     }
@@ -558,7 +494,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
-        const double2 acc = offdiag_sel<true, QC, CS>(nb[k], dq, src, zr[k]);
+        const double2 acc = offdiag_nb<true, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
       }
     }
@@ -578,10 +514,8 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     auto sweep_more = [&]() {
       double2 *dst = (cb ? zb0 : zb1);
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        zr[k] = cadd(qh[k], dn[k]);
-        if (ok[k]) dst[ee[k]] = zr[k];
-      }
+      for (int k = 0; k < EPT; ++k)
+        if (ok[k]) dst[ee[k]] = cadd(qh[k], dn[k]);
       __syncthreads();
       cb ^= 1;
     };
@@ -589,7 +523,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
-        const double2 acc = offdiag_sel<true, QC, CS>(nb[k], dq, src, zr[k]);
+        const double2 acc = offdiag_nb<true, QC>(nb[k], dq, src);
         dn[k] = cmul(wv[k], make_double2(hdq[k].x + h * acc.x, hdq[k].y + h * acc.y));
       }
     };
@@ -655,27 +589,12 @@ bool lds_fast_ok(int block, int ept, int Q) {
   return block <= 512 || Q == 1;
 }
 
-// Column-stride codes with a DPP kernel (see offdiag_dpp_acc): systems of
-// N = 16 in workgroups of 256 threads; two four-level subsystems.
-#define LBX_DPP_CODES(X) X(2, 0x14u)
-
-uint32_t lds_col_code(const SysDev &S, int block, int ept) {
-  if (S.N != 16 || block != 256 || ept != 1 || S.Q < 1 || S.Q > 4) return 0;
-  uint32_t cs = 0;
-  for (int q = 0; q < S.Q; ++q) cs |= (uint32_t)S.stride[q] << (4 * q);
-#define X(NQ, CODE) \
-  if (S.Q == NQ && cs == CODE) return cs;
-  LBX_DPP_CODES(X)
-#undef X
-  return 0;
-}
-
-template <int BLOCK, int EPT, int QC, uint32_t CS>
+template <int BLOCK, int EPT, int QC>
 static int fwd_t(const lb_plan *p, const LdsItem *d_items, int nitems, const double2 *ctab,
                  const double2 *ttab, const double2 *rho0, double2 *rhoT, double2 *states,
                  int64_t *sweeps, hipStream_t st) {
   const size_t shmem = (size_t)2 * BLOCK * EPT * sizeof(double2);
-  auto kern = lds_forward_fast_kernel<BLOCK, EPT, QC, CS>;
+  auto kern = lds_forward_fast_kernel<BLOCK, EPT, QC>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E, p->d_desc,
                      ctab, ttab, p->tol, p->NT, rho0, rhoT, states, sweeps);
@@ -683,12 +602,12 @@ static int fwd_t(const lb_plan *p, const LdsItem *d_items, int nitems, const dou
   return LB_OK;
 }
 
-template <int BLOCK, int EPT, int QC, uint32_t CS>
+template <int BLOCK, int EPT, int QC>
 static int adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, int kind, const double2 *ctab,
                  const double2 *ttab, const double2 *rhotar, const double2 *states, double *gpart,
                  int64_t *sweeps, hipStream_t st) {
   const size_t shmem = (size_t)2 * BLOCK * EPT * sizeof(double2);
-  auto kern = lds_adjoint_fast_kernel<BLOCK, EPT, QC, CS>;
+  auto kern = lds_adjoint_fast_kernel<BLOCK, EPT, QC>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E, p->d_desc,
                      ctab, ttab, p->tol, p->NT, kind, rhotar, states, gpart, sweeps);
@@ -702,38 +621,23 @@ static int adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, int kind,
   X(512, 1, 3) X(512, 1, 4) X(1024, 1, 1)
 
 int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, uint32_t cs, const double2 *ctab, const double2 *ttab,
-                            const double2 *rho0, double2 *rhoT, double2 *states, int64_t *sweeps,
-                            hipStream_t st) {
+                            int Q, const double2 *ctab, const double2 *ttab, const double2 *rho0,
+                            double2 *rhoT, double2 *states, int64_t *sweeps, hipStream_t st) {
   if (nitems == 0) return LB_OK;
-  if (cs) {
-#define X(C, S) \
-  if (block == 256 && ept == 1 && Q == C && cs == S) return fwd_t<256, 1, C, S>(p, d_items, nitems, ctab, ttab, rho0, rhoT, states, sweeps, st);
-    LBX_DPP_CODES(X)
-#undef X
-    return fail(LB_EUNSUPPORTED, "no DPP LDS-resident kernel for this column-stride code");
-  }
 #define X(B, E, C) \
-  if (block == B && ept == E && Q == C) return fwd_t<B, E, C, 0u>(p, d_items, nitems, ctab, ttab, rho0, rhoT, states, sweeps, st);
+  if (block == B && ept == E && Q == C) return fwd_t<B, E, C>(p, d_items, nitems, ctab, ttab, rho0, rhoT, states, sweeps, st);
   LBX_FAST_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "no specialised LDS-resident kernel for this shape");
 }
 
 int launch_lds_adjoint_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, uint32_t cs, int kind, const double2 *ctab, const double2 *ttab,
+                            int Q, int kind, const double2 *ctab, const double2 *ttab,
                             const double2 *rhotar, const double2 *states, double *gpart,
                             int64_t *sweeps, hipStream_t st) {
   if (nitems == 0) return LB_OK;
-  if (cs) {
-#define X(C, S) \
-  if (block == 256 && ept == 1 && Q == C && cs == S) return adj_t<256, 1, C, S>(p, d_items, nitems, kind, ctab, ttab, rhotar, states, gpart, sweeps, st);
-    LBX_DPP_CODES(X)
-#undef X
-    return fail(LB_EUNSUPPORTED, "no DPP LDS-resident kernel for this column-stride code");
-  }
 #define X(B, E, C) \
-  if (block == B && ept == E && Q == C) return adj_t<B, E, C, 0u>(p, d_items, nitems, kind, ctab, ttab, rhotar, states, gpart, sweeps, st);
+  if (block == B && ept == E && Q == C) return adj_t<B, E, C>(p, d_items, nitems, kind, ctab, ttab, rhotar, states, gpart, sweeps, st);
   LBX_FAST_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "no specialised LDS-resident kernel for this shape");

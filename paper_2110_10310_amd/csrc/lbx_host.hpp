@@ -28,7 +28,6 @@ struct lb_plan {
   int tile = 1;                   // LB_OPT_TILE
   int tile_ki = 0;                // LB_OPT_TILE_KI (0: default block)
   int graph_steps = 0;            // LB_OPT_GRAPH (0: launch directly)
-  int lds_dpp = 1;                // LB_OPT_LDS_DPP
   mutable bool capturing = false; // inside a stream capture: no profiling events
   double tol = 1.1102230246251565e-16;  // LB_OPT_SOLVE_TOL (2^-53)
   int device = 0;
@@ -190,15 +189,11 @@ int launch_tile_grad(const lb_plan *p, int sys, int B, const double2 *zh, const 
 bool lds_fast_ok(int block, int ept, int Q);
 // They pick the number of sweeps of every step a posteriori (see
 // extra_sweeps) and, when `sweeps` is not NULL, write each item's total.
-// Column-stride code of a system whose column neighbours the specialised
-// kernels take through DPP (N = 16, one matrix row per row of 16 lanes), or 0.
-uint32_t lds_col_code(const SysDev &S, int block, int ept);
 int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, uint32_t cs, const double2 *ctab, const double2 *ttab,
-                            const double2 *rho0, double2 *rhoT, double2 *states, int64_t *sweeps,
-                            hipStream_t st);
+                            int Q, const double2 *ctab, const double2 *ttab, const double2 *rho0,
+                            double2 *rhoT, double2 *states, int64_t *sweeps, hipStream_t st);
 int launch_lds_adjoint_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, uint32_t cs, int kind, const double2 *ctab, const double2 *ttab,
+                            int Q, int kind, const double2 *ctab, const double2 *ttab,
                             const double2 *rhotar, const double2 *states, double *gpart,
                             int64_t *sweeps, hipStream_t st);
 

@@ -345,32 +345,6 @@ def test_lds_extrapolated_start_on_short_horizons(lbx, NT):
     _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "lds", 1)
 
 
-def test_dpp_column_neighbours_match_lds_reads(lbx):
-    # Two four-level transmons (N = 16): the specialised kernels take column
-    # neighbours from neighbouring lanes; the same arithmetic on LDS reads
-    # must give the same bits, forward states and gradient alike.  A second
-    # system of another shape shares the batch (its own kernel class).
-    p = truncate_steps(make_config(2), 300)
-    systems, alphas, rho0s, _ = _multi([(131, (3, 3))], NT=300, T=p.systems[0].T)
-    systems = [p.systems[0]] + systems
-    alpha = dev(np.concatenate([p.alpha[0].reshape(-1)] + [a.reshape(-1) for a in alphas]))
-    rho0 = dev(np.concatenate([p.rho0[0].reshape(-1)] + [r.reshape(-1) for r in rho0s]))
-    tar = torch.zeros_like(rho0)
-    batch = [16] + [r.shape[0] for r in rho0s]
-    beta = dev(np.ones(sum(batch)))
-    nat = lbx._native
-    out = []
-    for dpp in (1, 0):
-        say("dpp column neighbours", dpp)
-        plan = lbx.Plan(systems, path="lds")
-        plan.set_option(nat.LB_OPT_LDS_DPP, dpp)
-        rhoT = lbx.forward_solve(plan, alpha, rho0, batch)
-        G, grad, _ = lbx.adjoint_gradient(plan, p.kind, alpha, rho0, tar, beta, batch)
-        out.append((rhoT.cpu().numpy(), np.asarray(G.cpu()), grad.cpu().numpy()))
-    for a, b in zip(*out):
-        assert np.array_equal(a, b)
-
-
 def test_profile_work_counts_sweeps(lbx):
     p = truncate_steps(make_config(2), 200)
     s = p.systems[0]
