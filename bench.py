@@ -45,9 +45,8 @@ APPLY_SOURCES = ["paper_2110_10310_amd/csrc/kernels_stream.hip",
 LDS_SOURCES = ["paper_2110_10310_amd/csrc/kernels_lds.hip",
                "paper_2110_10310_amd/csrc/kernels_lds_fast.hip",
                "paper_2110_10310_amd/csrc/lbx_device.hpp"]
-# traffic keys: (substring of the kernel name in the counter CSV, sources it is built from)
 # traffic keys: (substrings of the kernel name in the counter CSV, sources it is built from)
-TILE_KIS = {44: 512, 43: 256, 33: 256, 32: 256, 23: 256}  # eight-qutrit block shapes, threads
+TILE_KIS = {44: 512, 43: 256, 34: 256, 33: 256, 32: 256, 23: 256}  # eight-qutrit block shapes, threads
 TRAFFIC_KEYS = {
     "lds_forward_kernel": (["lds_forward_fast_kernel"], LDS_SOURCES),
     "lds_adjoint_kernel": (["lds_adjoint_fast_kernel"], LDS_SOURCES),
@@ -230,7 +229,7 @@ def run_apply_bench(lbx, torch, reps):
     y = torch.empty_like(x)
     alpha = torch.as_tensor(p.alpha[0].reshape(-1)).to("cuda")
     times = {}
-    for tile, ki in ((1, 44), (1, 43), (1, 33), (1, 32), (1, 23), (2, 0)):
+    for tile, ki in tuple((1, k) for k in TILE_KIS) + ((2, 0),):
         plan = lbx.Plan([s], tile=tile)
         plan.set_option(lbx._native.LB_OPT_TILE_KI, ki)
         for adj in (False, True):
@@ -343,7 +342,7 @@ def kernel_stats(db):
     print("| kernel | calls | total ms | average ms | % |")
     print("|---|---|---|---|---|")
     for name, calls, total, avg, pct in con.execute(
-            "select name, total_calls, total_duration, average, percentage from top_kernels limit 12"):
+            "select name, total_calls, total_duration, average, percentage from top_kernels limit 16"):
         short = name.split("(")[0].replace("void ", "")
         print(f"| `{short}` | {calls} | {total / 1e3:.3f} | {avg / 1e3:.4f} | {pct:.1f} |")
 

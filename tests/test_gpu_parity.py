@@ -84,7 +84,7 @@ def test_lindblad_apply_empty_batch_is_noop(lbx):
     assert y.shape == (0, 6, 6)
 
 
-@pytest.mark.parametrize("tile,ki", [(1, 44), (1, 33), (1, 32), (1, 23), (2, 0)])
+@pytest.mark.parametrize("tile,ki", [(1, 44), (1, 43), (1, 34), (1, 33), (1, 32), (1, 23), (2, 0)])
 def test_lindblad_apply_eight_qutrits_sampled(lbx, tile, ki):
     # The 8-qutrit ring at full size (N = 6561, 43M entries per state): check
     # sampled entries, each formed by the oracle from single operator rows,
