@@ -304,7 +304,8 @@ int ckpt_count(int NT, int c) { return (NT - 1) / c + 2; }
 
 // Workspace layout of one operation.
 struct Layout {
-  size_t ctab = 0, ktab = 0, ttab = 0, gstep = 0, objpart = 0, hist = 0, gpart = 0, items = 0;
+  size_t ctab = 0, ktab = 0, ttab = 0, gstep = 0, objpart = 0, hist = 0, zhist = 0, gpart = 0,
+         items = 0;
   size_t st_q0 = 0, st_q1 = 0, st_z0 = 0, st_z1 = 0, st_qh0 = 0, st_qh1 = 0, ckpt = 0, seg = 0,
          st_gpart = 0, st_gfin = 0, rhoT = 0;
   size_t total = 0;
@@ -337,6 +338,9 @@ Layout layout(const lb_plan *p, int op, const BatchMeta &m, int ckpt_every) {
   } else {
     L.gstep = take((size_t)2 * p->ctab_total * sizeof(double));
     L.hist = take((size_t)m.lds_hist_entries * sizeof(double2));
+    bool fast = false;
+    for (const auto &c : m.classes) fast = fast || c.qc > 0;
+    L.zhist = take(fast ? (size_t)m.lds_hist_entries * sizeof(double2) : 0);
     L.gpart = take((size_t)m.lds_gpart * sizeof(double));
     L.rhoT = take((size_t)m.total_entries * sizeof(double2));
     L.c = ckpt_interval(p, ckpt_every);
@@ -972,7 +976,8 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
       ProfScope ps(p, LB_KERNEL_LDS_ADJOINT, st);
       rc = c.qc > 0 ? launch_lds_adjoint_fast(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, kind,
                                               ctab, (const double2 *)(w + L.ttab),
-                                              (const double2 *)rhotar, hist, gpart,
+                                              (const double2 *)rhotar, hist,
+                                              (double2 *)(w + L.zhist), gpart,
                                               slots ? slots + c.i0 : nullptr, st)
                     : launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab,
                                          ktab, (const double2 *)rhotar, hist, gpart, st);

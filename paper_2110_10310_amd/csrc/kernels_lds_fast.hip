@@ -400,9 +400,8 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
     const double2 *__restrict__ ctab, const double2 *__restrict__ ttab, double tol, int NT,
     int kind, const double2 *__restrict__ rhotar, const double2 *__restrict__ states,
-    double *__restrict__ gpart, int64_t *__restrict__ sweeps) {
+    double2 *__restrict__ zhist, int64_t *__restrict__ sweeps) {
   extern __shared__ double2 zbuf[];
-  constexpr int ROWS = BLOCK / 16;
   constexpr int WAVES = BLOCK / 64;
   __shared__ uint32_t wmax[2][WAVES];
   const LdsItem it = items[blockIdx.x];
@@ -415,7 +414,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
   const double2 *hist = states + it.st_off;
 
   constexpr int HL = hist_len<BLOCK>();
-  double2 qh[EPT], wv[EPT], hd[EPT], dn[EPT], qn[EPT], dh[EPT][HL];
+  double2 qh[EPT], wv[EPT], hd[EPT], dn[EPT], dh[EPT][HL];
   Nb nb[EPT][QC];
   int ee[EPT];
   bool ok[EPT];
@@ -433,9 +432,9 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
 #pragma unroll
     for (int q = 0; q < QC; ++q) nb[k][q] = make_nb<true>(S, q, di, dj, ee[k]);
     // Terminal condition (App. B): qh = (beta/M) dJ/d(conj q) at q = rho(T).
-    qn[k] = ok[k] ? hist[(int64_t)NT * N2 + ee[k]] : make_double2(0.0, 0.0);
+    const double2 qT = ok[k] ? hist[(int64_t)NT * N2 + ee[k]] : make_double2(0.0, 0.0);
     const double2 t = ok[k] ? rhotar[it.off + ee[k]] : make_double2(0.0, 0.0);
-    qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qn[k], t)) : cscale(-it.wterm, t);
+    qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qT, t)) : cscale(-it.wterm, t);
     dn[k] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i < HL; ++i) dh[k][i] = make_double2(0.0, 0.0);
@@ -443,8 +442,8 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
   double2 *const zb0 = zbuf, *const zb1 = zbuf + N2;
   int cb = 0;
   int64_t nsw = 0;
-  // Controls of step j - 1 are loaded before the history load of step j and
-  // unpacked after the sweeps, where that history value is awaited anyway.
+  // Controls of step j - 1 are loaded at the top of step j and unpacked after
+  // its sweeps.
   const double2 *tq = ttab + (int64_t)it.sys * NT;
   double2 dq[QC];
   StepConst sc = unpack_controls<QC>(load_controls<QC>(cq, tq, NT - 1, NT, lane), dq);
@@ -458,10 +457,6 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
       d0[k] = extrapolated_start(NT - 1 - j, wv[k], hdq[k], dh[k]);
       if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qh[k], d0[k]);
     }
-    // Forward state q^j, consumed after the sweeps so that its load overlaps them.
-    double2 qj[EPT];
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) qj[k] = ok[k] ? hist[(int64_t)j * N2 + ee[k]] : make_double2(0.0, 0.0);
     __syncthreads();
     double e1 = 0.0, qm = 0.0;
     {
@@ -539,26 +534,75 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
         }
       }
     }
-    // Gradient integrands (see grad_term in lbx_device.hpp) need zh at neighbours.
-    double2 *zhb = (cb ? zb0 : zb1);
+    // The converged stage vector zh goes to HBM for the gradient integrands
+    // (lds_grad_fast_kernel, after this loop), which leaves them off the
+    // chain of dependent steps.
 #pragma unroll
     for (int k = 0; k < EPT; ++k)
-      if (ok[k]) zhb[ee[k]] = cadd(qh[k], dn[k]);
+      if (ok[k]) zhist[it.st_off + (int64_t)j * N2 + ee[k]] = cadd(qh[k], dn[k]);
+    sc = unpack_controls<QC>(cnext, dq);
+    // qh^j = qh^{j+1} + dt M^+ zh = qh^{j+1} + 2 delta.
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      qh[k] = make_double2(qh[k].x + 2.0 * dn[k].x, qh[k].y + 2.0 * dn[k].y);
+#pragma unroll
+      for (int i = HL - 1; i > 0; --i) dh[k][i] = dh[k][i - 1];
+      dh[k][0] = dn[k];
+    }
+    // The next step's first iterate goes to the buffer the last sweep did not
+    // read (all reads of the other one precede the last barrier).
+    cb ^= 1;
+  }
+  if (sweeps && tid == 0) sweeps[blockIdx.x] = nsw;
+}
+
+// Gradient integrands of the specialised adjoint (App. B eq. reducedgradient,
+// see grad_term in lbx_device.hpp), for all steps at once: workgroup (c, item)
+// takes steps [c GCHUNK, (c + 1) GCHUNK) of one item.  Per step, zh^j is
+// staged in LDS (two buffers by step parity, one barrier per step), z^j =
+// (q^j + q^{j+1})/2 comes from the forward history, and each row of 16 lanes
+// writes its partial sums, in the same order and layout as the integrands
+// formed inside the adjoint loop would be.
+constexpr int GCHUNK = 64;
+
+template <int BLOCK, int QC>
+__global__ __launch_bounds__(BLOCK) void lds_grad_fast_kernel(
+    const SysDev *__restrict__ sysv, const LdsItem *__restrict__ items,
+    const uint64_t *__restrict__ desc, int NT, const double2 *__restrict__ states,
+    const double2 *__restrict__ zhist, double *__restrict__ gpart) {
+  extern __shared__ double2 zbuf[];
+  constexpr int ROWS = BLOCK / 16;
+  const LdsItem it = items[blockIdx.y];
+  const SysDev &S = sysv[it.sys];
+  const int tid = threadIdx.x;
+  const int N = S.N;
+  const int N2 = (int)S.N2;
+  const bool ok = tid < N2;
+  const int e = ok ? tid : 0;
+  const int i = e / N, jj = e - (e / N) * N;
+  Nb nb[QC];
+#pragma unroll
+  for (int q = 0; q < QC; ++q) nb[q] = make_nb<true>(S, q, desc[S.tab_off + i], desc[S.tab_off + jj], e);
+  const double2 *hist = states + it.st_off;
+  const double2 *zh = zhist + it.st_off;
+  const int j0 = (int)blockIdx.x * GCHUNK;
+  const int j1 = min(NT, j0 + GCHUNK);
+  for (int j = j0; j < j1; ++j) {
+    double2 *zb = zbuf + (j & 1) * N2;
+    if (ok) zb[e] = zh[(int64_t)j * N2 + e];
+    const double2 qj = ok ? hist[(int64_t)j * N2 + e] : make_double2(0.0, 0.0);
+    const double2 qn = ok ? hist[(int64_t)(j + 1) * N2 + e] : make_double2(0.0, 0.0);
     __syncthreads();
-    sc = unpack_controls<QC>(cnext, dq);  // next step's; the integrands do not use them
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
       double gp = 0.0, gq = 0.0;
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        if (ok[k]) {
-          const double2 z = make_double2(0.5 * (qj[k].x + qn[k].x), 0.5 * (qj[k].y + qn[k].y));
-          double2 U, V;
-          uv(nb[k][q], zhb, U, V);
-          const double2 Sm = cadd(U, V), Dv = csub(U, V);
-          gp += Sm.x * z.y - Sm.y * z.x;
-          gq -= Dv.x * z.x + Dv.y * z.y;
-        }
+      if (ok) {
+        const double2 z = make_double2(0.5 * (qj.x + qn.x), 0.5 * (qj.y + qn.y));
+        double2 U, V;
+        uv(nb[q], zb, U, V);
+        const double2 Sm = cadd(U, V), Dv = csub(U, V);
+        gp += Sm.x * z.y - Sm.y * z.x;
+        gq -= Dv.x * z.x + Dv.y * z.y;
       }
       gp = row16_sum(gp);
       gq = row16_sum(gq);
@@ -568,17 +612,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
         dstp[1] = gq;
       }
     }
-    // qh^j = qh^{j+1} + dt M^+ zh = qh^{j+1} + 2 delta.
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      qh[k] = make_double2(qh[k].x + 2.0 * dn[k].x, qh[k].y + 2.0 * dn[k].y);
-      qn[k] = qj[k];
-#pragma unroll
-      for (int i = HL - 1; i > 0; --i) dh[k][i] = dh[k][i - 1];
-      dh[k][0] = dn[k];
-    }
   }
-  if (sweeps && tid == 0) sweeps[blockIdx.x] = nsw;
 }
 
 // Shapes with a specialised kernel: one entry per thread.  Workgroups of
@@ -604,13 +638,19 @@ static int fwd_t(const lb_plan *p, const LdsItem *d_items, int nitems, const dou
 
 template <int BLOCK, int EPT, int QC>
 static int adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, int kind, const double2 *ctab,
-                 const double2 *ttab, const double2 *rhotar, const double2 *states, double *gpart,
-                 int64_t *sweeps, hipStream_t st) {
+                 const double2 *ttab, const double2 *rhotar, const double2 *states, double2 *zhist,
+                 double *gpart, int64_t *sweeps, hipStream_t st) {
   const size_t shmem = (size_t)2 * BLOCK * EPT * sizeof(double2);
   auto kern = lds_adjoint_fast_kernel<BLOCK, EPT, QC>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E, p->d_desc,
-                     ctab, ttab, p->tol, p->NT, kind, rhotar, states, gpart, sweeps);
+                     ctab, ttab, p->tol, p->NT, kind, rhotar, states, zhist, sweeps);
+  LBX_HIP(hipGetLastError());
+  static_assert(EPT == 1, "the integrand kernel takes one entry per thread");
+  auto gk = lds_grad_fast_kernel<BLOCK, QC>;
+  LBX_HIP(hipFuncSetAttribute((const void *)gk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  hipLaunchKernelGGL(gk, dim3((p->NT + GCHUNK - 1) / GCHUNK, nitems), dim3(BLOCK), shmem, st, p->d_sys,
+                     d_items, p->d_desc, p->NT, states, zhist, gpart);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -633,11 +673,12 @@ int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems
 
 int launch_lds_adjoint_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                             int Q, int kind, const double2 *ctab, const double2 *ttab,
-                            const double2 *rhotar, const double2 *states, double *gpart,
-                            int64_t *sweeps, hipStream_t st) {
+                            const double2 *rhotar, const double2 *states, double2 *zhist,
+                            double *gpart, int64_t *sweeps, hipStream_t st) {
   if (nitems == 0) return LB_OK;
+  if (nitems > 65535) return fail(LB_EUNSUPPORTED, "more than 65535 states in one LDS kernel class");
 #define X(B, E, C) \
-  if (block == B && ept == E && Q == C) return adj_t<B, E, C>(p, d_items, nitems, kind, ctab, ttab, rhotar, states, gpart, sweeps, st);
+  if (block == B && ept == E && Q == C) return adj_t<B, E, C>(p, d_items, nitems, kind, ctab, ttab, rhotar, states, zhist, gpart, sweeps, st);
   LBX_FAST_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "no specialised LDS-resident kernel for this shape");

@@ -777,9 +777,9 @@ int launch_split(const lb_plan *p, int sys, int B, int mode, bool adj, const dou
 }
 
 // Block shapes: KR row digits and KC column digits inside a block.  The
-// default is the square block with the most entries up to 6561; the plan's
-// LB_OPT_TILE_KI selects another instantiated shape (encoded 10*KR + KC).
-constexpr int TILE_MAX = 6561;
+// default is the shape listed first in LBX_TILE_SHAPES for the system (the
+// largest square block, at most 6561 entries); the plan's LB_OPT_TILE_KI
+// selects another instantiated shape (encoded 10*KR + KC).
 
 template <int NL, int QC, int KR, int KC, int BLOCK, bool ADJ, int MODE>
 static int tile_launch(const lb_plan *p, int sys, int B, const double *alpha, double t,

@@ -192,9 +192,11 @@ bool lds_fast_ok(int block, int ept, int Q);
 int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                             int Q, const double2 *ctab, const double2 *ttab, const double2 *rho0,
                             double2 *rhoT, double2 *states, int64_t *sweeps, hipStream_t st);
+// The adjoint stores each step's converged stage vector in zhist (laid out
+// like the state history) and a second launch forms the gradient integrands.
 int launch_lds_adjoint_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                             int Q, int kind, const double2 *ctab, const double2 *ttab,
-                            const double2 *rhotar, const double2 *states, double *gpart,
-                            int64_t *sweeps, hipStream_t st);
+                            const double2 *rhotar, const double2 *states, double2 *zhist,
+                            double *gpart, int64_t *sweeps, hipStream_t st);
 
 }  // namespace lbx
