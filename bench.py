@@ -219,6 +219,10 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
         # applications of M per evaluation on the streamed path: every sweep of
         # every pass, plus the gradient integrands of every step
         "apply_equivalents": (work[nat.LB_KERNEL_SWEEP] / steps / st_entries + nt) if st_entries else None,
+        # Stage-sweep bytes (48 B per entry and sweep) over the whole timed
+        # region: the forward recomputation and the adjoint run on two streams,
+        # so a sweep's event-timed duration includes the other stream's share.
+        "sweep_GBps_timed_region": 48.0 * work[nat.LB_KERNEL_SWEEP] / elapsed / 1e9 if st_entries else None,
     }
 
 
@@ -470,6 +474,7 @@ def main():
         "detail": {"G": res["G"], "grad_max": res["grad_norm"],
                    "sweeps_per_step_mean": res["sweeps_per_step_mean"],
                    "kernel_avg_ms": res["kernel_ms"], "kernel_ms_per_eval": res["kernel_total_ms"],
+                   "sweep_GBps_timed_region": res["sweep_GBps_timed_region"],
                    "autotune": res["autotune"]},
     }
     if args.workload != 2:

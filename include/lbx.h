@@ -138,7 +138,9 @@ int lb_workspace_bytes(const lb_plan *plan, int32_t op, const int32_t *batch_per
                        int32_t ckpt_every, size_t *bytes);
 
 /* Launch count and summed duration [ms] of kernel family `kernel` (LB_KERNEL_*)
- * over the calls made while LB_OPT_PROFILE was on; reset != 0 clears them. */
+ * over the calls made while LB_OPT_PROFILE was on; reset != 0 clears them.
+ * The stage sweeps of one step are timed together (one event pair around
+ * their back-to-back launches), so total_ms / launches is their mean. */
 int lb_profile_read(const lb_plan *plan, int32_t kernel, int64_t *launches, double *total_ms,
                     int32_t reset);
 

@@ -36,7 +36,7 @@ int hip_fail(hipError_t e, const char *what) {
 static void prof_account(const lb_plan *p, const lbx_prof_pending &e) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e.start, e.stop) == hipSuccess) {
-    p->prof_n[e.kernel] += 1;
+    p->prof_n[e.kernel] += e.launches;
     p->prof_ms[e.kernel] += ms;
   }
   p->ev_pool.push_back(e.start);
@@ -491,7 +491,6 @@ struct GraphRun {
 int sweep(const lb_plan *p, const BatchMeta &m, int j, bool adj, bool last, const double2 *ctab,
           const double2 *zin, const double2 *qin, double2 *out, hipStream_t st,
           double2 *zout = nullptr) {
-  ProfScope ps(p, LB_KERNEL_SWEEP, st, m.st_entries);
   if (m.tile_sys >= 0)
     return launch_tile(p, m.tile_sys, m.tile_B, last ? 2 : 1, adj, nullptr, 0.0, ctab, j, zin, qin,
                        out, last ? zout : nullptr, st);
@@ -517,6 +516,7 @@ int stream_forward(const lb_plan *p, const BatchMeta &m, const std::vector<int32
       int K = 1;
       for (const auto &sg : m.segs) K = std::max(K, (int)k[((size_t)sg.sys * p->NT + j) * 2 + 1]);
       double2 *out = slot(j + 1);
+      ProfScope ps(p, LB_KERNEL_SWEEP, st, (int64_t)K * m.st_entries, K);
       for (int kk = 0; kk < K; ++kk) {
         const bool last = kk == K - 1;
         const double2 *zin = kk == 0 ? cur : (kk & 1 ? z0 : z1);
@@ -806,6 +806,7 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
   if (K < 1) return fail(LB_EUNSUPPORTED, "stage-solve contraction bound >= 0.5 at this step");
   double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
   const double2 *qi = (const double2 *)q_in;
+  ProfScope ps(p, LB_KERNEL_SWEEP, st, (int64_t)K * m->st_entries, K);
   for (int kk = 0; kk < K; ++kk) {
     const bool last = kk == K - 1;
     const double2 *zin = kk == 0 ? qi : (kk & 1 ? z0 : z1);
@@ -1027,12 +1028,15 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
           // The last sweep also writes the stage vector zh = qh^{j+1} + delta =
           // (qh^j + qh^{j+1})/2 into the z buffer it does not read.
           double2 *zh = nullptr;
-          for (int kk = 0; kk < K; ++kk) {
-            const bool last = kk == K - 1;
-            const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
-            double2 *dst = last ? qout : (kk & 1 ? z1 : z0);
-            if (last) zh = kk == 0 ? z0 : (kk & 1 ? z1 : z0);
-            if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, ast, zh))) return rc;
+          {
+            ProfScope ps(p, LB_KERNEL_SWEEP, ast, (int64_t)K * m->st_entries, K);
+            for (int kk = 0; kk < K; ++kk) {
+              const bool last = kk == K - 1;
+              const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
+              double2 *dst = last ? qout : (kk & 1 ? z1 : z0);
+              if (last) zh = kk == 0 ? z0 : (kk & 1 ? z1 : z0);
+              if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, ast, zh))) return rc;
+            }
           }
           int64_t rows = 0;
           {

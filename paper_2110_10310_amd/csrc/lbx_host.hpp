@@ -13,6 +13,7 @@
 
 struct lbx_prof_pending {
   int kernel;
+  int launches;  // kernel launches bracketed by the two events
   hipEvent_t start, stop;
 };
 
@@ -68,13 +69,18 @@ struct StreamSeg {
 
 constexpr int STREAM_BLOCK = 256;
 
-// HIP-event timing of one launch when the plan's profiling is on.
+// HIP-event timing of `launches` consecutive launches of one kernel family
+// when the plan's profiling is on.  Bracketing a run of back-to-back launches
+// (the sweeps of one step) keeps the events' own cost from inflating short
+// kernels.
 struct ProfScope {
   const lb_plan *p;
   int kernel;
+  int launches;
   hipStream_t st;
   hipEvent_t a = nullptr;
-  ProfScope(const lb_plan *p_, int k, hipStream_t s, int64_t work = 0) : p(p_), kernel(k), st(s) {
+  ProfScope(const lb_plan *p_, int k, hipStream_t s, int64_t work = 0, int n = 1)
+      : p(p_), kernel(k), launches(n), st(s) {
     if (!p->profile || p->capturing) return;
     p->prof_work[k] += work;
     a = prof_event(p);
@@ -85,7 +91,7 @@ struct ProfScope {
     hipEvent_t b = prof_event(p);
     if (!b) return;
     (void)hipEventRecord(b, st);
-    p->prof_pending.push_back({kernel, a, b});
+    p->prof_pending.push_back({kernel, launches, a, b});
     if (p->prof_pending.size() >= 2048) prof_drain(p);
   }
   static hipEvent_t prof_event(const lb_plan *p);
