@@ -310,6 +310,8 @@ struct Layout {
          st_gpart = 0, st_gfin = 0, rhoT = 0;
   size_t total = 0;
   int c = 1, nck = 0;
+  int64_t grows = 1;  // gradient partial rows per step (streamed systems)
+  int gbatch = 1;     // steps whose partial rows are reduced by one launch
 };
 
 Layout layout(const lb_plan *p, int op, const BatchMeta &m, int ckpt_every) {
@@ -353,10 +355,13 @@ Layout layout(const lb_plan *p, int op, const BatchMeta &m, int ckpt_every) {
     L.st_qh1 = take(E);
     L.ckpt = take((size_t)L.nck * E);
     L.seg = take((size_t)std::max(0, L.c - 1) * E);
-    const int64_t grows =
-        std::max<int64_t>(m.st_blocks, m.tile_sys >= 0 ? tile_grad_rows(p, m.tile_sys, m.tile_B) : 0);
-    L.st_gpart = take((size_t)std::max<int64_t>(1, grows) * 2 * QMAX * sizeof(double));
-    L.st_gfin = take(stream_grad_fin_doubles((int)m.segs.size()) * sizeof(double));
+    L.grows = std::max<int64_t>(
+        1, std::max<int64_t>(m.st_blocks, m.tile_sys >= 0 ? tile_grad_rows(p, m.tile_sys, m.tile_B) : 0));
+    // Up to a checkpoint interval of steps, within 256 MB of partial rows.
+    const size_t row_bytes = (size_t)L.grows * 2 * QMAX * sizeof(double);
+    L.gbatch = (int)std::max<int64_t>(1, std::min<int64_t>(L.c, (int64_t)((256u << 20) / row_bytes)));
+    L.st_gpart = take((size_t)L.gbatch * row_bytes);
+    L.st_gfin = take((size_t)L.gbatch * stream_grad_fin_doubles((int)m.segs.size()) * sizeof(double));
   }
   L.total = cur;
   return L;
@@ -997,6 +1002,9 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
     double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
     double2 *qh[2] = {(double2 *)(w + L.st_qh0), (double2 *)(w + L.st_qh1)};
     double *sgp = (double *)(w + L.st_gpart), *sgf = (double *)(w + L.st_gfin);
+    const int64_t gstride = L.grows * 2 * QMAX;  // doubles per step slot
+    int pend = 0, jtop = 0;
+    int64_t rows = 0;
     const int nseg = (int)m->segs.size();
     if ((rc = launch_terminal(p, kind, m->d_segs, nseg, m->st_blocks, ck + (size_t)(L.nck - 1) * E,
                               (const double2 *)rhotar, beta, m->d_seg_state0, qh[0], st)))
@@ -1038,17 +1046,24 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
               if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, ast, zh))) return rc;
             }
           }
-          int64_t rows = 0;
+          // Partial rows of the pending steps go to successive slots and are
+          // reduced together (every gbatch steps and at the end of a chunk).
+          if (pend == 0) jtop = j;
+          double *gp = sgp + (size_t)pend * gstride;
           {
             ProfScope ps(p, LB_KERNEL_STREAM_GRAD, ast, m->st_entries);
             rc = m->tile_sys >= 0
-                     ? launch_tile_grad(p, m->tile_sys, m->tile_B, zh, slot(j), slot(j + 1), sgp, &rows, ast)
-                     : launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, zh, slot(j), slot(j + 1), sgp,
+                     ? launch_tile_grad(p, m->tile_sys, m->tile_B, zh, slot(j), slot(j + 1), gp, &rows, ast)
+                     : launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, zh, slot(j), slot(j + 1), gp,
                                           ast);
             if (rc) return rc;
           }
-          if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, j, sgp, sgf, gstep, rows, ast)))
-            return rc;
+          if (++pend == L.gbatch || j == cb) {
+            if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, jtop, pend, sgp, gstride, sgf,
+                                                  gstep, rows, ast)))
+              return rc;
+            pend = 0;
+          }
           cur ^= 1;
         }
         if ((rc = gr.end())) return rc;

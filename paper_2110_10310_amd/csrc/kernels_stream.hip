@@ -258,13 +258,17 @@ int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int6
 // order passes: FIN_SPLIT workgroups per segment each reduce a contiguous
 // range of partial rows (one row of 2 QMAX doubles per thread and pass, so
 // that a wavefront reads consecutive rows), then one workgroup per segment
-// adds the FIN_SPLIT results.
+// adds the FIN_SPLIT results.  Several steps are reduced in one launch
+// (grid z / y: slot z holds step jtop - z), each in the same order as alone.
 constexpr int FIN_SPLIT = 64;
 
 __global__ __launch_bounds__(256) void stream_grad_partial_kernel(
     const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs,
-    const double *__restrict__ gpart, double *__restrict__ gfin, int64_t rows) {
+    const double *__restrict__ gpart, int64_t slot_stride, double *__restrict__ gfin,
+    int64_t fin_stride, int64_t rows) {
   __shared__ double red[4][2 * QMAX];
+  gpart += (int64_t)blockIdx.z * slot_stride;
+  gfin += (int64_t)blockIdx.z * fin_stride;
   const StreamSeg &sg = segs[blockIdx.x];
   const int Q2 = 2 * sysv[sg.sys].Q;
   // rows > 0: one segment whose partial rows start at 0 (block-tiled kernel)
@@ -296,8 +300,10 @@ __global__ __launch_bounds__(256) void stream_grad_partial_kernel(
 }
 
 __global__ __launch_bounds__(64) void stream_grad_finalize_kernel(
-    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int j,
-    const double *__restrict__ gfin, double *__restrict__ gstep) {
+    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int jtop,
+    const double *__restrict__ gfin, int64_t fin_stride, double *__restrict__ gstep) {
+  const int j = jtop - (int)blockIdx.y;
+  gfin += (int64_t)blockIdx.y * fin_stride;
   const StreamSeg &sg = segs[blockIdx.x];
   const SysDev &S = sysv[sg.sys];
   const int c = threadIdx.x;
@@ -309,15 +315,17 @@ __global__ __launch_bounds__(64) void stream_grad_finalize_kernel(
 
 size_t stream_grad_fin_doubles(int nseg) { return (size_t)std::max(nseg, 1) * FIN_SPLIT * 2 * QMAX; }
 
-int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int j,
-                                const double *gpart, double *gfin, double *gstep, int64_t rows,
-                                hipStream_t st) {
-  if (nseg == 0) return LB_OK;
-  hipLaunchKernelGGL(stream_grad_partial_kernel, dim3(nseg, FIN_SPLIT), dim3(256), 0, st, p->d_sys,
-                     d_segs, gpart, gfin, rows);
+int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int jtop,
+                                int nsteps, const double *gpart, int64_t slot_stride, double *gfin,
+                                double *gstep, int64_t rows, hipStream_t st) {
+  if (nseg == 0 || nsteps == 0) return LB_OK;
+  if (nsteps > 65535) return fail(LB_EINVAL, "too many steps in one gradient reduction");
+  const int64_t fin_stride = (int64_t)stream_grad_fin_doubles(nseg);
+  hipLaunchKernelGGL(stream_grad_partial_kernel, dim3(nseg, FIN_SPLIT, nsteps), dim3(256), 0, st,
+                     p->d_sys, d_segs, gpart, slot_stride, gfin, fin_stride, rows);
   LBX_HIP(hipGetLastError());
-  hipLaunchKernelGGL(stream_grad_finalize_kernel, dim3(nseg), dim3(64), 0, st, p->d_sys, d_segs, j,
-                     gfin, gstep);
+  hipLaunchKernelGGL(stream_grad_finalize_kernel, dim3(nseg, nsteps), dim3(64), 0, st, p->d_sys, d_segs,
+                     jtop, gfin, fin_stride, gstep);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }

@@ -133,12 +133,13 @@ int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int6
                        const double2 *zh, const double2 *q0, const double2 *q1, double *gpart,
                        hipStream_t st);
 
-// Two-pass fixed-order sum of the stream_grad partials into gstep; gfin is
-// scratch of stream_grad_fin_doubles(nseg) doubles.
+// Two-pass fixed-order sum of the stream_grad partials of nsteps steps into
+// gstep: slot z (partial rows at gpart + z slot_stride) holds step jtop - z;
+// gfin is scratch of nsteps stream_grad_fin_doubles(nseg) doubles.
 size_t stream_grad_fin_doubles(int nseg);
-int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int j,
-                                const double *gpart, double *gfin, double *gstep, int64_t rows,
-                                hipStream_t st);
+int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int nseg, int jtop,
+                                int nsteps, const double *gpart, int64_t slot_stride, double *gfin,
+                                double *gstep, int64_t rows, hipStream_t st);
 
 int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                        const double2 *ctab, const int32_t *ktab, const double2 *rho0,
