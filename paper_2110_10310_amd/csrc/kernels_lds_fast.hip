@@ -11,8 +11,9 @@
 // then LDS reads and FP64 FMAs only.  Unlike the generic kernels they start
 // each stage solve from an extrapolation of earlier steps and stop on an
 // a-posteriori bound (see extra_sweeps); the per-step controls come through a
-// vector load one step ahead.  The adjoint reduces its per-step gradient
-// integrands over 16-lane DPP rows.
+// vector load one step ahead.  The adjoint stores each step's stage vector,
+// and lds_grad_fast_kernel forms the gradient integrands of all steps after
+// it, reduced over 16-lane DPP rows.
 #include <hip/hip_runtime.h>
 
 #include "lbx_host.hpp"
