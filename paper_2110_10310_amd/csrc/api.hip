@@ -491,24 +491,45 @@ struct GraphRun {
   }
 };
 
-// One stage-solve sweep of every streamed segment at step j.
-// zout (last sweep only, may be NULL) receives the converged stage vector.
-int sweep(const lb_plan *p, const BatchMeta &m, int j, bool adj, bool last, const double2 *ctab,
-          const double2 *zin, const double2 *qin, double2 *out, hipStream_t st,
-          double2 *zout = nullptr) {
-  if (m.tile_sys >= 0)
-    return launch_tile(p, m.tile_sys, m.tile_B, last ? 2 : 1, adj, nullptr, 0.0, ctab, j, zin, qin,
-                       out, last ? zout : nullptr, st);
-  return launch_sweep(p, m.d_segs, (int)m.segs.size(), m.st_blocks, j, adj, last, ctab, zin, qin,
-                      out, last ? zout : nullptr, st);
+// Sweep kk of the stage solves of the streamed segments at step j, K being
+// the largest count among them.  The iterates alternate: sweep kk reads q
+// (kk = 0), z0 (kk odd) or z1 (kk even) and writes z1 / z0, or `out` on the
+// last one, which with want_zh also writes the converged stage vector into
+// the z buffer it does not read (stage_buffer).  The tiled kernels serve one
+// system, whose count is K; the generic kernel runs every segment at its own
+// count from ktab (kfix > 0 instead gives every segment kfix).
+double2 *stage_buffer(int K, double2 *z0, double2 *z1) {
+  const int kl = K - 1;
+  return kl == 0 ? z0 : (kl & 1 ? z1 : z0);
+}
+
+int sweep(const lb_plan *p, const BatchMeta &m, int j, int kk, int K, bool adj,
+          const double2 *ctab, const int32_t *ktab, const double2 *q, double2 *z0, double2 *z1,
+          double2 *out, hipStream_t st, bool want_zh = false, int kfix = 0) {
+  if (m.tile_sys >= 0) {
+    const bool last = kk == K - 1;
+    const double2 *zin = kk == 0 ? q : (kk & 1 ? z0 : z1);
+    double2 *dst = last ? out : (kk & 1 ? z1 : z0);
+    return launch_tile(p, m.tile_sys, m.tile_B, last ? 2 : 1, adj, nullptr, 0.0, ctab, j, zin, q, dst,
+                       last && want_zh ? stage_buffer(K, z0, z1) : nullptr, st);
+  }
+  return launch_sweep(p, m.d_segs, (int)m.segs.size(), m.st_blocks, j, kk, kfix, adj, ctab, ktab, q, z0,
+                      z1, out, want_zh, st);
+}
+
+// Entry-sweeps of step j over the streamed segments, each at its own count.
+int64_t step_sweep_work(const lb_plan *p, const BatchMeta &m, const std::vector<int32_t> &k, int j) {
+  int64_t w = 0;
+  for (const auto &sg : m.segs) w += (int64_t)k[((size_t)sg.sys * p->NT + j) * 2 + 1] * sg.count;
+  return w;
 }
 
 // Streaming forward steps j0..j1-1 of every segment.  slot(j) returns the
 // buffer that receives q^j (j > j0); q^{j0} is `qstart`.
 template <class Slot>
 int stream_forward(const lb_plan *p, const BatchMeta &m, const std::vector<int32_t> &k,
-                   const double2 *ctab, int j0, int j1, const double2 *qstart, Slot slot,
-                   double2 *z0, double2 *z1, hipStream_t user) {
+                   const int32_t *ktab, const double2 *ctab, int j0, int j1, const double2 *qstart,
+                   Slot slot, double2 *z0, double2 *z1, hipStream_t user) {
   GraphRun gr(p, user);
   if (int rc = gr.init()) return rc;
   const hipStream_t st = gr.stream();
@@ -521,13 +542,9 @@ int stream_forward(const lb_plan *p, const BatchMeta &m, const std::vector<int32
       int K = 1;
       for (const auto &sg : m.segs) K = std::max(K, (int)k[((size_t)sg.sys * p->NT + j) * 2 + 1]);
       double2 *out = slot(j + 1);
-      ProfScope ps(p, LB_KERNEL_SWEEP, st, (int64_t)K * m.st_entries, K);
-      for (int kk = 0; kk < K; ++kk) {
-        const bool last = kk == K - 1;
-        const double2 *zin = kk == 0 ? cur : (kk & 1 ? z0 : z1);
-        double2 *dst = last ? out : (kk & 1 ? z1 : z0);
-        if (int rc = sweep(p, m, j, false, last, ctab, zin, cur, dst, st)) return rc;
-      }
+      ProfScope ps(p, LB_KERNEL_SWEEP, st, step_sweep_work(p, m, k, j), K);
+      for (int kk = 0; kk < K; ++kk)
+        if (int rc = sweep(p, m, j, kk, K, false, ctab, ktab, cur, z0, z1, out, st)) return rc;
       cur = out;
     }
     if (int rc = gr.end()) return rc;
@@ -811,13 +828,10 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
   if (K < 1) return fail(LB_EUNSUPPORTED, "stage-solve contraction bound >= 0.5 at this step");
   double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
   const double2 *qi = (const double2 *)q_in;
-  ProfScope ps(p, LB_KERNEL_SWEEP, st, (int64_t)K * m->st_entries, K);
-  for (int kk = 0; kk < K; ++kk) {
-    const bool last = kk == K - 1;
-    const double2 *zin = kk == 0 ? qi : (kk & 1 ? z0 : z1);
-    double2 *dst = last ? (double2 *)q_out : (kk & 1 ? z1 : z0);
-    if ((rc = sweep(p, *m, j, adjoint != 0, last, ctab, zin, qi, dst, st))) return rc;
-  }
+  ProfScope ps(p, LB_KERNEL_SWEEP, st, step_sweep_work(p, *m, k, j), K);
+  for (int kk = 0; kk < K; ++kk)
+    if ((rc = sweep(p, *m, j, kk, K, adjoint != 0, ctab, ktab, qi, z0, z1, (double2 *)q_out, st)))
+      return rc;
   return LB_OK;
 }
 
@@ -896,7 +910,7 @@ static int run_forward(const lb_plan *p, const BatchMeta &m, const Layout &L, ch
     last_out = r;
     return r;
   };
-  if ((rc = stream_forward(p, m, k, ctab, 0, NT, start, slot, z0, z1, st))) return rc;
+  if ((rc = stream_forward(p, m, k, ktab, ctab, 0, NT, start, slot, z0, z1, st))) return rc;
   return copy_segments(m, last_out, false, rhoT, st);
 }
 
@@ -1020,7 +1034,8 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
       };
       // Recompute q^{j0+1} .. q^{j1-1} from the checkpoint.
       if (j1 - j0 > 1)
-        if ((rc = stream_forward(p, *m, k, ctab, j0, j1 - 1, slot(j0), slot, z0, z1, st))) return rc;
+        if ((rc = stream_forward(p, *m, k, ktab, ctab, j0, j1 - 1, slot(j0), slot, z0, z1, st)))
+          return rc;
       GraphRun gr(p, st);
       if ((rc = gr.init())) return rc;
       const hipStream_t ast = gr.stream();
@@ -1035,16 +1050,10 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
           double2 *qout = qh[cur ^ 1];
           // The last sweep also writes the stage vector zh = qh^{j+1} + delta =
           // (qh^j + qh^{j+1})/2 into the z buffer it does not read.
-          double2 *zh = nullptr;
           {
-            ProfScope ps(p, LB_KERNEL_SWEEP, ast, (int64_t)K * m->st_entries, K);
-            for (int kk = 0; kk < K; ++kk) {
-              const bool last = kk == K - 1;
-              const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
-              double2 *dst = last ? qout : (kk & 1 ? z1 : z0);
-              if (last) zh = kk == 0 ? z0 : (kk & 1 ? z1 : z0);
-              if ((rc = sweep(p, *m, j, true, last, ctab, zin, qin, dst, ast, zh))) return rc;
-            }
+            ProfScope ps(p, LB_KERNEL_SWEEP, ast, step_sweep_work(p, *m, k, j), K);
+            for (int kk = 0; kk < K; ++kk)
+              if ((rc = sweep(p, *m, j, kk, K, true, ctab, ktab, qin, z0, z1, qout, ast, true))) return rc;
           }
           // Partial rows of the pending steps go to successive slots and are
           // reduced together (every gbatch steps and at the end of a chunk).
@@ -1053,9 +1062,10 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
           {
             ProfScope ps(p, LB_KERNEL_STREAM_GRAD, ast, m->st_entries);
             rc = m->tile_sys >= 0
-                     ? launch_tile_grad(p, m->tile_sys, m->tile_B, zh, slot(j), slot(j + 1), gp, &rows, ast)
-                     : launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, zh, slot(j), slot(j + 1), gp,
-                                          ast);
+                     ? launch_tile_grad(p, m->tile_sys, m->tile_B, stage_buffer(K, z0, z1), slot(j),
+                                        slot(j + 1), gp, &rows, ast)
+                     : launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, z0, z1, ktab, j, slot(j),
+                                          slot(j + 1), gp, ast);
             if (rc) return rc;
           }
           if (++pend == L.gbatch || j == cb) {
@@ -1137,10 +1147,12 @@ int time_sweeps(const lb_plan *p, const BatchMeta &m, const Layout &L, char *w, 
   LBX_HIP(hipEventCreate(&a));
   LBX_HIP(hipEventCreate(&b));
   int rc = LB_OK;
-  for (int r = 0; r < 2 && !rc; ++r) rc = sweep(p, m, 0, false, false, ctab, z0, q0, z1, st);
+  // Never a last sweep: kk 1 and 2 of a count of 2^20 (z0 -> z1, z1 -> z0).
+  constexpr int KFIX = 1 << 20;
+  for (int r = 0; r < 2 && !rc; ++r) rc = sweep(p, m, 0, 1, KFIX, false, ctab, nullptr, q0, z0, z1, z1, st, false, KFIX);
   if (!rc) (void)hipEventRecord(a, st);
   for (int r = 0; r < reps && !rc; ++r)
-    rc = sweep(p, m, 0, false, false, ctab, (r & 1) ? z1 : z0, q0, (r & 1) ? z0 : z1, st);
+    rc = sweep(p, m, 0, (r & 1) ? 2 : 1, KFIX, false, ctab, nullptr, q0, z0, z1, z1, st, false, KFIX);
   if (!rc) {
     (void)hipEventRecord(b, st);
     const hipError_t e = hipEventSynchronize(b);
@@ -1237,7 +1249,8 @@ extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch
         last = r;
         return r;
       };
-      rc = stream_forward(p, *mb, k, (double2 *)(w + L.ctab), 0, steps, q0, slot, z0, z1, st);
+      rc = stream_forward(p, *mb, k, (const int32_t *)(w + L.ktab), (double2 *)(w + L.ctab), 0, steps, q0,
+                          slot, z0, z1, st);
       (void)hipEventRecord(b, st);
       if (!rc) {
         const hipError_t e = hipEventSynchronize(b);

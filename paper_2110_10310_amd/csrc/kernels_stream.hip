@@ -133,12 +133,26 @@ __device__ __forceinline__ int find_segment(const StreamSeg *segs, int nseg, int
   return lo;
 }
 
-template <bool ADJ, bool LAST>
+//
+// Each segment runs its own system's sweep count K (from ktab, or kfix when
+// kfix > 0): a launch for sweep kk skips the segments with K <= kk, and
+// sweep K - 1 is that segment's last.  The iterates alternate as in the
+// host's loop: sweep kk reads q (kk = 0) or z0 / z1 (kk odd / even) and
+// writes z1 / z0, the last one writes `out` and, when want_zh, the stage
+// vector into the z buffer it does not read (stage_vector_buffer).
+template <class T>
+__device__ __forceinline__ T *stage_vector_buffer(int K, T *z0, T *z1) {
+  const int kk = K - 1;
+  return kk == 0 ? z0 : (kk & 1 ? z1 : z0);
+}
+
+template <bool ADJ>
 __global__ __launch_bounds__(STREAM_BLOCK) void sweep_kernel(
     const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg,
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
-    const double2 *__restrict__ ctab, int j, const double2 *__restrict__ zin,
-    const double2 *__restrict__ qin, double2 *__restrict__ out, double2 *__restrict__ zout) {
+    const double2 *__restrict__ ctab, const int32_t *__restrict__ ktab, int NT, int j, int kk,
+    int kfix, const double2 *__restrict__ qin, double2 *__restrict__ z0, double2 *__restrict__ z1,
+    double2 *__restrict__ out, int want_zh) {
   __shared__ double sq[SQRT_TABLE];
   __shared__ double2 dq[QMAX];
   __shared__ int sseg;
@@ -150,6 +164,11 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_kernel(
   const SysDev &S = sysv[sg.sys];
   if (tid < S.Q) dq[tid] = ctab[S.ctab_off + (int64_t)j * S.Q + tid];
   __syncthreads();
+  const int K = kfix > 0 ? kfix : ktab[((int64_t)sg.sys * NT + j) * 2 + 1];
+  if (kk >= K) return;  // this system's solve is done (uniform per workgroup)
+  const bool last = kk == K - 1;
+  const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
+  double2 *dst = last ? out : (kk & 1 ? z1 : z0);
   const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + tid;
   if (local >= sg.count) return;
   const int64_t b = local / S.N2;
@@ -167,30 +186,22 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_kernel(
   // z = w (q + h O z) without rounding 1 + h*gamma (see kernels_lds.hip).
   const double2 hdq = cscale(S.h, cmul(diag_coef(gam, dE, ADJ), qv));
   const double2 dn = cmul(w, cadd(hdq, cscale(S.h, acc)));
-  out[base + r] = LAST ? cadd(qv, cscale(2.0, dn)) : cadd(qv, dn);
-  if (LAST && zout) zout[base + r] = cadd(qv, dn);  // the converged stage vector
+  dst[base + r] = last ? cadd(qv, cscale(2.0, dn)) : cadd(qv, dn);
+  if (last && want_zh)  // the converged stage vector
+    stage_vector_buffer(K, z0, z1)[base + r] = cadd(qv, dn);
 }
 
-int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
-                 bool adj, bool last, const double2 *ctab, const double2 *zin, const double2 *qin,
-                 double2 *out, double2 *zout, hipStream_t st) {
+int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j, int kk,
+                 int kfix, bool adj, const double2 *ctab, const int32_t *ktab, const double2 *qin,
+                 double2 *z0, double2 *z1, double2 *out, bool want_zh, hipStream_t st) {
   if (nblk == 0) return LB_OK;
   dim3 g((unsigned)nblk), b(STREAM_BLOCK);
-  if (adj) {
-    if (last)
-      hipLaunchKernelGGL((sweep_kernel<true, true>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E,
-                         p->d_desc, ctab, j, zin, qin, out, zout);
-    else
-      hipLaunchKernelGGL((sweep_kernel<true, false>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E,
-                         p->d_desc, ctab, j, zin, qin, out, zout);
-  } else {
-    if (last)
-      hipLaunchKernelGGL((sweep_kernel<false, true>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E,
-                         p->d_desc, ctab, j, zin, qin, out, zout);
-    else
-      hipLaunchKernelGGL((sweep_kernel<false, false>), g, b, 0, st, p->d_sys, d_segs, nseg,
-                         p->d_E, p->d_desc, ctab, j, zin, qin, out, zout);
-  }
+  if (adj)
+    hipLaunchKernelGGL((sweep_kernel<true>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E, p->d_desc,
+                       ctab, ktab, p->NT, j, kk, kfix, qin, z0, z1, out, (int)want_zh);
+  else
+    hipLaunchKernelGGL((sweep_kernel<false>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E, p->d_desc,
+                       ctab, ktab, p->NT, j, kk, kfix, qin, z0, z1, out, (int)want_zh);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -203,7 +214,8 @@ int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nb
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
     const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg,
-    const uint64_t *__restrict__ desc, const double2 *__restrict__ zh,
+    const uint64_t *__restrict__ desc, const double2 *__restrict__ z0,
+    const double2 *__restrict__ z1, const int32_t *__restrict__ ktab, int NT, int j,
     const double2 *__restrict__ q0, const double2 *__restrict__ q1, double *__restrict__ gpart) {
   __shared__ double sq[SQRT_TABLE];
   __shared__ int sseg;
@@ -214,6 +226,8 @@ __global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
   __syncthreads();
   const StreamSeg &sg = segs[sseg];
   const SysDev &S = sysv[sg.sys];
+  // this segment's stage vector, written by its last adjoint sweep
+  const double2 *zh = stage_vector_buffer(ktab[((int64_t)sg.sys * NT + j) * 2 + 1], z0, z1);
   const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + tid;
   const bool ok = local < sg.count;
   const int64_t b = ok ? local / S.N2 : 0;
@@ -245,11 +259,11 @@ __global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
 }
 
 int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk,
-                       const double2 *zh, const double2 *q0, const double2 *q1, double *gpart,
-                       hipStream_t st) {
+                       const double2 *z0, const double2 *z1, const int32_t *ktab, int j,
+                       const double2 *q0, const double2 *q1, double *gpart, hipStream_t st) {
   if (nblk == 0) return LB_OK;
   hipLaunchKernelGGL(stream_grad_kernel, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st, p->d_sys,
-                     d_segs, nseg, p->d_desc, zh, q0, q1, gpart);
+                     d_segs, nseg, p->d_desc, z0, z1, ktab, p->NT, j, q0, q1, gpart);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }

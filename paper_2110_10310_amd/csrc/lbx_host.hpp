@@ -123,15 +123,21 @@ int launch_control_table(const lb_plan *p, int s0, int nsys, const double *alpha
 int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const double2 *x,
                  double2 *y, int B, bool adj, hipStream_t st);
 
-// zout (may be NULL): the last sweep of a step also writes the converged
-// stage vector z = q + delta there.
-int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
-                 bool adj, bool last, const double2 *ctab, const double2 *zin, const double2 *qin,
-                 double2 *out, double2 *zout, hipStream_t st);
+// Sweep kk of the stage solve of every streamed segment at step j.  Each
+// segment runs its own system's count K = ktab[sys][j][1] (kfix > 0: K =
+// kfix for all) and skips sweeps kk >= K; sweep kk reads q (kk = 0), z0 (kk
+// odd) or z1 (kk even) and writes z1 / z0, or `out` on its last sweep, which
+// with want_zh also writes the converged stage vector z = q + delta into
+// the z buffer it does not read.
+int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j, int kk,
+                 int kfix, bool adj, const double2 *ctab, const int32_t *ktab, const double2 *qin,
+                 double2 *z0, double2 *z1, double2 *out, bool want_zh, hipStream_t st);
 
+// Gradient integrands of step j; each segment's stage vector is in z0 or z1
+// as its last adjoint sweep (ktab) left it.
 int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk,
-                       const double2 *zh, const double2 *q0, const double2 *q1, double *gpart,
-                       hipStream_t st);
+                       const double2 *z0, const double2 *z1, const int32_t *ktab, int j,
+                       const double2 *q0, const double2 *q1, double *gpart, hipStream_t st);
 
 // Two-pass fixed-order sum of the stream_grad partials of nsteps steps into
 // gstep: slot z (partial rows at gpart + z slot_stride) holds step jtop - z;
