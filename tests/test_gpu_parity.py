@@ -232,6 +232,26 @@ def _grad_case(lbx, systems, alphas, rho0, batch, kind, gamma2, path, ckpt, seed
         off_a += alphas[k].size
 
 
+def test_streamed_systems_at_their_own_sweep_counts(lbx):
+    # Streamed systems of one launch whose controls differ by two orders of
+    # magnitude need different numbers of stage sweeps per step; each must
+    # stop at its own count (last sweep, stage vector and integrands chosen
+    # per segment) and still match the oracle.
+    pairs = [(81, (3, 2), 0.1), (82, (2, 3), 0.001), (83, (3, 3), 0.03)]
+    systems, alphas, rho0, batch = [], [], [], []
+    for seed, nlev, amp in pairs:
+        s, a, rng = _sys(seed, nlev, NT=20, T=2.0, amp=amp)
+        systems.append(s)
+        alphas.append(a)
+        batch.append(2)
+        rho0.append(random_pure_states(rng, s.N, 2))
+    plan = lbx.Plan(systems, path="stream")
+    k = lbx.sweep_counts(plan, dev(flat_alpha(alphas)))[:, :, 1]
+    say("own sweep counts", k.min(axis=1), k.max(axis=1))
+    assert k[0].min() > k[1].max()  # the launch runs the largest count, system 1 stops early
+    _grad_case(lbx, systems, alphas, rho0, batch, 0, 0.0, "stream", 4)
+
+
 @pytest.mark.parametrize("path,ckpt", [("lds", 1), ("stream", 1), ("stream", 4), ("stream", 0), ("auto", 7)])
 @pytest.mark.parametrize("kind,gamma2", [(0, 0.0), (1, 0.25)])
 def test_adjoint_gradient_matches_oracle(lbx, path, ckpt, kind, gamma2):
