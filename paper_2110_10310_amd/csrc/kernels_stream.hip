@@ -458,18 +458,21 @@ int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const doub
 //   dG/dIm alpha_q^{s,f} = dt sum_j 2pi S_s(t) [-gp sin(W t) + gq cos(W t)] + gamma2 Im alpha
 // with t = t_{j+1/2}, W = 2 pi Omega_q^f, gp/gq the per-step integrands.
 // ----------------------------------------------------------------------------
-__global__ void grad_contract_kernel(const SysDev *__restrict__ sysv, int nsys,
-                                     const double *__restrict__ gstep,
-                                     const double *__restrict__ alpha,
-                                     const double *__restrict__ carrier, double gamma2,
-                                     double *__restrict__ grad, int64_t total) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= total) return;
+// One workgroup per (system, q, s, f): its threads take the steps of the
+// spline's support in turn (one sincos per step for both the Re and the Im
+// coefficient), and the workgroup sums them in a fixed order.
+constexpr int CONTRACT_BLOCK = 256;
+
+__global__ __launch_bounds__(CONTRACT_BLOCK) void grad_contract_kernel(
+    const SysDev *__restrict__ sysv, int nsys, const double *__restrict__ gstep,
+    const double *__restrict__ alpha, const double *__restrict__ carrier, double gamma2,
+    double *__restrict__ grad) {
+  __shared__ double red[CONTRACT_BLOCK / 64][2];
+  const int64_t k = 2 * (int64_t)blockIdx.x;  // the Re coefficient; k + 1 is the Im one
   int s = 0;
   while (s + 1 < nsys && sysv[s + 1].alpha_off <= k) ++s;
   const SysDev &S = sysv[s];
   const int64_t loc = k - S.alpha_off;
-  const int r = (int)(loc % 2);
   const int f = (int)((loc / 2) % S.Nf);
   const int sp = (int)((loc / (2 * S.Nf)) % S.Ns);
   const int q = (int)(loc / (2 * S.Nf * S.Ns));
@@ -478,8 +481,8 @@ __global__ void grad_contract_kernel(const SysDev *__restrict__ sysv, int nsys,
   int j1 = (int)ceil((sp + 1.0) * S.dtau / S.dt) + 1;
   j0 = j0 < 0 ? 0 : j0;
   j1 = j1 > S.NT - 1 ? S.NT - 1 : j1;
-  double acc = 0.0;
-  for (int j = j0; j <= j1; ++j) {
+  double are = 0.0, aim = 0.0;
+  for (int j = j0 + (int)threadIdx.x; j <= j1; j += CONTRACT_BLOCK) {
     const double t = ((double)j + 0.5) * S.dt;
     const double B = bspline2(t / S.dtau - (double)sp + 0.5);
     if (B == 0.0) continue;
@@ -487,17 +490,31 @@ __global__ void grad_contract_kernel(const SysDev *__restrict__ sysv, int nsys,
     sincos(Om * t, &sn, &cs);
     const double gp = gstep[2 * S.ctab_off + (int64_t)j * 2 * S.Q + 2 * q];
     const double gq = gstep[2 * S.ctab_off + (int64_t)j * 2 * S.Q + 2 * q + 1];
-    acc += B * (r == 0 ? gp * cs + gq * sn : -gp * sn + gq * cs);
+    are += B * (gp * cs + gq * sn);
+    aim += B * (-gp * sn + gq * cs);
   }
-  grad[k] = TWO_PI * S.dt * acc + gamma2 * alpha[k];
+  are = wave_sum<64>(are);
+  aim = wave_sum<64>(aim);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = are;
+    red[threadIdx.x >> 6][1] = aim;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < CONTRACT_BLOCK / 64; ++w) v += red[w][threadIdx.x];
+    grad[k + threadIdx.x] = TWO_PI * S.dt * v + gamma2 * alpha[k + threadIdx.x];
+  }
 }
 
 int launch_grad_contract(const lb_plan *p, const double *gstep, const double *alpha,
                          double gamma2, double *grad, hipStream_t st) {
   const int nsys = (int)p->sys.size();
   const int64_t total = p->sys[nsys - 1].alpha_off + p->sys[nsys - 1].nalpha;
-  hipLaunchKernelGGL(grad_contract_kernel, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, st,
-                     p->d_sys, nsys, gstep, alpha, p->d_carrier, gamma2, grad, total);
+  if (total == 0) return LB_OK;
+  hipLaunchKernelGGL(grad_contract_kernel, dim3((unsigned)(total / 2)), dim3(CONTRACT_BLOCK), 0, st,
+                     p->d_sys, nsys, gstep, alpha, p->d_carrier, gamma2, grad);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
