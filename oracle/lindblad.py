@@ -34,7 +34,9 @@ Readings of passages that are silent or garbled (listed in the design doc too):
   initial states of the system.
 
 Parity pins (tests/test_oracle_pins.py): discrete and continuum T1 decay,
-dephasing rate and phase, the T1 cascade, closed two-level Rabi oscillation,
+dephasing rate and phase, the T1 cascade, closed two-level Rabi oscillation
+and the phase of its coherence (which fixes d a + conj(d) a^+ against the
+swapped coupling),
 trace and Hermiticity preservation, norm preservation without collapse
 operators, IMR against the matrix exponential (second order), the Cayley form
 of one IMR step, the J_Frob/J_Tr identity, basis-matrix purity, B-spline

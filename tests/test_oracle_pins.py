@@ -164,6 +164,28 @@ def test_rabi_closed_two_level(ar, ai):
     assert abs(st[-1][0, 1, 1].real - np.sin(dabs * s.T) ** 2) < 5e-3
 
 
+@pytest.mark.parametrize("ar,ai", [(0.006, -0.008), (-0.002, 0.009)])
+def test_control_coupling_orientation_closed_two_level(ar, ai):
+    # H_c = d a + conj(d) a^+ (Sec. II).  From |0><0| under a constant complex
+    # d the exact solution has psi_1 = -i (conj(d)/|d|) sin(|d| t), so
+    # rho_10 = -i (conj(d)/|d|) sin(|d| t) cos(|d| t).  M is normal with
+    # eigenvalues 0 and -+2i|d|, which IMR maps to rotations by
+    # 2 atan(|d| dt) per step: rho_10^j = -i (conj(d)/|d|) sin(phi_j) cos(phi_j)
+    # with phi_j = j atan(|d| dt).  The phase of rho_10 fixes which of d and
+    # conj(d) multiplies the lowering operator; P1 alone depends on |d| only.
+    s = mk((2,), Ns=5, T=12.0, NT=120)
+    alpha = np.zeros((1, 5, 1, 2))
+    alpha[..., 0] = ar
+    alpha[..., 1] = ai
+    d = 2 * np.pi * (ar + 1j * ai)
+    _, st = oracle.imr_forward(s, alpha, proj(2, 0)[None], keep_states=True)
+    for j in range(0, 121, 5):
+        phi = j * np.arctan(abs(d) * s.dt)
+        ref = -1j * (np.conj(d) / abs(d)) * np.sin(phi) * np.cos(phi)
+        assert abs(st[j][0, 1, 0] - ref) < 1e-13
+        assert abs(st[j][0, 0, 1] - np.conj(ref)) < 1e-13
+
+
 def test_trace_hermiticity_and_closed_norm():
     rng = np.random.default_rng(5)
     s = random_system(rng, (2, 3), NT=30, T=3.0)
