@@ -37,12 +37,17 @@
  * destroyed with lb_plan_destroy.
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Kernels
- * are enqueued on it.  lindblad_apply, control_table and objective return
- * without synchronising.  imr_step, forward_solve and adjoint_gradient
- * synchronise the stream to read the per-step sweep counts (adjoint_gradient
- * again to check that G is finite); forward_solve and adjoint_gradient have
- * completed their work when they return OK.
- * Concurrent calls on one plan need separate workspaces.
+ * are enqueued on it; no entry point synchronises in the middle of its work
+ * (the number of stage-solve sweeps of every step is decided on the device).
+ * Conditions that only the device sees (a non-finite objective, a step whose
+ * stage solve cannot be handled) are raised in a status word at the start
+ * of the call's workspace.  With LB_OPT_SYNC on (the default) imr_step,
+ * forward_solve, objective, adjoint_backward and adjoint_gradient wait for
+ * their work at the end and return that status as their code; with it off
+ * they return as soon as the work is enqueued and lb_status() reads the
+ * status later.  lindblad_apply and control_table never synchronise.
+ * Options are copied when a call starts; concurrent calls on one plan (from
+ * several threads or streams) need separate workspaces.
  *
  * Errors: every entry point returns LB_OK (0) or a negative code; no C++
  * exception or abort crosses the ABI.  lb_last_error() returns a message for
@@ -63,15 +68,16 @@ extern "C" {
 #define LB_ENOMEM (-2)        /* workspace too small or device allocation failed */
 #define LB_EDEVICE (-3)       /* a HIP call failed; the message has the HIP error */
 #define LB_EUNSUPPORTED (-4)  /* inputs outside what the kernels handle */
-#define LB_ENONFINITE (-5)    /* NaN or Inf in the objective */
+#define LB_ENONFINITE (-5)    /* NaN or Inf in an objective */
 
 #define LB_J_FROB 0  /* J = 1/2 ||rho_tar - rho||_F^2            (Sec. III, eq. Jmeasure) */
 #define LB_J_TR 1    /* J = 1 - Re Tr(rho_tar^+ rho)              (Sec. III, eq. Jmeasure) */
 
 /* Workspace queries (lb_workspace_bytes). */
 #define LB_OP_IMR_STEP 0
-#define LB_OP_FORWARD 1
-#define LB_OP_GRADIENT 2
+#define LB_OP_FORWARD 1   /* forward_solve, objective */
+#define LB_OP_GRADIENT 2  /* adjoint_gradient (the trajectory is kept in the workspace) */
+#define LB_OP_BACKWARD 3  /* adjoint_backward (the trajectory is the caller's) */
 
 /* Plan options (lb_plan_set_option). */
 #define LB_OPT_PATH 0      /* 0 auto, 1 LDS-resident persistent kernels, 2 streaming sweeps */
@@ -79,20 +85,26 @@ extern "C" {
 #define LB_OPT_PROFILE 2   /* 1: time kernel launches of forward_solve and adjoint_gradient
                               with HIP events on the call's stream; 0 (default): off */
 #define LB_OPT_TILE 3      /* 1 (default): block-tiled kernels for large systems of
-                              equal-level subsystems; 2: the two-pass split kernels
-                              where the system is eligible (else as 1); 0: generic
-                              streaming kernels */
+                              equal-level subsystems; 2: as 1, but lindblad_apply runs
+                              the multi-pass kernels where the system has a pass plan;
+                              0: generic streaming kernels */
 #define LB_OPT_TILE_KI 4   /* block shape of the block-tiled kernels, 10*KR + KC with KR
                               (KC) row (column) digits inside a block; 0 (default): the
                               shape listed first for the system */
 #define LB_OPT_GRAPH 5     /* > 0: streamed time loops are captured as HIP graphs of this
                               many steps and replayed (one graph launch per chunk);
                               0 (default): kernels are launched directly */
+#define LB_OPT_HISTORY 6   /* 0..4, default 3: converged stage increments of earlier steps
+                              from which a streamed step extrapolates its first iterate
+                              (order HISTORY-1 in the frame of the diagonal Cayley factor);
+                              0 starts every stage solve from q */
+#define LB_OPT_SYNC 7      /* 1 (default): calls wait for their work and return the device
+                              status; 0: calls return once enqueued (see lb_status) */
 
 /* Kernel families timed by LB_OPT_PROFILE (lb_profile_read). */
 #define LB_KERNEL_LDS_FORWARD 0  /* persistent forward time loop, LDS-resident */
 #define LB_KERNEL_LDS_ADJOINT 1  /* persistent adjoint time loop + gradient integrands */
-#define LB_KERNEL_SWEEP 2        /* one streaming stage-solve sweep */
+#define LB_KERNEL_SWEEP 2        /* one streamed implicit-midpoint step (all its sweeps) */
 #define LB_KERNEL_STREAM_GRAD 3  /* streaming gradient integrands of one step */
 #define LB_KERNEL_COUNT 4
 
@@ -131,11 +143,27 @@ int lb_plan_set_option(lb_plan *plan, int32_t option, double value);
 
 /* Bytes of workspace the operation `op` (LB_OP_*) needs for the batch
  * batch_per_sys[nsys] (HOST).  For LB_OP_IMR_STEP, batch_per_sys may name
- * one system by giving 0 for every other.  ckpt_every (LB_OP_GRADIENT)
- * is the forward-state checkpoint interval of streamed systems: 1 keeps
- * every state, 0 picks ceil(sqrt(NT)). */
+ * one system by giving 0 for every other.  ckpt_every is the checkpoint
+ * interval of the forward trajectory (LB_OP_GRADIENT, LB_OP_BACKWARD, and
+ * LB_OP_FORWARD when forward_solve keeps a trajectory): 0 picks
+ * ceil(sqrt(NT)) for streamed systems and keeps every state of the systems
+ * small enough for the LDS-resident kernels; 1 keeps every state; c > 1
+ * keeps every c-th state of every system (systems that would be
+ * LDS-resident are streamed then, since those kernels keep every state).
+ * The workspace begins with the call's status word (see lb_status). */
 int lb_workspace_bytes(const lb_plan *plan, int32_t op, const int32_t *batch_per_sys,
                        int32_t ckpt_every, size_t *bytes);
+
+/* Bytes of the trajectory buffer that forward_solve fills and
+ * adjoint_backward reads, for the batch and ckpt_every (as above). */
+int lb_trajectory_bytes(const lb_plan *plan, const int32_t *batch_per_sys, int32_t ckpt_every,
+                        size_t *bytes);
+
+/* Waits for `stream` and returns the status that the last call using the
+ * workspace `ws` (DEVICE) raised on the device: LB_OK, LB_ENONFINITE (an
+ * objective is not finite) or LB_EUNSUPPORTED (a step's stage-solve
+ * contraction bound is >= 0.5, or a stage solve hit its sweep cap). */
+int lb_status(const lb_plan *plan, const void *ws, void *stream);
 
 /* Launch count and summed duration [ms] of kernel family `kernel` (LB_KERNEL_*)
  * over the calls made while LB_OPT_PROFILE was on; reset != 0 clears them.
@@ -182,25 +210,46 @@ int lindblad_apply(const lb_plan *plan, int32_t sys, double t, const double *alp
  * q_out = q_in + dt M z.  With adjoint != 0 it takes the adjoint step of
  * App. B eq. linsystem_adjoint: (I - dt/2 M^+) zh = q_in, q_out = q_in + dt M^+ zh.
  * q_in, q_out: DEVICE [B][N][N], distinct.  ws: DEVICE, at least
- * lb_workspace_bytes(LB_OP_IMR_STEP) bytes.  Uses the streaming sweeps. */
+ * lb_workspace_bytes(LB_OP_IMR_STEP) bytes.  One persistent launch takes the
+ * fixed-point sweeps of the stage solve, starting from q_in, as many as the
+ * a-posteriori bound after the first sweep asks for (at least two). */
 int imr_step(const lb_plan *plan, int32_t sys, int32_t j, const double *alpha, const void *q_in,
              void *q_out, int32_t B, int32_t adjoint, void *ws, size_t ws_bytes, void *stream);
 
 /* Integrates every state of every system from t = 0 to T (App. A).
  * alpha: DEVICE, all systems concatenated; rho0, rhoT: DEVICE batched states;
- * batch_per_sys: HOST [nsys].  ws: DEVICE, lb_workspace_bytes(LB_OP_FORWARD). */
+ * batch_per_sys: HOST [nsys].  traj: DEVICE buffer of lb_trajectory_bytes
+ * bytes that receives the forward states adjoint_backward needs (checkpoints
+ * every ckpt_every steps, see lb_workspace_bytes), or NULL (ckpt_every is
+ * then ignored).  ws: DEVICE, lb_workspace_bytes(LB_OP_FORWARD, ckpt_every). */
 int forward_solve(const lb_plan *plan, const double *alpha, const void *rho0, void *rhoT,
-                  const int32_t *batch_per_sys, void *ws, size_t ws_bytes, void *stream);
+                  const int32_t *batch_per_sys, void *traj, int32_t ckpt_every, void *ws,
+                  size_t ws_bytes, void *stream);
 
 /* G_s = (1/M_s) sum_i beta_i J(rho_tar_i, rho_i(T)) + gamma2/2 ||alpha_s||^2 for
  * every system s (Sec. III eq. optimproblem with gamma1 = 0), M_s = batch_per_sys[s].
  * rhoT, rhotar: DEVICE batched states; beta: DEVICE [total states];
  * alpha: DEVICE; G: DEVICE [nsys]; J: DEVICE [total states] or NULL, receives
- * each J_i (unweighted).  ws: DEVICE, lb_workspace_bytes(LB_OP_FORWARD). */
+ * each J_i (unweighted).  ws: DEVICE, lb_workspace_bytes(LB_OP_FORWARD).
+ * The status (LB_OPT_SYNC, lb_status) is LB_ENONFINITE when a G is not finite. */
 int objective(const lb_plan *plan, int32_t kind, const void *rhoT, const void *rhotar,
               const double *beta, const int32_t *batch_per_sys, double gamma2,
               const double *alpha, double *G, double *J, void *ws, size_t ws_bytes,
               void *stream);
+
+/* Adjoint pass and exact discrete gradient (App. B eqs. linsystem_adjoint,
+ * reducedgradient) from a trajectory that forward_solve kept with the same
+ * ckpt_every: terminal condition (beta_i/M) dJ/d(conj q) at the rho(T) of the
+ * trajectory, adjoint implicit-midpoint steps backwards with the forward
+ * states recomputed between checkpoints, and
+ *   grad = sum_s gscale[s] (dG_s/dalpha_s)   (gscale NULL: all ones),
+ * which is the backward pass of G for an incoming gradient gscale (the
+ * adjoint is linear in its terminal condition).  gscale: DEVICE [nsys] or
+ * NULL; grad: DEVICE like alpha.  ws: DEVICE, lb_workspace_bytes(LB_OP_BACKWARD). */
+int adjoint_backward(const lb_plan *plan, int32_t kind, const double *alpha, const void *traj,
+                     int32_t ckpt_every, const void *rhotar, const double *beta,
+                     const int32_t *batch_per_sys, double gamma2, const double *gscale,
+                     double *grad, void *ws, size_t ws_bytes, void *stream);
 
 /* Objective and its exact discrete gradient (App. B eqs. linsystem_adjoint,
  * reducedgradient): forward solve with checkpoints, terminal condition
@@ -209,20 +258,20 @@ int objective(const lb_plan *plan, int32_t kind, const void *rhoT, const void *r
  * dG/dalpha = sum_j dt Re <zh^j, dM/dalpha z^j> + gamma2 alpha.
  * G: DEVICE [nsys]; grad: DEVICE like alpha; rhoT: DEVICE batched states or
  * NULL.  ws: DEVICE, lb_workspace_bytes(LB_OP_GRADIENT, ckpt_every) bytes.
- * Returns LB_ENONFINITE when a G is not finite. */
+ * The status (LB_OPT_SYNC) is LB_ENONFINITE when a G is not finite. */
 int adjoint_gradient(const lb_plan *plan, int32_t kind, const double *alpha, const void *rho0,
                      const void *rhotar, const double *beta, const int32_t *batch_per_sys,
                      double gamma2, int32_t ckpt_every, double *G, double *grad, void *rhoT,
                      void *ws, size_t ws_bytes, void *stream);
 
-/* Autotuner for the streamed systems of batch_per_sys (HOST): times one stage
- * sweep of the generic kernel and of every instantiated block shape of the
- * block-tiled kernels, then a short streamed forward run with and without
- * graph capture, on the workspace (DEVICE, lb_workspace_bytes(LB_OP_FORWARD)
- * bytes; its contents are overwritten), and sets LB_OPT_TILE, LB_OPT_TILE_KI and
- * LB_OPT_GRAPH of the plan to the fastest.  result: HOST [3], the chosen
- * values.  alpha: DEVICE.  Synchronises the stream.  A plan without streamed
- * systems in this batch is left unchanged. */
+/* Autotuner for the streamed systems of batch_per_sys (HOST): times a few
+ * implicit-midpoint steps of the generic step kernel and of every
+ * instantiated block shape of the block-tiled one on the workspace (DEVICE,
+ * lb_workspace_bytes(LB_OP_FORWARD) bytes; its contents are overwritten), and
+ * sets LB_OPT_TILE and LB_OPT_TILE_KI of the plan to the fastest.  result:
+ * HOST [3], the values of LB_OPT_TILE, LB_OPT_TILE_KI and LB_OPT_GRAPH.
+ * alpha: DEVICE.  Synchronises the stream.  A plan without streamed systems
+ * in this batch is left unchanged. */
 int lb_autotune(lb_plan *plan, const double *alpha, const int32_t *batch_per_sys, void *ws,
                 size_t ws_bytes, void *stream, int32_t *result);
 

@@ -12,6 +12,7 @@ from .api import (  # noqa: F401
     forward_solve,
     objective,
     adjoint_gradient,
+    adjoint_backward,
     LindbladObjective,
     lindblad_objective,
 )

@@ -25,6 +25,7 @@ LB_J_TR = 1
 LB_OP_IMR_STEP = 0
 LB_OP_FORWARD = 1
 LB_OP_GRADIENT = 2
+LB_OP_BACKWARD = 3
 
 LB_OPT_PATH = 0
 LB_OPT_SOLVE_TOL = 1
@@ -32,6 +33,8 @@ LB_OPT_PROFILE = 2
 LB_OPT_TILE = 3
 LB_OPT_TILE_KI = 4
 LB_OPT_GRAPH = 5
+LB_OPT_HISTORY = 6
+LB_OPT_SYNC = 7
 
 LB_KERNEL_LDS_FORWARD = 0
 LB_KERNEL_LDS_ADJOINT = 1
@@ -62,11 +65,15 @@ SIGNATURES = {
     "control_table": (C.c_int, [_p, _i32, _p, _p, _p]),
     "lindblad_apply": (C.c_int, [_p, _i32, C.c_double, _p, _p, _p, _i32, _i32, _p]),
     "imr_step": (C.c_int, [_p, _i32, _i32, _p, _p, _p, _i32, _i32, _p, C.c_size_t, _p]),
-    "forward_solve": (C.c_int, [_p, _p, _p, _p, _ip, _p, C.c_size_t, _p]),
+    "forward_solve": (C.c_int, [_p, _p, _p, _p, _ip, _p, _i32, _p, C.c_size_t, _p]),
     "objective": (C.c_int, [_p, _i32, _p, _p, _p, _ip, C.c_double, _p, _p, _p, _p,
                             C.c_size_t, _p]),
     "adjoint_gradient": (C.c_int, [_p, _i32, _p, _p, _p, _p, _ip, C.c_double, _i32, _p, _p,
                                    _p, _p, C.c_size_t, _p]),
+    "adjoint_backward": (C.c_int, [_p, _i32, _p, _p, _i32, _p, _p, _ip, C.c_double, _p, _p,
+                                   _p, C.c_size_t, _p]),
+    "lb_trajectory_bytes": (C.c_int, [_p, _ip, _i32, C.POINTER(C.c_size_t)]),
+    "lb_status": (C.c_int, [_p, _p, _p]),
     "lb_profile_read": (C.c_int, [_p, _i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), _i32]),
     "lb_profile_work": (C.c_int, [_p, _i32, C.POINTER(C.c_int64)]),
     "sweep_counts": (C.c_int, [_p, _p, _ip, _p]),

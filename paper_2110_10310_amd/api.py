@@ -179,6 +179,21 @@ class Plan:
             self._ws[key] = ws
         return ws
 
+    def trajectory_bytes(self, batch: Sequence[int], ckpt_every: int = 0) -> int:
+        b = self.batch_array(batch)
+        out = C.c_size_t()
+        check(lib.lb_trajectory_bytes(self.handle, b.ctypes.data_as(nat._ip), int(ckpt_every), C.byref(out)),
+              "lb_trajectory_bytes")
+        return out.value
+
+    def trajectory(self, batch: Sequence[int], ckpt_every: int = 0) -> torch.Tensor:
+        """A new buffer for the forward trajectory of forward_solve."""
+        return torch.empty(max(self.trajectory_bytes(batch, ckpt_every), 1), dtype=torch.uint8, device="cuda")
+
+    def status(self, ws: torch.Tensor) -> None:
+        """Raises LbxError for the device status of the last call on ws."""
+        check(lib.lb_status(self.handle, _vp(ws), _stream()), "lb_status")
+
     def entries(self, batch: Sequence[int]) -> int:
         return int(sum(int(b) * n * n for b, n in zip(batch, self.N)))
 
@@ -243,15 +258,24 @@ def _states(plan: Plan, t: torch.Tensor, name: str, batch) -> torch.Tensor:
 
 
 def forward_solve(plan: Plan, alpha: torch.Tensor, rho0: torch.Tensor, batch: Sequence[int],
-                  out: torch.Tensor | None = None) -> torch.Tensor:
-    """rho(T) for every state of every system (batched layout)."""
+                  out: torch.Tensor | None = None, traj: torch.Tensor | None = None,
+                  ckpt_every: int = 0) -> torch.Tensor:
+    """rho(T) for every state of every system (batched layout).  With `traj`
+    (a uint8 tensor of Plan.trajectory_bytes(batch, ckpt_every) bytes) the
+    forward states that adjoint_backward needs are kept in it."""
     b = plan.batch_array(batch)
     _need(alpha, "alpha", torch.float64, int(plan.alpha_off[-1]))
     _states(plan, rho0, "rho0", batch)
     rhoT = torch.empty_like(rho0) if out is None else _states(plan, out, "out", batch)
-    ws = plan.workspace(nat.LB_OP_FORWARD, batch)
+    if traj is not None:
+        _need(traj, "traj", torch.uint8)
+        if traj.numel() < plan.trajectory_bytes(batch, ckpt_every):
+            raise ValueError("traj is smaller than Plan.trajectory_bytes")
+    ck = int(ckpt_every) if traj is not None else 1
+    ws = plan.workspace(nat.LB_OP_FORWARD, batch, ck)
     check(lib.forward_solve(plan.handle, _vp(alpha), _vp(rho0), _vp(rhoT), b.ctypes.data_as(nat._ip),
-                            _vp(ws), ws.numel(), _stream()), "forward_solve")
+                            _vp(traj) if traj is not None else None, ck, _vp(ws), ws.numel(), _stream()),
+          "forward_solve")
     return rhoT
 
 
@@ -292,35 +316,57 @@ def adjoint_gradient(plan: Plan, kind, alpha: torch.Tensor, rho0: torch.Tensor,
     return G, grad, rhoT
 
 
+def adjoint_backward(plan: Plan, kind, alpha: torch.Tensor, traj: torch.Tensor, ckpt_every: int,
+                     rhotar: torch.Tensor, beta: torch.Tensor, batch: Sequence[int], gamma2: float = 0.0,
+                     gscale: torch.Tensor | None = None) -> torch.Tensor:
+    """sum_s gscale[s] dG_s/dalpha from a trajectory kept by forward_solve."""
+    b = plan.batch_array(batch)
+    _need(alpha, "alpha", torch.float64, int(plan.alpha_off[-1]))
+    _need(traj, "traj", torch.uint8)
+    _states(plan, rhotar, "rhotar", batch)
+    _need(beta, "beta", torch.float64, int(b.sum()))
+    if gscale is not None:
+        _need(gscale, "gscale", torch.float64, len(plan.systems))
+    grad = torch.empty_like(alpha)
+    ws = plan.workspace(nat.LB_OP_BACKWARD, batch, ckpt_every)
+    check(lib.adjoint_backward(plan.handle, KIND[kind], _vp(alpha), _vp(traj), int(ckpt_every), _vp(rhotar),
+                               _vp(beta), b.ctypes.data_as(nat._ip), float(gamma2),
+                               _vp(gscale) if gscale is not None else None, _vp(grad), _vp(ws), ws.numel(),
+                               _stream()), "adjoint_backward")
+    return grad
+
+
 class LindbladObjective(torch.autograd.Function):
     """G(alpha) per system; backward runs the discrete adjoint (App. B).
 
     forward(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2, ckpt_every).
-    When alpha requires a gradient the forward pass calls adjoint_gradient
-    (forward solve with checkpoints, objective, adjoint sweep, gradient) and
-    keeps dG/dalpha for backward; otherwise it calls forward_solve and
-    objective only.
+    The forward pass integrates every state (forward_solve) and forms G
+    (objective); when alpha requires a gradient it keeps the forward
+    trajectory (checkpoints every ckpt_every steps, see lb_workspace_bytes)
+    for the backward pass.  The backward pass runs the adjoint sweep from that
+    trajectory with the incoming gradient of G as the weights of the terminal
+    conditions (adjoint_backward).
     """
 
     @staticmethod
-    def forward(ctx, alpha, plan, kind, rho0, rhotar, beta, batch, gamma2=0.0, ckpt_every=1):
+    def forward(ctx, alpha, plan, kind, rho0, rhotar, beta, batch, gamma2=0.0, ckpt_every=0):
         alpha = alpha.detach().contiguous()
-        if ctx.needs_input_grad[0]:
-            G, grad, _ = adjoint_gradient(plan, kind, alpha, rho0, rhotar, beta, batch, gamma2,
-                                          ckpt_every)
-            ctx.save_for_backward(grad)
-            ctx.plan = plan
-        else:
-            rhoT = forward_solve(plan, alpha, rho0, batch)
-            G, _ = objective(plan, kind, rhoT, rhotar, beta, batch, gamma2, alpha)
+        traj = plan.trajectory(batch, ckpt_every) if ctx.needs_input_grad[0] else None
+        rhoT = forward_solve(plan, alpha, rho0, batch, traj=traj, ckpt_every=ckpt_every)
+        G, _ = objective(plan, kind, rhoT, rhotar, beta, batch, gamma2, alpha)
+        if traj is not None:
+            ctx.save_for_backward(alpha, traj, rhotar, beta)
+            ctx.plan, ctx.kind, ctx.batch, ctx.gamma2, ctx.ckpt_every = plan, kind, batch, gamma2, ckpt_every
         return G
 
     @staticmethod
     def backward(ctx, gG):
-        (grad,) = ctx.saved_tensors
-        scale = gG.to(torch.float64)[ctx.plan.alpha_system_index()]
-        return grad * scale, None, None, None, None, None, None, None, None
+        alpha, traj, rhotar, beta = ctx.saved_tensors
+        gscale = gG.detach().to(torch.float64).contiguous()
+        grad = adjoint_backward(ctx.plan, ctx.kind, alpha, traj, ctx.ckpt_every, rhotar, beta, ctx.batch,
+                                ctx.gamma2, gscale)
+        return grad, None, None, None, None, None, None, None, None
 
 
-def lindblad_objective(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2=0.0, ckpt_every=1):
+def lindblad_objective(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2=0.0, ckpt_every=0):
     return LindbladObjective.apply(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2, ckpt_every)

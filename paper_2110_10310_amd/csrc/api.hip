@@ -1,6 +1,6 @@
 // C ABI of liblbx: plan construction, workspace layout and the entry points
 // declared in include/lbx.h.  Host code only; all arithmetic on states runs
-// in the kernels of kernels_stream.hip and kernels_lds.hip.
+// in the kernels (kernels_*.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +33,7 @@ int hip_fail(hipError_t e, const char *what) {
   return LB_EDEVICE;
 }
 
+// Profiling state is guarded by p->mu (held by every caller below).
 static void prof_account(const lb_plan *p, const lbx_prof_pending &e) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, e.start, e.stop) == hipSuccess) {
@@ -44,6 +45,7 @@ static void prof_account(const lb_plan *p, const lbx_prof_pending &e) {
 }
 
 void prof_resolve(const lb_plan *p) {
+  std::lock_guard<std::mutex> g(p->mu);
   for (auto &e : p->prof_pending) {
     if (hipEventSynchronize(e.stop) == hipSuccess) {
       prof_account(p, e);
@@ -53,6 +55,11 @@ void prof_resolve(const lb_plan *p) {
     }
   }
   p->prof_pending.clear();
+}
+
+void prof_add_work(const lb_plan *p, int kernel, int64_t work) {
+  std::lock_guard<std::mutex> g(p->mu);
+  p->prof_work[kernel] += work;
 }
 
 hipEvent_t ProfScope::prof_event(const lb_plan *p) {
@@ -83,6 +90,11 @@ void ProfScope::prof_drain(const lb_plan *p) {
 // ----------------------------------------------------------------------------
 namespace {
 
+lbx_opts snapshot(const lb_plan *p) {
+  std::lock_guard<std::mutex> g(p->mu);
+  return p->opts;
+}
+
 struct LdsClass {
   int block, ept;
   int qc;      // > 0: specialised kernel for qc subsystems; 0: generic kernel
@@ -109,6 +121,7 @@ struct BatchMeta {
   int64_t st_blocks = 0;
   int tile_sys = -1;       // single streamed system run by the block-tiled kernels
   int tile_B = 0;
+  int tile_k = 0;          // its block shape
   // device copies (one allocation)
   void *dmem = nullptr;
   LdsItem *d_items = nullptr;
@@ -137,12 +150,13 @@ PlanExtra *extra_of(const lb_plan *p) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int path_for(const lb_plan *p, int s, int path) {
+// Path of system s: 1 LDS-resident, 2 streamed, -1 not possible.
+int path_for(const lb_plan *p, int s, int path, bool stream_small) {
   int blk, ept;
   const bool fits = lds_shape(p->sys[s].N2, &blk, &ept);
-  if (path == 1) return fits ? 1 : -1;
+  if (path == 1) return fits && !stream_small ? 1 : -1;
   if (path == 2) return 2;
-  return fits ? 1 : 2;
+  return fits && !stream_small ? 1 : 2;
 }
 
 template <class T>
@@ -152,16 +166,30 @@ T *carve(char *&cur, size_t n) {
   return r;
 }
 
-// path_override: -1 uses the plan's LB_OPT_PATH.
-int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int path_override = -1) {
+// Checkpoint interval of streamed systems: 0 picks ceil(sqrt(NT)).
+int ckpt_interval(const lb_plan *p, int ckpt_every) {
+  if (ckpt_every > 0) return std::min(ckpt_every, p->NT);
+  return std::max(1, (int)std::ceil(std::sqrt((double)p->NT)));
+}
+int ckpt_count(int NT, int c) { return (NT - 1) / c + 2; }
+
+// An explicit checkpoint interval above 1 is honoured by every system: the
+// LDS-resident kernels keep every state, so systems that would run there are
+// streamed instead.
+bool streams_small(int ckpt_every) { return ckpt_every > 1; }
+
+// path_override: -1 uses the option LB_OPT_PATH.
+int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool stream_small,
+                BatchMeta **out, int path_override = -1) {
   const int nsys = (int)p->sys.size();
-  const int path = path_override >= 0 ? path_override : p->path;
+  const int path = path_override >= 0 ? path_override : o.path;
   std::vector<int32_t> key(batch, batch + nsys);
   for (int s = 0; s < nsys; ++s)
     if (key[s] < 0) return fail(LB_EINVAL, "batch_per_sys has a negative entry");
   key.push_back(path);
-  key.push_back(p->tile);
-  key.push_back(p->tile_ki);
+  key.push_back(o.tile);
+  key.push_back(o.tile_ki);
+  key.push_back(stream_small ? 1 : 0);
   PlanExtra *ex = extra_of(p);
   std::lock_guard<std::mutex> g(ex->mu);
   auto it = ex->batches.find(key);
@@ -185,10 +213,11 @@ int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int pat
       m->path[s] = 0;
       continue;
     }
-    m->path[s] = path_for(p, s, path);
+    m->path[s] = path_for(p, s, path, stream_small);
     if (m->path[s] < 0)
       return fail(LB_EUNSUPPORTED, "system " + std::to_string(s) +
-                                       " does not fit the LDS-resident kernels (N^2 > 4096)");
+                                       " cannot run on the LDS-resident kernels (N^2 > 4096, or a checkpoint "
+                                       "interval above 1)");
   }
   m->sys_state0[nsys] = st;
   m->total_entries = off;
@@ -220,7 +249,7 @@ int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int pat
         itm.parts = c.qc > 0 ? c.block / 16 : c.block / 64;
         itm.gp_off = m->lds_gpart;
         m->lds_gpart += (int64_t)NT * itm.parts * 2 * S.Q;
-        itm.wterm = 0.0;  // set per call (beta lives on the device); see below
+        itm.wterm = 0.0;  // set per call (beta lives on the device)
         m->items.push_back(itm);
       }
     }
@@ -244,11 +273,17 @@ int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int pat
       m->segs.push_back(sg);
       m->seg_state0.push_back(m->sys_state0[s]);
     }
+  if ((int)m->segs.size() > LB_STEP_MAXSEG)
+    return fail(LB_EUNSUPPORTED, "more than " + std::to_string(LB_STEP_MAXSEG) + " streamed systems in one batch");
   m->st_entries = coff;
   m->st_blocks = blk;
-  if (m->segs.size() == 1 && p->tile && tile_nl(p, m->segs[0].sys)) {
-    m->tile_sys = m->segs[0].sys;
-    m->tile_B = m->segs[0].nstates;
+  if (m->segs.size() == 1 && o.tile) {
+    const int k = tile_ki(p, m->segs[0].sys, o.tile_ki);
+    if (k) {
+      m->tile_sys = m->segs[0].sys;
+      m->tile_B = m->segs[0].nstates;
+      m->tile_k = k;
+    }
   }
   // Per-state tables for the objective.
   std::vector<int32_t> state_sys(std::max(1, st));
@@ -294,27 +329,45 @@ int build_batch(const lb_plan *p, const int32_t *batch, BatchMeta **out, int pat
   return LB_OK;
 }
 
-// Checkpoint bookkeeping of the streaming adjoint: states kept at multiples
-// of c below NT and at NT.
-int ckpt_interval(const lb_plan *p, int ckpt_every) {
-  if (ckpt_every > 0) return std::min(ckpt_every, p->NT);
-  return std::max(1, (int)std::ceil(std::sqrt((double)p->NT)));
+// Most workgroups a cooperative step launch can have (256-thread workgroups,
+// at most 2048 threads per compute unit, 256 compute units): the size of the
+// per-workgroup maxima of the block-tiled step kernels.
+constexpr int64_t MAX_STEP_GRID = 8192;
+
+// Trajectory storage (forward states the adjoint needs): LDS-resident items
+// keep every state, [items][NT+1][N^2]; streamed systems keep checkpoints
+// [nck][streamed entries] at multiples of c and at NT.
+struct TrajLayout {
+  size_t hist = 0, ckpt = 0, total = 0;
+  int c = 1, nck = 0;
+};
+
+TrajLayout traj_layout(const lb_plan *p, const BatchMeta &m, int ckpt_every) {
+  TrajLayout T;
+  T.c = ckpt_interval(p, ckpt_every);
+  T.nck = ckpt_count(p->NT, T.c);
+  T.hist = 0;
+  T.ckpt = align256((size_t)m.lds_hist_entries * sizeof(double2));
+  T.total = T.ckpt + align256((m.segs.empty() ? 0 : (size_t)T.nck) * m.st_entries * sizeof(double2));
+  return T;
 }
-int ckpt_count(int NT, int c) { return (NT - 1) / c + 2; }
 
 // Workspace layout of one operation.
 struct Layout {
-  size_t ctab = 0, ktab = 0, ttab = 0, gstep = 0, objpart = 0, hist = 0, zhist = 0, gpart = 0,
-         items = 0;
-  size_t st_q0 = 0, st_q1 = 0, st_z0 = 0, st_z1 = 0, st_qh0 = 0, st_qh1 = 0, ckpt = 0, seg = 0,
-         st_gpart = 0, st_gfin = 0, rhoT = 0;
+  size_t status = 0, ctab = 0, ktab = 0, ttab = 0, objpart = 0, items = 0, sweeps = 0, kout = 0, gstep = 0;
+  size_t traj = 0;  // LB_OP_GRADIENT: the trajectory lives in the workspace
+  size_t rhoT = 0;  // LB_OP_GRADIENT: rho(T) when the caller does not want it
+  size_t zhist = 0, gpart = 0;
+  size_t q0 = 0, q1 = 0, z0 = 0, z1 = 0, zsf = 0, ringf = 0, zsa = 0, ringa = 0, zh = 0, qh0 = 0, qh1 = 0,
+         seg = 0, st_gpart = 0, st_gfin = 0, part = 0, segk = 0;
   size_t total = 0;
-  int c = 1, nck = 0;
+  TrajLayout T;
+  int H = 0;
   int64_t grows = 1;  // gradient partial rows per step (streamed systems)
   int gbatch = 1;     // steps whose partial rows are reduced by one launch
 };
 
-Layout layout(const lb_plan *p, int op, const BatchMeta &m, int ckpt_every) {
+Layout layout(const lb_plan *p, const lbx_opts &o, int op, const BatchMeta &m, int ckpt_every) {
   Layout L;
   size_t cur = 0;
   auto take = [&](size_t bytes) {
@@ -324,45 +377,56 @@ Layout layout(const lb_plan *p, int op, const BatchMeta &m, int ckpt_every) {
   };
   const int nsys = (int)p->sys.size();
   const size_t E = (size_t)m.st_entries * sizeof(double2);
+  const bool st = !m.segs.empty();
+  L.H = st && op != LB_OP_IMR_STEP ? o.history : 0;
+  L.status = take(sizeof(int32_t));
   L.ctab = take((size_t)p->ctab_total * sizeof(double2));
   L.ktab = take((size_t)nsys * p->NT * 2 * sizeof(int32_t));
   L.ttab = take((size_t)nsys * p->NT * sizeof(double2));
+  L.kout = take((size_t)nsys * p->NT * sizeof(int32_t));
   L.objpart = take((size_t)std::max(1, m.total_states) * 64 * sizeof(double));
   L.items = take(std::max<size_t>(1, m.items.size()) * sizeof(LdsItem));
+  L.sweeps = take(std::max<size_t>(1, m.items.size()) * sizeof(int64_t));
+  L.part = take((size_t)std::max<int64_t>(m.st_blocks, MAX_STEP_GRID) * sizeof(double2));
+  L.segk = take(std::max<size_t>(1, m.segs.size()) * sizeof(int32_t));
+  L.z0 = take(st ? E : 0);
+  L.z1 = take(st ? E : 0);
+  L.T = traj_layout(p, m, ckpt_every);
   if (op == LB_OP_IMR_STEP) {
-    L.st_z0 = take(E);
-    L.st_z1 = take(E);
-  } else if (op == LB_OP_FORWARD) {
-    L.st_q0 = take(E);
-    L.st_q1 = take(E);
-    L.st_z0 = take(E);
-    L.st_z1 = take(E);
-  } else {
-    L.gstep = take((size_t)2 * p->ctab_total * sizeof(double));
-    L.hist = take((size_t)m.lds_hist_entries * sizeof(double2));
-    bool fast = false;
-    for (const auto &c : m.classes) fast = fast || c.qc > 0;
-    L.zhist = take(fast ? (size_t)m.lds_hist_entries * sizeof(double2) : 0);
-    L.gpart = take((size_t)m.lds_gpart * sizeof(double));
-    L.rhoT = take((size_t)m.total_entries * sizeof(double2));
-    L.c = ckpt_interval(p, ckpt_every);
-    L.nck = ckpt_count(p->NT, L.c);
-    L.st_q0 = take(E);
-    L.st_q1 = take(E);
-    L.st_z0 = take(E);
-    L.st_z1 = take(E);
-    L.st_qh0 = take(E);
-    L.st_qh1 = take(E);
-    L.ckpt = take((size_t)L.nck * E);
-    L.seg = take((size_t)std::max(0, L.c - 1) * E);
-    L.grows = std::max<int64_t>(
-        1, std::max<int64_t>(m.st_blocks, m.tile_sys >= 0 ? tile_grad_rows(p, m.tile_sys, m.tile_B) : 0));
-    // Up to a checkpoint interval of steps, within 256 MB of partial rows.
-    const size_t row_bytes = (size_t)L.grows * 2 * QMAX * sizeof(double);
-    L.gbatch = (int)std::max<int64_t>(1, std::min<int64_t>(L.c, (int64_t)((256u << 20) / row_bytes)));
-    L.st_gpart = take((size_t)L.gbatch * row_bytes);
-    L.st_gfin = take((size_t)L.gbatch * stream_grad_fin_doubles((int)m.segs.size()) * sizeof(double));
+    L.total = cur;
+    return L;
   }
+  L.q0 = take(st ? E : 0);
+  L.q1 = take(st ? E : 0);
+  L.zsf = take(st && L.H ? E : 0);
+  L.ringf = take(st ? (size_t)L.H * E : 0);
+  if (op == LB_OP_FORWARD) {
+    L.total = cur;
+    return L;
+  }
+  // LB_OP_GRADIENT (trajectory included) and LB_OP_BACKWARD
+  if (op == LB_OP_GRADIENT) {
+    L.traj = take(L.T.total);
+    L.rhoT = take((size_t)m.total_entries * sizeof(double2));
+  }
+  L.gstep = take((size_t)2 * p->ctab_total * sizeof(double));
+  bool fast = false;
+  for (const auto &c : m.classes) fast = fast || c.qc > 0;
+  L.zhist = take(fast ? (size_t)m.lds_hist_entries * sizeof(double2) : 0);
+  L.gpart = take((size_t)m.lds_gpart * sizeof(double));
+  L.zsa = take(st && L.H ? E : 0);
+  L.ringa = take(st ? (size_t)L.H * E : 0);
+  L.zh = take(st ? E : 0);
+  L.qh0 = take(st ? E : 0);
+  L.qh1 = take(st ? E : 0);
+  L.seg = take(st ? (size_t)std::max(0, L.T.c - 1) * E : 0);
+  L.grows = std::max<int64_t>(
+      1, std::max<int64_t>(m.st_blocks, m.tile_sys >= 0 ? tile_grad_rows(p, m.tile_sys, m.tile_B, m.tile_k) : 0));
+  // Up to a checkpoint interval of steps, within 256 MB of partial rows.
+  const size_t row_bytes = (size_t)L.grows * 2 * QMAX * sizeof(double);
+  L.gbatch = (int)std::max<int64_t>(1, std::min<int64_t>(L.T.c, (int64_t)((256u << 20) / row_bytes)));
+  L.st_gpart = take(st ? (size_t)L.gbatch * row_bytes : 0);
+  L.st_gfin = take(st ? (size_t)L.gbatch * stream_grad_fin_doubles((int)m.segs.size()) * sizeof(double) : 0);
   L.total = cur;
   return L;
 }
@@ -372,40 +436,19 @@ int check_plan(const lb_plan *p) {
   return LB_OK;
 }
 
-int fetch_ktab(const lb_plan *p, const int32_t *d_ktab, std::vector<int32_t> &k, hipStream_t st) {
-  const size_t n = p->sys.size() * (size_t)p->NT * 2;
-  k.resize(n);
-  LBX_HIP(hipMemcpyAsync(k.data(), d_ktab, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  LBX_HIP(hipStreamSynchronize(st));
-  return LB_OK;
-}
-
-int check_k(const lb_plan *p, const std::vector<int32_t> &k, const BatchMeta &m) {
-  const int nsys = (int)p->sys.size();
-  for (int s = 0; s < nsys; ++s) {
-    if (m.path[s] == 0) continue;
-    for (int j = 0; j < p->NT; ++j)
-      if (k[((size_t)s * p->NT + j) * 2] < 1)
-        return fail(LB_EUNSUPPORTED,
-                    "system " + std::to_string(s) + " step " + std::to_string(j) +
-                        ": the stage-solve contraction bound is >= 0.5 (step or control amplitude too large)");
-  }
-  return LB_OK;
-}
-
-// Weights beta_b / M_s of the LDS items live on the device (beta is a device
-// array), so the adjoint kernels read them through a per-call item copy.
-__global__ void item_weights_kernel(LdsItem *items, int n, const double *beta,
-                                    const int32_t *sys_state0) {
+// Weights (beta_b / M_s) times gscale[s] of the LDS items live on the device
+// (beta is a device array), so the adjoint kernels read them through a
+// per-call item copy.
+__global__ void item_weights_kernel(LdsItem *items, int n, const double *beta, const int32_t *sys_state0,
+                                    const double *gscale) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   LdsItem &it = items[k];
   const int M = sys_state0[it.sys + 1] - sys_state0[it.sys];
-  it.wterm = beta[sys_state0[it.sys] + it.b] / (double)M;
+  it.wterm = beta[sys_state0[it.sys] + it.b] / (double)M * (gscale ? gscale[it.sys] : 1.0);
 }
 
-int copy_segments(const BatchMeta &m, const double2 *src, bool src_batched, double2 *dst,
-                  hipStream_t st) {
+int copy_segments(const BatchMeta &m, const double2 *src, bool src_batched, double2 *dst, hipStream_t st) {
   for (const auto &sg : m.segs) {
     const double2 *a = src + (src_batched ? sg.boff : sg.off);
     double2 *b = dst + (src_batched ? sg.off : sg.boff);
@@ -414,19 +457,32 @@ int copy_segments(const BatchMeta &m, const double2 *src, bool src_batched, doub
   return LB_OK;
 }
 
+// Reads the status word of a workspace (synchronises the stream) and turns
+// its bits into an error code.
+int status_code(const int32_t *d_status, hipStream_t st) {
+  int32_t s = 0;
+  LBX_HIP(hipMemcpyAsync(&s, d_status, sizeof(s), hipMemcpyDeviceToHost, st));
+  LBX_HIP(hipStreamSynchronize(st));
+  if (s & LB_STATUS_NONFINITE) return fail(LB_ENONFINITE, "an objective is not finite");
+  if (s & LB_STATUS_THETA)
+    return fail(LB_EUNSUPPORTED,
+                "a stage-solve contraction bound is >= 0.5 (step or control amplitude too large)");
+  if (s & LB_STATUS_NOCONV) return fail(LB_EUNSUPPORTED, "a stage solve did not converge within the sweep cap");
+  return LB_OK;
+}
+
 // LB_OPT_GRAPH: the streamed time loop is recorded in chunks of steps with
 // stream capture on a private stream and replayed as one graph launch per
 // chunk.  Chunks of equal shape reuse the executable graph through
 // hipGraphExecUpdate.  Only kernel launches are captured.
 struct GraphRun {
-  const lb_plan *p;
   hipStream_t user;
   hipStream_t cap = nullptr;
   hipEvent_t ev = nullptr;
   hipGraphExec_t exec = nullptr;
   bool on;
   bool active = false;  // a capture is open
-  GraphRun(const lb_plan *p_, hipStream_t s) : p(p_), user(s), on(p_->graph_steps > 0) {}
+  GraphRun(const lbx_opts &o, hipStream_t s) : user(s), on(o.graph_steps > 0) {}
   int init() {
     if (!on) return LB_OK;
     LBX_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -440,12 +496,10 @@ struct GraphRun {
     LBX_HIP(hipStreamWaitEvent(cap, ev, 0));
     LBX_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     active = true;
-    p->capturing = true;
     return LB_OK;
   }
   int end() {
     if (!on) return LB_OK;
-    p->capturing = false;
     active = false;
     hipGraph_t g = nullptr;
     LBX_HIP(hipStreamEndCapture(cap, &g));
@@ -475,7 +529,6 @@ struct GraphRun {
   }
   ~GraphRun() {
     if (!on) return;
-    p->capturing = false;
     if (active) {  // an error left the capture open: close and drop it
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(cap, &g);
@@ -491,65 +544,289 @@ struct GraphRun {
   }
 };
 
-// Sweep kk of the stage solves of the streamed segments at step j, K being
-// the largest count among them.  The iterates alternate: sweep kk reads q
-// (kk = 0), z0 (kk odd) or z1 (kk even) and writes z1 / z0, or `out` on the
-// last one, which with want_zh also writes the converged stage vector into
-// the z buffer it does not read (stage_buffer).  The tiled kernels serve one
-// system, whose count is K; the generic kernel runs every segment at its own
-// count from ktab (kfix > 0 instead gives every segment kfix).
-double2 *stage_buffer(int K, double2 *z0, double2 *z1) {
-  const int kl = K - 1;
-  return kl == 0 ? z0 : (kl & 1 ? z1 : z0);
-}
-
-int sweep(const lb_plan *p, const BatchMeta &m, int j, int kk, int K, bool adj,
-          const double2 *ctab, const int32_t *ktab, const double2 *q, double2 *z0, double2 *z1,
-          double2 *out, hipStream_t st, bool want_zh = false, int kfix = 0) {
-  if (m.tile_sys >= 0) {
-    const bool last = kk == K - 1;
-    const double2 *zin = kk == 0 ? q : (kk & 1 ? z0 : z1);
-    double2 *dst = last ? out : (kk & 1 ? z1 : z0);
-    return launch_tile(p, m.tile_sys, m.tile_B, last ? 2 : 1, adj, nullptr, 0.0, ctab, j, zin, q, dst,
-                       last && want_zh ? stage_buffer(K, z0, z1) : nullptr, st);
+// Everything one call's streamed steps need.
+struct StreamCtx {
+  const lb_plan *p;
+  const lbx_opts *o;
+  const BatchMeta *m;
+  const Layout *L;
+  char *w;
+  bool prof;
+  StepArgs base() const {
+    StepArgs A{};
+    A.sysv = p->d_sys;
+    A.Etab = p->d_E;
+    A.desc = p->d_desc;
+    A.ctab = (const double2 *)(w + L->ctab);
+    A.ttab = (const double2 *)(w + L->ttab);
+    A.NT = p->NT;
+    A.z0 = (double2 *)(w + L->z0);
+    A.z1 = (double2 *)(w + L->z1);
+    A.part = (double2 *)(w + L->part);
+    A.segk = (int32_t *)(w + L->segk);
+    A.kout = prof ? (int32_t *)(w + L->kout) : nullptr;
+    A.status = (int32_t *)(w + L->status);
+    A.tol = o->tol;
+    A.kcap = 64;
+    A.B = m->tile_B;
+    A.segs = m->d_segs;
+    A.nseg = (int)m->segs.size();
+    A.nblk = m->st_blocks;
+    return A;
   }
-  return launch_sweep(p, m.d_segs, (int)m.segs.size(), m.st_blocks, j, kk, kfix, adj, ctab, ktab, q, z0,
-                      z1, out, want_zh, st);
+};
+
+// History of one streamed pass: the start iterate of the next step and the
+// ring of converged increments; n counts the steps taken in the pass.
+struct PassHist {
+  double2 *zs = nullptr;
+  double2 *ring = nullptr;
+  int H = 0;
+  int n = 0;
+};
+
+// One persistent step launch over every streamed system: q -> out at step j.
+int stream_step(const StreamCtx &c, int j, bool adj, const double2 *q, double2 *out, PassHist &ph, double2 *zh,
+                hipStream_t st) {
+  StepArgs A = c.base();
+  A.j = j;
+  A.q = q;
+  A.out = out;
+  A.zh = zh;
+  A.H = ph.H;
+  A.n = ph.n;
+  A.m = ph.H > 0 ? std::min(ph.n + 1, ph.H) : 0;
+  A.zstart = (ph.H > 0 && ph.n > 0) ? ph.zs : nullptr;
+  A.znext = ph.H > 0 ? ph.zs : nullptr;
+  A.ring = ph.ring;
+  A.ring_stride = c.m->st_entries;
+  ProfScope ps(c.p, c.prof, LB_KERNEL_SWEEP, st);
+  const int rc = launch_step(c.p, A, adj, c.m->tile_sys, c.m->tile_k, st);
+  ph.n++;
+  return rc;
 }
 
-// Entry-sweeps of step j over the streamed segments, each at its own count.
-int64_t step_sweep_work(const lb_plan *p, const BatchMeta &m, const std::vector<int32_t> &k, int j) {
-  int64_t w = 0;
-  for (const auto &sg : m.segs) w += (int64_t)k[((size_t)sg.sys * p->NT + j) * 2 + 1] * sg.count;
-  return w;
-}
-
-// Streaming forward steps j0..j1-1 of every segment.  slot(j) returns the
-// buffer that receives q^j (j > j0); q^{j0} is `qstart`.
+// Streamed forward steps j0..j1-1.  slot(j) returns the buffer that receives
+// q^j (j > j0); q^{j0} is `qstart`.  Each call starts a fresh history.
 template <class Slot>
-int stream_forward(const lb_plan *p, const BatchMeta &m, const std::vector<int32_t> &k,
-                   const int32_t *ktab, const double2 *ctab, int j0, int j1, const double2 *qstart,
-                   Slot slot, double2 *z0, double2 *z1, hipStream_t user) {
-  GraphRun gr(p, user);
+int stream_forward(const StreamCtx &c, int j0, int j1, const double2 *qstart, Slot slot, hipStream_t user) {
+  GraphRun gr(*c.o, user);
   if (int rc = gr.init()) return rc;
   const hipStream_t st = gr.stream();
-  const int chunk = gr.on ? p->graph_steps : (j1 - j0);
+  const int chunk = gr.on ? c.o->graph_steps : std::max(1, j1 - j0);
+  PassHist ph;
+  ph.H = c.L->H;
+  ph.zs = (double2 *)(c.w + c.L->zsf);
+  ph.ring = (double2 *)(c.w + c.L->ringf);
   const double2 *cur = qstart;
   for (int c0 = j0; c0 < j1; c0 += chunk) {
     const int c1 = std::min(j1, c0 + chunk);
     if (int rc = gr.begin()) return rc;
     for (int j = c0; j < c1; ++j) {
-      int K = 1;
-      for (const auto &sg : m.segs) K = std::max(K, (int)k[((size_t)sg.sys * p->NT + j) * 2 + 1]);
       double2 *out = slot(j + 1);
-      ProfScope ps(p, LB_KERNEL_SWEEP, st, step_sweep_work(p, m, k, j), K);
-      for (int kk = 0; kk < K; ++kk)
-        if (int rc = sweep(p, m, j, kk, K, false, ctab, ktab, cur, z0, z1, out, st)) return rc;
+      if (int rc = stream_step(c, j, false, cur, out, ph, nullptr, st)) return rc;
       cur = out;
     }
     if (int rc = gr.end()) return rc;
   }
   return LB_OK;
+}
+
+// Adds the entry-sweeps of one LDS-resident pass to the profile (read back
+// from the kernels: a synchronisation, only while profiling).
+int lds_profile_work(const lb_plan *p, const BatchMeta &m, int kernel, const int64_t *slots, hipStream_t st) {
+  if (!slots || m.items.empty()) return LB_OK;
+  std::vector<int64_t> sw(m.items.size());
+  LBX_HIP(hipMemcpyAsync(sw.data(), slots, sw.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  LBX_HIP(hipStreamSynchronize(st));
+  int64_t work = 0;
+  for (size_t i = 0; i < m.items.size(); ++i) work += sw[i] * p->sys[m.items[i].sys].N2;
+  prof_add_work(p, kernel, work);
+  return LB_OK;
+}
+
+// Adds the entry-sweeps of the streamed steps of a call (kout) to the profile.
+int stream_profile_work(const lb_plan *p, const BatchMeta &m, const int32_t *kout, hipStream_t st) {
+  if (m.segs.empty()) return LB_OK;
+  const size_t n = p->sys.size() * (size_t)p->NT;
+  std::vector<int32_t> k(n);
+  LBX_HIP(hipMemcpyAsync(k.data(), kout, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  LBX_HIP(hipStreamSynchronize(st));
+  int64_t work = 0;
+  for (const auto &sg : m.segs) {
+    int64_t ks = 0;
+    for (int j = 0; j < p->NT; ++j) ks += k[(size_t)sg.sys * p->NT + j];
+    work += ks * sg.count;
+  }
+  prof_add_work(p, LB_KERNEL_SWEEP, work);
+  return LB_OK;
+}
+
+// Start of a call: status word and profiling counters cleared.
+int call_begin(const lb_plan *p, const Layout &L, char *w, bool prof, hipStream_t st) {
+  if (int rc = launch_fill_zero(w + L.status, 4, st)) return rc;
+  if (prof)
+    if (int rc = launch_fill_zero(w + L.kout, p->sys.size() * (size_t)p->NT * sizeof(int32_t), st)) return rc;
+  return LB_OK;
+}
+
+// End of a call: profiling read-back, then (LB_OPT_SYNC) the status.
+int call_end(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w, bool prof,
+             hipStream_t st) {
+  if (prof) {
+    if (int rc = stream_profile_work(p, m, (const int32_t *)(w + L.kout), st)) return rc;
+    prof_resolve(p);
+  }
+  if (o.sync) return status_code((const int32_t *)(w + L.status), st);
+  return LB_OK;
+}
+
+// Forward pass of every system: LDS-resident items keep every state in the
+// trajectory (when traj is not NULL), streamed systems keep checkpoints.
+int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w,
+                const double *alpha, const double2 *rho0, double2 *rhoT, char *traj, bool prof, hipStream_t st) {
+  double2 *ctab = (double2 *)(w + L.ctab);
+  int32_t *ktab = (int32_t *)(w + L.ktab);
+  double2 *ttab = (double2 *)(w + L.ttab);
+  int32_t *status = (int32_t *)(w + L.status);
+  int rc;
+  if ((rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, ttab, o.tol, st))) return rc;
+  // LDS-resident systems: one persistent launch per kernel class.
+  double2 *hist = traj ? (double2 *)(traj + L.T.hist) : nullptr;
+  int64_t *slots = prof ? (int64_t *)(w + L.sweeps) : nullptr;
+  for (const auto &c : m.classes) {
+    ProfScope ps(p, prof, LB_KERNEL_LDS_FORWARD, st);
+    rc = c.qc > 0 ? launch_lds_forward_fast(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, ctab, ttab,
+                                            o.tol, rho0, rhoT, hist, slots ? slots + c.i0 : nullptr, status, st)
+                  : launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab, rho0, rhoT,
+                                       hist, slots ? slots + c.i0 : nullptr, status, st);
+    if (rc) return rc;
+  }
+  if ((rc = lds_profile_work(p, m, LB_KERNEL_LDS_FORWARD, slots, st))) return rc;
+  if (m.segs.empty()) return LB_OK;
+  // Streamed systems: one persistent launch per step over all of them.
+  StreamCtx sc{p, &o, &m, &L, w, prof};
+  double2 *q0 = (double2 *)(w + L.q0), *q1 = (double2 *)(w + L.q1);
+  const size_t E = (size_t)m.st_entries;
+  double2 *ck = traj ? (double2 *)(traj + L.T.ckpt) : nullptr;
+  double2 *start = ck ? ck : q0;
+  if ((rc = copy_segments(m, rho0, true, start, st))) return rc;
+  const int NT = p->NT, c = L.T.c;
+  const double2 *last_out = start;
+  auto slot = [&](int j) -> double2 * {
+    double2 *r;
+    if (ck && (j % c == 0 || j == NT)) r = ck + (size_t)(j == NT ? L.T.nck - 1 : j / c) * E;
+    else r = (last_out == q0) ? q1 : q0;
+    last_out = r;
+    return r;
+  };
+  if ((rc = stream_forward(sc, 0, NT, start, slot, st))) return rc;
+  return copy_segments(m, last_out, false, rhoT, st);
+}
+
+// Adjoint pass and gradient of every system from a forward trajectory.
+int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w, int kind,
+                 const double *alpha, const char *traj, const double2 *rhotar, const double *beta, double gamma2,
+                 const double *gscale, double *grad, bool prof, hipStream_t st) {
+  int rc;
+  double2 *ctab = (double2 *)(w + L.ctab);
+  int32_t *ktab = (int32_t *)(w + L.ktab);
+  double2 *ttab = (double2 *)(w + L.ttab);
+  int32_t *status = (int32_t *)(w + L.status);
+  double *gstep = (double *)(w + L.gstep);
+  if ((rc = launch_fill_zero(gstep, (size_t)2 * p->ctab_total * sizeof(double), st))) return rc;
+  // LDS-resident adjoint.
+  if (!m.items.empty()) {
+    const double2 *hist = (const double2 *)(traj + L.T.hist);
+    LdsItem *items = (LdsItem *)(w + L.items);
+    LBX_HIP(hipMemcpyAsync(items, m.d_items, m.items.size() * sizeof(LdsItem), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(item_weights_kernel, dim3(((int)m.items.size() + 127) / 128), dim3(128), 0, st, items,
+                       (int)m.items.size(), beta, m.d_sys_state0, gscale);
+    LBX_HIP(hipGetLastError());
+    double *gpart = (double *)(w + L.gpart);
+    int64_t *slots = prof ? (int64_t *)(w + L.sweeps) : nullptr;
+    for (const auto &c : m.classes) {
+      ProfScope ps(p, prof, LB_KERNEL_LDS_ADJOINT, st);
+      rc = c.qc > 0 ? launch_lds_adjoint_fast(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, kind, ctab, ttab,
+                                              o.tol, rhotar, hist, (double2 *)(w + L.zhist), gpart,
+                                              slots ? slots + c.i0 : nullptr, status, st)
+                    : launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab, ktab, rhotar,
+                                         hist, gpart, slots ? slots + c.i0 : nullptr, status, st);
+      if (rc) return rc;
+    }
+    if ((rc = lds_profile_work(p, m, LB_KERNEL_LDS_ADJOINT, slots, st))) return rc;
+    if ((rc = launch_lds_grad_reduce(p, m.d_lds_item_range, (int)m.lds_sys.size(), m.d_lds_sys, items, gpart,
+                                     gstep, st)))
+      return rc;
+  }
+  // Streamed adjoint with checkpoint recomputation.
+  if (!m.segs.empty()) {
+    StreamCtx sc{p, &o, &m, &L, w, prof};
+    const size_t E = (size_t)m.st_entries;
+    const int NT = p->NT, c = L.T.c;
+    double2 *ck = (double2 *)(traj + L.T.ckpt);
+    double2 *seg = (double2 *)(w + L.seg);
+    double2 *qh[2] = {(double2 *)(w + L.qh0), (double2 *)(w + L.qh1)};
+    double2 *zh = (double2 *)(w + L.zh);
+    double *sgp = (double *)(w + L.st_gpart), *sgf = (double *)(w + L.st_gfin);
+    const int64_t gstride = L.grows * 2 * QMAX;  // doubles per step slot
+    int pend = 0, jtop = 0;
+    int64_t rows = 0;
+    const int nseg = (int)m.segs.size();
+    if ((rc = launch_terminal(p, kind, m.d_segs, nseg, m.st_blocks, ck + (size_t)(L.T.nck - 1) * E, rhotar, beta,
+                              m.d_seg_state0, gscale, qh[0], st)))
+      return rc;
+    PassHist ah;  // the adjoint's history runs across segments
+    ah.H = L.H;
+    ah.zs = (double2 *)(w + L.zsa);
+    ah.ring = (double2 *)(w + L.ringa);
+    int cur = 0;
+    const int nsegs_t = (NT + c - 1) / c;
+    for (int sgi = nsegs_t - 1; sgi >= 0; --sgi) {
+      const int j0 = sgi * c, j1 = std::min(NT, j0 + c);
+      auto slot = [&](int j) -> double2 * {
+        if (j == j0) return ck + (size_t)(j0 / c) * E;
+        if (j == j1) return ck + (size_t)(j1 == NT ? L.T.nck - 1 : j1 / c) * E;
+        return seg + (size_t)(j - j0 - 1) * E;
+      };
+      // Recompute q^{j0+1} .. q^{j1-1} from the checkpoint.
+      if (j1 - j0 > 1)
+        if ((rc = stream_forward(sc, j0, j1 - 1, slot(j0), slot, st))) return rc;
+      GraphRun gr(o, st);
+      if ((rc = gr.init())) return rc;
+      const hipStream_t ast = gr.stream();
+      const int chunk = gr.on ? o.graph_steps : c;
+      for (int ce = j1; ce > j0; ce -= chunk) {
+        const int cb = std::max(j0, ce - chunk);
+        if ((rc = gr.begin())) return rc;
+        for (int j = ce - 1; j >= cb; --j) {
+          // The last sweep also writes the stage vector zh = qh^{j+1} + delta
+          // = (qh^j + qh^{j+1})/2.
+          if ((rc = stream_step(sc, j, true, qh[cur], qh[cur ^ 1], ah, zh, ast))) return rc;
+          // Partial rows of the pending steps go to successive slots and are
+          // reduced together (every gbatch steps and at the end of a chunk).
+          if (pend == 0) jtop = j;
+          double *gp = sgp + (size_t)pend * gstride;
+          {
+            ProfScope ps(p, prof, LB_KERNEL_STREAM_GRAD, ast, m.st_entries);
+            rc = m.tile_sys >= 0
+                     ? launch_tile_grad(p, m.tile_sys, m.tile_B, m.tile_k, zh, slot(j), slot(j + 1), gp, &rows, ast)
+                     : launch_stream_grad(p, m.d_segs, nseg, m.st_blocks, zh, slot(j), slot(j + 1), gp, ast);
+            if (rc) return rc;
+          }
+          if (++pend == L.gbatch || j == cb) {
+            if ((rc = launch_stream_grad_finalize(p, m.d_segs, nseg, jtop, pend, sgp, gstride, sgf, gstep, rows,
+                                                  ast)))
+              return rc;
+            pend = 0;
+          }
+          cur ^= 1;
+        }
+        if ((rc = gr.end())) return rc;
+      }
+    }
+  }
+  return launch_grad_contract(p, gstep, alpha, gamma2, gscale, grad, st);
 }
 
 }  // namespace
@@ -699,7 +976,6 @@ extern "C" void lb_plan_destroy(lb_plan *p) {
   (void)hipFree(p->d_E);
   (void)hipFree(p->d_desc);
   (void)hipFree(p->d_carrier);
-  if (p->d_sweeps) (void)hipFree(p->d_sweeps);
   for (auto &e : p->prof_pending) {
     (void)hipEventSynchronize(e.stop);
     (void)hipEventDestroy(e.start);
@@ -720,67 +996,98 @@ extern "C" int lb_plan_info(const lb_plan *p, int32_t sys, int32_t *N, int32_t *
 
 extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
   if (int rc = check_plan(p)) return rc;
+  std::lock_guard<std::mutex> g(p->mu);
+  lbx_opts &o = p->opts;
   if (option == LB_OPT_PATH) {
     if (value != 0 && value != 1 && value != 2) return fail(LB_EINVAL, "LB_OPT_PATH must be 0, 1 or 2");
-    p->path = (int)value;
+    o.path = (int)value;
     return LB_OK;
   }
   if (option == LB_OPT_TILE) {
     if (value != 0 && value != 1 && value != 2) return fail(LB_EINVAL, "LB_OPT_TILE must be 0, 1 or 2");
-    p->tile = (int)value;
+    o.tile = (int)value;
     return LB_OK;
   }
   if (option == LB_OPT_TILE_KI) {
     if (value < 0 || value > 99 || value != (int)value) return fail(LB_EINVAL, "LB_OPT_TILE_KI must be 0..99");
-    p->tile_ki = (int)value;
+    o.tile_ki = (int)value;
     return LB_OK;
   }
   if (option == LB_OPT_GRAPH) {
     if (value < 0 || value > 100000 || value != (int)value) return fail(LB_EINVAL, "LB_OPT_GRAPH must be 0..100000");
-    p->graph_steps = (int)value;
+    o.graph_steps = (int)value;
     return LB_OK;
   }
   if (option == LB_OPT_PROFILE) {
-    p->profile = value != 0.0;
+    o.profile = value != 0.0;
     return LB_OK;
   }
   if (option == LB_OPT_SOLVE_TOL) {
     if (!(value > 0.0 && value < 1.0)) return fail(LB_EINVAL, "LB_OPT_SOLVE_TOL must be in (0, 1)");
-    p->tol = value;
+    o.tol = value;
+    return LB_OK;
+  }
+  if (option == LB_OPT_HISTORY) {
+    if (value < 0 || value > 4 || value != (int)value) return fail(LB_EINVAL, "LB_OPT_HISTORY must be 0..4");
+    o.history = (int)value;
+    return LB_OK;
+  }
+  if (option == LB_OPT_SYNC) {
+    o.sync = value != 0.0;
     return LB_OK;
   }
   return fail(LB_EINVAL, "unknown option");
 }
 
-extern "C" int lb_workspace_bytes(const lb_plan *p, int32_t op, const int32_t *batch_per_sys,
-                                  int32_t ckpt_every, size_t *bytes) {
+extern "C" int lb_workspace_bytes(const lb_plan *p, int32_t op, const int32_t *batch_per_sys, int32_t ckpt_every,
+                                  size_t *bytes) {
   if (int rc = check_plan(p)) return rc;
   if (!batch_per_sys || !bytes) return fail(LB_EINVAL, "NULL argument");
-  if (op < LB_OP_IMR_STEP || op > LB_OP_GRADIENT) return fail(LB_EINVAL, "unknown op");
+  if (op < LB_OP_IMR_STEP || op > LB_OP_BACKWARD) return fail(LB_EINVAL, "unknown op");
   if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
+  const lbx_opts o = snapshot(p);
   BatchMeta *m;
-  // imr_step always streams.
-  if (int rc = build_batch(p, batch_per_sys, &m, op == LB_OP_IMR_STEP ? 2 : -1)) return rc;
-  *bytes = layout(p, op, *m, ckpt_every).total;
+  // imr_step always streams; only the trajectory-keeping operations honour ckpt_every.
+  const bool small = op != LB_OP_IMR_STEP && streams_small(ckpt_every);
+  if (int rc = build_batch(p, o, batch_per_sys, small, &m, op == LB_OP_IMR_STEP ? 2 : -1)) return rc;
+  *bytes = layout(p, o, op, *m, ckpt_every).total;
   return LB_OK;
+}
+
+extern "C" int lb_trajectory_bytes(const lb_plan *p, const int32_t *batch_per_sys, int32_t ckpt_every,
+                                   size_t *bytes) {
+  if (int rc = check_plan(p)) return rc;
+  if (!batch_per_sys || !bytes) return fail(LB_EINVAL, "NULL argument");
+  if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
+  const lbx_opts o = snapshot(p);
+  BatchMeta *m;
+  if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &m)) return rc;
+  *bytes = traj_layout(p, *m, ckpt_every).total;
+  return LB_OK;
+}
+
+extern "C" int lb_status(const lb_plan *p, const void *ws, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!ws) return fail(LB_EINVAL, "NULL argument");
+  return status_code((const int32_t *)ws, (hipStream_t)stream);
 }
 
 // ----------------------------------------------------------------------------
 // Entry points
 // ----------------------------------------------------------------------------
-extern "C" int control_table(const lb_plan *p, int32_t sys, const double *alpha, void *table,
-                             void *stream) {
+extern "C" int control_table(const lb_plan *p, int32_t sys, const double *alpha, void *table, void *stream) {
   if (int rc = check_plan(p)) return rc;
   if (sys < 0 || sys >= (int)p->sys.size()) return fail(LB_EINVAL, "sys out of range");
   if (!alpha || !table) return fail(LB_EINVAL, "NULL argument");
+  const lbx_opts o = snapshot(p);
   // alpha is this system's block; the kernel adds alpha_off, so shift it back.
   const double *abase = alpha - p->sys[sys].alpha_off;
-  return launch_control_table(p, sys, 1, abase, (double2 *)table, p->sys[sys].ctab_off, nullptr, nullptr,
+  return launch_control_table(p, sys, 1, abase, (double2 *)table, p->sys[sys].ctab_off, nullptr, nullptr, o.tol,
                               (hipStream_t)stream);
 }
 
-extern "C" int lindblad_apply(const lb_plan *p, int32_t sys, double t, const double *alpha,
-                              const void *x, void *y, int32_t B, int32_t adjoint, void *stream) {
+extern "C" int lindblad_apply(const lb_plan *p, int32_t sys, double t, const double *alpha, const void *x,
+                              void *y, int32_t B, int32_t adjoint, void *stream) {
   if (int rc = check_plan(p)) return rc;
   if (sys < 0 || sys >= (int)p->sys.size()) return fail(LB_EINVAL, "sys out of range");
   if (B < 0) return fail(LB_EINVAL, "B must be >= 0");
@@ -790,13 +1097,13 @@ extern "C" int lindblad_apply(const lb_plan *p, int32_t sys, double t, const dou
   const size_t bytes = (size_t)B * p->sys[sys].N2 * sizeof(double2);
   const char *xa = (const char *)x, *ya = (const char *)y;
   if (xa < ya + bytes && ya < xa + bytes) return fail(LB_EINVAL, "x and y overlap");
-  return launch_apply(p, sys, t, alpha, (const double2 *)x, (double2 *)y, B, adjoint != 0,
+  const lbx_opts o = snapshot(p);
+  return launch_apply(p, sys, t, alpha, (const double2 *)x, (double2 *)y, B, adjoint != 0, o.tile, o.tile_ki,
                       (hipStream_t)stream);
 }
 
-extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *alpha,
-                        const void *q_in, void *q_out, int32_t B, int32_t adjoint, void *ws,
-                        size_t ws_bytes, void *stream) {
+extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *alpha, const void *q_in,
+                        void *q_out, int32_t B, int32_t adjoint, void *ws, size_t ws_bytes, void *stream) {
   if (int rc = check_plan(p)) return rc;
   const int nsys = (int)p->sys.size();
   if (sys < 0 || sys >= nsys) return fail(LB_EINVAL, "sys out of range");
@@ -809,153 +1116,125 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
     const size_t bytes = (size_t)B * p->sys[sys].N2 * sizeof(double2);
     if (a < c + bytes && c < a + bytes) return fail(LB_EINVAL, "q_in and q_out overlap");
   }
+  const lbx_opts o = snapshot(p);
   hipStream_t st = (hipStream_t)stream;
   std::vector<int32_t> batch(nsys, 0);
   batch[sys] = B;
   BatchMeta *m;
-  int rc = build_batch(p, batch.data(), &m, 2);
+  int rc = build_batch(p, o, batch.data(), false, &m, 2);
   if (rc) return rc;
-  const Layout L = layout(p, LB_OP_IMR_STEP, *m, 1);
+  const Layout L = layout(p, o, LB_OP_IMR_STEP, *m, 1);
   if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
   char *w = (char *)ws;
+  const bool prof = o.profile;
+  if ((rc = call_begin(p, L, w, prof, st))) return rc;
   double2 *ctab = (double2 *)(w + L.ctab);
-  int32_t *ktab = (int32_t *)(w + L.ktab);
   const double *abase = alpha - p->sys[sys].alpha_off;
-  if ((rc = launch_control_table(p, sys, 1, abase, ctab, 0, ktab, nullptr, st))) return rc;
-  std::vector<int32_t> k;
-  if ((rc = fetch_ktab(p, ktab, k, st))) return rc;
-  const int K = k[((size_t)sys * p->NT + j) * 2 + 1];
-  if (K < 1) return fail(LB_EUNSUPPORTED, "stage-solve contraction bound >= 0.5 at this step");
-  double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
-  const double2 *qi = (const double2 *)q_in;
-  ProfScope ps(p, LB_KERNEL_SWEEP, st, step_sweep_work(p, *m, k, j), K);
-  for (int kk = 0; kk < K; ++kk)
-    if ((rc = sweep(p, *m, j, kk, K, adjoint != 0, ctab, ktab, qi, z0, z1, (double2 *)q_out, st)))
-      return rc;
-  return LB_OK;
-}
-
-// Per-item sweep totals of the LDS-resident kernels, kept only while profiling.
-static int64_t *lds_sweep_slots(const lb_plan *p, const BatchMeta &m) {
-  if (!p->profile || p->capturing || m.items.empty()) return nullptr;
-  if (p->sweeps_cap < m.items.size()) {
-    if (p->d_sweeps) (void)hipFree(p->d_sweeps);
-    p->d_sweeps = nullptr;
-    p->sweeps_cap = 0;
-    if (hipMalloc((void **)&p->d_sweeps, m.items.size() * sizeof(int64_t)) != hipSuccess) return nullptr;
-    p->sweeps_cap = m.items.size();
+  if ((rc = launch_control_table(p, sys, 1, abase, ctab, 0, (int32_t *)(w + L.ktab), (double2 *)(w + L.ttab),
+                                 o.tol, st)))
+    return rc;
+  // (the tables are written at the system's own offsets, where the step
+  // kernels read them)
+  StreamCtx sc{p, &o, m, &L, w, prof};
+  StepArgs A = sc.base();
+  A.j = j;
+  A.q = (const double2 *)q_in;
+  A.out = (double2 *)q_out;
+  {
+    ProfScope ps(p, prof, LB_KERNEL_SWEEP, st);
+    if ((rc = launch_step(p, A, adjoint != 0, m->tile_sys, m->tile_k, st))) return rc;
   }
-  return p->d_sweeps;
-}
-
-// Adds the entry-sweeps of one LDS-resident pass to the profile: read back
-// for the specialised kernels, from the a-priori counts for the generic ones.
-static int lds_profile_work(const lb_plan *p, const BatchMeta &m, const std::vector<int32_t> &k,
-                            int kernel, const int64_t *slots, hipStream_t st) {
-  if (!slots) return LB_OK;
-  std::vector<int64_t> sw(m.items.size());
-  LBX_HIP(hipMemcpyAsync(sw.data(), slots, sw.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  LBX_HIP(hipStreamSynchronize(st));
-  int64_t work = 0;
-  for (const auto &c : m.classes)
-    for (int i = c.i0; i < c.i1; ++i) {
-      const int s = m.items[i].sys;
-      const int64_t n2 = p->sys[s].N2;
-      if (c.qc > 0) {
-        work += sw[i] * n2;
-      } else {
-        for (int j = 0; j < p->NT; ++j) work += (int64_t)k[((size_t)s * p->NT + j) * 2] * n2;
-      }
-    }
-  p->prof_work[kernel] += work;
-  return LB_OK;
-}
-
-static int run_forward(const lb_plan *p, const BatchMeta &m, const Layout &L, char *w,
-                       const double *alpha, const double2 *rho0, double2 *rhoT, double2 *hist,
-                       std::vector<int32_t> &k, hipStream_t st, bool keep_ckpt) {
-  double2 *ctab = (double2 *)(w + L.ctab);
-  int32_t *ktab = (int32_t *)(w + L.ktab);
-  int rc;
-  double2 *ttab = (double2 *)(w + L.ttab);
-  if ((rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, ttab, st))) return rc;
-  if ((rc = fetch_ktab(p, ktab, k, st))) return rc;
-  if ((rc = check_k(p, k, m))) return rc;
-  // LDS-resident systems: one persistent launch per kernel class.
-  int64_t *slots = lds_sweep_slots(p, m);
-  for (const auto &c : m.classes) {
-    ProfScope ps(p, LB_KERNEL_LDS_FORWARD, st);
-    rc = c.qc > 0 ? launch_lds_forward_fast(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc,
-                                            ctab, ttab, rho0, rhoT, hist, slots ? slots + c.i0 : nullptr,
-                                            st)
-                  : launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab,
-                                       rho0, rhoT, hist, st);
-    if (rc) return rc;
+  if (prof) {
+    int32_t k = 0;
+    LBX_HIP(hipMemcpyAsync(&k, w + L.kout + ((size_t)sys * p->NT + j) * sizeof(int32_t), sizeof(k),
+                           hipMemcpyDeviceToHost, st));
+    LBX_HIP(hipStreamSynchronize(st));
+    prof_add_work(p, LB_KERNEL_SWEEP, (int64_t)k * m->st_entries);
+    prof_resolve(p);
   }
-  if ((rc = lds_profile_work(p, m, k, LB_KERNEL_LDS_FORWARD, slots, st))) return rc;
-  if (m.segs.empty()) return LB_OK;
-  // Streamed systems: one launch per sweep over all of them.
-  double2 *q0 = (double2 *)(w + L.st_q0), *q1 = (double2 *)(w + L.st_q1);
-  double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
-  const size_t E = (size_t)m.st_entries;
-  double2 *ck = keep_ckpt ? (double2 *)(w + L.ckpt) : nullptr;
-  double2 *start = keep_ckpt ? ck : q0;
-  if ((rc = copy_segments(m, rho0, true, start, st))) return rc;
-  const int NT = p->NT, c = L.c;
-  const double2 *last_out = start;
-  auto slot = [&](int j) -> double2 * {
-    double2 *r;
-    if (keep_ckpt && (j % c == 0 || j == NT)) r = ck + (size_t)(j == NT ? L.nck - 1 : j / c) * E;
-    else r = (last_out == q0) ? q1 : q0;
-    last_out = r;
-    return r;
-  };
-  if ((rc = stream_forward(p, m, k, ktab, ctab, 0, NT, start, slot, z0, z1, st))) return rc;
-  return copy_segments(m, last_out, false, rhoT, st);
+  if (o.sync) return status_code((const int32_t *)(w + L.status), st);
+  return LB_OK;
 }
 
 extern "C" int forward_solve(const lb_plan *p, const double *alpha, const void *rho0, void *rhoT,
-                             const int32_t *batch_per_sys, void *ws, size_t ws_bytes, void *stream) {
+                             const int32_t *batch_per_sys, void *traj, int32_t ckpt_every, void *ws, size_t ws_bytes,
+                             void *stream) {
   if (int rc = check_plan(p)) return rc;
   if (!alpha || !rho0 || !rhoT || !batch_per_sys || !ws) return fail(LB_EINVAL, "NULL argument");
+  if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
+  const lbx_opts o = snapshot(p);
   BatchMeta *m;
-  if (int rc = build_batch(p, batch_per_sys, &m)) return rc;
+  const bool small = traj && streams_small(ckpt_every);
+  if (int rc = build_batch(p, o, batch_per_sys, small, &m)) return rc;
   if (m->total_entries == 0) return LB_OK;
-  const Layout L = layout(p, LB_OP_FORWARD, *m, 1);
+  const Layout L = layout(p, o, LB_OP_FORWARD, *m, traj ? ckpt_every : 1);
   if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
-  std::vector<int32_t> k;
   hipStream_t st = (hipStream_t)stream;
-  int rc = run_forward(p, *m, L, (char *)ws, alpha, (const double2 *)rho0, (double2 *)rhoT, nullptr,
-                       k, st, false);
+  char *w = (char *)ws;
+  const bool prof = o.profile;
+  int rc = call_begin(p, L, w, prof, st);
+  if (!rc)
+    rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, (double2 *)rhoT, (char *)traj, prof, st);
   if (rc) return rc;
-  LBX_HIP(hipStreamSynchronize(st));
-  prof_resolve(p);
+  return call_end(p, o, *m, L, w, prof, st);
+}
+
+extern "C" int objective(const lb_plan *p, int32_t kind, const void *rhoT, const void *rhotar, const double *beta,
+                         const int32_t *batch_per_sys, double gamma2, const double *alpha, double *G, double *J,
+                         void *ws, size_t ws_bytes, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (kind != LB_J_FROB && kind != LB_J_TR) return fail(LB_EINVAL, "unknown merit functional");
+  if (!rhoT || !rhotar || !beta || !batch_per_sys || !alpha || !G || !ws) return fail(LB_EINVAL, "NULL argument");
+  if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
+  const lbx_opts o = snapshot(p);
+  BatchMeta *m;
+  if (int rc = build_batch(p, o, batch_per_sys, false, &m)) return rc;
+  const Layout L = layout(p, o, LB_OP_FORWARD, *m, 1);
+  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  char *w = (char *)ws;
+  hipStream_t st = (hipStream_t)stream;
+  int32_t *status = (int32_t *)(w + L.status);
+  if (int rc = launch_fill_zero(status, 4, st)) return rc;
+  if (int rc = launch_objective(p, kind, (const double2 *)rhoT, (const double2 *)rhotar, beta, m->d_state_sys,
+                                m->d_state_off, m->d_sys_state0, m->total_states, gamma2, alpha,
+                                (double *)(w + L.objpart), J, G, status, st))
+    return rc;
+  if (o.sync) return status_code(status, st);
   return LB_OK;
 }
 
-extern "C" int objective(const lb_plan *p, int32_t kind, const void *rhoT, const void *rhotar,
-                         const double *beta, const int32_t *batch_per_sys, double gamma2,
-                         const double *alpha, double *G, double *J, void *ws, size_t ws_bytes,
-                         void *stream) {
+extern "C" int adjoint_backward(const lb_plan *p, int32_t kind, const double *alpha, const void *traj,
+                                int32_t ckpt_every, const void *rhotar, const double *beta,
+                                const int32_t *batch_per_sys, double gamma2, const double *gscale, double *grad,
+                                void *ws, size_t ws_bytes, void *stream) {
   if (int rc = check_plan(p)) return rc;
   if (kind != LB_J_FROB && kind != LB_J_TR) return fail(LB_EINVAL, "unknown merit functional");
-  if (!rhoT || !rhotar || !beta || !batch_per_sys || !alpha || !G || !ws)
-    return fail(LB_EINVAL, "NULL argument");
+  if (!alpha || !traj || !rhotar || !beta || !batch_per_sys || !grad || !ws) return fail(LB_EINVAL, "NULL argument");
+  if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
   if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
+  const lbx_opts o = snapshot(p);
   BatchMeta *m;
-  if (int rc = build_batch(p, batch_per_sys, &m)) return rc;
-  const Layout L = layout(p, LB_OP_FORWARD, *m, 1);
+  if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &m)) return rc;
+  const Layout L = layout(p, o, LB_OP_BACKWARD, *m, ckpt_every);
   if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
-  return launch_objective(p, kind, (const double2 *)rhoT, (const double2 *)rhotar, beta,
-                          m->d_state_sys, m->d_state_off, m->d_sys_state0, m->total_states, gamma2,
-                          alpha, (double *)(w + L.objpart), J, G, (hipStream_t)stream);
+  const bool prof = o.profile;
+  int rc = call_begin(p, L, w, prof, st);
+  // The controls (and their tables) are rebuilt for this call.
+  if (!rc)
+    rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, (double2 *)(w + L.ctab), 0, (int32_t *)(w + L.ktab),
+                              (double2 *)(w + L.ttab), o.tol, st);
+  if (!rc)
+    rc = run_backward(p, o, *m, L, w, kind, alpha, (const char *)traj, (const double2 *)rhotar, beta, gamma2, gscale,
+                      grad, prof, st);
+  if (rc) return rc;
+  return call_end(p, o, *m, L, w, prof, st);
 }
 
-extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *alpha,
-                                const void *rho0, const void *rhotar, const double *beta,
-                                const int32_t *batch_per_sys, double gamma2, int32_t ckpt_every,
-                                double *G, double *grad, void *rhoT_out, void *ws, size_t ws_bytes,
+extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *alpha, const void *rho0,
+                                const void *rhotar, const double *beta, const int32_t *batch_per_sys, double gamma2,
+                                int32_t ckpt_every, double *G, double *grad, void *rhoT_out, void *ws, size_t ws_bytes,
                                 void *stream) {
   if (int rc = check_plan(p)) return rc;
   if (kind != LB_J_FROB && kind != LB_J_TR) return fail(LB_EINVAL, "unknown merit functional");
@@ -963,139 +1242,35 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
     return fail(LB_EINVAL, "NULL argument");
   if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
   if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
+  const lbx_opts o = snapshot(p);
   BatchMeta *m;
-  if (int rc = build_batch(p, batch_per_sys, &m)) return rc;
-  const Layout L = layout(p, LB_OP_GRADIENT, *m, ckpt_every);
+  if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &m)) return rc;
+  const Layout L = layout(p, o, LB_OP_GRADIENT, *m, ckpt_every);
   if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
-  int rc;
+  char *traj = w + L.traj;
+  const bool prof = o.profile;
+  int rc = call_begin(p, L, w, prof, st);
+  // rho(T) goes to the caller's buffer, or to the workspace.
   double2 *rhoT = rhoT_out ? (double2 *)rhoT_out : (double2 *)(w + L.rhoT);
-  double2 *hist = (double2 *)(w + L.hist);
-  double *gstep = (double *)(w + L.gstep);
-  double2 *ctab = (double2 *)(w + L.ctab);
-  int32_t *ktab = (int32_t *)(w + L.ktab);
-  LBX_HIP(hipMemsetAsync(gstep, 0, (size_t)2 * p->ctab_total * sizeof(double), st));
-  std::vector<int32_t> k;
-  if ((rc = run_forward(p, *m, L, w, alpha, (const double2 *)rho0, rhoT, hist, k, st, true))) return rc;
-  if ((rc = launch_objective(p, kind, rhoT, (const double2 *)rhotar, beta, m->d_state_sys,
-                             m->d_state_off, m->d_sys_state0, m->total_states, gamma2, alpha,
-                             (double *)(w + L.objpart), nullptr, G, st)))
-    return rc;
-  // LDS-resident adjoint.
-  if (!m->items.empty()) {
-    LdsItem *items = (LdsItem *)(w + L.items);
-    LBX_HIP(hipMemcpyAsync(items, m->d_items, m->items.size() * sizeof(LdsItem),
-                           hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(item_weights_kernel, dim3(((int)m->items.size() + 127) / 128), dim3(128), 0,
-                       st, items, (int)m->items.size(), beta, m->d_sys_state0);
-    LBX_HIP(hipGetLastError());
-    double *gpart = (double *)(w + L.gpart);
-    int64_t *slots = lds_sweep_slots(p, *m);
-    for (const auto &c : m->classes) {
-      ProfScope ps(p, LB_KERNEL_LDS_ADJOINT, st);
-      rc = c.qc > 0 ? launch_lds_adjoint_fast(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, kind,
-                                              ctab, (const double2 *)(w + L.ttab),
-                                              (const double2 *)rhotar, hist,
-                                              (double2 *)(w + L.zhist), gpart,
-                                              slots ? slots + c.i0 : nullptr, st)
-                    : launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab,
-                                         ktab, (const double2 *)rhotar, hist, gpart, st);
-      if (rc) return rc;
-    }
-    if ((rc = lds_profile_work(p, *m, k, LB_KERNEL_LDS_ADJOINT, slots, st))) return rc;
-    if ((rc = launch_lds_grad_reduce(p, m->d_lds_item_range, (int)m->lds_sys.size(), m->d_lds_sys,
-                                     items, gpart, gstep, st)))
-      return rc;
-  }
-  // Streamed adjoint with checkpoint recomputation.
-  if (!m->segs.empty()) {
-    const size_t E = (size_t)m->st_entries;
-    const int NT = p->NT, c = L.c;
-    double2 *ck = (double2 *)(w + L.ckpt), *seg = (double2 *)(w + L.seg);
-    double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
-    double2 *qh[2] = {(double2 *)(w + L.st_qh0), (double2 *)(w + L.st_qh1)};
-    double *sgp = (double *)(w + L.st_gpart), *sgf = (double *)(w + L.st_gfin);
-    const int64_t gstride = L.grows * 2 * QMAX;  // doubles per step slot
-    int pend = 0, jtop = 0;
-    int64_t rows = 0;
-    const int nseg = (int)m->segs.size();
-    if ((rc = launch_terminal(p, kind, m->d_segs, nseg, m->st_blocks, ck + (size_t)(L.nck - 1) * E,
-                              (const double2 *)rhotar, beta, m->d_seg_state0, qh[0], st)))
-      return rc;
-    int cur = 0;
-    const int nsegs_t = (NT + c - 1) / c;
-    for (int sgi = nsegs_t - 1; sgi >= 0; --sgi) {
-      const int j0 = sgi * c, j1 = std::min(NT, j0 + c);
-      auto slot = [&](int j) -> double2 * {
-        if (j == j0) return ck + (size_t)(j0 / c) * E;
-        if (j == j1) return ck + (size_t)(j1 == NT ? L.nck - 1 : j1 / c) * E;
-        return seg + (size_t)(j - j0 - 1) * E;
-      };
-      // Recompute q^{j0+1} .. q^{j1-1} from the checkpoint.
-      if (j1 - j0 > 1)
-        if ((rc = stream_forward(p, *m, k, ktab, ctab, j0, j1 - 1, slot(j0), slot, z0, z1, st)))
-          return rc;
-      GraphRun gr(p, st);
-      if ((rc = gr.init())) return rc;
-      const hipStream_t ast = gr.stream();
-      const int chunk = gr.on ? p->graph_steps : c;
-      for (int ce = j1; ce > j0; ce -= chunk) {
-        const int cb = std::max(j0, ce - chunk);
-        if ((rc = gr.begin())) return rc;
-        for (int j = ce - 1; j >= cb; --j) {
-          int K = 1;
-          for (const auto &sg : m->segs) K = std::max(K, (int)k[((size_t)sg.sys * NT + j) * 2 + 1]);
-          const double2 *qin = qh[cur];
-          double2 *qout = qh[cur ^ 1];
-          // The last sweep also writes the stage vector zh = qh^{j+1} + delta =
-          // (qh^j + qh^{j+1})/2 into the z buffer it does not read.
-          {
-            ProfScope ps(p, LB_KERNEL_SWEEP, ast, step_sweep_work(p, *m, k, j), K);
-            for (int kk = 0; kk < K; ++kk)
-              if ((rc = sweep(p, *m, j, kk, K, true, ctab, ktab, qin, z0, z1, qout, ast, true))) return rc;
-          }
-          // Partial rows of the pending steps go to successive slots and are
-          // reduced together (every gbatch steps and at the end of a chunk).
-          if (pend == 0) jtop = j;
-          double *gp = sgp + (size_t)pend * gstride;
-          {
-            ProfScope ps(p, LB_KERNEL_STREAM_GRAD, ast, m->st_entries);
-            rc = m->tile_sys >= 0
-                     ? launch_tile_grad(p, m->tile_sys, m->tile_B, stage_buffer(K, z0, z1), slot(j),
-                                        slot(j + 1), gp, &rows, ast)
-                     : launch_stream_grad(p, m->d_segs, nseg, m->st_blocks, z0, z1, ktab, j, slot(j),
-                                          slot(j + 1), gp, ast);
-            if (rc) return rc;
-          }
-          if (++pend == L.gbatch || j == cb) {
-            if ((rc = launch_stream_grad_finalize(p, m->d_segs, nseg, jtop, pend, sgp, gstride, sgf,
-                                                  gstep, rows, ast)))
-              return rc;
-            pend = 0;
-          }
-          cur ^= 1;
-        }
-        if ((rc = gr.end())) return rc;
-      }
-    }
-  }
-  if ((rc = launch_grad_contract(p, gstep, alpha, gamma2, grad, st))) return rc;
-  std::vector<double> hG(p->sys.size());
-  LBX_HIP(hipMemcpyAsync(hG.data(), G, hG.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  LBX_HIP(hipStreamSynchronize(st));
-  prof_resolve(p);
-  for (size_t s = 0; s < hG.size(); ++s)
-    if (!std::isfinite(hG[s]) && m->batch[s] > 0)
-      return fail(LB_ENONFINITE, "objective of system " + std::to_string(s) + " is not finite");
-  return LB_OK;
+  if (!rc) rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, rhoT, traj, prof, st);
+  if (!rc)
+    rc = launch_objective(p, kind, rhoT, (const double2 *)rhotar, beta, m->d_state_sys, m->d_state_off,
+                          m->d_sys_state0, m->total_states, gamma2, alpha, (double *)(w + L.objpart), nullptr, G,
+                          (int32_t *)(w + L.status), st);
+  if (!rc)
+    rc = run_backward(p, o, *m, L, w, kind, alpha, traj, (const double2 *)rhotar, beta, gamma2, nullptr, grad, prof,
+                      st);
+  if (rc) return rc;
+  return call_end(p, o, *m, L, w, prof, st);
 }
 
-extern "C" int lb_profile_read(const lb_plan *p, int32_t kernel, int64_t *launches, double *total_ms,
-                               int32_t reset) {
+extern "C" int lb_profile_read(const lb_plan *p, int32_t kernel, int64_t *launches, double *total_ms, int32_t reset) {
   if (int rc = check_plan(p)) return rc;
   if (kernel < 0 || kernel >= LB_KERNEL_COUNT) return fail(LB_EINVAL, "unknown kernel family");
   prof_resolve(p);
+  std::lock_guard<std::mutex> g(p->mu);
   if (launches) *launches = p->prof_n[kernel];
   if (total_ms) *total_ms = p->prof_ms[kernel];
   if (reset) {
@@ -1110,6 +1285,7 @@ extern "C" int lb_profile_work(const lb_plan *p, int32_t kernel, int64_t *entry_
   if (int rc = check_plan(p)) return rc;
   if (kernel < 0 || kernel >= LB_KERNEL_COUNT) return fail(LB_EINVAL, "unknown kernel family");
   if (!entry_sweeps) return fail(LB_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> g(p->mu);
   *entry_sweeps = p->prof_work[kernel];
   return LB_OK;
 }
@@ -1117,13 +1293,14 @@ extern "C" int lb_profile_work(const lb_plan *p, int32_t kernel, int64_t *entry_
 extern "C" int sweep_counts(const lb_plan *p, const double *alpha, int32_t *counts, void *stream) {
   if (int rc = check_plan(p)) return rc;
   if (!alpha || !counts) return fail(LB_EINVAL, "NULL argument");
+  const lbx_opts o = snapshot(p);
   hipStream_t st = (hipStream_t)stream;
   const size_t nk = p->sys.size() * (size_t)p->NT * 2;
   void *tmp = nullptr;
   LBX_HIP(hipMalloc(&tmp, align256(p->ctab_total * sizeof(double2)) + nk * sizeof(int32_t)));
   double2 *ctab = (double2 *)tmp;
   int32_t *ktab = (int32_t *)((char *)tmp + align256(p->ctab_total * sizeof(double2)));
-  int rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, nullptr, st);
+  int rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, nullptr, o.tol, st);
   if (rc == LB_OK) {
     hipError_t e = hipMemcpyAsync(counts, ktab, nk * sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1139,20 +1316,19 @@ extern "C" int sweep_counts(const lb_plan *p, const double *alpha, int32_t *coun
 // ----------------------------------------------------------------------------
 namespace {
 
-int time_sweeps(const lb_plan *p, const BatchMeta &m, const Layout &L, char *w, int reps,
-                hipStream_t st, float *ms) {
-  double2 *ctab = (double2 *)(w + L.ctab);
-  double2 *q0 = (double2 *)(w + L.st_q0), *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
+// Mean time of `reps` first steps (forward, no history) with the options o.
+int time_steps(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w, int reps,
+               hipStream_t st, float *ms) {
+  StreamCtx sc{p, &o, &m, &L, w, false};
+  double2 *q0 = (double2 *)(w + L.q0), *q1 = (double2 *)(w + L.q1);
   hipEvent_t a, b;
   LBX_HIP(hipEventCreate(&a));
   LBX_HIP(hipEventCreate(&b));
   int rc = LB_OK;
-  // Never a last sweep: kk 1 and 2 of a count of 2^20 (z0 -> z1, z1 -> z0).
-  constexpr int KFIX = 1 << 20;
-  for (int r = 0; r < 2 && !rc; ++r) rc = sweep(p, m, 0, 1, KFIX, false, ctab, nullptr, q0, z0, z1, z1, st, false, KFIX);
+  PassHist ph;  // H = 0: every step starts from q
+  for (int r = 0; r < 2 && !rc; ++r) rc = stream_step(sc, 0, false, q0, q1, ph, nullptr, st);
   if (!rc) (void)hipEventRecord(a, st);
-  for (int r = 0; r < reps && !rc; ++r)
-    rc = sweep(p, m, 0, (r & 1) ? 2 : 1, KFIX, false, ctab, nullptr, q0, z0, z1, z1, st, false, KFIX);
+  for (int r = 0; r < reps && !rc; ++r) rc = stream_step(sc, 0, false, (r & 1) ? q1 : q0, (r & 1) ? q0 : q1, ph, nullptr, st);
   if (!rc) {
     (void)hipEventRecord(b, st);
     const hipError_t e = hipEventSynchronize(b);
@@ -1166,109 +1342,61 @@ int time_sweeps(const lb_plan *p, const BatchMeta &m, const Layout &L, char *w, 
 
 }  // namespace
 
-extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch_per_sys, void *ws,
-                           size_t ws_bytes, void *stream, int32_t *result) {
+extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch_per_sys, void *ws, size_t ws_bytes,
+                           void *stream, int32_t *result) {
   if (int rc = check_plan(p)) return rc;
   if (!alpha || !batch_per_sys || !ws || !result) return fail(LB_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
+  lbx_opts o = snapshot(p);
   BatchMeta *m;
-  if (int rc = build_batch(p, batch_per_sys, &m)) return rc;
-  result[0] = p->tile;
-  result[1] = p->tile_ki;
-  result[2] = p->graph_steps;
+  if (int rc = build_batch(p, o, batch_per_sys, false, &m)) return rc;
+  result[0] = o.tile;
+  result[1] = o.tile_ki;
+  result[2] = o.graph_steps;
   if (m->segs.empty()) return LB_OK;
-  // Workspace must hold the forward layout of every candidate (the generic
-  // and tiled layouts are the same size).
-  const Layout L = layout(p, LB_OP_FORWARD, *m, 1);
+  // The workspace must hold the forward layout of every candidate (the
+  // generic and tiled layouts are the same size).
+  const Layout L = layout(p, o, LB_OP_FORWARD, *m, 1);
   if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
-  int rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, (double2 *)(w + L.ctab), 0,
-                                (int32_t *)(w + L.ktab), nullptr, st);
+  int rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, (double2 *)(w + L.ctab), 0, (int32_t *)(w + L.ktab),
+                                (double2 *)(w + L.ttab), o.tol, st);
   if (rc) return rc;
-  std::vector<int32_t> k;
-  if ((rc = fetch_ktab(p, (int32_t *)(w + L.ktab), k, st))) return rc;
-  if ((rc = check_k(p, k, *m))) return rc;
   const size_t E = (size_t)m->st_entries * sizeof(double2);
-  LBX_HIP(hipMemsetAsync(w + L.st_q0, 0, E, st));
-  LBX_HIP(hipMemsetAsync(w + L.st_z0, 0, E, st));
-  LBX_HIP(hipMemsetAsync(w + L.st_z1, 0, E, st));
+  if ((rc = launch_fill_zero(w + L.q0, E, st)) || (rc = launch_fill_zero(w + L.q1, E, st))) return rc;
   // Kernel family and block shape.
   std::vector<std::pair<int, int>> cand = {{0, 0}};
-  const int saved_tile = p->tile, saved_ki = p->tile_ki, saved_graph = p->graph_steps;
   if (m->segs.size() == 1) {
     const int sys = m->segs[0].sys;
-    if (split_kl(p, sys)) cand.push_back({2, 0});
-    for (int ki : {44, 43, 34, 42, 33, 66, 55, 32, 23}) {
-      p->tile = 1;
-      p->tile_ki = ki;
-      if (tile_ki(p, sys) == ki) cand.push_back({1, ki});
-    }
+    for (int ki : {44, 43, 34, 42, 33, 66, 55, 32, 23})
+      if (tile_ki(p, sys, ki) == ki) cand.push_back({1, ki});
   }
   const int reps = m->st_entries > (1 << 22) ? 4 : 20;
   float best = 1e30f;
-  int bt = 0, bk = 0;
-  p->graph_steps = 0;
+  int bt = o.tile, bk = o.tile_ki;
+  lbx_opts oc = o;
+  oc.graph_steps = 0;
   for (const auto &c : cand) {
-    p->tile = c.first;
-    p->tile_ki = c.second;
+    oc.tile = c.first;
+    oc.tile_ki = c.second;
     BatchMeta *mc;
-    if ((rc = build_batch(p, batch_per_sys, &mc))) break;
+    if ((rc = build_batch(p, oc, batch_per_sys, false, &mc))) return rc;
     float ms = 0.f;
-    if ((rc = time_sweeps(p, *mc, L, w, reps, st, &ms))) break;
+    if ((rc = time_steps(p, oc, *mc, L, w, reps, st, &ms))) return rc;
     if (ms < best) {
       best = ms;
       bt = c.first;
       bk = c.second;
     }
   }
-  if (rc) {
-    p->tile = saved_tile;
-    p->tile_ki = saved_ki;
-    p->graph_steps = saved_graph;
-    return rc;
+  {
+    std::lock_guard<std::mutex> g(p->mu);
+    p->opts.tile = bt;
+    p->opts.tile_ki = bk;
   }
-  p->tile = bt;
-  p->tile_ki = bk;
-  // Direct launches against graph-captured chunks of the time loop.
-  BatchMeta *mb;
-  if ((rc = build_batch(p, batch_per_sys, &mb))) return rc;
-  const int steps = std::min(p->NT, 32);
-  double2 *q0 = (double2 *)(w + L.st_q0), *q1 = (double2 *)(w + L.st_q1);
-  double2 *z0 = (double2 *)(w + L.st_z0), *z1 = (double2 *)(w + L.st_z1);
-  float tg[2] = {0.f, 0.f};
-  for (int g = 0; g < 2 && !rc; ++g) {
-    p->graph_steps = g ? steps : 0;
-    for (int rep = 0; rep < 2 && !rc; ++rep) {  // first repetition warms up
-      hipEvent_t a, b;
-      LBX_HIP(hipEventCreate(&a));
-      LBX_HIP(hipEventCreate(&b));
-      (void)hipEventRecord(a, st);
-      const double2 *last = q0;
-      auto slot = [&](int) -> double2 * {
-        double2 *r = last == q0 ? q1 : q0;
-        last = r;
-        return r;
-      };
-      rc = stream_forward(p, *mb, k, (const int32_t *)(w + L.ktab), (double2 *)(w + L.ctab), 0, steps, q0,
-                          slot, z0, z1, st);
-      (void)hipEventRecord(b, st);
-      if (!rc) {
-        const hipError_t e = hipEventSynchronize(b);
-        if (e != hipSuccess) rc = hip_fail(e, "autotune timing");
-        else (void)hipEventElapsedTime(&tg[g], a, b);
-      }
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
-    }
-  }
-  if (rc) {
-    p->graph_steps = saved_graph;
-    return rc;
-  }
-  p->graph_steps = tg[1] < 0.95f * tg[0] ? steps : 0;
-  result[0] = p->tile;
-  result[1] = p->tile_ki;
-  result[2] = p->graph_steps;
+  result[0] = bt;
+  result[1] = bk;
+  result[2] = o.graph_steps;
   return LB_OK;
 }
 

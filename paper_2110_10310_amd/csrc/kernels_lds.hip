@@ -13,12 +13,22 @@
 
 namespace lbx {
 
+// A-priori sweep count of a step; a step whose contraction bound is >= 0.5
+// (count -1) raises LB_STATUS_THETA and takes one sweep, so that the loop
+// still ends.
+__device__ __forceinline__ int a_priori_sweeps(int k, int32_t *status) {
+  if (k >= 1) return k;
+  if (status && threadIdx.x == 0) atomicOr(status, LB_STATUS_THETA);
+  return 1;
+}
+
 template <int BLOCK, int EPT>
 __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
     const SysDev *__restrict__ sysv, const LdsItem *__restrict__ items,
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
     const double2 *__restrict__ ctab, const int32_t *__restrict__ ktab, int NT,
-    const double2 *__restrict__ rho0, double2 *__restrict__ rhoT, double2 *__restrict__ states) {
+    const double2 *__restrict__ rho0, double2 *__restrict__ rhoT, double2 *__restrict__ states,
+    int64_t *__restrict__ sweeps, int32_t *__restrict__ status) {
   extern __shared__ double2 zbuf[];  // two stage buffers of N^2 entries
   __shared__ double sq[SQRT_TABLE];
   __shared__ double2 dsh[2][QMAX];
@@ -61,6 +71,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
   // so that every access stays an LDS instruction.
   double2 *const zb0 = zbuf, *const zb1 = zbuf + N2;
   int cb = 0;
+  int64_t nsw = 0;
   for (int j = 0; j < NT; ++j) {
     // (I - h M) z = q^j (App. A eq. linsystem_primal): z0 = w q, then K sweeps.
     double2 hdq[EPT];
@@ -71,7 +82,8 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
     }
     if (tid < S.Q) dsh[j & 1][tid] = ctab[S.ctab_off + (int64_t)j * S.Q + tid];
     __syncthreads();
-    const int K = ktab[((int64_t)it.sys * NT + j) * 2 + 0];
+    const int K = a_priori_sweeps(ktab[((int64_t)it.sys * NT + j) * 2 + 0], status);
+    nsw += K;
     for (int kk = 0; kk < K; ++kk) {
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
@@ -102,6 +114,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
 #pragma unroll
   for (int k = 0; k < EPT; ++k)
     if (ok[k]) rhoT[it.off + ee[k]] = qv[k];
+  if (sweeps && tid == 0) sweeps[blockIdx.x] = nsw;
 }
 
 template <int BLOCK, int EPT>
@@ -110,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
     const double2 *__restrict__ ctab, const int32_t *__restrict__ ktab, int NT, int kind,
     const double2 *__restrict__ rhotar, const double2 *__restrict__ states,
-    double *__restrict__ gpart) {
+    double *__restrict__ gpart, int64_t *__restrict__ sweeps, int32_t *__restrict__ status) {
   extern __shared__ double2 zbuf[];
   __shared__ double sq[SQRT_TABLE];
   __shared__ double2 dsh[2][QMAX];
@@ -153,6 +166,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
   // so that every access stays an LDS instruction.
   double2 *const zb0 = zbuf, *const zb1 = zbuf + N2;
   int cb = 0;
+  int64_t nsw = 0;
   for (int j = NT - 1; j >= 0; --j) {
     // (I - h M^+) zh = qh^{j+1} (App. B eq. linsystem_adjoint), zh = qh + delta.
     double2 hdq[EPT];
@@ -167,7 +181,8 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
 #pragma unroll
     for (int k = 0; k < EPT; ++k) qj[k] = ok[k] ? hist[(int64_t)j * N2 + ee[k]] : make_double2(0.0, 0.0);
     __syncthreads();
-    const int K = ktab[((int64_t)it.sys * NT + j) * 2 + 0];
+    const int K = a_priori_sweeps(ktab[((int64_t)it.sys * NT + j) * 2 + 0], status);
+    nsw += K;
     for (int kk = 0; kk < K; ++kk) {
       const double2 *src = (cb ? zb1 : zb0);
 #pragma unroll
@@ -220,6 +235,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
     // The next step writes its first iterate into (cb ? zb1 : zb0): the last sweep's
     // reads of it finished before the barrier above.
   }
+  if (sweeps && tid == 0) sweeps[blockIdx.x] = nsw;
 }
 
 bool lds_shape(int64_t n2, int *block, int *ept) {
@@ -237,12 +253,12 @@ bool lds_shape(int64_t n2, int *block, int *ept) {
 template <int BLOCK, int EPT>
 static int launch_fwd_t(const lb_plan *p, const LdsItem *d_items, int nitems, size_t shmem,
                         const double2 *ctab, const int32_t *ktab, const double2 *rho0,
-                        double2 *rhoT, double2 *states, hipStream_t st) {
+                        double2 *rhoT, double2 *states, int64_t *sweeps, int32_t *status, hipStream_t st) {
   auto kern = lds_forward_kernel<BLOCK, EPT>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E,
-                     p->d_desc, ctab, ktab, p->NT, rho0, rhoT, states);
+                     p->d_desc, ctab, ktab, p->NT, rho0, rhoT, states, sweeps, status);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -251,12 +267,12 @@ template <int BLOCK, int EPT>
 static int launch_adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, size_t shmem,
                         int kind, const double2 *ctab, const int32_t *ktab,
                         const double2 *rhotar, const double2 *states, double *gpart,
-                        hipStream_t st) {
+                        int64_t *sweeps, int32_t *status, hipStream_t st) {
   auto kern = lds_adjoint_kernel<BLOCK, EPT>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E,
-                     p->d_desc, ctab, ktab, p->NT, kind, rhotar, states, gpart);
+                     p->d_desc, ctab, ktab, p->NT, kind, rhotar, states, gpart, sweeps, status);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -265,11 +281,11 @@ static size_t lds_bytes(int block, int ept) { return (size_t)2 * block * ept * s
 
 int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                        const double2 *ctab, const int32_t *ktab, const double2 *rho0,
-                       double2 *rhoT, double2 *states, hipStream_t st) {
+                       double2 *rhoT, double2 *states, int64_t *sweeps, int32_t *status, hipStream_t st) {
   if (nitems == 0) return LB_OK;
   const size_t sh = lds_bytes(block, ept);
 #define LBX_FWD(Bk, Ep) \
-  if (block == Bk && ept == Ep) return launch_fwd_t<Bk, Ep>(p, d_items, nitems, sh, ctab, ktab, rho0, rhoT, states, st);
+  if (block == Bk && ept == Ep) return launch_fwd_t<Bk, Ep>(p, d_items, nitems, sh, ctab, ktab, rho0, rhoT, states, sweeps, status, st);
   LBX_FWD(64, 1) LBX_FWD(128, 1) LBX_FWD(256, 1) LBX_FWD(512, 1) LBX_FWD(1024, 1)
   LBX_FWD(1024, 2) LBX_FWD(1024, 4)
 #undef LBX_FWD
@@ -278,11 +294,12 @@ int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int
 
 int launch_lds_adjoint(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                        int kind, const double2 *ctab, const int32_t *ktab, const double2 *rhotar,
-                       const double2 *states, double *gpart, hipStream_t st) {
+                       const double2 *states, double *gpart, int64_t *sweeps, int32_t *status,
+                       hipStream_t st) {
   if (nitems == 0) return LB_OK;
   const size_t sh = lds_bytes(block, ept);
 #define LBX_ADJ(Bk, Ep) \
-  if (block == Bk && ept == Ep) return launch_adj_t<Bk, Ep>(p, d_items, nitems, sh, kind, ctab, ktab, rhotar, states, gpart, st);
+  if (block == Bk && ept == Ep) return launch_adj_t<Bk, Ep>(p, d_items, nitems, sh, kind, ctab, ktab, rhotar, states, gpart, sweeps, status, st);
   LBX_ADJ(64, 1) LBX_ADJ(128, 1) LBX_ADJ(256, 1) LBX_ADJ(512, 1) LBX_ADJ(1024, 1)
   LBX_ADJ(1024, 2) LBX_ADJ(1024, 4)
 #undef LBX_ADJ

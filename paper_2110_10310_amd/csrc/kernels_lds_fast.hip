@@ -120,7 +120,7 @@ __device__ __forceinline__ double2 offdiag_nb(const Nb (&nb)[QC], const double2 
 // below tol max|q|.  Every thread reads the same two maxima from LDS, so the
 // count is uniform.
 __device__ __forceinline__ int extra_sweeps(double theta, double ratio, double e1, double qmax,
-                                            double tol) {
+                                            double tol, int32_t *status) {
   double r = ratio * e1;  // ratio = theta / (1 - theta), from the control table
   const double lim = tol * qmax;
   int k = 0;
@@ -136,6 +136,10 @@ __device__ __forceinline__ int extra_sweeps(double theta, double ratio, double e
     r *= theta;
     ++k;
   }
+  // A step whose contraction bound is >= 0.5, or that the cap stops, is
+  // reported through the status word (LB_STATUS_*).
+  if (status && threadIdx.x == 0 && (!(theta < 0.5) || r > lim))
+    atomicOr(status, !(theta < 0.5) ? LB_STATUS_THETA : LB_STATUS_NOCONV);
   return k;
 }
 
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
     const double2 *__restrict__ ctab, const double2 *__restrict__ ttab, double tol, int NT,
     const double2 *__restrict__ rho0, double2 *__restrict__ rhoT, double2 *__restrict__ states,
-    int64_t *__restrict__ sweeps) {
+    int64_t *__restrict__ sweeps, int32_t *__restrict__ status) {
   extern __shared__ double2 zbuf[];
   constexpr int WAVES = BLOCK / 64;
   __shared__ uint32_t wmax[2][WAVES];
@@ -342,7 +346,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_fast_kernel(
       he = max(he, wmax[0][w]);
       hq = max(hq, wmax[1][w]);
     }
-    const int K = extra_sweeps(sc.theta, sc.ratio, hi_upper(he), hi_lower(hq), tol);
+    const int K = extra_sweeps(sc.theta, sc.ratio, hi_upper(he), hi_lower(hq), tol, status);
     const int rest = K > 1 ? K - 1 : 0;
     nsw += 2 + rest;
     // Further sweeps: the iterate for the third is written (and the barrier
@@ -401,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
     const double2 *__restrict__ ctab, const double2 *__restrict__ ttab, double tol, int NT,
     int kind, const double2 *__restrict__ rhotar, const double2 *__restrict__ states,
-    double2 *__restrict__ zhist, int64_t *__restrict__ sweeps) {
+    double2 *__restrict__ zhist, int64_t *__restrict__ sweeps, int32_t *__restrict__ status) {
   extern __shared__ double2 zbuf[];
   constexpr int WAVES = BLOCK / 64;
   __shared__ uint32_t wmax[2][WAVES];
@@ -500,7 +504,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
       he = max(he, wmax[0][w]);
       hq = max(hq, wmax[1][w]);
     }
-    const int K = extra_sweeps(sc.theta, sc.ratio, hi_upper(he), hi_lower(hq), tol);
+    const int K = extra_sweeps(sc.theta, sc.ratio, hi_upper(he), hi_lower(hq), tol, status);
     const int rest = K > 1 ? K - 1 : 0;
     nsw += 2 + rest;
     // Further sweeps: the iterate for the third is written (and the barrier
@@ -626,26 +630,26 @@ bool lds_fast_ok(int block, int ept, int Q) {
 
 template <int BLOCK, int EPT, int QC>
 static int fwd_t(const lb_plan *p, const LdsItem *d_items, int nitems, const double2 *ctab,
-                 const double2 *ttab, const double2 *rho0, double2 *rhoT, double2 *states,
-                 int64_t *sweeps, hipStream_t st) {
+                 const double2 *ttab, double tol, const double2 *rho0, double2 *rhoT, double2 *states,
+                 int64_t *sweeps, int32_t *status, hipStream_t st) {
   const size_t shmem = (size_t)2 * BLOCK * EPT * sizeof(double2);
   auto kern = lds_forward_fast_kernel<BLOCK, EPT, QC>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E, p->d_desc,
-                     ctab, ttab, p->tol, p->NT, rho0, rhoT, states, sweeps);
+                     ctab, ttab, tol, p->NT, rho0, rhoT, states, sweeps, status);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
 
 template <int BLOCK, int EPT, int QC>
 static int adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, int kind, const double2 *ctab,
-                 const double2 *ttab, const double2 *rhotar, const double2 *states, double2 *zhist,
-                 double *gpart, int64_t *sweeps, hipStream_t st) {
+                 const double2 *ttab, double tol, const double2 *rhotar, const double2 *states,
+                 double2 *zhist, double *gpart, int64_t *sweeps, int32_t *status, hipStream_t st) {
   const size_t shmem = (size_t)2 * BLOCK * EPT * sizeof(double2);
   auto kern = lds_adjoint_fast_kernel<BLOCK, EPT, QC>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E, p->d_desc,
-                     ctab, ttab, p->tol, p->NT, kind, rhotar, states, zhist, sweeps);
+                     ctab, ttab, tol, p->NT, kind, rhotar, states, zhist, sweeps, status);
   LBX_HIP(hipGetLastError());
   static_assert(EPT == 1, "the integrand kernel takes one entry per thread");
   auto gk = lds_grad_fast_kernel<BLOCK, QC>;
@@ -662,24 +666,24 @@ static int adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, int kind,
   X(512, 1, 3) X(512, 1, 4) X(1024, 1, 1)
 
 int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, const double2 *ctab, const double2 *ttab, const double2 *rho0,
-                            double2 *rhoT, double2 *states, int64_t *sweeps, hipStream_t st) {
+                            int Q, const double2 *ctab, const double2 *ttab, double tol, const double2 *rho0,
+                            double2 *rhoT, double2 *states, int64_t *sweeps, int32_t *status, hipStream_t st) {
   if (nitems == 0) return LB_OK;
 #define X(B, E, C) \
-  if (block == B && ept == E && Q == C) return fwd_t<B, E, C>(p, d_items, nitems, ctab, ttab, rho0, rhoT, states, sweeps, st);
+  if (block == B && ept == E && Q == C) return fwd_t<B, E, C>(p, d_items, nitems, ctab, ttab, tol, rho0, rhoT, states, sweeps, status, st);
   LBX_FAST_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "no specialised LDS-resident kernel for this shape");
 }
 
 int launch_lds_adjoint_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, int kind, const double2 *ctab, const double2 *ttab,
+                            int Q, int kind, const double2 *ctab, const double2 *ttab, double tol,
                             const double2 *rhotar, const double2 *states, double2 *zhist,
-                            double *gpart, int64_t *sweeps, hipStream_t st) {
+                            double *gpart, int64_t *sweeps, int32_t *status, hipStream_t st) {
   if (nitems == 0) return LB_OK;
   if (nitems > 65535) return fail(LB_EUNSUPPORTED, "more than 65535 states in one LDS kernel class");
 #define X(B, E, C) \
-  if (block == B && ept == E && Q == C) return adj_t<B, E, C>(p, d_items, nitems, kind, ctab, ttab, rhotar, states, zhist, gpart, sweeps, st);
+  if (block == B && ept == E && Q == C) return adj_t<B, E, C>(p, d_items, nitems, kind, ctab, ttab, tol, rhotar, states, zhist, gpart, sweeps, status, st);
   LBX_FAST_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "no specialised LDS-resident kernel for this shape");

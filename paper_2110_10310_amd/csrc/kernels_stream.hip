@@ -1,8 +1,9 @@
-// Streaming kernels: control table, matrix-free apply of M(t), one
-// fixed-point sweep of the implicit-midpoint stage solve, the adjoint
-// gradient integrands, objective reductions and the gradient contraction.
-// Every kernel reads and writes states in HBM (or cache); the LDS-resident
-// persistent kernels for small systems live in kernels_lds.hip.
+// Streaming kernels: control table, matrix-free apply of M(t), the adjoint
+// gradient integrands, the adjoint terminal condition, objective reductions
+// and the gradient contraction.  Every kernel reads and writes states in HBM
+// (or cache).  The stage solves of streamed systems run in the persistent
+// step kernels of kernels_step.hip; the LDS-resident persistent kernels for
+// small systems live in kernels_lds.hip and kernels_lds_fast.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,16 +12,35 @@
 
 namespace lbx {
 
+// Zeroes n 32-bit words (a kernel rather than hipMemsetAsync, so that a
+// caller may capture the launches of a call in a graph).
+__global__ void fill_zero_kernel(uint32_t *__restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+int launch_fill_zero(void *ptr, size_t bytes, hipStream_t st) {
+  const int64_t n = (int64_t)(bytes / 4);
+  if (n == 0) return LB_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)ptr, n);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
 // ----------------------------------------------------------------------------
 // Control table (Sec. II eq. rotctrl, evaluated at step midpoints, App. A)
-// and the number of stage-solve sweeps per step.
+// and the contraction bound of every step's stage solve.
 //
 // The stage system (I - h M) z = q, h = dt/2, M = D + O, is solved by the
 // fixed-point iteration z <- w (q + h O z) with w = (1 - h D)^-1.  Since
 // Re D <= 0, |w| <= 1 and the iteration contracts in the max norm with
 // factor theta <= h max_row sum|O| <= h sum_q (2 |d_q| c_q + (n_q - 1)/T1_q).
-// Started from z0 = w q the error after K sweeps is <= theta^(K+1) |z|;
-// started from z0 = q it is <= theta^K (h max|D| + theta) |z|.
+// ttab receives (theta, theta / (1 - theta)) for the a-posteriori counts of
+// the streamed step kernels and the specialised LDS kernels; ktab the
+// a-priori counts of the generic LDS kernels (started from z0 = w q the
+// error after K sweeps is <= theta^(K+1) |z|) and of a start from z0 = q
+// (<= theta^K (h max|D| + theta) |z|), which sweep_counts reports.
 // ----------------------------------------------------------------------------
 __global__ void control_table_kernel(const SysDev *__restrict__ sysv, int s0, int NT,
                                      const double *__restrict__ alpha,
@@ -38,8 +58,6 @@ __global__ void control_table_kernel(const SysDev *__restrict__ sysv, int s0, in
     ctab[S.ctab_off - ctab_shift + (int64_t)j * S.Q + q] = d;
     theta += S.h * 2.0 * hypot(d.x, d.y) * S.csum[q];
   }
-  // (theta, theta / (1 - theta)) for the a-posteriori sweep counts of the
-  // specialised LDS-resident kernels.
   if (ttab) ttab[(int64_t)s * NT + j] = make_double2(theta, theta < 1.0 ? theta / (1.0 - theta) : 0.0);
   if (ktab) {
     int klds, kst;
@@ -62,10 +80,10 @@ __global__ void control_table_kernel(const SysDev *__restrict__ sysv, int s0, in
 }
 
 int launch_control_table(const lb_plan *p, int s0, int nsys, const double *alpha, double2 *ctab,
-                         int64_t ctab_shift, int32_t *ktab, double2 *ttab, hipStream_t st) {
+                         int64_t ctab_shift, int32_t *ktab, double2 *ttab, double tol, hipStream_t st) {
   dim3 grid((p->NT + 255) / 256, nsys);
   hipLaunchKernelGGL(control_table_kernel, grid, dim3(256), 0, st, p->d_sys, s0, p->NT, alpha,
-                     p->d_carrier, ctab, ctab_shift, ktab, ttab, p->tol);
+                     p->d_carrier, ctab, ctab_shift, ktab, ttab, tol);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -101,11 +119,11 @@ __global__ __launch_bounds__(STREAM_BLOCK) void apply_kernel(
 }
 
 int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const double2 *x,
-                 double2 *y, int B, bool adj, hipStream_t st) {
+                 double2 *y, int B, bool adj, int tile_opt, int ki_opt, hipStream_t st) {
   const int64_t total = (int64_t)B * p->sys[sys].N2;
   if (total == 0) return LB_OK;
-  if (p->tile && tile_nl(p, sys))
-    return launch_tile(p, sys, B, 0, adj, alpha, t, nullptr, 0, x, nullptr, y, nullptr, st);
+  if (tile_opt && (tile_ki(p, sys, ki_opt) > 0 || (tile_opt == 2 && split_kl(p, sys) > 0)))
+    return launch_tile_apply(p, sys, B, adj, alpha, t, x, y, tile_opt, ki_opt, st);
   const int64_t nblk = (total + STREAM_BLOCK - 1) / STREAM_BLOCK;
   if (adj)
     hipLaunchKernelGGL(apply_kernel<true>, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st,
@@ -117,12 +135,6 @@ int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const
   return LB_OK;
 }
 
-// ----------------------------------------------------------------------------
-// One sweep of the stage solve over a list of segments (all states of some
-// systems), at step j:  out = q + delta with delta = w (h D q + h O zin), or
-// on the last sweep of a step the implicit-midpoint update
-// out = q + 2 delta (= q + dt M z, since h M z = z - q = delta).
-// ----------------------------------------------------------------------------
 __device__ __forceinline__ int find_segment(const StreamSeg *segs, int nseg, int64_t blk) {
   int lo = 0, hi = nseg - 1;
   while (lo < hi) {
@@ -133,89 +145,15 @@ __device__ __forceinline__ int find_segment(const StreamSeg *segs, int nseg, int
   return lo;
 }
 
-//
-// Each segment runs its own system's sweep count K (from ktab, or kfix when
-// kfix > 0): a launch for sweep kk skips the segments with K <= kk, and
-// sweep K - 1 is that segment's last.  The iterates alternate as in the
-// host's loop: sweep kk reads q (kk = 0) or z0 / z1 (kk odd / even) and
-// writes z1 / z0, the last one writes `out` and, when want_zh, the stage
-// vector into the z buffer it does not read (stage_vector_buffer).
-template <class T>
-__device__ __forceinline__ T *stage_vector_buffer(int K, T *z0, T *z1) {
-  const int kk = K - 1;
-  return kk == 0 ? z0 : (kk & 1 ? z1 : z0);
-}
-
-template <bool ADJ>
-__global__ __launch_bounds__(STREAM_BLOCK) void sweep_kernel(
-    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg,
-    const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
-    const double2 *__restrict__ ctab, const int32_t *__restrict__ ktab, int NT, int j, int kk,
-    int kfix, const double2 *__restrict__ qin, double2 *__restrict__ z0, double2 *__restrict__ z1,
-    double2 *__restrict__ out, int want_zh) {
-  __shared__ double sq[SQRT_TABLE];
-  __shared__ double2 dq[QMAX];
-  __shared__ int sseg;
-  const int tid = threadIdx.x;
-  if (tid == 0) sseg = find_segment(segs, nseg, blockIdx.x);
-  if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
-  __syncthreads();
-  const StreamSeg &sg = segs[sseg];
-  const SysDev &S = sysv[sg.sys];
-  if (tid < S.Q) dq[tid] = ctab[S.ctab_off + (int64_t)j * S.Q + tid];
-  __syncthreads();
-  const int K = kfix > 0 ? kfix : ktab[((int64_t)sg.sys * NT + j) * 2 + 1];
-  if (kk >= K) return;  // this system's solve is done (uniform per workgroup)
-  const bool last = kk == K - 1;
-  const double2 *zin = kk == 0 ? qin : (kk & 1 ? z0 : z1);
-  double2 *dst = last ? out : (kk & 1 ? z1 : z0);
-  const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + tid;
-  if (local >= sg.count) return;
-  const int64_t b = local / S.N2;
-  const int64_t r = local - b * S.N2;
-  const int i = (int)(r / S.N);
-  const int jj = (int)(r - (int64_t)i * S.N);
-  const uint64_t di = desc[S.tab_off + i], dj = desc[S.tab_off + jj];
-  const double gam = diag_rate(S, di, dj);
-  const double dE = Etab[S.tab_off + i] - Etab[S.tab_off + jj];
-  const double2 w = stage_weight(S.h, gam, dE, ADJ);
-  const int64_t base = sg.off + b * S.N2;
-  const double2 acc = offdiag<ADJ>(S, di, dj, r, dq, sq, [&](int64_t idx) { return zin[base + idx]; });
-  const double2 qv = qin[base + r];
-  // z = q + delta, delta = w (h D q + h O z): the same solve as
-  // z = w (q + h O z) without rounding 1 + h*gamma (see kernels_lds.hip).
-  const double2 hdq = cscale(S.h, cmul(diag_coef(gam, dE, ADJ), qv));
-  const double2 dn = cmul(w, cadd(hdq, cscale(S.h, acc)));
-  dst[base + r] = last ? cadd(qv, cscale(2.0, dn)) : cadd(qv, dn);
-  if (last && want_zh)  // the converged stage vector
-    stage_vector_buffer(K, z0, z1)[base + r] = cadd(qv, dn);
-}
-
-int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j, int kk,
-                 int kfix, bool adj, const double2 *ctab, const int32_t *ktab, const double2 *qin,
-                 double2 *z0, double2 *z1, double2 *out, bool want_zh, hipStream_t st) {
-  if (nblk == 0) return LB_OK;
-  dim3 g((unsigned)nblk), b(STREAM_BLOCK);
-  if (adj)
-    hipLaunchKernelGGL((sweep_kernel<true>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E, p->d_desc,
-                       ctab, ktab, p->NT, j, kk, kfix, qin, z0, z1, out, (int)want_zh);
-  else
-    hipLaunchKernelGGL((sweep_kernel<false>), g, b, 0, st, p->d_sys, d_segs, nseg, p->d_E, p->d_desc,
-                       ctab, ktab, p->NT, j, kk, kfix, qin, z0, z1, out, (int)want_zh);
-  LBX_HIP(hipGetLastError());
-  return LB_OK;
-}
-
 // ----------------------------------------------------------------------------
 // Gradient integrands of one step for streamed systems (App. B eq.
 // reducedgradient):  zh = (qh^j + qh^{j+1})/2 is the adjoint stage vector
-// (written by the last adjoint sweep of the step), z = (q^j + q^{j+1})/2 the
+// (written by the last sweep of the adjoint step), z = (q^j + q^{j+1})/2 the
 // forward one.  Per-block partial sums.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
     const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg,
-    const uint64_t *__restrict__ desc, const double2 *__restrict__ z0,
-    const double2 *__restrict__ z1, const int32_t *__restrict__ ktab, int NT, int j,
+    const uint64_t *__restrict__ desc, const double2 *__restrict__ zh,
     const double2 *__restrict__ q0, const double2 *__restrict__ q1, double *__restrict__ gpart) {
   __shared__ double sq[SQRT_TABLE];
   __shared__ int sseg;
@@ -226,8 +164,6 @@ __global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
   __syncthreads();
   const StreamSeg &sg = segs[sseg];
   const SysDev &S = sysv[sg.sys];
-  // this segment's stage vector, written by its last adjoint sweep
-  const double2 *zh = stage_vector_buffer(ktab[((int64_t)sg.sys * NT + j) * 2 + 1], z0, z1);
   const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + tid;
   const bool ok = local < sg.count;
   const int64_t b = ok ? local / S.N2 : 0;
@@ -259,11 +195,11 @@ __global__ __launch_bounds__(STREAM_BLOCK) void stream_grad_kernel(
 }
 
 int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk,
-                       const double2 *z0, const double2 *z1, const int32_t *ktab, int j,
-                       const double2 *q0, const double2 *q1, double *gpart, hipStream_t st) {
+                       const double2 *zh, const double2 *q0, const double2 *q1, double *gpart,
+                       hipStream_t st) {
   if (nblk == 0) return LB_OK;
   hipLaunchKernelGGL(stream_grad_kernel, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st, p->d_sys,
-                     d_segs, nseg, p->d_desc, z0, z1, ktab, p->NT, j, q0, q1, gpart);
+                     d_segs, nseg, p->d_desc, zh, q0, q1, gpart);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -345,14 +281,16 @@ int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int n
 }
 
 // ----------------------------------------------------------------------------
-// Adjoint terminal condition (App. B): qh = (beta_i/M) dJ/d(conj q).
+// Adjoint terminal condition (App. B): qh = (beta_i/M) dJ/d(conj q), times
+// the weight gscale[s] of the system's objective when gscale is given (the
+// incoming gradient of a backward pass; the adjoint is linear in it).
 //   J_Frob: rho(T) - rho_tar;   J_Tr: -rho_tar.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(STREAM_BLOCK) void terminal_kernel(
     const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg, int kind,
     const double2 *__restrict__ rhoT, const double2 *__restrict__ rhotar,
     const double *__restrict__ beta, const int32_t *__restrict__ seg_state0,
-    double2 *__restrict__ qh) {
+    const double *__restrict__ gscale, double2 *__restrict__ qh) {
   __shared__ int sseg;
   if (threadIdx.x == 0) sseg = find_segment(segs, nseg, blockIdx.x);
   __syncthreads();
@@ -361,7 +299,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void terminal_kernel(
   const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + threadIdx.x;
   if (local >= sg.count) return;
   const int64_t b = local / S.N2;
-  const double wgt = beta[seg_state0[sseg] + b] / (double)sg.nstates;
+  const double wgt = beta[seg_state0[sseg] + b] / (double)sg.nstates * (gscale ? gscale[sg.sys] : 1.0);
   const int64_t e = sg.off + local;
   const double2 t = rhotar[sg.boff + local];
   qh[e] = kind == LB_J_FROB ? cscale(wgt, csub(rhoT[e], t)) : cscale(-wgt, t);
@@ -369,10 +307,10 @@ __global__ __launch_bounds__(STREAM_BLOCK) void terminal_kernel(
 
 int launch_terminal(const lb_plan *p, int kind, const StreamSeg *d_segs, int nseg, int64_t nblk,
                     const double2 *rhoT, const double2 *rhotar, const double *beta,
-                    const int32_t *d_seg_state0, double2 *qh, hipStream_t st) {
+                    const int32_t *d_seg_state0, const double *gscale, double2 *qh, hipStream_t st) {
   if (nblk == 0) return LB_OK;
   hipLaunchKernelGGL(terminal_kernel, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st, p->d_sys,
-                     d_segs, nseg, kind, rhoT, rhotar, beta, d_seg_state0, qh);
+                     d_segs, nseg, kind, rhoT, rhotar, beta, d_seg_state0, gscale, qh);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -413,7 +351,7 @@ __global__ void objective_final_kernel(const SysDev *__restrict__ sysv, int nsys
                                        const double *__restrict__ beta,
                                        const int32_t *__restrict__ sys_state0, double gamma2,
                                        const double *__restrict__ alpha, double *__restrict__ J,
-                                       double *__restrict__ G) {
+                                       double *__restrict__ G, int32_t *__restrict__ status) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsys) return;
   const SysDev &S = sysv[s];
@@ -432,13 +370,15 @@ __global__ void objective_final_kernel(const SysDev *__restrict__ sysv, int nsys
     reg += a * a;
   }
   const int M = st1 - st0;
-  G[s] = (M > 0 ? acc / (double)M : 0.0) + 0.5 * gamma2 * reg;
+  const double g = (M > 0 ? acc / (double)M : 0.0) + 0.5 * gamma2 * reg;
+  if (G) G[s] = g;
+  if (status && M > 0 && !isfinite(g)) atomicOr(status, LB_STATUS_NONFINITE);
 }
 
 int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const double2 *rhotar,
                      const double *beta, const int32_t *d_state_sys, const int64_t *d_state_off,
                      const int32_t *d_sys_state0, int nstates, double gamma2, const double *alpha,
-                     double *partial, double *J, double *G, hipStream_t st) {
+                     double *partial, double *J, double *G, int32_t *status, hipStream_t st) {
   if (nstates > 0) {
     hipLaunchKernelGGL(objective_partial_kernel, dim3(OBJ_PARTS, nstates), dim3(256), 0, st,
                        p->d_sys, kind, rhoT, rhotar, d_state_sys, d_state_off, partial);
@@ -446,7 +386,7 @@ int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const doub
   }
   const int nsys = (int)p->sys.size();
   hipLaunchKernelGGL(objective_final_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, p->d_sys, nsys,
-                     kind, partial, beta, d_sys_state0, gamma2, alpha, J, G);
+                     kind, partial, beta, d_sys_state0, gamma2, alpha, J, G, status);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -456,7 +396,9 @@ int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const doub
 // parameterisation of eq. rotctrl):
 //   dG/dRe alpha_q^{s,f} = dt sum_j 2pi S_s(t) [gp cos(W t) + gq sin(W t)] + gamma2 Re alpha
 //   dG/dIm alpha_q^{s,f} = dt sum_j 2pi S_s(t) [-gp sin(W t) + gq cos(W t)] + gamma2 Im alpha
-// with t = t_{j+1/2}, W = 2 pi Omega_q^f, gp/gq the per-step integrands.
+// with t = t_{j+1/2}, W = 2 pi Omega_q^f, gp/gq the per-step integrands.  With
+// gscale (a backward pass) the integrands already carry the system's weight
+// through the terminal condition, and the Tikhonov term is scaled by it.
 // ----------------------------------------------------------------------------
 // One workgroup per (system, q, s, f): its threads take the steps of the
 // spline's support in turn (one sincos per step for both the Re and the Im
@@ -466,7 +408,7 @@ constexpr int CONTRACT_BLOCK = 256;
 __global__ __launch_bounds__(CONTRACT_BLOCK) void grad_contract_kernel(
     const SysDev *__restrict__ sysv, int nsys, const double *__restrict__ gstep,
     const double *__restrict__ alpha, const double *__restrict__ carrier, double gamma2,
-    double *__restrict__ grad) {
+    const double *__restrict__ gscale, double *__restrict__ grad) {
   __shared__ double red[CONTRACT_BLOCK / 64][2];
   const int64_t k = 2 * (int64_t)blockIdx.x;  // the Re coefficient; k + 1 is the Im one
   int s = 0;
@@ -504,17 +446,18 @@ __global__ __launch_bounds__(CONTRACT_BLOCK) void grad_contract_kernel(
     double v = 0.0;
 #pragma unroll
     for (int w = 0; w < CONTRACT_BLOCK / 64; ++w) v += red[w][threadIdx.x];
-    grad[k + threadIdx.x] = TWO_PI * S.dt * v + gamma2 * alpha[k + threadIdx.x];
+    const double gw = gscale ? gscale[s] : 1.0;
+    grad[k + threadIdx.x] = TWO_PI * S.dt * v + gw * gamma2 * alpha[k + threadIdx.x];
   }
 }
 
 int launch_grad_contract(const lb_plan *p, const double *gstep, const double *alpha,
-                         double gamma2, double *grad, hipStream_t st) {
+                         double gamma2, const double *gscale, double *grad, hipStream_t st) {
   const int nsys = (int)p->sys.size();
   const int64_t total = p->sys[nsys - 1].alpha_off + p->sys[nsys - 1].nalpha;
   if (total == 0) return LB_OK;
   hipLaunchKernelGGL(grad_contract_kernel, dim3((unsigned)(total / 2)), dim3(CONTRACT_BLOCK), 0, st,
-                     p->d_sys, nsys, gstep, alpha, p->d_carrier, gamma2, grad);
+                     p->d_sys, nsys, gstep, alpha, p->d_carrier, gamma2, gscale, grad);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }

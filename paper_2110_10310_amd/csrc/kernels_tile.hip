@@ -1,368 +1,58 @@
 // Block-tiled streaming kernels for large systems of equal-level subsystems
-// (the eight-qutrit ring is the design case): lindblad_apply, the stage-solve
-// sweeps and the gradient integrands of a single streamed system whose
-// subsystems all have NL levels, in one of the LBX_TILE_SHAPES (tile_kernel,
-// tile_grad_kernel), and the multi-pass variant (pass_kernel, LB_OPT_TILE 2).
+// (the eight-qutrit ring is the design case): lindblad_apply (tile_kernel)
+// and the gradient integrands of one step (tile_grad_kernel) of a single
+// streamed system whose subsystems all have NL levels, in one of the
+// LBX_TILE_SHAPES, and the multi-pass apply (pass_kernel, LB_OPT_TILE 2).
+// The stage sweeps of the implicit-midpoint steps use the same tiles inside
+// the persistent step kernels of kernels_step.hip.
 #include <hip/hip_runtime.h>
 
 #include "lbx_host.hpp"
+#include "tile_unit.hpp"
 
 namespace lbx {
 
 constexpr int TILE_BLOCK = 512;  // threads of the multi-pass kernels
 
-namespace {
+using tile::cmac;
+using tile::ctl_coef;
+using tile::DIR_CM;
+using tile::DIR_CP;
+using tile::DIR_RM;
+using tile::DIR_RP;
+using tile::ipow;
+using tile::sqrt_small;
+using tile::uniform;
 
-// sqrt(k) for 0 <= k <= NL as a select chain (k varies per lane).
-template <int NL>
-__device__ __forceinline__ double sqrt_small(int k) {
-  double r = 0.0;
-  if (k == 1) r = 1.0;
-  if (NL >= 2 && k == 2) r = 1.4142135623730951;
-  if (NL >= 3 && k == 3) r = 1.7320508075688772;
-  if (NL >= 4 && k == 4) r = 2.0;
-  return r;
-}
-
-constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
-
-// Value of lane l (uniform l) of a double / int64.
-__device__ __forceinline__ double lane_d(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ int64_t lane_i64(int64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ double uniform(double v) {
-  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
-  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
-  return __hiloint2double(hi, lo);
-}
-
-// Every off-diagonal term is a complex multiple of one neighbour value.  With
-// d = a + i b the control of subsystem q, the forward control commutator
-// contributes
-//   row shift +e (weight sqrt(n+1)):  (b, -a) x_{i+e,j}
-//   row shift -e (weight sqrt(n)):    (-b, -a) x_{i-e,j}
-//   column shift +e (sqrt(m+1)):      (b, a) x_{i,j+e}
-//   column shift -e (sqrt(m)):        (-b, a) x_{i,j-e}
-// times the weight, and the adjoint the negatives; the decay jump
-// contributes g1 sqrt((n+1)(m+1)) x_{i+e,j+e} (adjoint: g1 sqrt(nm) x_{i-e,j-e}).
-// These are the terms of `offdiag` in lbx_device.hpp regrouped by neighbour.
-enum { DIR_RP = 0, DIR_RM = 1, DIR_CP = 2, DIR_CM = 3 };
-
-template <int DIR, bool ADJ>
-__device__ __forceinline__ double2 ctl_coef(double a, double b, double wgt) {
-  const double s = ADJ ? -wgt : wgt;
-  if (DIR == DIR_RP) return make_double2(s * b, -s * a);
-  if (DIR == DIR_RM) return make_double2(-s * b, -s * a);
-  if (DIR == DIR_CP) return make_double2(s * b, s * a);
-  return make_double2(-s * b, s * a);
-}
-
-__device__ __forceinline__ void cmac(double2 &acc, double2 c, double2 v) {
-  acc.x += c.x * v.x - c.y * v.y;
-  acc.y += c.x * v.y + c.y * v.x;
-}
-
-}  // namespace
-
-// MODE 0: y = M x (or M^+ x).  MODE 1: out = q + delta.  MODE 2: out = q + 2 delta,
-// delta = w (h D q + h O zin) as in sweep_kernel.
-//
-// A workgroup owns one TR x TC block of a state, TR = NL^KR rows and
-// TC = NL^KC columns: the KR (KC) least significant digits of the row
-// (column) index vary and the others are fixed.  The block is staged in LDS,
-// so every neighbour along an internal digit (row or column ladder shift, or
-// decay jump of a subsystem internal in both) is an LDS read.  Along the
-// external digits every neighbour of the block is the block shifted by a
-// constant offset, with a coefficient that depends only on the fixed digits.
-// Each wavefront tabulates those directions, one per lane (existence,
-// coefficient, shift), and walks the existing ones from the ballot mask with
-// readlane, G directions at a time: G coalesced loads per entry of a thread
-// are in flight together, the neighbour values need no per-entry weights,
-// and no direction that does not exist for the block is loaded.  The
-// block's own loads are all issued before its LDS stores.  Jumps of a
-// subsystem with one internal and one external digit are per-entry global
-// loads.  Blocks are remapped so that each XCD (blocks are dealt to the 8
-// XCDs round-robin) walks a contiguous band of block rows.
-template <int NL, int QC, int KR, int KC, bool ADJ, int MODE, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void tile_kernel(
-    const SysDev *__restrict__ sysv, int sys, int64_t nblocks, const double *__restrict__ Etab,
-    const double *__restrict__ alpha, const double *__restrict__ carrier, double t,
-    const double2 *__restrict__ ctab, int jstep, const double2 *__restrict__ zin,
-    const double2 *__restrict__ qin, double2 *__restrict__ out, double2 *__restrict__ zout) {
-  extern __shared__ double2 tile[];
-  constexpr int ER = QC - KR, EC = QC - KC;  // external row / column digits
-  constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
-  constexpr int TT = TR * TC;
-  constexpr int EPT = (TT + BLOCK - 1) / BLOCK;
-  // External direction slots: two ladder shifts per external digit and one
-  // jump per subsystem external in both (at most 40 for 8 subsystems), one
-  // per lane; the existing ones are applied G at a time.
-  constexpr int ND = 2 * ER + 2 * EC + (ER < EC ? ER : EC);
-  static_assert(ND < 64, "one lane per direction slot, and a lane without one");
-  constexpr int G = EPT >= 8 ? 1 : EPT >= 4 ? 2 : 4;
-  constexpr bool TABLE = EPT > 1 && EPT < 12;
+// y = M x (or M^+ x) for B states, one unit per workgroup (tile_unit.hpp);
+// blocks are remapped so that each XCD (blocks are dealt to the 8 XCDs
+// round-robin) walks a contiguous band of units.  Every wavefront forms the
+// controls, lane q holding d_q, before the block's loads, so that no loaded
+// value is live across the evaluation.
+template <int NL, int QC, int KR, int KC, bool ADJ, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tile_kernel(const SysDev *__restrict__ sysv, int sys, int64_t nblocks,
+                                                     const double *__restrict__ Etab,
+                                                     const double *__restrict__ alpha,
+                                                     const double *__restrict__ carrier, double t,
+                                                     const double2 *__restrict__ x, double2 *__restrict__ y) {
+  extern __shared__ double2 tileb[];
   const SysDev &S = sysv[sys];
-  const int N = S.N;
-  const int NBR = N / TR, NBC = N / TC;
-  const int64_t N2 = S.N2;
-  const int tid = threadIdx.x;
   const int64_t per = (nblocks + 7) / 8;
   const int64_t lb = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (lb >= nblocks) return;
-  const int64_t b = lb / ((int64_t)NBR * NBC);
-  const int rem = (int)(lb - b * NBR * NBC);
-  const int bi = rem / NBC, bj = rem - (rem / NBC) * NBC;
-  const double2 *X = zin + b * N2;
-  const int64_t base = (int64_t)bi * TR * N + (int64_t)bj * TC;
-  // flat offset (within the state) of this thread's k-th entry
-  auto off_of = [&](int k) -> int64_t {
-    const int f = tid + k * BLOCK;
-    const int ff = f < TT ? f : 0;
-    const int a = ff / TC, c = ff - (ff / TC) * TC;
-    return base + (int64_t)a * N + c;
-  };
-  // fixed (external) digits of the row and column index
-  int ne[ER > 0 ? ER : 1], me[EC > 0 ? EC : 1];
-  {
-    int ri = bi;
-#pragma unroll
-    for (int q = ER - 1; q >= 0; --q) {
-      ne[q] = ri % NL;
-      ri /= NL;
-    }
-    int rj = bj;
-#pragma unroll
-    for (int q = EC - 1; q >= 0; --q) {
-      me[q] = rj % NL;
-      rj /= NL;
-    }
-  }
-  // Every wavefront forms the controls, lane q holding d_q: the apply (MODE
-  // 0) evaluates them before the block's loads, so that no loaded value is
-  // live across the evaluation; the sweeps read them from the control table.
-  const int lane = tid & 63;
+  const int lane = threadIdx.x & 63;
   double2 dv = make_double2(0.0, 0.0);
-  if (MODE == 0 && lane < QC) dv = control_value(S, alpha, carrier + S.carrier_off, lane, t);
-  int64_t offs[EPT];
-  double2 tv[EPT];
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {  // (past the block's end: entry 0, unused)
-    offs[k] = off_of(k);
-    tv[k] = X[offs[k]];
-  }
-  if (MODE != 0 && lane < QC) dv = ctab[S.ctab_off + (int64_t)jstep * QC + lane];
+  if (lane < QC) dv = control_value(S, alpha, carrier + S.carrier_off, lane, t);
   double da[QC], db[QC];
 #pragma unroll
   for (int q = 0; q < QC; ++q) {
-    da[q] = lane_d(dv.x, q);
-    db[q] = lane_d(dv.y, q);
+    da[q] = tile::lane_d(dv.x, q);
+    db[q] = tile::lane_d(dv.y, q);
   }
-  // While the block loads, every wavefront builds its table of external
-  // directions (blocks of 2 to 11 entries per thread): lane d takes slot
-  // d (row digit d / 2, column digit (d - 2 ER) / 2, then jumps) and decides
-  // whether its neighbour exists for this block, with its coefficient and
-  // shift.
-  bool ex = false;
-  double2 cf = make_double2(0.0, 0.0);
-  int64_t sh = 0;
-  if constexpr (TABLE) {
-    if (lane < ND) {
-      const int d = lane;
-      const int kind = d < 2 * ER ? 0 : d < 2 * ER + 2 * EC ? 1 : 2;
-      const int q = kind == 0 ? d >> 1 : kind == 1 ? (d - 2 * ER) >> 1 : d - 2 * ER - 2 * EC;
-      const bool plus = kind == 2 || !(d & 1);
-      int n = 0, m = 0;
-      int64_t st = 0;
-      double g1 = 0.0, a = 0.0, bq = 0.0;
-#pragma unroll
-      for (int qq = 0; qq < QC; ++qq)
-        if (q == qq) {
-          st = S.stride[qq];
-          g1 = S.g1[qq];
-          a = da[qq];
-          bq = db[qq];
-        }
-#pragma unroll
-      for (int qq = 0; qq < ER; ++qq)
-        if (q == qq) n = ne[qq];
-#pragma unroll
-      for (int qq = 0; qq < EC; ++qq)
-        if (q == qq) m = me[qq];
-      if (kind == 0) {
-        ex = plus ? n + 1 < NL : n > 0;
-        cf = plus ? ctl_coef<DIR_RP, ADJ>(a, bq, sqrt_small<NL>(n + 1))
-                  : ctl_coef<DIR_RM, ADJ>(a, bq, sqrt_small<NL>(n));
-        sh = plus ? st * N : -st * N;
-      } else if (kind == 1) {
-        ex = plus ? m + 1 < NL : m > 0;
-        cf = plus ? ctl_coef<DIR_CP, ADJ>(a, bq, sqrt_small<NL>(m + 1))
-                  : ctl_coef<DIR_CM, ADJ>(a, bq, sqrt_small<NL>(m));
-        sh = plus ? st : -st;
-      } else {
-        ex = !ADJ ? (n + 1 < NL && m + 1 < NL) : (n > 0 && m > 0);
-        cf = make_double2(!ADJ ? g1 * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
-                               : g1 * sqrt_small<NL>(n) * sqrt_small<NL>(m),
-                          0.0);
-        sh = !ADJ ? st * N + st : -(st * N + st);
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int f = tid + k * BLOCK;
-    if (f < TT) tile[f] = tv[k];
-  }
-  const double h = S.h;
-  const double *Es = Etab + S.tab_off;
-  // External directions first (they do not read the LDS block), G at a time:
-  // the existing slots are taken in order from the ballot mask, a missing
-  // G-th one is the last lane (no slot: weight zero, shift zero); one
-  // coalesced load per entry of the thread and direction, G x EPT in flight.
-  double2 acc[EPT];
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) acc[k] = make_double2(0.0, 0.0);
-  if constexpr (TABLE) {
-    uint64_t emask = __ballot(ex);
-    while (emask) {
-      int dl[G];
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        dl[g] = emask ? (int)__builtin_ctzll(emask) : 63;
-        emask &= emask - 1;
-      }
-      double2 cg[G], v[G][EPT];
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int64_t s = lane_i64(sh, dl[g]);
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) v[g][k] = X[offs[k] + s];
-      }
-#pragma unroll
-      for (int g = 0; g < G; ++g) cg[g] = make_double2(lane_d(cf.x, dl[g]), lane_d(cf.y, dl[g]));
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) cmac(acc[k], cg[g], v[g][k]);
-    }
-  } else {
-    // One entry per thread, or the largest blocks: the directions one at a
-    // time under uniform branches (measured faster there than the table).
-    auto direction = [&](double2 c, int64_t shift) {
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) cmac(acc[k], c, X[offs[k] + shift]);
-    };
-#pragma unroll
-    for (int q = 0; q < ER; ++q) {
-      const int n = ne[q];
-      const int64_t sN = (int64_t)S.stride[q] * N;
-      if (n + 1 < NL) direction(ctl_coef<DIR_RP, ADJ>(da[q], db[q], sqrt_small<NL>(n + 1)), sN);
-      if (n > 0) direction(ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), -sN);
-    }
-#pragma unroll
-    for (int q = 0; q < EC; ++q) {
-      const int m = me[q];
-      const int64_t s1 = S.stride[q];
-      if (m + 1 < NL) direction(ctl_coef<DIR_CP, ADJ>(da[q], db[q], sqrt_small<NL>(m + 1)), s1);
-      if (m > 0) direction(ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), -s1);
-    }
-#pragma unroll
-    for (int q = 0; q < (ER < EC ? ER : EC); ++q) {
-      const int n = ne[q], m = me[q];
-      const bool jr = !ADJ ? (n + 1 < NL && m + 1 < NL) : (n > 0 && m > 0);
-      if (jr) {
-        const double cj = !ADJ ? S.g1[q] * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
-                               : S.g1[q] * sqrt_small<NL>(n) * sqrt_small<NL>(m);
-        const int64_t sj = (int64_t)S.stride[q] * N + S.stride[q];
-        direction(make_double2(cj, 0.0), !ADJ ? sj : -sj);
-      }
-    }
-  }
-  __syncthreads();
-  // Internal terms (LDS), the diagonal part and the output, entry by entry.
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int f = tid + k * BLOCK;
-    if (f >= TT) continue;
-    const int a = f / TC, c = f - (f / TC) * TC;
-    int nd[QC], md[QC];
-    {
-      int ra = a;
-#pragma unroll
-      for (int q = QC - 1; q >= ER; --q) {
-        nd[q] = ra % NL;
-        ra /= NL;
-      }
-#pragma unroll
-      for (int q = 0; q < ER; ++q) nd[q] = ne[q];
-      int rc = c;
-#pragma unroll
-      for (int q = QC - 1; q >= EC; --q) {
-        md[q] = rc % NL;
-        rc /= NL;
-      }
-#pragma unroll
-      for (int q = 0; q < EC; ++q) md[q] = me[q];
-    }
-    double gam = 0.0;
-    double2 ac = acc[k];
-#pragma unroll
-    for (int q = 0; q < QC; ++q) {
-      const int n = nd[q], m = md[q];
-      const double dnm = (double)(n - m);
-      gam += 0.5 * (S.g1[q] * (double)(n + m) + S.g2[q] * dnm * dnm);
-      const int st = S.stride[q];
-      // Internal neighbours are LDS reads; a missing one reads the entry
-      // itself with a zero weight (no divergent branches).
-      const bool rp = n + 1 < NL, rm = n > 0, cp = m + 1 < NL, cm = m > 0;
-      if (q >= ER) {  // internal row digit: a row shift of st is st*TC entries in the block
-        cmac(ac, ctl_coef<DIR_RP, ADJ>(da[q], db[q], rp ? sqrt_small<NL>(n + 1) : 0.0),
-             tile[f + (rp ? st * TC : 0)]);
-        cmac(ac, ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), tile[f - (rm ? st * TC : 0)]);
-      }
-      if (q >= EC) {
-        cmac(ac, ctl_coef<DIR_CP, ADJ>(da[q], db[q], cp ? sqrt_small<NL>(m + 1) : 0.0),
-             tile[f + (cp ? st : 0)]);
-        cmac(ac, ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), tile[f - (cm ? st : 0)]);
-      }
-      const bool jr = !ADJ ? (rp && cp) : (rm && cm);
-      const double cj = !jr ? 0.0
-                            : !ADJ ? S.g1[q] * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
-                                   : S.g1[q] * sqrt_small<NL>(n) * sqrt_small<NL>(m);
-      if (q >= ER && q >= EC) {
-        const double2 v = tile[f + (!jr ? 0 : !ADJ ? st * TC + st : -(st * TC + st))];
-        ac.x += cj * v.x;
-        ac.y += cj * v.y;
-      } else if (q >= ER || q >= EC) {  // one digit internal: a per-entry global load
-        const int64_t sj = (int64_t)st * N + st;
-        const double2 v = X[offs[k] + (!jr ? 0 : !ADJ ? sj : -sj)];
-        ac.x += cj * v.x;
-        ac.y += cj * v.y;
-      }
-    }
-    const int i = bi * TR + a, j = bj * TC + c;
-    const double dE = Es[i] - Es[j];
-    const double2 D = diag_coef(gam, dE, ADJ);
-    const int64_t e = b * N2 + offs[k];
-    if (MODE == 0) {
-      out[e] = cadd(ac, cmul(D, tile[f]));
-    } else {
-      const double2 qv = qin[e];
-      const double2 w = stage_weight(h, gam, dE, ADJ);
-      const double2 hdq = cscale(h, cmul(D, qv));
-      const double2 dn = cmul(w, make_double2(hdq.x + h * ac.x, hdq.y + h * ac.y));
-      out[e] = MODE == 2 ? make_double2(qv.x + 2.0 * dn.x, qv.y + 2.0 * dn.y) : cadd(qv, dn);
-      if (MODE == 2 && zout) zout[e] = cadd(qv, dn);  // the converged stage vector
-    }
-  }
+  tile::tile_unit<NL, QC, KR, KC, ADJ, BLOCK>(S, lb, x, tileb, da, db, Etab + S.tab_off, false,
+                                              [&](const tile::Entry &en) {
+                                                y[en.e] = cadd(en.acc, cmul(diag_coef(en.gam, en.dE, ADJ), en.own));
+                                              });
 }
 
 // Gradient integrands of one step (App. B eq. reducedgradient) with the same
@@ -382,7 +72,7 @@ template <int NL, int QC, int KR, int KC, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void tile_grad_kernel(
     const SysDev *__restrict__ sysv, int sys, int64_t nblocks, const double2 *__restrict__ zh,
     const double2 *__restrict__ q0, const double2 *__restrict__ q1, double *__restrict__ gpart) {
-  extern __shared__ double2 tile[];
+  extern __shared__ double2 tls[];
   __shared__ double red[BLOCK / 64][2 * QC];
   constexpr int ER = QC - KR, EC = QC - KC;
   constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
@@ -414,7 +104,7 @@ __global__ __launch_bounds__(BLOCK) void tile_grad_kernel(
     const int64_t e = off_of(k);  // (past the block's end: entry 0, unused)
     const double2 v = Z[e];
     const double2 a = q0[b * N2 + e], c = q1[b * N2 + e];
-    if (f < TT) tile[f] = v;
+    if (f < TT) tls[f] = v;
     z[k] = f < TT ? make_double2(0.5 * (a.x + c.x), 0.5 * (a.y + c.y)) : make_double2(0.0, 0.0);
   }
   int ne[ER > 0 ? ER : 1], me[EC > 0 ? EC : 1];
@@ -478,7 +168,7 @@ __global__ __launch_bounds__(BLOCK) void tile_grad_kernel(
         const int n = ra % NL;
         ra /= NL;
         const bool rp = n + 1 < NL, rm = n > 0;
-        const double2 vp = tile[f + (rp ? st * TC : 0)], vm = tile[f - (rm ? st * TC : 0)];
+        const double2 vp = tls[f + (rp ? st * TC : 0)], vm = tls[f - (rm ? st * TC : 0)];
         const double wp = rp ? sqrt_small<NL>(n + 1) : 0.0, wm = sqrt_small<NL>(n);
         gp[q] += wp * cross2(vp, z[k]) + wm * cross2(vm, z[k]);
         gq[q] += -wp * dot2(vp, z[k]) + wm * dot2(vm, z[k]);
@@ -487,7 +177,7 @@ __global__ __launch_bounds__(BLOCK) void tile_grad_kernel(
         const int m = rc % NL;
         rc /= NL;
         const bool cp = m + 1 < NL, cm = m > 0;
-        const double2 vp = tile[f + (cp ? st : 0)], vm = tile[f - (cm ? st : 0)];
+        const double2 vp = tls[f + (cp ? st : 0)], vm = tls[f - (cm ? st : 0)];
         const double wp = cp ? sqrt_small<NL>(m + 1) : 0.0, wm = sqrt_small<NL>(m);
         gp[q] += -wp * cross2(vp, z[k]) - wm * cross2(vm, z[k]);
         gq[q] += -wp * dot2(vp, z[k]) + wm * dot2(vm, z[k]);
@@ -534,7 +224,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void pass_kernel(
     const double *__restrict__ alpha, const double *__restrict__ carrier, double t,
     const double2 *__restrict__ ctab, int jstep, const double2 *__restrict__ zin,
     const double2 *__restrict__ qin, double2 *__restrict__ out, double2 *__restrict__ zout) {
-  extern __shared__ double2 tile[];
+  extern __shared__ double2 tls[];
   __shared__ double2 dqs[QC];
   constexpr int NR = popc(RM), NC = popc(CM);
   constexpr int TRn = ipow(NL, NR), TCn = ipow(NL, NC), TT = TRn * TCn;
@@ -611,7 +301,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void pass_kernel(
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int f = tid + k * TILE_BLOCK;
-      if (f < TT) tile[f] = tv[k];
+      if (f < TT) tls[f] = tv[k];
     }
   }
   const double h = S.h;
@@ -656,15 +346,15 @@ __global__ __launch_bounds__(TILE_BLOCK) void pass_kernel(
       const int sr = ipow(NL, popc(RM & (~0u << (q + 1)))) * TCn;
       const int sc = ipow(NL, popc(CM & (~0u << (q + 1))));
       const bool rp = n + 1 < NL, rm = n > 0, cp = m + 1 < NL, cm = m > 0;
-      cmac(ac, ctl_coef<DIR_RP, ADJ>(da[q], db[q], rp ? sqrt_small<NL>(n + 1) : 0.0), tile[f + (rp ? sr : 0)]);
-      cmac(ac, ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), tile[f - (rm ? sr : 0)]);
-      cmac(ac, ctl_coef<DIR_CP, ADJ>(da[q], db[q], cp ? sqrt_small<NL>(m + 1) : 0.0), tile[f + (cp ? sc : 0)]);
-      cmac(ac, ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), tile[f - (cm ? sc : 0)]);
+      cmac(ac, ctl_coef<DIR_RP, ADJ>(da[q], db[q], rp ? sqrt_small<NL>(n + 1) : 0.0), tls[f + (rp ? sr : 0)]);
+      cmac(ac, ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), tls[f - (rm ? sr : 0)]);
+      cmac(ac, ctl_coef<DIR_CP, ADJ>(da[q], db[q], cp ? sqrt_small<NL>(m + 1) : 0.0), tls[f + (cp ? sc : 0)]);
+      cmac(ac, ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), tls[f - (cm ? sc : 0)]);
       const bool jr = !ADJ ? (rp && cp) : (rm && cm);
       const double cj = !jr ? 0.0
                             : !ADJ ? S.g1[q] * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
                                    : S.g1[q] * sqrt_small<NL>(n) * sqrt_small<NL>(m);
-      const double2 vj = tile[f + (!jr ? 0 : !ADJ ? sr + sc : -(sr + sc))];
+      const double2 vj = tls[f + (!jr ? 0 : !ADJ ? sr + sc : -(sr + sc))];
       ac.x += cj * vj.x;
       ac.y += cj * vj.y;
     }
@@ -688,7 +378,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void pass_kernel(
     const double dE = Es[i] - Es[j];
     const double2 D = diag_coef(gam, dE, ADJ);
     if (MODE == 0) {
-      out[e] = cadd(ac, cmul(D, tile[f]));
+      out[e] = cadd(ac, cmul(D, tls[f]));
     } else {
       const double2 qv = qin[e];
       const double2 w = stage_weight(h, gam, dE, ADJ);
@@ -776,54 +466,11 @@ int launch_split(const lb_plan *p, int sys, int B, int mode, bool adj, const dou
   return fail(LB_EUNSUPPORTED, "system not eligible for the multi-pass kernels");
 }
 
-// Block shapes: KR row digits and KC column digits inside a block.  The
-// default is the shape listed first in LBX_TILE_SHAPES for the system (the
-// largest square block, at most 6561 entries); the plan's LB_OPT_TILE_KI
-// selects another instantiated shape (encoded 10*KR + KC).
-
-template <int NL, int QC, int KR, int KC, int BLOCK, bool ADJ, int MODE>
-static int tile_launch(const lb_plan *p, int sys, int B, const double *alpha, double t,
-                       const double2 *ctab, int j, const double2 *zin, const double2 *qin,
-                       double2 *out, double2 *zout, hipStream_t st) {
-  constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
-  const int N = p->sys[sys].N;
-  const size_t shmem = (size_t)TR * TC * sizeof(double2);
-  auto kern = tile_kernel<NL, QC, KR, KC, ADJ, MODE, BLOCK>;
-  LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  const int64_t nblocks = (int64_t)B * (N / TR) * (N / TC);
-  const int64_t grid = ((nblocks + 7) / 8) * 8;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(BLOCK), shmem, st, p->d_sys, sys, nblocks,
-                     p->d_E, alpha, p->d_carrier, t, ctab, j, zin, qin, out, zout);
-  LBX_HIP(hipGetLastError());
-  return LB_OK;
-}
-
-template <int NL, int QC, int KR, int KC, int BLOCK>
-static int tile_modes(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha,
-                      double t, const double2 *ctab, int j, const double2 *zin, const double2 *qin,
-                      double2 *out, double2 *zout, hipStream_t st) {
-  if (adj) {
-    if (mode == 0) return tile_launch<NL, QC, KR, KC, BLOCK, true, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
-    if (mode == 1) return tile_launch<NL, QC, KR, KC, BLOCK, true, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
-    return tile_launch<NL, QC, KR, KC, BLOCK, true, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
-  }
-  if (mode == 0) return tile_launch<NL, QC, KR, KC, BLOCK, false, 0>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
-  if (mode == 1) return tile_launch<NL, QC, KR, KC, BLOCK, false, 1>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
-  return tile_launch<NL, QC, KR, KC, BLOCK, false, 2>(p, sys, B, alpha, t, ctab, j, zin, qin, out, zout, st);
-}
-
-// Instantiated shapes (NL, Q, KR, KC, threads per block); the first listed
-// for a (NL, Q) is the default.  Blocks of up to 2187 entries run 256
-// threads, so that several fit on one compute unit.
-#define LBX_TILE_SHAPES(X)                                                                    \
-  X(3, 8, 4, 4, 512) X(3, 8, 4, 3, 256) X(3, 8, 3, 4, 256) X(3, 8, 4, 2, 256)                  \
-  X(3, 8, 3, 3, 256) X(3, 8, 3, 2, 256) X(3, 8, 2, 3, 256)                                     \
-  X(3, 7, 4, 4, 512) X(3, 7, 4, 3, 256) X(3, 7, 3, 3, 256) X(3, 6, 4, 4, 512)                  \
-  X(3, 6, 4, 3, 256) X(3, 5, 3, 3, 256) X(3, 5, 3, 2, 256) X(3, 5, 2, 3, 256)                  \
-  X(2, 9, 6, 6, 512) X(2, 10, 6, 6, 512) X(2, 11, 6, 6, 512) X(2, 12, 6, 6, 512)               \
-  X(4, 5, 3, 3, 512) X(4, 6, 3, 3, 512)
-
-int tile_ki(const lb_plan *p, int sys) {
+// Block shapes: KR row digits and KC column digits inside a block
+// (LBX_TILE_SHAPES in tile_unit.hpp).  The default is the shape listed first
+// for the system (the largest square block, at most 6561 entries); the
+// LB_OPT_TILE_KI option selects another instantiated shape (10*KR + KC).
+int tile_ki(const lb_plan *p, int sys, int ki_opt) {
   const SysDev &S = p->sys[sys];
   const int nl = S.nlev[0];
   for (int q = 1; q < S.Q; ++q)
@@ -832,22 +479,36 @@ int tile_ki(const lb_plan *p, int sys) {
 #define X(A, B, R, C, T)                                           \
   if (nl == A && S.Q == B) {                                       \
     if (!first) first = 10 * R + C;                                \
-    if (p->tile_ki == 10 * R + C) return 10 * R + C;               \
+    if (ki_opt == 10 * R + C) return 10 * R + C;                   \
   }
   LBX_TILE_SHAPES(X)
 #undef X
   return first;
 }
 
+template <int NL, int QC, int KR, int KC, int BLOCK, bool ADJ>
+static int tile_launch(const lb_plan *p, int sys, int B, const double *alpha, double t, const double2 *x,
+                       double2 *y, hipStream_t st) {
+  using Sh = tile::Shape<NL, QC, KR, KC, BLOCK>;
+  const size_t shmem = Sh::lds_bytes();
+  auto kern = tile_kernel<NL, QC, KR, KC, ADJ, BLOCK>;
+  LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  const int64_t nblocks = tile::tile_units(p->sys[sys].N, Sh::TR, Sh::TC, B);
+  const int64_t grid = ((nblocks + 7) / 8) * 8;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(BLOCK), shmem, st, p->d_sys, sys, nblocks, p->d_E, alpha,
+                     p->d_carrier, t, x, y);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
 template <int NL, int QC, int KR, int KC, int BLOCK>
 static int tile_grad_launch(const lb_plan *p, int sys, int B, const double2 *zh, const double2 *q0,
                             const double2 *q1, double *gpart, int64_t *rows, hipStream_t st) {
-  constexpr int TR = ipow(NL, KR), TC = ipow(NL, KC);
-  const int N = p->sys[sys].N;
-  const size_t shmem = (size_t)TR * TC * sizeof(double2);
+  using Sh = tile::Shape<NL, QC, KR, KC, BLOCK>;
+  const size_t shmem = Sh::lds_bytes();
   auto kern = tile_grad_kernel<NL, QC, KR, KC, BLOCK>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  const int64_t nblocks = (int64_t)B * (N / TR) * (N / TC);
+  const int64_t nblocks = tile::tile_units(p->sys[sys].N, Sh::TR, Sh::TC, B);
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(BLOCK), shmem, st, p->d_sys, sys, nblocks, zh, q0,
                      q1, gpart);
@@ -857,14 +518,13 @@ static int tile_grad_launch(const lb_plan *p, int sys, int B, const double2 *zh,
 }
 
 // Gradient integrands of one step for a system on the block-tiled path, in
-// the block shape of its sweeps (the single-pass shape even when the sweeps
-// use the multi-pass kernels).  *rows receives the number of partial rows.
-int launch_tile_grad(const lb_plan *p, int sys, int B, const double2 *zh, const double2 *q0,
+// block shape k.  *rows receives the number of partial rows.
+int launch_tile_grad(const lb_plan *p, int sys, int B, int k, const double2 *zh, const double2 *q0,
                      const double2 *q1, double *gpart, int64_t *rows, hipStream_t st) {
   *rows = 0;
   if (B == 0) return LB_OK;
   const SysDev &S = p->sys[sys];
-  const int nl = S.nlev[0], k = tile_ki(p, sys);
+  const int nl = S.nlev[0];
 #define X(A, Bq, R, C, T) \
   if (nl == A && S.Q == Bq && k == 10 * R + C) return tile_grad_launch<A, Bq, R, C, T>(p, sys, B, zh, q0, q1, gpart, rows, st);
   LBX_TILE_SHAPES(X)
@@ -872,9 +532,8 @@ int launch_tile_grad(const lb_plan *p, int sys, int B, const double2 *zh, const 
   return fail(LB_EUNSUPPORTED, "system not eligible for the tiled gradient kernel");
 }
 
-int64_t tile_grad_rows(const lb_plan *p, int sys, int B) {
+int64_t tile_grad_rows(const lb_plan *p, int sys, int B, int k) {
   const SysDev &S = p->sys[sys];
-  const int k = tile_ki(p, sys);
   if (!k) return 0;
   int tr = 1, tc = 1;
   for (int i = 0; i < k / 10; ++i) tr *= S.nlev[0];
@@ -882,21 +541,17 @@ int64_t tile_grad_rows(const lb_plan *p, int sys, int B) {
   return (int64_t)B * (S.N / tr) * (S.N / tc);
 }
 
-int tile_nl(const lb_plan *p, int sys) {
-  return (tile_ki(p, sys) > 0 || (p->tile == 2 && split_kl(p, sys) > 0)) ? p->sys[sys].nlev[0] : 0;
-}
-
-int launch_tile(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
-                const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
-                double2 *zout, hipStream_t st) {
+int launch_tile_apply(const lb_plan *p, int sys, int B, bool adj, const double *alpha, double t, const double2 *x,
+                      double2 *y, int tile_opt, int ki_opt, hipStream_t st) {
   if (B == 0) return LB_OK;
-  if (p->tile == 2 && split_kl(p, sys))
-    return launch_split(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, zout, st);
-  if (mode != 0 && !ctab) return fail(LB_EINVAL, "stage sweeps need the control table");
+  if (tile_opt == 2 && split_kl(p, sys))
+    return launch_split(p, sys, B, 0, adj, alpha, t, nullptr, 0, x, nullptr, y, nullptr, st);
   const SysDev &S = p->sys[sys];
-  const int nl = tile_nl(p, sys), k = tile_ki(p, sys);
-#define X(A, Bq, R, C, T) \
-  if (nl == A && S.Q == Bq && k == 10 * R + C) return tile_modes<A, Bq, R, C, T>(p, sys, B, mode, adj, alpha, t, ctab, j, zin, qin, out, zout, st);
+  const int nl = S.nlev[0], k = tile_ki(p, sys, ki_opt);
+#define X(A, Bq, R, C, T)                                                                     \
+  if (nl == A && S.Q == Bq && k == 10 * R + C)                                                \
+    return adj ? tile_launch<A, Bq, R, C, T, true>(p, sys, B, alpha, t, x, y, st)             \
+               : tile_launch<A, Bq, R, C, T, false>(p, sys, B, alpha, t, x, y, st);
   LBX_TILE_SHAPES(X)
 #undef X
   return fail(LB_EUNSUPPORTED, "system not eligible for the tiled kernels");

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,19 @@ struct lbx_prof_pending {
   hipEvent_t start, stop;
 };
 
+// Options of a plan (lb_plan_set_option); every call works on a copy taken
+// when it starts, so options may change while other calls are running.
+struct lbx_opts {
+  int path = 0;                          // LB_OPT_PATH
+  int tile = 1;                          // LB_OPT_TILE
+  int tile_ki = 0;                       // LB_OPT_TILE_KI (0: default block)
+  int graph_steps = 0;                   // LB_OPT_GRAPH (0: launch directly)
+  int history = 3;                       // LB_OPT_HISTORY
+  bool profile = false;                  // LB_OPT_PROFILE
+  bool sync = true;                      // LB_OPT_SYNC
+  double tol = 1.1102230246251565e-16;   // LB_OPT_SOLVE_TOL (2^-53)
+};
+
 struct lb_plan {
   std::vector<lbx::SysDev> sys;   // host copy of the per-system constants
   lbx::SysDev *d_sys = nullptr;   // device copy
@@ -25,22 +39,15 @@ struct lb_plan {
   double *d_carrier = nullptr;    // carriers [GHz], per system [Q][Nf]
   int32_t NT = 0;                 // common number of steps
   int64_t ctab_total = 0;         // sum over systems of NT*Q
-  int path = 0;                   // LB_OPT_PATH
-  int tile = 1;                   // LB_OPT_TILE
-  int tile_ki = 0;                // LB_OPT_TILE_KI (0: default block)
-  int graph_steps = 0;            // LB_OPT_GRAPH (0: launch directly)
-  mutable bool capturing = false; // inside a stream capture: no profiling events
-  double tol = 1.1102230246251565e-16;  // LB_OPT_SOLVE_TOL (2^-53)
   int device = 0;
+  mutable std::mutex mu;          // guards opts and the profiling state
+  lbx_opts opts;
   // LB_OPT_PROFILE: per-kernel-family launch counts and durations.
-  bool profile = false;
   mutable int64_t prof_n[LB_KERNEL_COUNT] = {};
   mutable double prof_ms[LB_KERNEL_COUNT] = {};
   mutable int64_t prof_work[LB_KERNEL_COUNT] = {};  // entries x sweeps (x steps for STREAM_GRAD)
   mutable std::vector<lbx_prof_pending> prof_pending;
   mutable std::vector<hipEvent_t> ev_pool;  // recycled profiling events
-  mutable int64_t *d_sweeps = nullptr;  // per-item sweep totals of the LDS kernels (profiling)
-  mutable size_t sweeps_cap = 0;
 };
 
 namespace lbx {
@@ -79,27 +86,76 @@ struct ProfScope {
   int launches;
   hipStream_t st;
   hipEvent_t a = nullptr;
-  ProfScope(const lb_plan *p_, int k, hipStream_t s, int64_t work = 0, int n = 1)
+  ProfScope(const lb_plan *p_, bool on, int k, hipStream_t s, int64_t work = 0, int n = 1)
       : p(p_), kernel(k), launches(n), st(s) {
-    if (!p->profile || p->capturing) return;
+    if (!on) return;
+    std::lock_guard<std::mutex> g(p->mu);
     p->prof_work[k] += work;
     a = prof_event(p);
     if (a) (void)hipEventRecord(a, st);
   }
   ~ProfScope() {
     if (!a) return;
+    std::lock_guard<std::mutex> g(p->mu);
     hipEvent_t b = prof_event(p);
     if (!b) return;
     (void)hipEventRecord(b, st);
     p->prof_pending.push_back({kernel, launches, a, b});
     if (p->prof_pending.size() >= 2048) prof_drain(p);
   }
+  // both called with p->mu held
   static hipEvent_t prof_event(const lb_plan *p);
   static void prof_drain(const lb_plan *p);
 };
 
 // Waits for every profiled launch, accumulates its time and recycles its events.
 void prof_resolve(const lb_plan *p);
+void prof_add_work(const lb_plan *p, int kernel, int64_t work);
+
+// Status bits that kernels raise in the status word of a call's workspace.
+constexpr int LB_STATUS_THETA = 1;      // a stage-solve contraction bound >= 0.5
+constexpr int LB_STATUS_NOCONV = 2;     // a stage solve hit the sweep cap
+constexpr int LB_STATUS_NONFINITE = 4;  // an objective is not finite
+
+// Most streamed systems one batch may hold (persistent step kernels).
+constexpr int LB_STEP_MAXSEG = 1024;
+
+// Arguments of one persistent step launch (kernels_step.hip), passed by value.
+struct StepArgs {
+  const SysDev *sysv;
+  const double *Etab;
+  const uint64_t *desc;
+  const double2 *ctab;      // control table (rad/ns) of every system
+  const double2 *ttab;      // [nsys][NT] (theta, theta / (1 - theta))
+  int NT;
+  int j;                    // step index: controls at t_j + dt/2
+  int n, m, H;              // steps already taken in this pass; history used; ring length
+  const double2 *q;         // q^j (adjoint: qh^{j+1})
+  double2 *out;             // q^{j+1} (adjoint: qh^j)
+  const double2 *zstart;    // first iterate q + delta0, or NULL (delta0 = 0)
+  double2 *z0, *z1;         // sweep iterates
+  double2 *znext;           // first iterate of the next step, or NULL
+  double2 *zh;              // stage vector q + delta (adjoint), or NULL
+  double2 *ring;            // H increment buffers, ring_stride entries apart
+  int64_t ring_stride;
+  double2 *part;            // per-workgroup (tiled) or per-unit (generic) maxima
+  int32_t *segk;            // per-segment sweep counts (generic)
+  int32_t *kout;            // sweeps taken are added to [nsys][NT], or NULL
+  int32_t *status;          // status word (LB_STATUS_*)
+  double tol;
+  int kcap;                 // most sweeps after the first
+  int sys, B;               // tiled: the system and its states
+  int64_t units;            // tiled: units of the launch (set by the launcher)
+  const StreamSeg *segs;    // generic: segments
+  int nseg;
+  int64_t nblk;             // generic: units (STREAM_BLOCK entries each)
+};
+
+// One persistent step launch: the block-tiled kernel of system tile_sys in
+// block shape tile_k (10 KR + KC) when tile_sys >= 0, else the generic one.
+int launch_step(const lb_plan *p, StepArgs &A, bool adj, int tile_sys, int tile_k, hipStream_t st);
+// Workgroups that launch will use (the size of its maxima array).
+int step_grid(const lb_plan *p, int tile_sys, int tile_k, int B, int64_t nblk, int adj, int *grid);
 
 // Thread-local error message helpers.
 void set_error(const std::string &msg);
@@ -114,30 +170,24 @@ int hip_fail(hipError_t e, const char *what);
 
 // ---- launchers (each returns LB_OK or an error code) ----
 
+// Zeroes `bytes` (a multiple of 4) with a kernel.
+int launch_fill_zero(void *ptr, size_t bytes, hipStream_t st);
+
 // Control table of systems s0..s0+nsys-1; entry (s, j, q) goes to
 // ctab[ctab_off(s) - ctab_shift + j*Q + q].  ktab ([s][j][2] a-priori sweep
 // counts) and ttab ([s][j] = (theta, theta / (1 - theta))) may be NULL.
 int launch_control_table(const lb_plan *p, int s0, int nsys, const double *alpha, double2 *ctab,
-                         int64_t ctab_shift, int32_t *ktab, double2 *ttab, hipStream_t st);
+                         int64_t ctab_shift, int32_t *ktab, double2 *ttab, double tol, hipStream_t st);
 
+// y = M(t) x or M(t)^+ x; tile_opt / ki_opt are LB_OPT_TILE / LB_OPT_TILE_KI.
 int launch_apply(const lb_plan *p, int sys, double t, const double *alpha, const double2 *x,
-                 double2 *y, int B, bool adj, hipStream_t st);
+                 double2 *y, int B, bool adj, int tile_opt, int ki_opt, hipStream_t st);
 
-// Sweep kk of the stage solve of every streamed segment at step j.  Each
-// segment runs its own system's count K = ktab[sys][j][1] (kfix > 0: K =
-// kfix for all) and skips sweeps kk >= K; sweep kk reads q (kk = 0), z0 (kk
-// odd) or z1 (kk even) and writes z1 / z0, or `out` on its last sweep, which
-// with want_zh also writes the converged stage vector z = q + delta into
-// the z buffer it does not read.
-int launch_sweep(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk, int j, int kk,
-                 int kfix, bool adj, const double2 *ctab, const int32_t *ktab, const double2 *qin,
-                 double2 *z0, double2 *z1, double2 *out, bool want_zh, hipStream_t st);
-
-// Gradient integrands of step j; each segment's stage vector is in z0 or z1
-// as its last adjoint sweep (ktab) left it.
+// Gradient integrands of one step from the adjoint stage vector zh and the
+// forward states q0 = q^j, q1 = q^{j+1} (per-block partial rows).
 int launch_stream_grad(const lb_plan *p, const StreamSeg *d_segs, int nseg, int64_t nblk,
-                       const double2 *z0, const double2 *z1, const int32_t *ktab, int j,
-                       const double2 *q0, const double2 *q1, double *gpart, hipStream_t st);
+                       const double2 *zh, const double2 *q0, const double2 *q1, double *gpart,
+                       hipStream_t st);
 
 // Two-pass fixed-order sum of the stream_grad partials of nsteps steps into
 // gstep: slot z (partial rows at gpart + z slot_stride) holds step jtop - z;
@@ -147,55 +197,59 @@ int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int n
                                 int nsteps, const double *gpart, int64_t slot_stride, double *gfin,
                                 double *gstep, int64_t rows, hipStream_t st);
 
+// Generic LDS-resident kernels: a-priori sweep counts from ktab; sweeps
+// (nullable) receives each item's total; status collects LB_STATUS_* bits.
 int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                        const double2 *ctab, const int32_t *ktab, const double2 *rho0,
-                       double2 *rhoT, double2 *states, hipStream_t st);
+                       double2 *rhoT, double2 *states, int64_t *sweeps, int32_t *status, hipStream_t st);
 
 int launch_lds_adjoint(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                        int kind, const double2 *ctab, const int32_t *ktab, const double2 *rhotar,
-                       const double2 *states, double *gpart, hipStream_t st);
+                       const double2 *states, double *gpart, int64_t *sweeps, int32_t *status,
+                       hipStream_t st);
 
 int launch_lds_grad_reduce(const lb_plan *p, const int32_t *d_item_range, int nsys_lds,
                            const int32_t *d_sys_ids, const LdsItem *d_items, const double *gpart,
                            double *gstep, hipStream_t st);
 
+// G (nullable) and J (nullable) per system / state; status (nullable)
+// receives LB_STATUS_NONFINITE when a G is not finite.
 int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const double2 *rhotar,
                      const double *beta, const int32_t *d_state_sys, const int64_t *d_state_off,
                      const int32_t *d_sys_state0, int nstates, double gamma2, const double *alpha,
-                     double *partial, double *J, double *G, hipStream_t st);
+                     double *partial, double *J, double *G, int32_t *status, hipStream_t st);
 
+// Terminal condition of the streamed states; gscale (nullable, DEVICE
+// [nsys]) weights each system's objective.
 int launch_terminal(const lb_plan *p, int kind, const StreamSeg *d_segs, int nseg, int64_t nblk,
                     const double2 *rhoT, const double2 *rhotar, const double *beta,
-                    const int32_t *d_seg_state0, double2 *qh, hipStream_t st);
+                    const int32_t *d_seg_state0, const double *gscale, double2 *qh, hipStream_t st);
 
 int launch_grad_contract(const lb_plan *p, const double *gstep, const double *alpha,
-                         double gamma2, double *grad, hipStream_t st);
+                         double gamma2, const double *gscale, double *grad, hipStream_t st);
 
 // LDS path: block size and entries per thread for a state of n2 entries;
 // returns false when the state does not fit the LDS-resident kernels.
 bool lds_shape(int64_t n2, int *block, int *ept);
 
-// Block-tiled streaming kernels (kernels_tile.hip).  tile_nl returns the
-// common level count of an eligible system (equal-level subsystems whose
-// (NL, Q) has an instantiated block shape or, with LB_OPT_TILE 2, a pass
-// plan) or 0.
-int tile_nl(const lb_plan *p, int sys);
-int tile_ki(const lb_plan *p, int sys);  // block shape 10*KR + KC, 0 if not eligible
-// mode 0: y = M x (alpha, t); mode 1: sweep (q + delta); mode 2: last sweep (q + 2 delta),
-// with the controls of step j from ctab.
-// Two-pass split kernels (kernels_tile.hip): number of low subsystems of the
-// split of system sys, 0 if not eligible; launch_split runs both passes.
-// launch_tile uses them when LB_OPT_TILE is 2 and the system is eligible.
+// Block-tiled kernels (kernels_tile.hip).  tile_ki returns the block shape
+// 10*KR + KC of an eligible system (equal-level subsystems with an
+// instantiated shape; ki_opt selects among them, 0 the default) or 0.
+int tile_ki(const lb_plan *p, int sys, int ki_opt);
+// Multi-pass apply kernels: number of passes of the system's plan, 0 if not
+// eligible; launch_split runs them (mode 0: apply).
 int split_kl(const lb_plan *p, int sys);
 int launch_split(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
                  const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
                  double2 *zout, hipStream_t st);
-int launch_tile(const lb_plan *p, int sys, int B, int mode, bool adj, const double *alpha, double t,
-                const double2 *ctab, int j, const double2 *zin, const double2 *qin, double2 *out,
-                double2 *zout, hipStream_t st);
-// Block-tiled gradient integrands of one step (partial rows: tile_grad_rows).
-int64_t tile_grad_rows(const lb_plan *p, int sys, int B);
-int launch_tile_grad(const lb_plan *p, int sys, int B, const double2 *zh, const double2 *q0,
+// lindblad_apply of an eligible system (multi-pass when tile_opt is 2 and the
+// system has a pass plan).
+int launch_tile_apply(const lb_plan *p, int sys, int B, bool adj, const double *alpha, double t,
+                      const double2 *x, double2 *y, int tile_opt, int ki_opt, hipStream_t st);
+// Block-tiled gradient integrands of one step in block shape k (partial rows:
+// tile_grad_rows).
+int64_t tile_grad_rows(const lb_plan *p, int sys, int B, int k);
+int launch_tile_grad(const lb_plan *p, int sys, int B, int k, const double2 *zh, const double2 *q0,
                      const double2 *q1, double *gpart, int64_t *rows, hipStream_t st);
 
 // Specialised LDS-resident kernels (kernels_lds_fast.hip) for Q subsystems.
@@ -203,13 +257,13 @@ bool lds_fast_ok(int block, int ept, int Q);
 // They pick the number of sweeps of every step a posteriori (see
 // extra_sweeps) and, when `sweeps` is not NULL, write each item's total.
 int launch_lds_forward_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, const double2 *ctab, const double2 *ttab, const double2 *rho0,
-                            double2 *rhoT, double2 *states, int64_t *sweeps, hipStream_t st);
+                            int Q, const double2 *ctab, const double2 *ttab, double tol, const double2 *rho0,
+                            double2 *rhoT, double2 *states, int64_t *sweeps, int32_t *status, hipStream_t st);
 // The adjoint stores each step's converged stage vector in zhist (laid out
 // like the state history) and a second launch forms the gradient integrands.
 int launch_lds_adjoint_fast(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
-                            int Q, int kind, const double2 *ctab, const double2 *ttab,
+                            int Q, int kind, const double2 *ctab, const double2 *ttab, double tol,
                             const double2 *rhotar, const double2 *states, double2 *zhist,
-                            double *gpart, int64_t *sweeps, hipStream_t st);
+                            double *gpart, int64_t *sweeps, int32_t *status, hipStream_t st);
 
 }  // namespace lbx
