@@ -94,12 +94,19 @@ extern "C" {
 #define LB_OPT_GRAPH 5     /* > 0: streamed time loops are captured as HIP graphs of this
                               many steps and replayed (one graph launch per chunk);
                               0 (default): kernels are launched directly */
-#define LB_OPT_HISTORY 6   /* 0..4, default 3: converged stage increments of earlier steps
+#define LB_OPT_HISTORY 6   /* 0..4, default 4: converged stage increments of earlier steps
                               from which a streamed step extrapolates its first iterate
                               (order HISTORY-1 in the frame of the diagonal Cayley factor);
                               0 starts every stage solve from q */
 #define LB_OPT_SYNC 7      /* 1 (default): calls wait for their work and return the device
                               status; 0: calls return once enqueued (see lb_status) */
+#define LB_OPT_SWEEPS 8    /* stage-solve sweeps launched per streamed step: 0 (default)
+                              8 for steps started from a full history, 12 for the others;
+                              2..64: that many for every step.  A step runs only the sweeps
+                              its a-posteriori bound asks for; one that needs more than were
+                              launched makes an LB_OPT_SYNC call repeat itself once with the
+                              a-priori counts of every step read on the host (else lb_status
+                              reports LB_EUNSUPPORTED) */
 
 /* Kernel families timed by LB_OPT_PROFILE (lb_profile_read). */
 #define LB_KERNEL_LDS_FORWARD 0  /* persistent forward time loop, LDS-resident */

@@ -35,6 +35,7 @@ LB_OPT_TILE_KI = 4
 LB_OPT_GRAPH = 5
 LB_OPT_HISTORY = 6
 LB_OPT_SYNC = 7
+LB_OPT_SWEEPS = 8
 
 LB_KERNEL_LDS_FORWARD = 0
 LB_KERNEL_LDS_ADJOINT = 1

@@ -273,8 +273,6 @@ int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool 
       m->segs.push_back(sg);
       m->seg_state0.push_back(m->sys_state0[s]);
     }
-  if ((int)m->segs.size() > LB_STEP_MAXSEG)
-    return fail(LB_EUNSUPPORTED, "more than " + std::to_string(LB_STEP_MAXSEG) + " streamed systems in one batch");
   m->st_entries = coff;
   m->st_blocks = blk;
   if (m->segs.size() == 1 && o.tile) {
@@ -329,10 +327,12 @@ int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool 
   return LB_OK;
 }
 
-// Most workgroups a cooperative step launch can have (256-thread workgroups,
-// at most 2048 threads per compute unit, 256 compute units): the size of the
-// per-workgroup maxima of the block-tiled step kernels.
-constexpr int64_t MAX_STEP_GRID = 8192;
+// Sweeps launched per streamed step: steps whose first iterate is
+// extrapolated from a full history, and the others (started from fewer
+// increments or from q).  The kernels run only as many as the step needs; a
+// step that needs more raises LB_STATUS_RETRY.
+constexpr int SWEEPS_HIST = 8;
+constexpr int SWEEPS_START = 12;
 
 // Trajectory storage (forward states the adjoint needs): LDS-resident items
 // keep every state, [items][NT+1][N^2]; streamed systems keep checkpoints
@@ -359,7 +359,7 @@ struct Layout {
   size_t rhoT = 0;  // LB_OP_GRADIENT: rho(T) when the caller does not want it
   size_t zhist = 0, gpart = 0;
   size_t q0 = 0, q1 = 0, z0 = 0, z1 = 0, zsf = 0, ringf = 0, zsa = 0, ringa = 0, zh = 0, qh0 = 0, qh1 = 0,
-         seg = 0, st_gpart = 0, st_gfin = 0, part = 0, segk = 0;
+         seg = 0, st_gpart = 0, st_gfin = 0, slots = 0, kstep = 0;
   size_t total = 0;
   TrajLayout T;
   int H = 0;
@@ -387,8 +387,8 @@ Layout layout(const lb_plan *p, const lbx_opts &o, int op, const BatchMeta &m, i
   L.objpart = take((size_t)std::max(1, m.total_states) * 64 * sizeof(double));
   L.items = take(std::max<size_t>(1, m.items.size()) * sizeof(LdsItem));
   L.sweeps = take(std::max<size_t>(1, m.items.size()) * sizeof(int64_t));
-  L.part = take((size_t)std::max<int64_t>(m.st_blocks, MAX_STEP_GRID) * sizeof(double2));
-  L.segk = take(std::max<size_t>(1, m.segs.size()) * sizeof(int32_t));
+  L.slots = take((size_t)2 * nsys * 2 * LB_STEP_SLOTS * sizeof(unsigned long long));
+  L.kstep = take((size_t)2 * nsys * sizeof(int32_t));
   L.z0 = take(st ? E : 0);
   L.z1 = take(st ? E : 0);
   L.T = traj_layout(p, m, ckpt_every);
@@ -457,18 +457,31 @@ int copy_segments(const BatchMeta &m, const double2 *src, bool src_batched, doub
   return LB_OK;
 }
 
-// Reads the status word of a workspace (synchronises the stream) and turns
-// its bits into an error code.
-int status_code(const int32_t *d_status, hipStream_t st) {
-  int32_t s = 0;
-  LBX_HIP(hipMemcpyAsync(&s, d_status, sizeof(s), hipMemcpyDeviceToHost, st));
+// Reads the status word of a workspace (synchronises the stream).
+int read_status(const int32_t *d_status, hipStream_t st, int32_t *bits) {
+  *bits = 0;
+  LBX_HIP(hipMemcpyAsync(bits, d_status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   LBX_HIP(hipStreamSynchronize(st));
+  return LB_OK;
+}
+
+// Error code of the status bits.
+int status_code(int32_t s) {
   if (s & LB_STATUS_NONFINITE) return fail(LB_ENONFINITE, "an objective is not finite");
   if (s & LB_STATUS_THETA)
     return fail(LB_EUNSUPPORTED,
                 "a stage-solve contraction bound is >= 0.5 (step or control amplitude too large)");
   if (s & LB_STATUS_NOCONV) return fail(LB_EUNSUPPORTED, "a stage solve did not converge within the sweep cap");
+  if (s & LB_STATUS_RETRY)
+    return fail(LB_EUNSUPPORTED, "a streamed step needed more stage sweeps than were launched; repeat the call "
+                                 "with LB_OPT_SYNC on, which repeats it with a-priori counts");
   return LB_OK;
+}
+
+int status_code(const int32_t *d_status, hipStream_t st) {
+  int32_t s = 0;
+  if (int rc = read_status(d_status, st, &s)) return rc;
+  return status_code(s);
 }
 
 // LB_OPT_GRAPH: the streamed time loop is recorded in chunks of steps with
@@ -552,6 +565,10 @@ struct StreamCtx {
   const Layout *L;
   char *w;
   bool prof;
+  // a-priori mode (the retry of a call): per-step counts known on the host
+  // (kst[j], every launched sweep runs, every step starts from q)
+  const std::vector<int32_t> *kst = nullptr;
+  mutable int64_t seq = 0;  // steps launched by the call (parity of the maxima slots)
   StepArgs base() const {
     StepArgs A{};
     A.sysv = p->d_sys;
@@ -560,10 +577,11 @@ struct StreamCtx {
     A.ctab = (const double2 *)(w + L->ctab);
     A.ttab = (const double2 *)(w + L->ttab);
     A.NT = p->NT;
+    A.nsys = (int)p->sys.size();
     A.z0 = (double2 *)(w + L->z0);
     A.z1 = (double2 *)(w + L->z1);
-    A.part = (double2 *)(w + L->part);
-    A.segk = (int32_t *)(w + L->segk);
+    A.slots = (unsigned long long *)(w + L->slots);
+    A.kstep = (int32_t *)(w + L->kstep);
     A.kout = prof ? (int32_t *)(w + L->kout) : nullptr;
     A.status = (int32_t *)(w + L->status);
     A.tol = o->tol;
@@ -585,7 +603,8 @@ struct PassHist {
   int n = 0;
 };
 
-// One persistent step launch over every streamed system: q -> out at step j.
+// One implicit-midpoint step of every streamed system, q -> out at step j:
+// the sweep launches of the stage solve (each runs only if the step needs it).
 int stream_step(const StreamCtx &c, int j, bool adj, const double2 *q, double2 *out, PassHist &ph, double2 *zh,
                 hipStream_t st) {
   StepArgs A = c.base();
@@ -593,17 +612,50 @@ int stream_step(const StreamCtx &c, int j, bool adj, const double2 *q, double2 *
   A.q = q;
   A.out = out;
   A.zh = zh;
-  A.H = ph.H;
+  A.par = (int)(c.seq++ & 1);
+  const int H = c.kst ? 0 : ph.H;
+  A.H = H;
   A.n = ph.n;
-  A.m = ph.H > 0 ? std::min(ph.n + 1, ph.H) : 0;
-  A.zstart = (ph.H > 0 && ph.n > 0) ? ph.zs : nullptr;
-  A.znext = ph.H > 0 ? ph.zs : nullptr;
+  A.m = H > 0 ? std::min(ph.n + 1, H) : 0;
+  A.zstart = (H > 0 && ph.n > 0) ? ph.zs : nullptr;
+  A.znext = H > 0 ? ph.zs : nullptr;
   A.ring = ph.ring;
   A.ring_stride = c.m->st_entries;
-  ProfScope ps(c.p, c.prof, LB_KERNEL_SWEEP, st);
-  const int rc = launch_step(c.p, A, adj, c.m->tile_sys, c.m->tile_k, st);
+  if (c.kst) {
+    A.apriori = 1;
+    A.L = std::max(2, (*c.kst)[j]);
+  } else if (c.o->sweeps > 0) {
+    A.L = c.o->sweeps;
+  } else {
+    A.L = (H > 0 && ph.n >= H) ? SWEEPS_HIST : SWEEPS_START;
+  }
+  ProfScope ps(c.p, c.prof, LB_KERNEL_SWEEP, st);  // one timed unit per step
+  for (int kk = 0; kk < A.L; ++kk)
+    if (int rc = launch_sweep(c.p, A, kk, adj, c.m->tile_sys, c.m->tile_k, st)) return rc;
   ph.n++;
-  return rc;
+  return LB_OK;
+}
+
+// A-priori sweep counts from q of every step (the largest over the streamed
+// systems), read on the host: the counts of a call repeated after
+// LB_STATUS_RETRY.  Synchronises the stream.
+int apriori_counts(const lb_plan *p, const BatchMeta &m, const int32_t *d_ktab, std::vector<int32_t> &kst,
+                   hipStream_t st) {
+  const size_t n = p->sys.size() * (size_t)p->NT * 2;
+  std::vector<int32_t> k(n);
+  LBX_HIP(hipMemcpyAsync(k.data(), d_ktab, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  LBX_HIP(hipStreamSynchronize(st));
+  kst.assign(p->NT, 1);
+  for (const auto &sg : m.segs)
+    for (int j = 0; j < p->NT; ++j) {
+      const int kj = k[((size_t)sg.sys * p->NT + j) * 2 + 1];
+      if (kj < 1)
+        return fail(LB_EUNSUPPORTED, "system " + std::to_string(sg.sys) + " step " + std::to_string(j) +
+                                         ": the stage-solve contraction bound is >= 0.5 (step or control "
+                                         "amplitude too large)");
+      kst[j] = std::max(kst[j], kj);
+    }
+  return LB_OK;
 }
 
 // Streamed forward steps j0..j1-1.  slot(j) returns the buffer that receives
@@ -662,29 +714,49 @@ int stream_profile_work(const lb_plan *p, const BatchMeta &m, const int32_t *kou
   return LB_OK;
 }
 
-// Start of a call: status word and profiling counters cleared.
+// Start of a call: status word, maxima slots and profiling counters cleared.
 int call_begin(const lb_plan *p, const Layout &L, char *w, bool prof, hipStream_t st) {
   if (int rc = launch_fill_zero(w + L.status, 4, st)) return rc;
+  if (int rc = launch_slots_clear((unsigned long long *)(w + L.slots), (int)p->sys.size(), st)) return rc;
   if (prof)
     if (int rc = launch_fill_zero(w + L.kout, p->sys.size() * (size_t)p->NT * sizeof(int32_t), st)) return rc;
   return LB_OK;
 }
 
-// End of a call: profiling read-back, then (LB_OPT_SYNC) the status.
+// End of an attempt: profiling read-back, then (LB_OPT_SYNC) the status bits.
 int call_end(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w, bool prof,
-             hipStream_t st) {
+             hipStream_t st, int32_t *bits) {
+  *bits = 0;
   if (prof) {
     if (int rc = stream_profile_work(p, m, (const int32_t *)(w + L.kout), st)) return rc;
     prof_resolve(p);
   }
-  if (o.sync) return status_code((const int32_t *)(w + L.status), st);
+  if (o.sync) return read_status((const int32_t *)(w + L.status), st, bits);
   return LB_OK;
+}
+
+// Runs attempt(kst) (kst NULL: device-side counts).  In LB_OPT_SYNC mode a
+// step that needed more sweeps than were launched makes the call run once
+// more with the a-priori counts of every step; the result is the status.
+template <class Attempt>
+int run_call(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w, hipStream_t st,
+             Attempt attempt) {
+  int32_t bits = 0;
+  int rc = attempt(nullptr, &bits);
+  if (rc || !o.sync) return rc;
+  if ((bits & LB_STATUS_RETRY) && !(bits & (LB_STATUS_THETA | LB_STATUS_NONFINITE))) {
+    std::vector<int32_t> kst;
+    if ((rc = apriori_counts(p, m, (const int32_t *)(w + L.ktab), kst, st))) return rc;
+    if ((rc = attempt(&kst, &bits))) return rc;
+  }
+  return status_code(bits);
 }
 
 // Forward pass of every system: LDS-resident items keep every state in the
 // trajectory (when traj is not NULL), streamed systems keep checkpoints.
 int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w,
-                const double *alpha, const double2 *rho0, double2 *rhoT, char *traj, bool prof, hipStream_t st) {
+                const double *alpha, const double2 *rho0, double2 *rhoT, char *traj, bool prof,
+                const std::vector<int32_t> *kst, hipStream_t st) {
   double2 *ctab = (double2 *)(w + L.ctab);
   int32_t *ktab = (int32_t *)(w + L.ktab);
   double2 *ttab = (double2 *)(w + L.ttab);
@@ -704,8 +776,8 @@ int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const L
   }
   if ((rc = lds_profile_work(p, m, LB_KERNEL_LDS_FORWARD, slots, st))) return rc;
   if (m.segs.empty()) return LB_OK;
-  // Streamed systems: one persistent launch per step over all of them.
-  StreamCtx sc{p, &o, &m, &L, w, prof};
+  // Streamed systems: the sweeps of every step over all of them.
+  StreamCtx sc{p, &o, &m, &L, w, prof, kst};
   double2 *q0 = (double2 *)(w + L.q0), *q1 = (double2 *)(w + L.q1);
   const size_t E = (size_t)m.st_entries;
   double2 *ck = traj ? (double2 *)(traj + L.T.ckpt) : nullptr;
@@ -727,7 +799,8 @@ int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const L
 // Adjoint pass and gradient of every system from a forward trajectory.
 int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w, int kind,
                  const double *alpha, const char *traj, const double2 *rhotar, const double *beta, double gamma2,
-                 const double *gscale, double *grad, bool prof, hipStream_t st) {
+                 const double *gscale, double *grad, bool prof, const std::vector<int32_t> *kst,
+                 hipStream_t st) {
   int rc;
   double2 *ctab = (double2 *)(w + L.ctab);
   int32_t *ktab = (int32_t *)(w + L.ktab);
@@ -761,7 +834,7 @@ int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const 
   }
   // Streamed adjoint with checkpoint recomputation.
   if (!m.segs.empty()) {
-    StreamCtx sc{p, &o, &m, &L, w, prof};
+    StreamCtx sc{p, &o, &m, &L, w, prof, kst};
     const size_t E = (size_t)m.st_entries;
     const int NT = p->NT, c = L.T.c;
     double2 *ck = (double2 *)(traj + L.T.ckpt);
@@ -1032,6 +1105,12 @@ extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
     o.history = (int)value;
     return LB_OK;
   }
+  if (option == LB_OPT_SWEEPS) {
+    if (value != 0 && (value < 2 || value > 64 || value != (int)value))
+      return fail(LB_EINVAL, "LB_OPT_SWEEPS must be 0 or 2..64");
+    o.sweeps = (int)value;
+    return LB_OK;
+  }
   if (option == LB_OPT_SYNC) {
     o.sync = value != 0.0;
     return LB_OK;
@@ -1127,33 +1206,22 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
   if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
   char *w = (char *)ws;
   const bool prof = o.profile;
-  if ((rc = call_begin(p, L, w, prof, st))) return rc;
   double2 *ctab = (double2 *)(w + L.ctab);
   const double *abase = alpha - p->sys[sys].alpha_off;
-  if ((rc = launch_control_table(p, sys, 1, abase, ctab, 0, (int32_t *)(w + L.ktab), (double2 *)(w + L.ttab),
-                                 o.tol, st)))
-    return rc;
-  // (the tables are written at the system's own offsets, where the step
-  // kernels read them)
-  StreamCtx sc{p, &o, m, &L, w, prof};
-  StepArgs A = sc.base();
-  A.j = j;
-  A.q = (const double2 *)q_in;
-  A.out = (double2 *)q_out;
-  {
-    ProfScope ps(p, prof, LB_KERNEL_SWEEP, st);
-    if ((rc = launch_step(p, A, adjoint != 0, m->tile_sys, m->tile_k, st))) return rc;
-  }
-  if (prof) {
-    int32_t k = 0;
-    LBX_HIP(hipMemcpyAsync(&k, w + L.kout + ((size_t)sys * p->NT + j) * sizeof(int32_t), sizeof(k),
-                           hipMemcpyDeviceToHost, st));
-    LBX_HIP(hipStreamSynchronize(st));
-    prof_add_work(p, LB_KERNEL_SWEEP, (int64_t)k * m->st_entries);
-    prof_resolve(p);
-  }
-  if (o.sync) return status_code((const int32_t *)(w + L.status), st);
-  return LB_OK;
+  auto attempt = [&](const std::vector<int32_t> *kst, int32_t *bits) -> int {
+    int rc = call_begin(p, L, w, prof, st);
+    if (!rc)
+      rc = launch_control_table(p, sys, 1, abase, ctab, 0, (int32_t *)(w + L.ktab), (double2 *)(w + L.ttab), o.tol,
+                                st);
+    // (the tables are written at the system's own offsets, where the sweep
+    // kernels read them)
+    StreamCtx sc{p, &o, m, &L, w, prof, kst};
+    PassHist ph;  // a single step starts from q
+    if (!rc) rc = stream_step(sc, j, adjoint != 0, (const double2 *)q_in, (double2 *)q_out, ph, nullptr, st);
+    if (rc) return rc;
+    return call_end(p, o, *m, L, w, prof, st, bits);
+  };
+  return run_call(p, o, *m, L, w, st, attempt);
 }
 
 extern "C" int forward_solve(const lb_plan *p, const double *alpha, const void *rho0, void *rhoT,
@@ -1172,11 +1240,14 @@ extern "C" int forward_solve(const lb_plan *p, const double *alpha, const void *
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   const bool prof = o.profile;
-  int rc = call_begin(p, L, w, prof, st);
-  if (!rc)
-    rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, (double2 *)rhoT, (char *)traj, prof, st);
-  if (rc) return rc;
-  return call_end(p, o, *m, L, w, prof, st);
+  auto attempt = [&](const std::vector<int32_t> *kst, int32_t *bits) -> int {
+    int rc = call_begin(p, L, w, prof, st);
+    if (!rc)
+      rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, (double2 *)rhoT, (char *)traj, prof, kst, st);
+    if (rc) return rc;
+    return call_end(p, o, *m, L, w, prof, st, bits);
+  };
+  return run_call(p, o, *m, L, w, st, attempt);
 }
 
 extern "C" int objective(const lb_plan *p, int32_t kind, const void *rhoT, const void *rhotar, const double *beta,
@@ -1220,16 +1291,19 @@ extern "C" int adjoint_backward(const lb_plan *p, int32_t kind, const double *al
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   const bool prof = o.profile;
-  int rc = call_begin(p, L, w, prof, st);
-  // The controls (and their tables) are rebuilt for this call.
-  if (!rc)
-    rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, (double2 *)(w + L.ctab), 0, (int32_t *)(w + L.ktab),
-                              (double2 *)(w + L.ttab), o.tol, st);
-  if (!rc)
-    rc = run_backward(p, o, *m, L, w, kind, alpha, (const char *)traj, (const double2 *)rhotar, beta, gamma2, gscale,
-                      grad, prof, st);
-  if (rc) return rc;
-  return call_end(p, o, *m, L, w, prof, st);
+  auto attempt = [&](const std::vector<int32_t> *kst, int32_t *bits) -> int {
+    int rc = call_begin(p, L, w, prof, st);
+    // The controls (and their tables) are rebuilt for this call.
+    if (!rc)
+      rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, (double2 *)(w + L.ctab), 0,
+                                (int32_t *)(w + L.ktab), (double2 *)(w + L.ttab), o.tol, st);
+    if (!rc)
+      rc = run_backward(p, o, *m, L, w, kind, alpha, (const char *)traj, (const double2 *)rhotar, beta, gamma2,
+                        gscale, grad, prof, kst, st);
+    if (rc) return rc;
+    return call_end(p, o, *m, L, w, prof, st, bits);
+  };
+  return run_call(p, o, *m, L, w, st, attempt);
 }
 
 extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *alpha, const void *rho0,
@@ -1251,19 +1325,22 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
   char *w = (char *)ws;
   char *traj = w + L.traj;
   const bool prof = o.profile;
-  int rc = call_begin(p, L, w, prof, st);
   // rho(T) goes to the caller's buffer, or to the workspace.
   double2 *rhoT = rhoT_out ? (double2 *)rhoT_out : (double2 *)(w + L.rhoT);
-  if (!rc) rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, rhoT, traj, prof, st);
-  if (!rc)
-    rc = launch_objective(p, kind, rhoT, (const double2 *)rhotar, beta, m->d_state_sys, m->d_state_off,
-                          m->d_sys_state0, m->total_states, gamma2, alpha, (double *)(w + L.objpart), nullptr, G,
-                          (int32_t *)(w + L.status), st);
-  if (!rc)
-    rc = run_backward(p, o, *m, L, w, kind, alpha, traj, (const double2 *)rhotar, beta, gamma2, nullptr, grad, prof,
-                      st);
-  if (rc) return rc;
-  return call_end(p, o, *m, L, w, prof, st);
+  auto attempt = [&](const std::vector<int32_t> *kst, int32_t *bits) -> int {
+    int rc = call_begin(p, L, w, prof, st);
+    if (!rc) rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, rhoT, traj, prof, kst, st);
+    if (!rc)
+      rc = launch_objective(p, kind, rhoT, (const double2 *)rhotar, beta, m->d_state_sys, m->d_state_off,
+                            m->d_sys_state0, m->total_states, gamma2, alpha, (double *)(w + L.objpart), nullptr, G,
+                            (int32_t *)(w + L.status), st);
+    if (!rc)
+      rc = run_backward(p, o, *m, L, w, kind, alpha, traj, (const double2 *)rhotar, beta, gamma2, nullptr, grad,
+                        prof, kst, st);
+    if (rc) return rc;
+    return call_end(p, o, *m, L, w, prof, st, bits);
+  };
+  return run_call(p, o, *m, L, w, st, attempt);
 }
 
 extern "C" int lb_profile_read(const lb_plan *p, int32_t kernel, int64_t *launches, double *total_ms, int32_t reset) {
@@ -1319,7 +1396,7 @@ namespace {
 // Mean time of `reps` first steps (forward, no history) with the options o.
 int time_steps(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w, int reps,
                hipStream_t st, float *ms) {
-  StreamCtx sc{p, &o, &m, &L, w, false};
+  StreamCtx sc{p, &o, &m, &L, w, false, nullptr};
   double2 *q0 = (double2 *)(w + L.q0), *q1 = (double2 *)(w + L.q1);
   hipEvent_t a, b;
   LBX_HIP(hipEventCreate(&a));
@@ -1364,6 +1441,7 @@ extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch
   if (rc) return rc;
   const size_t E = (size_t)m->st_entries * sizeof(double2);
   if ((rc = launch_fill_zero(w + L.q0, E, st)) || (rc = launch_fill_zero(w + L.q1, E, st))) return rc;
+  if ((rc = launch_slots_clear((unsigned long long *)(w + L.slots), (int)p->sys.size(), st))) return rc;
   // Kernel family and block shape.
   std::vector<std::pair<int, int>> cand = {{0, 0}};
   if (m->segs.size() == 1) {

@@ -1,8 +1,7 @@
-// Persistent implicit-midpoint step kernels for streamed systems (states in
-// HBM): one cooperative launch takes every stage-solve sweep of one step
-// (App. A eqs. IMR and linsystem_primal; App. B eq. linsystem_adjoint for
-// the adjoint), with grid-wide barriers between the sweeps.  The number of
-// sweeps is decided on the device, a posteriori, so the host never needs it.
+// Stage-solve sweeps of the implicit-midpoint steps of streamed systems
+// (states in HBM), App. A eqs. IMR and linsystem_primal; App. B eq.
+// linsystem_adjoint for the adjoint.  One launch per sweep, one unit per
+// workgroup; the number of sweeps of every step is decided on the device.
 //
 // Stage solve.  (I - h M) z = q with h = dt/2 and M = D + O is solved in
 // delta form, z = q + delta:  delta <- w (h D q + h O (q + delta)),
@@ -10,12 +9,17 @@
 // max norm with a factor theta_j <= h sum_q (2 |d_q| c_q + (n_q - 1)/T1_q)
 // (control_table_kernel).  After a first sweep delta0 -> delta1 the error obeys
 //   |delta1 - delta*| <= theta/(1 - theta) |delta1 - delta0|,
-// and every further sweep multiplies the bound by theta; the kernel runs at
+// and every further sweep multiplies the bound by theta; a step takes at
 // least two sweeps and otherwise the fewest that bring the bound below
-// tol * max|q|.  Both maxima are grid-wide: every workgroup writes its own
-// partial maxima after the first sweep, and after the barrier every
-// workgroup reduces all of them in the same order, so the count is the same
-// in every workgroup (and every workgroup takes the same barriers).
+// tol * max|q|.  Sweep 0 folds its workgroup maxima of |delta1 - delta0| and
+// |q| into LB_STEP_SLOTS slots per system with atomic maxima (exact, so the
+// order does not matter); a one-wavefront count kernel reduces those slots
+// into the step's count K, and every workgroup of a later sweep reads K,
+// runs if its sweep index is below K, takes the update if it is K - 1, and
+// returns at once otherwise.  The host launches a fixed number of sweeps per
+// step; a step that would need more raises LB_STATUS_RETRY, and the library
+// repeats the call with counts known on the host (A.apriori: every launched
+// sweep runs).
 //
 // Start.  A step starts from delta0 = 0 (z = q) or from an extrapolation of
 // the converged increments of the previous steps of the same pass.  For
@@ -30,12 +34,9 @@
 // Update.  q^{j+1} = q^j + dt M z = q^j + 2 delta (h M z = z - q = delta).
 // The adjoint step has the same form with M^+ and also writes its stage
 // vector zh = q + delta for the gradient integrands.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
-#include <map>
-#include <mutex>
-#include <tuple>
+#include <algorithm>
 
 #include "lbx_host.hpp"
 #include "tile_unit.hpp"
@@ -44,12 +45,10 @@ namespace lbx {
 
 namespace {
 
-namespace cg = cooperative_groups;
-
 // Total sweeps of a stage solve after a first sweep that changed the iterate
 // by e1 (max norm), with |q| <= qmax: at least two, at most kcap + 1.
 __device__ __forceinline__ int stage_sweeps(double theta, double ratio, double e1, double qmax, double tol,
-                                            int kcap, bool *capped) {
+                                            int kcap) {
   double r = ratio * e1;
   const double lim = tol * qmax;
   int k = 0;
@@ -57,11 +56,15 @@ __device__ __forceinline__ int stage_sweeps(double theta, double ratio, double e
     r *= theta;
     ++k;
   }
-  *capped = r > lim;
   return 1 + (k > 1 ? k : 1);
 }
 
-// Maximum over the workgroup (non-negative values), valid in thread 0.
+// Order-preserving bits of a non-negative double (NaN orders above every
+// finite value, so a NaN iterate still yields a count).
+__device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+__device__ __forceinline__ double bdbl(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// Maximum over the workgroup of two non-negative values, valid in thread 0.
 template <int BLOCK>
 __device__ __forceinline__ void block_max2(double &a, double &b, double (*red)[BLOCK / 64]) {
 #pragma unroll
@@ -82,183 +85,135 @@ __device__ __forceinline__ void block_max2(double &a, double &b, double (*red)[B
       b = fmax(b, red[1][k]);
     }
   }
-  __syncthreads();
 }
 
-// Units of one launch dealt to workgroups: the workgroups of one XCD (they
-// are dispatched to the 8 XCDs round-robin) walk a contiguous band of units.
-struct Band {
-  int64_t u0, u1, stride;
-};
-__device__ __forceinline__ Band xcd_band(int64_t units) {
-  const int G = gridDim.x;  // a multiple of 8
-  const int x = blockIdx.x & 7;
-  const int64_t band = (units + 7) / 8;
-  const int64_t lo = (int64_t)x * band;
-  const int64_t hi = lo + band < units ? lo + band : units;
-  return {lo + (blockIdx.x >> 3), hi, G / 8};
+// Slots of system `sys` for the step with parity `par`: LB_STEP_SLOTS maxima
+// of |delta1 - delta0|, then LB_STEP_SLOTS maxima of |q|.
+__device__ __forceinline__ unsigned long long *slot_base(const StepArgs &A, int par, int sys) {
+  return A.slots + ((int64_t)par * A.nsys + sys) * 2 * LB_STEP_SLOTS;
+}
+
+// Sweeps of the current step of system `sys` (written by step_count_kernel).
+__device__ __forceinline__ int step_sweeps_of(const StepArgs &A, int sys) {
+  return A.kstep[(int64_t)A.par * A.nsys + sys];
 }
 
 __device__ __forceinline__ double2 cfma(double2 acc, double c, double2 r, double2 d) {
-  // acc + c * r * d
   const double2 rd = cmul(r, d);
   return make_double2(acc.x + c * rd.x, acc.y + c * rd.y);
 }
 
 // Start of the next step from the history (see the file comment): dn is this
-// step's increment delta_n, R the diagonal Cayley factor, ring[k] holds
-// delta_{n-k} for k = 1 .. m-1 at slot (n - k) mod H.
-template <int HMAX>
+// step's increment delta_n, R the diagonal Cayley factor, ring slot
+// (n - k) mod H holds delta_{n-k} for k = 1 .. m-1.
+constexpr int HMAX = 4;
+
 __device__ __forceinline__ double2 next_start(double2 dn, double2 R, int m, int n, int H,
                                               const double2 *__restrict__ ring, int64_t stride, int64_t e) {
-  // coefficients (-1)^k C(m, k+1)
   double2 Rk = R;
-  double2 pred = make_double2(0.0, 0.0);
   double binom = (double)m;  // C(m, 1)
-  pred = cfma(pred, binom, Rk, dn);
+  double2 pred = cfma(make_double2(0.0, 0.0), binom, Rk, dn);
 #pragma unroll
   for (int k = 1; k < HMAX; ++k) {
     if (k >= m) break;
     binom = binom * (double)(m - k) / (double)(k + 1);  // C(m, k+1)
     Rk = cmul(Rk, R);
     const int slot = ((n - k) % H + H) % H;
-    const double2 d = ring[(int64_t)slot * stride + e];
-    pred = cfma(pred, (k & 1) ? -binom : binom, Rk, d);
+    pred = cfma(pred, (k & 1) ? -binom : binom, Rk, ring[(int64_t)slot * stride + e]);
   }
   return pred;
 }
 
-constexpr int HMAX = 4;  // longest increment history
+// The output of one entry of sweep kk (first: kk == 0; last: takes the update).
+struct SweepOut {
+  double2 *zo;
+  bool first, last;
+  double e1 = 0.0, qm = 0.0;
+};
+
+template <bool ADJ>
+__device__ __forceinline__ void sweep_entry(const StepArgs &A, SweepOut &so, int64_t e, double h, double gam,
+                                            double dE, double2 acc, double2 own) {
+  const double2 qv = A.q[e];
+  const double2 D = diag_coef(gam, dE, ADJ);
+  const double2 w = stage_weight(h, gam, dE, ADJ);
+  const double2 hdq = cscale(h, cmul(D, qv));
+  const double2 dn = cmul(w, make_double2(hdq.x + h * acc.x, hdq.y + h * acc.y));
+  if (so.first) {
+    const double2 d0 = csub(own, qv);
+    so.e1 = fmax(so.e1, fabs(dn.x - d0.x) + fabs(dn.y - d0.y));
+    so.qm = fmax(so.qm, fmax(fabs(qv.x), fabs(qv.y)));
+  }
+  if (!so.last) {
+    so.zo[e] = cadd(qv, dn);
+    return;
+  }
+  const double2 qn = make_double2(qv.x + 2.0 * dn.x, qv.y + 2.0 * dn.y);
+  A.out[e] = qn;
+  if (ADJ && A.zh) A.zh[e] = cadd(qv, dn);
+  if (A.znext) {
+    const double2 R = cmul(make_double2(1.0 + h * D.x, h * D.y), w);
+    A.znext[e] = cadd(qn, next_start(dn, R, A.m, A.n, A.H, A.ring, A.ring_stride, e));
+    A.ring[(int64_t)(A.n % A.H) * A.ring_stride + e] = dn;
+  }
+}
+
+// The iterate sweep kk reads: the start for kk = 0, then the output of kk - 1.
+__device__ __forceinline__ const double2 *sweep_input(const StepArgs &A, int kk) {
+  if (kk == 0) return A.zstart ? A.zstart : A.q;
+  return (kk & 1) ? A.z0 : A.z1;
+}
 
 }  // namespace
 
-// Status bits written by the kernels into the call's status word.
-__device__ __forceinline__ void raise_status(int32_t *status, int bits) {
-  if (status) atomicOr(status, bits);
-}
-
 // ----------------------------------------------------------------------------
-// Block-tiled persistent step for one system of equal-level subsystems.
+// Block-tiled sweep of one system of equal-level subsystems.
 // ----------------------------------------------------------------------------
-enum { SWEEP_FIRST = 1, SWEEP_LAST = 2 };
-
-// One unit of one sweep.  Each unit builds its own stencil data (controls,
-// subsystem tables, direction table), so nothing is hoisted across the
-// persistent loop over units, whose live state would otherwise exceed the
-// register file.  Returns the unit's maxima of |delta1 - delta0| and |q| on
-// a first sweep.
 template <int NL, int QC, int KR, int KC, bool ADJ, int BLOCK>
-__device__ __forceinline__ double2 step_tile_unit(const SysDev *__restrict__ sysv, int sys, int64_t u, int j,
-                                               const double2 *__restrict__ ctab, const double *__restrict__ Etab,
-                                               const double2 *__restrict__ zin, const double2 *__restrict__ q,
-                                               double2 *__restrict__ zo, double2 *__restrict__ out,
-                                               double2 *__restrict__ zh, double2 *__restrict__ znext,
-                                               double2 *__restrict__ ring, int64_t ring_stride, int n, int m,
-                                               int H, int mode, bool again, double2 *tileb) {
-  const SysDev &S = sysv[sys];
-  const int lane = threadIdx.x & 63;
-  const double h = S.h;
-  double2 dv = make_double2(0.0, 0.0);
-  if (lane < QC) dv = ctab[S.ctab_off + (int64_t)j * QC + lane];
-  double da[QC], db[QC];
-#pragma unroll
-  for (int k = 0; k < QC; ++k) {
-    da[k] = tile::lane_d(dv.x, k);
-    db[k] = tile::lane_d(dv.y, k);
-  }
-  const bool first = mode & SWEEP_FIRST, last = mode & SWEEP_LAST;
-  double e1 = 0.0, qm = 0.0;
-  tile::tile_unit<NL, QC, KR, KC, ADJ, BLOCK>(S, u, zin, tileb, da, db, Etab + S.tab_off, again,
-                                              [&](const tile::Entry &en) {
-    const double2 qv = q[en.e];
-    const double2 D = diag_coef(en.gam, en.dE, ADJ);
-    const double2 w = stage_weight(h, en.gam, en.dE, ADJ);
-    const double2 hdq = cscale(h, cmul(D, qv));
-    const double2 dn = cmul(w, make_double2(hdq.x + h * en.acc.x, hdq.y + h * en.acc.y));
-    if (first) {
-      const double2 d0 = csub(en.own, qv);
-      e1 = fmax(e1, fabs(dn.x - d0.x) + fabs(dn.y - d0.y));
-      qm = fmax(qm, fmax(fabs(qv.x), fabs(qv.y)));
-    }
-    if (!last) {
-      zo[en.e] = cadd(qv, dn);
-      return;
-    }
-    const double2 qn = make_double2(qv.x + 2.0 * dn.x, qv.y + 2.0 * dn.y);
-    out[en.e] = qn;
-    if (ADJ && zh) zh[en.e] = cadd(qv, dn);
-    if (znext) {
-      const double2 R = cmul(make_double2(1.0 + h * D.x, h * D.y), w);
-      const double2 pred = next_start<HMAX>(dn, R, m, n, H, ring, ring_stride, en.e);
-      znext[en.e] = cadd(qn, pred);
-      ring[(int64_t)(n % H) * ring_stride + en.e] = dn;
-    }
-  });
-  return make_double2(e1, qm);
-}
-
-template <int NL, int QC, int KR, int KC, bool ADJ, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void step_tile_kernel(StepArgs A) {
+__global__ __launch_bounds__(BLOCK) void sweep_tile_kernel(StepArgs A, int kk) {
   extern __shared__ double2 tileb[];
   __shared__ double red[2][BLOCK / 64];
-  __shared__ int sK;
-  cg::grid_group grid = cg::this_grid();
-  const int tid = threadIdx.x;
-  const Band bd = xcd_band(A.units);
-  // Sweep kk reads zin (q + delta of sweep kk - 1; the start for kk = 0) and
-  // writes z0 / z1 alternately; the count K is settled after sweep 0.
+  const int64_t per = (A.units + 7) / 8;
+  const int64_t lb = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (lb >= A.units) return;
+  const SysDev &S = A.sysv[A.sys];
   int K = 2;
-#pragma unroll 1
-  for (int kk = 0; kk < K; ++kk) {
-    const bool first = kk == 0, last = kk == K - 1;
-    const double2 *zin = first ? (A.zstart ? A.zstart : A.q) : ((kk & 1) ? A.z0 : A.z1);
-    double2 *zo = (kk & 1) ? A.z1 : A.z0;
-    const int mode = (first ? SWEEP_FIRST : 0) | (last ? SWEEP_LAST : 0);
-    double e1 = 0.0, qm = 0.0;
-    bool again = false;
-#pragma unroll 1
-    for (int64_t u = bd.u0; u < bd.u1; u += bd.stride) {
-      const double2 r = step_tile_unit<NL, QC, KR, KC, ADJ, BLOCK>(
-          A.sysv, A.sys, u, A.j, A.ctab, A.Etab, zin, A.q, zo, A.out, A.zh, A.znext, A.ring, A.ring_stride, A.n,
-          A.m, A.H, mode, again, tileb);
-      e1 = fmax(e1, r.x);
-      qm = fmax(qm, r.y);
-      again = true;
-    }
-    if (first) {
-      // sweep count from the grid-wide maxima, identical in every workgroup
-      block_max2<BLOCK>(e1, qm, red);
-      if (tid == 0) A.part[blockIdx.x] = make_double2(e1, qm);
-      grid.sync();
-      double ge = 0.0, gq = 0.0;
-      for (int k = tid; k < (int)gridDim.x; k += BLOCK) {
-        const double2 p = A.part[k];
-        ge = fmax(ge, p.x);
-        gq = fmax(gq, p.y);
-      }
-      block_max2<BLOCK>(ge, gq, red);
-      if (tid == 0) {
-        const double2 tt = A.ttab[(int64_t)A.sys * A.NT + A.j];
-        bool capped = false;
-        sK = stage_sweeps(tt.x, tt.y, ge, gq, A.tol, A.kcap, &capped);
-        if (blockIdx.x == 0) {
-          if (!(tt.x < 0.5)) raise_status(A.status, LB_STATUS_THETA);
-          if (capped) raise_status(A.status, LB_STATUS_NOCONV);
-          if (A.kout) A.kout[(int64_t)A.sys * A.NT + A.j] += sK;
-        }
-      }
-      __syncthreads();
-      K = sK;
-    } else if (!last) {
-      grid.sync();
+  if (kk > 0) {
+    K = step_sweeps_of(A, A.sys);
+    if (kk >= K) return;  // this step's solve is done (uniform per launch)
+  }
+  const int lane = threadIdx.x & 63;
+  double2 dv = make_double2(0.0, 0.0);
+  if (lane < QC) dv = A.ctab[S.ctab_off + (int64_t)A.j * QC + lane];
+  double da[QC], db[QC];
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    da[q] = tile::lane_d(dv.x, q);
+    db[q] = tile::lane_d(dv.y, q);
+  }
+  SweepOut so;
+  so.first = kk == 0;
+  so.last = kk > 0 && kk == K - 1;
+  so.zo = (kk & 1) ? A.z1 : A.z0;
+  const double h = S.h;
+  tile::tile_unit<NL, QC, KR, KC, ADJ, BLOCK>(S, lb, sweep_input(A, kk), tileb, da, db, A.Etab + S.tab_off, false,
+                                              [&](const tile::Entry &en) {
+                                                sweep_entry<ADJ>(A, so, en.e, h, en.gam, en.dE, en.acc, en.own);
+                                              });
+  if (so.first) {
+    block_max2<BLOCK>(so.e1, so.qm, red);
+    if (threadIdx.x == 0) {
+      unsigned long long *sl = slot_base(A, A.par, A.sys);
+      atomicMax(&sl[blockIdx.x % LB_STEP_SLOTS], dbits(so.e1));
+      atomicMax(&sl[LB_STEP_SLOTS + blockIdx.x % LB_STEP_SLOTS], dbits(so.qm));
     }
   }
 }
 
 // ----------------------------------------------------------------------------
-// Generic persistent step over the segments of a streamed batch (any
-// systems): one entry per thread, neighbours read directly from the batch.
-// Every segment runs its own sweep count.
+// Generic sweep over the segments of a streamed batch (any systems): one
+// entry per thread, neighbours read directly from the batch.  Every segment
+// runs its own sweep count.
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ int find_seg(const StreamSeg *segs, int nseg, int64_t blk) {
   int lo = 0, hi = nseg - 1;
@@ -271,135 +226,98 @@ __device__ __forceinline__ int find_seg(const StreamSeg *segs, int nseg, int64_t
 }
 
 template <bool ADJ>
-__global__ __launch_bounds__(STREAM_BLOCK) void step_generic_kernel(StepArgs A) {
+__global__ __launch_bounds__(STREAM_BLOCK) void sweep_generic_kernel(StepArgs A, int kk) {
   constexpr int BLOCK = STREAM_BLOCK;
   __shared__ double sq[SQRT_TABLE];
+  __shared__ double2 dq[QMAX];
   __shared__ double red[2][BLOCK / 64];
-  __shared__ int sK[LB_STEP_MAXSEG];
-  __shared__ int sKmax;
-  cg::grid_group grid = cg::this_grid();
   const int tid = threadIdx.x;
+  const int64_t u = blockIdx.x;
+  const int sgi = find_seg(A.segs, A.nseg, u);
+  const StreamSeg &sg = A.segs[sgi];
+  const SysDev &S = A.sysv[sg.sys];
+  int K = 2;
+  if (kk > 0) {
+    K = step_sweeps_of(A, sg.sys);
+    if (kk >= K) return;  // uniform per workgroup
+  }
   if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
+  if (tid < S.Q) dq[tid] = A.ctab[S.ctab_off + (int64_t)A.j * S.Q + tid];
   __syncthreads();
-  const Band bd = xcd_band(A.nblk);
-  // One unit = STREAM_BLOCK entries of one segment.  `body` forms delta at
-  // this thread's entry of unit u with zin as the iterate.
-  struct Loc {
-    int seg;
-    bool ok;
-    int64_t e;  // entry in the compact streamed buffers
-    double2 D, w;
-    double2 dn;
-    double2 qv;
-    double2 own;
-  };
-  auto body = [&](int64_t u, const double2 *zin, Loc &L) {
-    const int sgi = find_seg(A.segs, A.nseg, u);
-    const StreamSeg &sg = A.segs[sgi];
-    const SysDev &S = A.sysv[sg.sys];
-    L.seg = sgi;
-    const int64_t local = (u - sg.blk0) * BLOCK + tid;
-    L.ok = local < sg.count;
-    const int64_t lc = L.ok ? local : 0;
-    const int64_t b = lc / S.N2;
-    const int64_t r = lc - b * S.N2;
+  SweepOut so;
+  so.first = kk == 0;
+  so.last = kk > 0 && kk == K - 1;
+  so.zo = (kk & 1) ? A.z1 : A.z0;
+  const double2 *zin = sweep_input(A, kk);
+  const int64_t local = (u - sg.blk0) * BLOCK + tid;
+  if (local < sg.count) {
+    const int64_t b = local / S.N2;
+    const int64_t r = local - b * S.N2;
     const int i = (int)(r / S.N);
     const int jj = (int)(r - (int64_t)i * S.N);
     const uint64_t di = A.desc[S.tab_off + i], dj = A.desc[S.tab_off + jj];
-    const double gam = diag_rate(S, di, dj);
-    const double dE = A.Etab[S.tab_off + i] - A.Etab[S.tab_off + jj];
-    double2 dq[QMAX];
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q)
-      dq[q] = q < S.Q ? A.ctab[S.ctab_off + (int64_t)A.j * S.Q + q] : make_double2(0.0, 0.0);
     const int64_t base = sg.off + b * S.N2;
-    L.e = base + r;
-    L.D = diag_coef(gam, dE, ADJ);
-    L.w = stage_weight(S.h, gam, dE, ADJ);
     const double2 acc = offdiag<ADJ>(S, di, dj, r, dq, sq, [&](int64_t idx) { return zin[base + idx]; });
-    L.qv = A.q[L.e];
-    L.own = zin[L.e];
-    const double2 hdq = cscale(S.h, cmul(L.D, L.qv));
-    L.dn = cmul(L.w, make_double2(hdq.x + S.h * acc.x, hdq.y + S.h * acc.y));
-  };
-  // Sweep kk reads zin and writes z0 / z1 alternately (see the tiled kernel);
-  // the per-segment counts are settled after sweep 0.
-  int Kmax = 2;
-  for (int kk = 0; kk < Kmax; ++kk) {
-    const bool first = kk == 0;
-    const double2 *zin = first ? (A.zstart ? A.zstart : A.q) : ((kk & 1) ? A.z0 : A.z1);
-    double2 *zo = (kk & 1) ? A.z1 : A.z0;
-    for (int64_t u = bd.u0; u < bd.u1; u += bd.stride) {
-      const int sgi = find_seg(A.segs, A.nseg, u);
-      const int K = first ? 2 : sK[sgi];
-      if (kk >= K) continue;  // uniform per unit
-      const bool last = !first && kk == K - 1;
-      Loc L;
-      body(u, zin, L);
-      double e1 = 0.0, qm = 0.0;
-      if (L.ok) {
-        if (first) {
-          const double2 d0 = csub(L.own, L.qv);
-          e1 = fabs(L.dn.x - d0.x) + fabs(L.dn.y - d0.y);
-          qm = fmax(fabs(L.qv.x), fabs(L.qv.y));
-        }
-        if (!last) {
-          zo[L.e] = cadd(L.qv, L.dn);
-        } else {
-          const SysDev &S = A.sysv[A.segs[sgi].sys];
-          const double2 qn = make_double2(L.qv.x + 2.0 * L.dn.x, L.qv.y + 2.0 * L.dn.y);
-          A.out[L.e] = qn;
-          if (ADJ && A.zh) A.zh[L.e] = cadd(L.qv, L.dn);
-          if (A.znext) {
-            const double2 R = cmul(make_double2(1.0 + S.h * L.D.x, S.h * L.D.y), L.w);
-            const double2 pred = next_start<HMAX>(L.dn, R, A.m, A.n, A.H, A.ring, A.ring_stride, L.e);
-            A.znext[L.e] = cadd(qn, pred);
-            A.ring[(int64_t)(A.n % A.H) * A.ring_stride + L.e] = L.dn;
-          }
-        }
-      }
-      if (first) {
-        block_max2<BLOCK>(e1, qm, red);
-        if (tid == 0) A.part[u] = make_double2(e1, qm);
-      }
-    }
-    if (first) {
-      grid.sync();
-      // per-segment maxima: workgroup s reduces the units of segment s
-      for (int s = blockIdx.x; s < A.nseg; s += gridDim.x) {
-        const StreamSeg &sg = A.segs[s];
-        const int64_t nu = (sg.count + BLOCK - 1) / BLOCK;
-        double ge = 0.0, gq = 0.0;
-        for (int64_t k = tid; k < nu; k += BLOCK) {
-          const double2 p = A.part[sg.blk0 + k];
-          ge = fmax(ge, p.x);
-          gq = fmax(gq, p.y);
-        }
-        block_max2<BLOCK>(ge, gq, red);
-        if (tid == 0) {
-          const double2 tt = A.ttab[(int64_t)sg.sys * A.NT + A.j];
-          bool capped = false;
-          const int K = stage_sweeps(tt.x, tt.y, ge, gq, A.tol, A.kcap, &capped);
-          A.segk[s] = K;
-          if (!(tt.x < 0.5)) raise_status(A.status, LB_STATUS_THETA);
-          if (capped) raise_status(A.status, LB_STATUS_NOCONV);
-          if (A.kout) A.kout[(int64_t)sg.sys * A.NT + A.j] += K;
-        }
-      }
-      grid.sync();
-      if (tid == 0) sKmax = 0;
-      __syncthreads();
-      for (int s = tid; s < A.nseg; s += BLOCK) {
-        const int K = A.segk[s];
-        sK[s] = K;
-        atomicMax(&sKmax, K);
-      }
-      __syncthreads();
-      Kmax = sKmax;
-    } else if (kk + 1 < Kmax) {
-      grid.sync();
+    sweep_entry<ADJ>(A, so, base + r, S.h, diag_rate(S, di, dj), A.Etab[S.tab_off + i] - A.Etab[S.tab_off + jj],
+                     acc, zin[base + r]);
+  }
+  if (so.first) {
+    block_max2<BLOCK>(so.e1, so.qm, red);
+    if (tid == 0) {
+      unsigned long long *sl = slot_base(A, A.par, sg.sys);
+      const int k = (int)((u - sg.blk0) % LB_STEP_SLOTS);
+      atomicMax(&sl[k], dbits(so.e1));
+      atomicMax(&sl[LB_STEP_SLOTS + k], dbits(so.qm));
     }
   }
+}
+
+// Sweep count of the current step of every streamed system, after sweep 0:
+// workgroup g takes segment g, reduces the system's slots (one per lane),
+// writes the count, raises status bits, adds the count to kout and clears
+// the slots that the next step's sweep 0 fills.
+__global__ __launch_bounds__(64) void step_count_kernel(StepArgs A) {
+  const int sys = A.segs[blockIdx.x].sys;
+  const int lane = threadIdx.x;
+  unsigned long long *sl = slot_base(A, A.par, sys);
+  double e1 = bdbl(sl[lane]), qm = bdbl(sl[LB_STEP_SLOTS + lane]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    e1 = fmax(e1, __shfl_xor(e1, off, 64));
+    qm = fmax(qm, __shfl_xor(qm, off, 64));
+  }
+  unsigned long long *nx = slot_base(A, A.par ^ 1, sys);
+  nx[lane] = 0ull;
+  nx[LB_STEP_SLOTS + lane] = 0ull;
+  if (lane != 0) return;
+  const double2 tt = A.ttab[(int64_t)sys * A.NT + A.j];
+  int K = A.L;
+  int bits = 0;
+  if (!A.apriori) {
+    K = stage_sweeps(tt.x, tt.y, e1, qm, A.tol, A.kcap);
+    if (K > A.L) {
+      bits |= LB_STATUS_RETRY;
+      K = A.L;
+    }
+  }
+  if (!(tt.x < 0.5)) bits |= LB_STATUS_THETA;
+  if (bits && A.status) atomicOr(A.status, bits);
+  A.kstep[(int64_t)A.par * A.nsys + sys] = K;
+  if (A.kout) A.kout[(int64_t)sys * A.NT + A.j] += K;
+}
+
+// Clears the slots of both parities of every system (start of a call).
+__global__ void slots_clear_kernel(unsigned long long *slots, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    slots[i] = 0ull;
+}
+
+int launch_slots_clear(unsigned long long *slots, int nsys, hipStream_t st) {
+  const int64_t n = (int64_t)2 * nsys * 2 * LB_STEP_SLOTS;
+  hipLaunchKernelGGL(slots_clear_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st,
+                     slots, n);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
 }
 
 // ----------------------------------------------------------------------------
@@ -407,113 +325,56 @@ __global__ __launch_bounds__(STREAM_BLOCK) void step_generic_kernel(StepArgs A) 
 // ----------------------------------------------------------------------------
 namespace {
 
-struct CoopShape {
-  int grid = 0;
-  hipError_t err = hipSuccess;
-};
-
-// Workgroups of a cooperative launch: as many as can be resident at once
-// (occupancy x compute units), a multiple of 8, at most `units` rounded up
-// to a multiple of 8.
-CoopShape coop_grid(const void *fn, int block, size_t shmem, int64_t units, int device) {
-  static std::mutex mu;
-  static std::map<std::tuple<const void *, int, size_t, int>, int> cache;
-  int resident = 0;
-  {
-    std::lock_guard<std::mutex> g(mu);
-    auto key = std::make_tuple(fn, block, shmem, device);
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-      resident = it->second;
-    } else {
-      int per_cu = 0, cus = 0;
-      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, shmem);
-      if (e != hipSuccess) return {0, e};
-      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-      if (e != hipSuccess) return {0, e};
-      resident = per_cu * cus;
-      cache[key] = resident;
-    }
-  }
-  int g = resident - resident % 8;
-  const int64_t want = ((units + 7) / 8) * 8;
-  if (want < g) g = (int)want;
-  if (g < 8) return {0, hipErrorInvalidConfiguration};
-  return {g, hipSuccess};
-}
-
-template <class F>
-int coop_launch(F fn, int block, size_t shmem, int64_t units, int device, StepArgs &A, hipStream_t st,
-                int *grid_out) {
-  const void *f = (const void *)fn;
-  if (shmem > 0) LBX_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  const CoopShape cs = coop_grid(f, block, shmem, units, device);
-  if (cs.err != hipSuccess) return hip_fail(cs.err, "cooperative grid size");
-  if (grid_out) *grid_out = cs.grid;
-  void *args[] = {&A};
-  LBX_HIP(hipLaunchCooperativeKernel(f, dim3(cs.grid), dim3(block), args, (unsigned)shmem, st));
-  return LB_OK;
-}
-
 template <int NL, int QC, int KR, int KC, int BLOCK>
-int step_tile_launch(const lb_plan *p, StepArgs &A, bool adj, hipStream_t st, int *grid) {
+int sweep_tile_launch(const lb_plan *p, StepArgs &A, int kk, bool adj, hipStream_t st) {
   using Sh = tile::Shape<NL, QC, KR, KC, BLOCK>;
   A.units = tile::tile_units(p->sys[A.sys].N, Sh::TR, Sh::TC, A.B);
+  const size_t shmem = Sh::lds_bytes();
+  const void *f = adj ? (const void *)sweep_tile_kernel<NL, QC, KR, KC, true, BLOCK>
+                      : (const void *)sweep_tile_kernel<NL, QC, KR, KC, false, BLOCK>;
+  LBX_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  const dim3 grid((unsigned)(((A.units + 7) / 8) * 8));
   if (adj)
-    return coop_launch(step_tile_kernel<NL, QC, KR, KC, true, BLOCK>, BLOCK, Sh::lds_bytes(), A.units,
-                       p->device, A, st, grid);
-  return coop_launch(step_tile_kernel<NL, QC, KR, KC, false, BLOCK>, BLOCK, Sh::lds_bytes(), A.units,
-                     p->device, A, st, grid);
+    hipLaunchKernelGGL((sweep_tile_kernel<NL, QC, KR, KC, true, BLOCK>), grid, dim3(BLOCK), shmem, st, A, kk);
+  else
+    hipLaunchKernelGGL((sweep_tile_kernel<NL, QC, KR, KC, false, BLOCK>), grid, dim3(BLOCK), shmem, st, A, kk);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
 }
 
 }  // namespace
 
-int launch_step(const lb_plan *p, StepArgs &A, bool adj, int tile_sys, int tile_k, hipStream_t st) {
-  if (A.H > HMAX) return fail(LB_EINVAL, "increment history longer than the kernels keep");
+namespace {
+
+int sweep_only(const lb_plan *p, StepArgs &A, int kk, bool adj, int tile_sys, int tile_k, hipStream_t st) {
   if (tile_sys >= 0) {
     const SysDev &S = p->sys[tile_sys];
     const int nl = S.nlev[0];
     A.sys = tile_sys;
-#define X(NL_, Q_, R_, C_, T_)                                                    \
-  if (nl == NL_ && S.Q == Q_ && tile_k == 10 * R_ + C_)                           \
-    return step_tile_launch<NL_, Q_, R_, C_, T_>(p, A, adj, st, nullptr);
+#define X(NL_, Q_, R_, C_, T_) \
+  if (nl == NL_ && S.Q == Q_ && tile_k == 10 * R_ + C_) return sweep_tile_launch<NL_, Q_, R_, C_, T_>(p, A, kk, adj, st);
     LBX_TILE_SHAPES(X)
 #undef X
-    return fail(LB_EUNSUPPORTED, "no block-tiled step kernel for this system");
+    return fail(LB_EUNSUPPORTED, "no block-tiled sweep kernel for this system");
   }
-  if (A.nseg > LB_STEP_MAXSEG) return fail(LB_EUNSUPPORTED, "too many streamed systems in one batch");
+  if (A.nblk == 0) return LB_OK;
   if (adj)
-    return coop_launch(step_generic_kernel<true>, STREAM_BLOCK, 0, A.nblk, p->device, A, st, nullptr);
-  return coop_launch(step_generic_kernel<false>, STREAM_BLOCK, 0, A.nblk, p->device, A, st, nullptr);
+    hipLaunchKernelGGL(sweep_generic_kernel<true>, dim3((unsigned)A.nblk), dim3(STREAM_BLOCK), 0, st, A, kk);
+  else
+    hipLaunchKernelGGL(sweep_generic_kernel<false>, dim3((unsigned)A.nblk), dim3(STREAM_BLOCK), 0, st, A, kk);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
 }
 
-// Grid (workgroups) the step kernels launch with: the size of the partial
-// maxima array for the tiled kernels.
-int step_grid(const lb_plan *p, int tile_sys, int tile_k, int B, int64_t nblk, int adj, int *grid) {
-  *grid = 0;
-  if (tile_sys >= 0) {
-    const SysDev &S = p->sys[tile_sys];
-    const int nl = S.nlev[0];
-#define X(NL_, Q_, R_, C_, T_)                                                                        \
-  if (nl == NL_ && S.Q == Q_ && tile_k == 10 * R_ + C_) {                                             \
-    using Sh = tile::Shape<NL_, Q_, R_, C_, T_>;                                                      \
-    const void *f = adj ? (const void *)step_tile_kernel<NL_, Q_, R_, C_, true, T_>                   \
-                        : (const void *)step_tile_kernel<NL_, Q_, R_, C_, false, T_>;                 \
-    LBX_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Sh::lds_bytes())); \
-    const CoopShape cs = coop_grid(f, T_, Sh::lds_bytes(), tile::tile_units(S.N, Sh::TR, Sh::TC, B),  \
-                                   p->device);                                                        \
-    if (cs.err != hipSuccess) return hip_fail(cs.err, "cooperative grid size");                       \
-    *grid = cs.grid;                                                                                  \
-    return LB_OK;                                                                                     \
+}  // namespace
+
+int launch_sweep(const lb_plan *p, StepArgs &A, int kk, bool adj, int tile_sys, int tile_k, hipStream_t st) {
+  if (A.H > HMAX) return fail(LB_EINVAL, "increment history longer than the kernels keep");
+  if (int rc = sweep_only(p, A, kk, adj, tile_sys, tile_k, st)) return rc;
+  if (kk == 0 && A.nseg > 0) {
+    hipLaunchKernelGGL(step_count_kernel, dim3((unsigned)A.nseg), dim3(64), 0, st, A);
+    LBX_HIP(hipGetLastError());
   }
-    LBX_TILE_SHAPES(X)
-#undef X
-    return fail(LB_EUNSUPPORTED, "no block-tiled step kernel for this system");
-  }
-  const void *f = adj ? (const void *)step_generic_kernel<true> : (const void *)step_generic_kernel<false>;
-  const CoopShape cs = coop_grid(f, STREAM_BLOCK, 0, nblk, p->device);
-  if (cs.err != hipSuccess) return hip_fail(cs.err, "cooperative grid size");
-  *grid = cs.grid;
   return LB_OK;
 }
 

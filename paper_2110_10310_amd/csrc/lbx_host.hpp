@@ -25,7 +25,8 @@ struct lbx_opts {
   int tile = 1;                          // LB_OPT_TILE
   int tile_ki = 0;                       // LB_OPT_TILE_KI (0: default block)
   int graph_steps = 0;                   // LB_OPT_GRAPH (0: launch directly)
-  int history = 3;                       // LB_OPT_HISTORY
+  int history = 4;                       // LB_OPT_HISTORY
+  int sweeps = 0;                        // LB_OPT_SWEEPS (0: built-in)
   bool profile = false;                  // LB_OPT_PROFILE
   bool sync = true;                      // LB_OPT_SYNC
   double tol = 1.1102230246251565e-16;   // LB_OPT_SOLVE_TOL (2^-53)
@@ -112,24 +113,39 @@ struct ProfScope {
 void prof_resolve(const lb_plan *p);
 void prof_add_work(const lb_plan *p, int kernel, int64_t work);
 
+// Thread-local error message helpers.
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define LBX_HIP(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return lbx::hip_fail(_e, #call); \
+  } while (0)
+
 // Status bits that kernels raise in the status word of a call's workspace.
 constexpr int LB_STATUS_THETA = 1;      // a stage-solve contraction bound >= 0.5
 constexpr int LB_STATUS_NOCONV = 2;     // a stage solve hit the sweep cap
 constexpr int LB_STATUS_NONFINITE = 4;  // an objective is not finite
+constexpr int LB_STATUS_RETRY = 8;      // a streamed step needed more sweeps than were launched
 
-// Most streamed systems one batch may hold (persistent step kernels).
-constexpr int LB_STEP_MAXSEG = 1024;
+// Slots per system and step parity for the grid-wide maxima of sweep 0.
+constexpr int LB_STEP_SLOTS = 64;
 
-// Arguments of one persistent step launch (kernels_step.hip), passed by value.
+// Arguments of one sweep launch (kernels_step.hip), passed by value.
 struct StepArgs {
   const SysDev *sysv;
   const double *Etab;
   const uint64_t *desc;
   const double2 *ctab;      // control table (rad/ns) of every system
   const double2 *ttab;      // [nsys][NT] (theta, theta / (1 - theta))
-  int NT;
+  int NT, nsys;
   int j;                    // step index: controls at t_j + dt/2
   int n, m, H;              // steps already taken in this pass; history used; ring length
+  int par;                  // parity of the step (selects its maxima slots)
+  int L;                    // sweeps launched for this step
+  int apriori;              // 1: every launched sweep runs (counts known on the host)
   const double2 *q;         // q^j (adjoint: qh^{j+1})
   double2 *out;             // q^{j+1} (adjoint: qh^j)
   const double2 *zstart;    // first iterate q + delta0, or NULL (delta0 = 0)
@@ -138,8 +154,8 @@ struct StepArgs {
   double2 *zh;              // stage vector q + delta (adjoint), or NULL
   double2 *ring;            // H increment buffers, ring_stride entries apart
   int64_t ring_stride;
-  double2 *part;            // per-workgroup (tiled) or per-unit (generic) maxima
-  int32_t *segk;            // per-segment sweep counts (generic)
+  unsigned long long *slots;  // [2][nsys][2][LB_STEP_SLOTS] maxima (bits of doubles)
+  int32_t *kstep;           // [2][nsys] sweeps of the step (by parity)
   int32_t *kout;            // sweeps taken are added to [nsys][NT], or NULL
   int32_t *status;          // status word (LB_STATUS_*)
   double tol;
@@ -151,22 +167,11 @@ struct StepArgs {
   int64_t nblk;             // generic: units (STREAM_BLOCK entries each)
 };
 
-// One persistent step launch: the block-tiled kernel of system tile_sys in
-// block shape tile_k (10 KR + KC) when tile_sys >= 0, else the generic one.
-int launch_step(const lb_plan *p, StepArgs &A, bool adj, int tile_sys, int tile_k, hipStream_t st);
-// Workgroups that launch will use (the size of its maxima array).
-int step_grid(const lb_plan *p, int tile_sys, int tile_k, int B, int64_t nblk, int adj, int *grid);
-
-// Thread-local error message helpers.
-void set_error(const std::string &msg);
-int fail(int code, const std::string &msg);
-int hip_fail(hipError_t e, const char *what);
-
-#define LBX_HIP(call)                                   \
-  do {                                                  \
-    hipError_t _e = (call);                             \
-    if (_e != hipSuccess) return lbx::hip_fail(_e, #call); \
-  } while (0)
+// Sweep kk of one step: the block-tiled kernel of system tile_sys in block
+// shape tile_k (10 KR + KC) when tile_sys >= 0, else the generic one.
+int launch_sweep(const lb_plan *p, StepArgs &A, int kk, bool adj, int tile_sys, int tile_k, hipStream_t st);
+// Clears the maxima slots of both parities of nsys systems.
+int launch_slots_clear(unsigned long long *slots, int nsys, hipStream_t st);
 
 // ---- launchers (each returns LB_OK or an error code) ----
 

@@ -121,8 +121,9 @@ struct Entry {
 // One unit.  zin: the batch [B][N][N] whose neighbours are read; tile: LDS of
 // Shape::TT entries; da, db: real and imaginary controls of every subsystem
 // (uniform); Es: energies of this system.  When `sync_first` the workgroup
-// waits before its LDS stores (a previous unit of a persistent loop may still
-// read the buffer).  out(const Entry &) is called once per entry of the unit.
+// waits before its LDS stores (a previous unit in the same workgroup may
+// still read the buffer).  out(const Entry &) is called once per entry of
+// the unit.
 template <int NL, int QC, int KR, int KC, bool ADJ, int BLOCK, class Out>
 __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const double2 *__restrict__ zin,
                                           double2 *tile, const double (&da)[QC], const double (&db)[QC],
@@ -134,12 +135,7 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
   const int N = S.N;
   const int NBR = N / TR, NBC = N / TC;
   const int64_t N2 = S.N2;
-  // Everything per entry derives from the thread index.  It is made opaque
-  // here so that, in a persistent loop over units, the per-entry data is
-  // recomputed in every unit rather than hoisted out of the loop and kept
-  // live across it (which would exceed the register file).
-  int tid = threadIdx.x;
-  asm volatile("" : "+v"(tid));
+  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int64_t b = lb / ((int64_t)NBR * NBC);
   const int rem = (int)(lb - b * NBR * NBC);

@@ -623,3 +623,56 @@ def test_autotuner_choice_and_cache(lbx, tmp_path):
     rT = lbx.forward_solve(plan, al, dev(flat_states(rho0)), batch).cpu().numpy()
     ref = [oracle.imr_forward(systems[0], alphas[0], rho0[0])]
     assert rel_state_err(split_states(rT, systems, batch), ref) < STATE_TOL
+
+
+# --------------------------------------------------------------- stage-solve counts on the device
+
+def test_streamed_steps_repeat_with_a_priori_counts(lbx):
+    # Two sweeps launched per step are too few for these steps: every step
+    # raises the retry bit, and the synchronous call repeats itself with the
+    # a-priori counts read on the host; the result must still match the oracle.
+    shapes = [(3, 3), (2, 3)]
+    systems, alphas, rho0, batch = _multi(list(enumerate(shapes, start=140)), NT=10, B=(2, 1), T=1.0)
+    say("retry with a-priori counts")
+    nat = lbx._native
+    plan = lbx.Plan(systems, path="stream")
+    plan.set_option(nat.LB_OPT_SWEEPS, 2)
+    rhoT = lbx.forward_solve(plan, dev(flat_alpha(alphas)), dev(flat_states(rho0)), batch)
+    ref = [oracle.imr_forward(s, a, r) for s, a, r in zip(systems, alphas, rho0)]
+    assert rel_state_err(split_states(rhoT.cpu().numpy(), systems, batch), ref) < STATE_TOL
+    # asynchronous calls report the condition through lb_status instead
+    plan.set_option(nat.LB_OPT_SYNC, 0)
+    ws = plan.workspace(nat.LB_OP_FORWARD, batch)
+    lbx.forward_solve(plan, dev(flat_alpha(alphas)), dev(flat_states(rho0)), batch)
+    with pytest.raises(lbx._native.LbxError) as e:
+        plan.status(ws)
+    assert e.value.code == nat.LB_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("H", [0, 1, 2, 4])
+def test_streamed_history_lengths_match_oracle(lbx, H):
+    # The first iterate of a streamed step extrapolated from 0 to 4 earlier
+    # increments (in the diagonal Cayley frame): the converged steps agree
+    # with the oracle whatever the start.
+    shapes = [(3, 3), (2, 2, 2)]
+    systems, alphas, rho0, batch = _multi(list(enumerate(shapes, start=150)), NT=14, B=(2, 1), T=1.4)
+    say("history", H)
+    rng = np.random.default_rng(151)
+    tars = [random_pure_states(rng, s.N, b) for s, b in zip(systems, batch)]
+    beta = np.ones(sum(batch))
+    plan = lbx.Plan(systems, path="stream")
+    plan.set_option(lbx._native.LB_OPT_HISTORY, H)
+    G, grad, rhoT = lbx.adjoint_gradient(plan, 0, dev(flat_alpha(alphas)), dev(flat_states(rho0)),
+                                         dev(flat_states(tars)), dev(beta), batch, 0.0, 5, want_rhoT=True)
+    got = split_states(rhoT.cpu().numpy(), systems, batch)
+    G, grad = G.cpu().numpy(), grad.cpu().numpy()
+    off_b = off_a = 0
+    for k, s in enumerate(systems):
+        Gr, gr, rT = oracle.value_and_gradient(s, alphas[k], rho0[k], tars[k], beta[off_b:off_b + batch[k]], 0,
+                                               return_final=True)
+        assert rel_state_err([got[k]], [rT]) < STATE_TOL
+        assert abs(G[k] - Gr) <= 1e-12 * abs(Gr)
+        ga = grad[off_a:off_a + alphas[k].size].reshape(alphas[k].shape)
+        assert np.max(np.abs(ga - gr)) <= GRAD_TOL * np.max(np.abs(gr))
+        off_b += batch[k]
+        off_a += alphas[k].size
