@@ -118,6 +118,12 @@ extern "C" {
 #define LB_LIMIT_QMAX 12   /* subsystems per system */
 #define LB_LIMIT_NLEV 31   /* levels per subsystem */
 
+/* imr_step_noalloc: its scratch array (bytes per device), the most state
+ * entries B*N^2 one call may take, and the most systems its plan may hold. */
+#define LB_NOALLOC_SCRATCH_BYTES 67108864
+#define LB_NOALLOC_MAX_ENTRIES 2064384
+#define LB_NOALLOC_MAX_SYSTEMS 256
+
 /* One composite system (Sec. II).  Host memory; copied by lb_plan_create. */
 typedef struct {
   int32_t Q;                /* number of subsystems, 1..LB_LIMIT_QMAX */
@@ -169,7 +175,9 @@ int lb_trajectory_bytes(const lb_plan *plan, const int32_t *batch_per_sys, int32
 /* Waits for `stream` and returns the status that the last call using the
  * workspace `ws` (DEVICE) raised on the device: LB_OK, LB_ENONFINITE (an
  * objective is not finite) or LB_EUNSUPPORTED (a step's stage-solve
- * contraction bound is >= 0.5, or a stage solve hit its sweep cap). */
+ * contraction bound is >= 0.5, a stage solve hit its sweep cap, or a
+ * streamed step needed more sweeps than were launched).  With ws NULL: the
+ * status of the last imr_step_noalloc call on the current device. */
 int lb_status(const lb_plan *plan, const void *ws, void *stream);
 
 /* Launch count and summed duration [ms] of kernel family `kernel` (LB_KERNEL_*)
@@ -222,6 +230,20 @@ int lindblad_apply(const lb_plan *plan, int32_t sys, double t, const double *alp
  * a-posteriori bound after the first sweep asks for (at least two). */
 int imr_step(const lb_plan *plan, int32_t sys, int32_t j, const double *alpha, const void *q_in,
              void *q_out, int32_t B, int32_t adjoint, void *ws, size_t ws_bytes, void *stream);
+
+/* imr_step without allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, allocation-free serving loops.
+ * Same step, arguments and results as imr_step with no workspace: its
+ * scratch (LB_NOALLOC_SCRATCH_BYTES) is a static device array that every
+ * device the library runs on holds until the process ends; it calls no
+ * hipMalloc or hipFree.  B*N^2 must not exceed LB_NOALLOC_MAX_ENTRIES and the
+ * plan must hold at most LB_NOALLOC_MAX_SYSTEMS systems (else LB_EINVAL).
+ * Every call on a device shares that device's scratch (which keeps the last
+ * call's contents): calls that overlap on one device race.  With LB_OPT_SYNC
+ * off the call returns once enqueued and lb_status(plan, NULL, stream) reads
+ * its status. */
+int imr_step_noalloc(const lb_plan *plan, int32_t sys, int32_t j, const double *alpha, const void *q_in,
+                     void *q_out, int32_t B, int32_t adjoint, void *stream);
 
 /* Integrates every state of every system from t = 0 to T (App. A).
  * alpha: DEVICE, all systems concatenated; rho0, rhoT: DEVICE batched states;

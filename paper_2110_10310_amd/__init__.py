@@ -9,6 +9,7 @@ from .api import (  # noqa: F401
     sweep_counts,
     lindblad_apply,
     imr_step,
+    imr_step_noalloc,
     forward_solve,
     objective,
     adjoint_gradient,

@@ -37,6 +37,10 @@ LB_OPT_HISTORY = 6
 LB_OPT_SYNC = 7
 LB_OPT_SWEEPS = 8
 
+LB_NOALLOC_SCRATCH_BYTES = 67108864
+LB_NOALLOC_MAX_ENTRIES = 2064384
+LB_NOALLOC_MAX_SYSTEMS = 256
+
 LB_KERNEL_LDS_FORWARD = 0
 LB_KERNEL_LDS_ADJOINT = 1
 LB_KERNEL_SWEEP = 2
@@ -75,6 +79,7 @@ SIGNATURES = {
                                    _p, C.c_size_t, _p]),
     "lb_trajectory_bytes": (C.c_int, [_p, _ip, _i32, C.POINTER(C.c_size_t)]),
     "lb_status": (C.c_int, [_p, _p, _p]),
+    "imr_step_noalloc": (C.c_int, [_p, _i32, _i32, _p, _p, _p, _i32, _i32, _p]),
     "lb_profile_read": (C.c_int, [_p, _i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), _i32]),
     "lb_profile_work": (C.c_int, [_p, _i32, C.POINTER(C.c_int64)]),
     "sweep_counts": (C.c_int, [_p, _p, _ip, _p]),

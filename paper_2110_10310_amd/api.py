@@ -190,9 +190,10 @@ class Plan:
         """A new buffer for the forward trajectory of forward_solve."""
         return torch.empty(max(self.trajectory_bytes(batch, ckpt_every), 1), dtype=torch.uint8, device="cuda")
 
-    def status(self, ws: torch.Tensor) -> None:
-        """Raises LbxError for the device status of the last call on ws."""
-        check(lib.lb_status(self.handle, _vp(ws), _stream()), "lb_status")
+    def status(self, ws: torch.Tensor | None) -> None:
+        """Raises LbxError for the device status of the last call on ws (with
+        ws None: of the last imr_step_noalloc call on the current device)."""
+        check(lib.lb_status(self.handle, _vp(ws) if ws is not None else None, _stream()), "lb_status")
 
     def entries(self, batch: Sequence[int]) -> int:
         return int(sum(int(b) * n * n for b, n in zip(batch, self.N)))
@@ -251,6 +252,21 @@ def imr_step(plan: Plan, sys: int, j: int, alpha: torch.Tensor, q_in: torch.Tens
     check(lib.imr_step(plan.handle, sys, int(j), _vp(alpha), _vp(q_in), _vp(q_out), B,
                        int(bool(adjoint)), _vp(ws), ws.numel(), _stream()), "imr_step")
     return q_out
+
+
+def imr_step_noalloc(plan: Plan, sys: int, j: int, alpha: torch.Tensor, q_in: torch.Tensor,
+                     out: torch.Tensor, adjoint: bool = False) -> torch.Tensor:
+    """imr_step without a workspace: the library's static device scratch
+    serves it, so the call allocates nothing (out is the caller's)."""
+    N = plan.N[sys]
+    _need(alpha, "alpha", torch.float64, plan.nalpha[sys])
+    _need(q_in, "q_in", torch.complex128)
+    if q_in.dim() != 3 or q_in.shape[1:] != (N, N):
+        raise ValueError(f"q_in must be [B, {N}, {N}]")
+    _need(out, "out", torch.complex128, q_in.numel())
+    check(lib.imr_step_noalloc(plan.handle, sys, int(j), _vp(alpha), _vp(q_in), _vp(out), q_in.shape[0],
+                               int(bool(adjoint)), _stream()), "imr_step_noalloc")
+    return out
 
 
 def _states(plan: Plan, t: torch.Tensor, name: str, batch) -> torch.Tensor:

@@ -83,6 +83,23 @@ void ProfScope::prof_drain(const lb_plan *p) {
   p->prof_pending.erase(p->prof_pending.begin(), p->prof_pending.begin() + n);
 }
 
+lbx_opts plan_options(const lb_plan *p) {
+  std::lock_guard<std::mutex> g(p->mu);
+  return p->opts;
+}
+
+int status_bits_code(int32_t s) {
+  if (s & LB_STATUS_NONFINITE) return fail(LB_ENONFINITE, "an objective is not finite");
+  if (s & LB_STATUS_THETA)
+    return fail(LB_EUNSUPPORTED,
+                "a stage-solve contraction bound is >= 0.5 (step or control amplitude too large)");
+  if (s & LB_STATUS_NOCONV) return fail(LB_EUNSUPPORTED, "a stage solve did not converge within the sweep cap");
+  if (s & LB_STATUS_RETRY)
+    return fail(LB_EUNSUPPORTED, "a streamed step needed more stage sweeps than were launched; repeat the call "
+                                 "with LB_OPT_SYNC on, which repeats it with a-priori counts");
+  return LB_OK;
+}
+
 }  // namespace lbx
 
 // ----------------------------------------------------------------------------
@@ -90,10 +107,7 @@ void ProfScope::prof_drain(const lb_plan *p) {
 // ----------------------------------------------------------------------------
 namespace {
 
-lbx_opts snapshot(const lb_plan *p) {
-  std::lock_guard<std::mutex> g(p->mu);
-  return p->opts;
-}
+lbx_opts snapshot(const lb_plan *p) { return plan_options(p); }
 
 struct LdsClass {
   int block, ept;
@@ -466,17 +480,7 @@ int read_status(const int32_t *d_status, hipStream_t st, int32_t *bits) {
 }
 
 // Error code of the status bits.
-int status_code(int32_t s) {
-  if (s & LB_STATUS_NONFINITE) return fail(LB_ENONFINITE, "an objective is not finite");
-  if (s & LB_STATUS_THETA)
-    return fail(LB_EUNSUPPORTED,
-                "a stage-solve contraction bound is >= 0.5 (step or control amplitude too large)");
-  if (s & LB_STATUS_NOCONV) return fail(LB_EUNSUPPORTED, "a stage solve did not converge within the sweep cap");
-  if (s & LB_STATUS_RETRY)
-    return fail(LB_EUNSUPPORTED, "a streamed step needed more stage sweeps than were launched; repeat the call "
-                                 "with LB_OPT_SYNC on, which repeats it with a-priori counts");
-  return LB_OK;
-}
+int status_code(int32_t s) { return status_bits_code(s); }
 
 int status_code(const int32_t *d_status, hipStream_t st) {
   int32_t s = 0;
@@ -1147,7 +1151,7 @@ extern "C" int lb_trajectory_bytes(const lb_plan *p, const int32_t *batch_per_sy
 
 extern "C" int lb_status(const lb_plan *p, const void *ws, void *stream) {
   if (int rc = check_plan(p)) return rc;
-  if (!ws) return fail(LB_EINVAL, "NULL argument");
+  if (!ws) return noalloc_status(p, (hipStream_t)stream);
   return status_code((const int32_t *)ws, (hipStream_t)stream);
 }
 

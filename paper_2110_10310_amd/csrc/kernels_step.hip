@@ -184,7 +184,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_tile_kernel(StepArgs A, int kk) {
   }
   const int lane = threadIdx.x & 63;
   double2 dv = make_double2(0.0, 0.0);
-  if (lane < QC) dv = A.ctab[S.ctab_off + (int64_t)A.j * QC + lane];
+  if (lane < QC) dv = A.ctab[S.ctab_off + (int64_t)A.j * QC + lane - A.cshift];
   double da[QC], db[QC];
 #pragma unroll
   for (int q = 0; q < QC; ++q) {
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_generic_kernel(StepArgs A,
     if (kk >= K) return;  // uniform per workgroup
   }
   if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
-  if (tid < S.Q) dq[tid] = A.ctab[S.ctab_off + (int64_t)A.j * S.Q + tid];
+  if (tid < S.Q) dq[tid] = A.ctab[S.ctab_off + (int64_t)A.j * S.Q + tid - A.cshift];
   __syncthreads();
   SweepOut so;
   so.first = kk == 0;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(64) void step_count_kernel(StepArgs A) {
   nx[lane] = 0ull;
   nx[LB_STEP_SLOTS + lane] = 0ull;
   if (lane != 0) return;
-  const double2 tt = A.ttab[(int64_t)sys * A.NT + A.j];
+  const double2 tt = A.ttab[(int64_t)sys * A.NT + A.j - A.tshift];
   int K = A.L;
   int bits = 0;
   if (!A.apriori) {

@@ -140,6 +140,7 @@ struct StepArgs {
   const uint64_t *desc;
   const double2 *ctab;      // control table (rad/ns) of every system
   const double2 *ttab;      // [nsys][NT] (theta, theta / (1 - theta))
+  int64_t cshift, tshift;   // the tables hold entries from these indices on (0: all)
   int NT, nsys;
   int j;                    // step index: controls at t_j + dt/2
   int n, m, H;              // steps already taken in this pass; history used; ring length
@@ -166,6 +167,14 @@ struct StepArgs {
   int nseg;
   int64_t nblk;             // generic: units (STREAM_BLOCK entries each)
 };
+
+// A copy of the plan's options (taken when a call starts).
+lbx_opts plan_options(const lb_plan *p);
+// Error code of LB_STATUS_* bits (LB_OK when none is set).
+int status_bits_code(int32_t bits);
+// Waits for `st` and returns the status of the last imr_step_noalloc call
+// on the current device.
+int noalloc_status(const lb_plan *p, hipStream_t st);
 
 // Sweep kk of one step: the block-tiled kernel of system tile_sys in block
 // shape tile_k (10 KR + KC) when tile_sys >= 0, else the generic one.

@@ -53,6 +53,7 @@ def test_invalid_arguments_rejected_before_device_calls(built_lib):
     assert lib.adjoint_gradient(None, 0, None, None, None, None, None, 0.0, 1, None, None, None,
                                 None, 0, None) == nat.LB_EINVAL
     assert lib.lb_plan_set_option(None, 0, 0.0) == nat.LB_EINVAL
+    assert lib.imr_step_noalloc(None, 0, 0, None, None, None, 1, 0, None) == nat.LB_EINVAL
 
 
 def test_plan_validation_of_parameters(built_lib):
