@@ -1,26 +1,32 @@
 #!/usr/bin/env python3
 """Throughput of the Lindblad optimal-control hot path on one MI355X.
 
-Workload (one "step" = one forward + adjoint gradient evaluation): two
-coupled transmons with 4 levels each (N = 16), all 16 basis density matrices
-of the 2x2 essential subspace batched, CNOT target, Frobenius merit,
-20 B-splines x 2 carriers per control (160 real coefficients), T = 200 ns,
-10000 implicit-midpoint steps.  Inputs are seeded and synthetic and already
+Headline workload: the eight-qutrit ring (N = 6561, 43,046,721 complex FP64
+entries per state, 689 MB), one state |0..0>, J_Frob to |1..1>, 20
+B-splines per control, T = 100 ns, 5000 implicit-midpoint steps, forward
+pass plus discrete-adjoint gradient with checkpoints every ceil(sqrt(5000))
+= 71 steps recomputed in the adjoint.  One bench step is one gradient
+evaluation of that system at full size over a window of the horizon (default
+142 steps = two checkpoint segments of 71, the segment structure of the full
+run): control table, forward pass with checkpoints, objective, adjoint with
+recomputation and gradient contraction.  `value` is c5 gradient evaluations
+per second derived from it (time per window x 5000 / 142); `--window 5000`
+times the whole horizon.  Inputs are seeded and synthetic and already
 resident in GPU memory when the timed region starts.
 
 Printed as one JSON line:
-  value          gradient evaluations per second,
-  roofline       the dominant kernel of the step (the LDS-resident adjoint
-                 time loop), algorithmic FP64 flops per launch over its
-                 HIP-event duration, against the FP64 vector peak,
-  apply_roofline lindblad_apply on the eight-qutrit ring (N = 6561,
-                 43,046,721 entries per state), algorithmic bytes (read x,
-                 write y: 32 B per entry) over its HIP-event duration,
-                 against the HBM peak,
-  per_state_loop the same gradient with one state at a time through the
-                 streaming kernels (one launch per sweep), for the speedup of
-                 batching and persistence,
-  cpu_baseline   the CPU oracle on a bounded sample of the same workload.
+  value          c5 gradient evaluations per second (scaled from the window),
+  roofline       the dominant kernel: the block-tiled stage sweep, 48
+                 algorithmic bytes per entry and executed sweep (read the
+                 iterate and q, write the next iterate) over the HIP-event
+                 time of the streamed steps, against the HBM peak,
+  apply_roofline lindblad_apply on the same state, 32 B per entry (read x,
+                 write y), against the HBM peak,
+  c2_cnot        the two-transmon CNOT gradient (N = 16, 16 states, 10000
+                 steps) with its LDS-resident roofline, the per-state loop
+                 speedup and its own CPU baseline,
+  cpu_baseline   the CPU oracle on a bounded sample of the headline workload,
+                 one process per core of the box's share.
 """
 from __future__ import annotations
 
@@ -42,6 +48,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 APPLY_SOURCES = ["paper_2110_10310_amd/csrc/kernels_stream.hip",
                  "paper_2110_10310_amd/csrc/kernels_tile.hip",
                  "paper_2110_10310_amd/csrc/lbx_device.hpp"]
+STEP_SOURCES = ["paper_2110_10310_amd/csrc/kernels_step.hip",
+                "paper_2110_10310_amd/csrc/tile_unit.hpp"]
 LDS_SOURCES = ["paper_2110_10310_amd/csrc/kernels_lds.hip",
                "paper_2110_10310_amd/csrc/kernels_lds_fast.hip",
                "paper_2110_10310_amd/csrc/lbx_device.hpp"]
@@ -53,11 +61,13 @@ TRAFFIC_KEYS = {
     "lds_adjoint_integrands": (["lds_grad_fast_kernel"], LDS_SOURCES),
 }
 for _ki, _thr in TILE_KIS.items():
-    _sh = f"tile_kernel<3, 8, {_ki // 10}, {_ki % 10}"
-    TRAFFIC_KEYS[f"apply_kernel_forward_ki{_ki}"] = ([f"{_sh}, false, 0, {_thr}>"], APPLY_SOURCES)
-    TRAFFIC_KEYS[f"apply_kernel_adjoint_ki{_ki}"] = ([f"{_sh}, true, 0, {_thr}>"], APPLY_SOURCES)
-    TRAFFIC_KEYS[f"stage_sweep_kernel_c5_ki{_ki}"] = ([f"{_sh}, false, 1, {_thr}>", f"{_sh}, false, 2, {_thr}>"],
-                                                      APPLY_SOURCES)
+    _tail = f"<3, 8, {_ki // 10}, {_ki % 10}"
+    TRAFFIC_KEYS[f"apply_kernel_forward_ki{_ki}"] = ([f"lbx::tile_kernel{_tail}, false, {_thr}>"], APPLY_SOURCES)
+    TRAFFIC_KEYS[f"apply_kernel_adjoint_ki{_ki}"] = ([f"lbx::tile_kernel{_tail}, true, {_thr}>"], APPLY_SOURCES)
+    # executed launches only (a launch after the step's solve has converged
+    # returns at once and moves nothing)
+    TRAFFIC_KEYS[f"stage_sweep_c5_ki{_ki}"] = ([f"lbx::sweep_tile_kernel{_tail}, "], APPLY_SOURCES + STEP_SOURCES,
+                                               "executed")
 
 
 def source_sha(files):
@@ -111,16 +121,41 @@ WORKLOADS = {
     4: "c4_5qutrit_chain: 5 qutrits (N=243), 10 states, 20000 IMR steps, 300 controls, J_Tr, "
        "checkpoints every 200 steps",
     5: "c5_8qutrit_ring: 8 qutrits (N=6561, 43M entries), 1 state, 5000 IMR steps, 320 controls, "
-       "J_Frob, checkpoints every ceil(sqrt(NT)) steps",
+       "J_Frob, checkpoints every ceil(sqrt(5000)) = 71 steps",
 }
 
 
-def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
+HEADLINE = 5
+WORKLOADS_NT = {1: 2000, 2: 10000, 3: 5000, 4: 20000, 5: 5000}
+DEFAULT_WINDOW = {5: 142, 3: 500}   # time-step windows of the workloads whose evaluation runs for minutes
+
+
+LDS_MAX_N2 = 4096   # systems up to this N^2 run LDS-resident (every state kept, no recomputation)
+
+
+def window_ckpt(p):
+    """Checkpoint interval that gives a window of the horizon the segments of
+    the full evaluation: the workload's own, or, where every system streams,
+    the library's automatic ceil(sqrt(NT)) of the full horizon made explicit.
+    (An explicit interval above 1 would move LDS-resident systems to the
+    streamed path, so mixed workloads keep the automatic choice.)"""
+    import math
+    if p.ckpt_every > 0:
+        return p.ckpt_every
+    if all(s.N * s.N > LDS_MAX_N2 for s in p.systems):
+        return max(1, math.ceil(math.sqrt(p.systems[0].NT)))
+    return 0
+
+
+def run_gradient_bench(lbx, torch, steps, warmup, workload=HEADLINE, window=0):
     from workloads import make_config, truncate_steps
     p = make_config(workload)
     nt_full = p.systems[0].NT
-    if sample_steps and sample_steps < nt_full:
-        p = truncate_steps(p, sample_steps)
+    ckpt = p.ckpt_every
+    if window and window < nt_full:
+        ckpt = window_ckpt(p)
+        p = truncate_steps(p, window)
+        ckpt = min(ckpt, window)
     nat = lbx._native
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda")
     alpha = dev(np.concatenate([a.reshape(-1) for a in p.alpha]))
@@ -130,7 +165,6 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
     batch = p.batch
     plan = lbx.Plan(p.systems)
     tuned = plan.autotune(alpha, batch)
-    ckpt = p.ckpt_every
     for _ in range(warmup):
         lbx.adjoint_gradient(plan, p.kind, alpha, rho0, tar, beta, batch, p.gamma2, ckpt)
     plan.profile(True)
@@ -153,7 +187,7 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
     lds_entries = st_entries = 0
     for k, s in enumerate(p.systems):
         entries = batch[k] * s.N * s.N
-        if s.N * s.N <= 4096:
+        if s.N * s.N <= LDS_MAX_N2 and ckpt <= 1:
             f_sweep, f_grad = flops_per_entry(s.nlev)
             wk = float(counts[k, :, 0].sum()) * entries
             wsum += wk
@@ -185,14 +219,32 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
                 "traffic": traffic,
                 "avg_launch_ms": 1e3 * avg_s, "launches": prof[dom][0], "flops_per_launch": fl,
                 "workgroups": sum(b for k, b in enumerate(batch) if p.systems[k].N ** 2 <= 4096)}
+    elif dom == nat.LB_KERNEL_SWEEP:
+        # A profiled unit is the sweep launches of one streamed step: the
+        # sweeps that run, the launches that return at once because the step's
+        # solve has converged, and the count kernel.  The work read back from
+        # the device is entries x executed sweeps, so work / entries executed
+        # launches share the unit time; each moves 48 B per entry by the
+        # algorithm (read the iterate and q, write the next iterate).
+        launches = work[dom] / st_entries
+        by = 48.0 * st_entries
+        avg_s = ms[dom] / 1e3 / launches
+        achieved = by / avg_s / 1e9
+        ki = tuned.get("tile_ki", 0)
+        tiled = tuned.get("tile", 0) == 1 and ki > 0 and len(p.systems) == 1
+        roof = {"kernel": (f"sweep_tile_kernel<3, 8, {ki // 10}, {ki % 10}, forward|adjoint, {TILE_KIS.get(ki)}>"
+                           if tiled else "sweep_generic_kernel<forward|adjoint>"),
+                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(f"stage_sweep_c{workload}_ki{ki}", APPLY_SOURCES + STEP_SOURCES)
+                if tiled else None,
+                "avg_launch_ms": 1e3 * avg_s, "launches": launches, "bytes_per_launch": by,
+                "step_units": prof[dom][0], "unit_ms": ms[dom] / n[dom]}
     else:
-        per_entry = 48.0 if dom == nat.LB_KERNEL_SWEEP else 64.0
-        by = per_entry * work[dom] / n[dom]
+        by = 64.0 * work[dom] / n[dom]
         achieved = by / avg_s / 1e9
         roof = {"kernel": name_of[dom], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(name_of[dom] + f"_c{workload}_ki{tuned.get('tile_ki', 0)}",
-                                            APPLY_SOURCES),
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "avg_launch_ms": 1e3 * avg_s, "launches": prof[dom][0], "bytes_per_launch": by}
     nt = p.systems[0].NT
     sweeps = {}
@@ -207,7 +259,11 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
         "scale": scale,
         "value": steps / (elapsed * scale),
         "ms_per_step": 1e3 * elapsed * scale / steps,
-        "sample": None if scale == 1 else f"{p.systems[0].NT} of {nt_full} steps timed, scaled x{scale:g}",
+        "sample": None if scale == 1 else (f"{p.systems[0].NT} of {nt_full} time steps of the full-size "
+                                           f"evaluation timed, checkpoint interval {ckpt or 'automatic'}, "
+                                           f"time scaled x{scale:g}"),
+        "window_ms": 1e3 * elapsed / steps,
+        "ckpt_every": ckpt,
         "G": [float(v) for v in G.cpu().numpy()[:4]],
         "grad_norm": float(grad.abs().max().item()),
         "sweeps_per_step_mean": sweeps,
@@ -219,9 +275,8 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=2, sample_steps=0):
         # applications of M per evaluation on the streamed path: every sweep of
         # every pass, plus the gradient integrands of every step
         "apply_equivalents": (work[nat.LB_KERNEL_SWEEP] / steps / st_entries + nt) if st_entries else None,
-        # Stage-sweep bytes (48 B per entry and sweep) over the whole timed
-        # region: the forward recomputation and the adjoint run on two streams,
-        # so a sweep's event-timed duration includes the other stream's share.
+        # stage-sweep bytes (48 B per entry and executed sweep) over the whole
+        # timed region, host clock
         "sweep_GBps_timed_region": 48.0 * work[nat.LB_KERNEL_SWEEP] / elapsed / 1e9 if st_entries else None,
     }
 
@@ -272,10 +327,12 @@ def run_apply_bench(lbx, torch, reps):
 
 def run_traffic_probe(lbx, torch):
     """Launches whose HBM counters are read by rocprofv3 --pmc: a plain device
-    copy of one eight-qutrit state (the calibration of the counters), for each
-    block shape two forward and two adjoint applies and one IMR step on that
-    state, and one two-transmon gradient evaluation."""
-    from workloads import make_config
+    copy of one eight-qutrit state (the calibration of the counters); for each
+    block shape two forward and two adjoint applies of that state and one
+    gradient evaluation of the eight-qutrit ring over 24 steps with
+    checkpoints every 12 (forward, recomputation and adjoint sweeps in the mix
+    of the timed window); and one two-transmon gradient evaluation."""
+    from workloads import make_config, truncate_steps
     p = make_config(5)
     s = p.systems[0]
     N = s.N
@@ -292,12 +349,20 @@ def run_traffic_probe(lbx, torch):
         for adj in (False, True):
             for _ in range(2):
                 lbx.lindblad_apply(plan, 0, 41.0, alpha, x, adjoint=adj, out=y)
-        lbx.imr_step(plan, 0, 2000, alpha, x, out=y)
-    torch.cuda.synchronize()
     del x, y
-    print("[probe] eight-qutrit launches done", file=sys.stderr, flush=True)
-    p = make_config(2)
+    torch.cuda.synchronize()
+    print("[probe] eight-qutrit applies done", file=sys.stderr, flush=True)
+    pw = truncate_steps(p, 24)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda")
+    args = (dev(pw.rho0[0]), dev(pw.rhotar[0]), dev(pw.beta[0]), pw.batch, pw.gamma2, 12)
+    for ki in TILE_KIS:
+        plan = lbx.Plan(pw.systems)
+        plan.set_option(lbx._native.LB_OPT_TILE_KI, ki)
+        lbx.adjoint_gradient(plan, pw.kind, alpha, *args)
+        torch.cuda.synchronize()
+        print(f"[probe] eight-qutrit gradient window, block shape {ki} done", file=sys.stderr, flush=True)
+        del plan
+    p = make_config(2)
     plan = lbx.Plan(p.systems)
     lbx.adjoint_gradient(plan, p.kind, dev(p.alpha[0].reshape(-1)), dev(p.rho0[0]), dev(p.rhotar[0]),
                          dev(p.beta[0]), p.batch, p.gamma2, p.ckpt_every)
@@ -325,11 +390,15 @@ def traffic_summary(fetch_csv, write_csv, copy_bytes, out_path=None):
     cal_w = copy_bytes / 1024 / max(write.get("__amd_rocclr_copyBuffer", [0]))
     table = {"calibration": {"copy_bytes": copy_bytes, "fetch_factor": cal_f, "write_factor": cal_w}}
     rows = []
-    for key, (pats, files) in TRAFFIC_KEYS.items():
+    for key, (pats, files, *mode) in TRAFFIC_KEYS.items():
         fv = [v for k, vs in fetch.items() if any(pt in k for pt in pats) for v in vs]
         wv = [v for k, vs in write.items() if any(pt in k for pt in pats) for v in vs]
         if not fv or not wv:
             continue
+        if mode and mode[0] == "executed":
+            # launches that returned at once read and write almost nothing
+            fv = [v for v in fv if v >= 0.01 * max(fv)]
+            wv = [v for v in wv if v >= 0.01 * max(wv)]
         fb = 1024 * cal_f * float(np.mean(fv))
         wb = 1024 * cal_w * float(np.mean(wv))
         table[key] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
@@ -346,7 +415,9 @@ def traffic_summary(fetch_csv, write_csv, copy_bytes, out_path=None):
 
 
 def kernel_stats(db):
-    """Markdown table of the per-kernel summary in a rocprofv3 --stats database."""
+    """Markdown table of the per-kernel summary in a rocprofv3 --stats database;
+    for the stage sweep kernels also the average over executed launches (a
+    launch after its step's solve has converged returns at once)."""
     import sqlite3
     con = sqlite3.connect(db)
     # durations in the summary view are in microseconds
@@ -356,6 +427,28 @@ def kernel_stats(db):
             "select name, total_calls, total_duration, average, percentage from top_kernels limit 16"):
         short = name.split("(")[0].replace("void ", "")
         print(f"| `{short}` | {calls} | {total / 1e3:.3f} | {avg / 1e3:.4f} | {pct:.1f} |")
+    try:
+        rows = con.execute("select name, start, end from kernels").fetchall()
+    except sqlite3.Error:
+        return
+    by = {}
+    for name, t0, t1 in rows:
+        if "sweep_tile_kernel" in name or "sweep_generic_kernel" in name:
+            by.setdefault(name.split("(")[0].replace("void ", ""), []).append((t1 - t0) / 1e6)
+    if not by:
+        return
+    print()
+    print("| stage sweep kernel | launches | executed (>= 5 % of the longest) | executed average ms | "
+          "others average ms |")
+    print("|---|---|---|---|---|")
+    for name, d in sorted(by.items()):
+        cut = 0.05 * max(d)
+        ex = [v for v in d if v >= cut]
+        rest = [v for v in d if v < cut]
+        print(f"| `{name}` | {len(d)} | {len(ex)} | {np.mean(ex):.4f} | "
+              f"{np.mean(rest) if rest else 0.0:.4f} |")
+    allex = [v for d in by.values() for v in d if v >= 0.05 * max(d)]
+    print(f"\nall executed stage sweep launches: {len(allex)}, average {np.mean(allex):.4f} ms")
 
 
 def run_loop_baseline(lbx, torch, nsteps):
@@ -380,58 +473,154 @@ def run_loop_baseline(lbx, torch, nsteps):
             "sample": f"16 states one by one, streaming path, {nsteps} of 10000 steps, time x{scale:g}"}
 
 
-def run_cpu_apply_baseline(workload, apply_equivalents, scale):
-    """The oracle's operator-form apply of M(t) on one state of a large
-    workload, timed once on one core and extrapolated to a whole gradient
-    evaluation (applications of M per evaluation on the GPU path)."""
+CPU_PROCS_MAX = 16        # the host-core share of one GPU on the box
+CPU_PROC_BYTES = {5: 6 << 30, 2: 1 << 30}   # host memory one oracle worker of a workload may hold
+
+
+def host_info():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count()
+    mem = None
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemAvailable"):
+                    mem = int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": aff, "mem_available": mem}
+
+
+def cpu_procs(workload, info):
+    n = min(CPU_PROCS_MAX, info["affinity"] or 1)
+    if info["mem_available"]:
+        n = min(n, max(1, int(0.5 * info["mem_available"] // CPU_PROC_BYTES[workload])))
+    return n
+
+
+def _oracle_worker(kind, tasks, barrier, out):
+    """One CPU process: prepares its tasks, waits for the others, then times
+    the oracle on them (one BLAS thread, the oracle's own setting)."""
     import oracle
-    from threadpoolctl import threadpool_limits
-    from workloads import make_config
-    p = make_config(workload)
-    s = p.systems[0]
-    N = s.N
-    rng = np.random.default_rng(1)
-    x = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
-    with threadpool_limits(1):
+    from workloads import make_config, truncate_steps
+    if kind == "apply5":
+        p = make_config(5)
+        s = p.systems[0]
+        xs = []
+        for seed in tasks:
+            rng = np.random.default_rng(seed)
+            xs.append(rng.standard_normal((s.N, s.N)) + 1j * rng.standard_normal((s.N, s.N)))
+        barrier.wait()
         t0 = time.perf_counter()
-        oracle.lindbladian(s, p.alpha[0], 41.0, x)
-        el = time.perf_counter() - t0
-    per_eval = el * apply_equivalents * scale * p.rho0[0].shape[0]
-    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"one operator-form apply of M on one state ({el:.1f} s), extrapolated x"
-                      f"{apply_equivalents * scale:.0f} applies per state and evaluation"}
+        for x in xs:
+            oracle.lindbladian(s, p.alpha[0], 41.0, x)
+    else:
+        # the whole 16-state evaluation per task (the oracle solves all states
+        # of a system together)
+        nsteps = kind[1]
+        p = truncate_steps(make_config(2), nsteps)
+        s = p.systems[0]
+        barrier.wait()
+        t0 = time.perf_counter()
+        for _ in tasks:
+            oracle.value_and_gradient(s, p.alpha[0], p.rho0[0], p.rhotar[0], p.beta[0], p.kind)
+    out.put(time.perf_counter() - t0)
+
+
+def run_oracle_pool(kind, tasks, nproc):
+    """Runs the tasks over nproc fresh processes (round robin) that start
+    together; returns the wall time of the slowest."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(nproc)
+    out = ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker, args=(kind, tasks[k::nproc], barrier, out)) for k in range(nproc)]
+    for pr in procs:
+        pr.start()
+    times = [out.get(timeout=600) for _ in procs]
+    for pr in procs:
+        pr.join()
+        if pr.exitcode != 0:
+            raise RuntimeError(f"oracle worker ended with {pr.exitcode}")
+    return max(times)
+
+
+def run_cpu_apply_baseline(apply_equivalents, scale):
+    """The oracle's operator-form apply of M(t) on the eight-qutrit state, one
+    apply per process on its own state, all processes at once, extrapolated to
+    whole gradient evaluations by the applications of M per evaluation that
+    the GPU path makes (one per stage sweep and one per gradient integrand)."""
+    info = host_info()
+    n = cpu_procs(5, info)
+    wall = run_oracle_pool("apply5", list(range(1, n + 1)), n)
+    applies = apply_equivalents * scale
+    return {"value": n / (wall * applies), "unit": "evals/s", "cores": n, "kind": "oracle",
+            "sample": f"{n} processes, each one operator-form apply of M(t) on its own eight-qutrit state, "
+                      f"all at once ({wall:.1f} s wall); each process extrapolated x{applies:.0f} applies per "
+                      f"gradient evaluation (value = {n} evaluations in parallel)",
+            **info}
 
 
 def run_cpu_baseline(nsteps):
-    import oracle
-    from workloads import make_config, truncate_steps
-    p = truncate_steps(make_config(2), nsteps)
-    s = p.systems[0]
-    t0 = time.perf_counter()
-    oracle.value_and_gradient(s, p.alpha[0], p.rho0[0], p.rhotar[0], p.beta[0], p.kind)
-    el = time.perf_counter() - t0
+    """The oracle's two-transmon gradient (all 16 states), one evaluation per
+    process on every process of the share at once, over nsteps of the 10000
+    steps, scaled to the horizon."""
+    from workloads import make_config
+    info = host_info()
+    n = cpu_procs(2, info)
+    wall = run_oracle_pool(("grad2", nsteps), list(range(n)), n)
     scale = make_config(2).systems[0].NT / nsteps
-    return {"value": 1.0 / (el * scale), "unit": "evals/s", "cores": oracle.lindblad.ORACLE_BLAS_THREADS,
-            "kind": "oracle",
-            "sample": f"two-transmon CNOT, 16 states, {nsteps} of 10000 steps ({el:.1f} s), scaled x{scale:g}"}
+    return {"value": n / (wall * scale), "unit": "evals/s", "cores": n, "kind": "oracle",
+            "sample": f"two-transmon CNOT (16 states), {n} processes each one evaluation over {nsteps} of 10000 "
+                      f"steps, all at once ({wall:.1f} s wall), scaled x{scale:g} (value = {n} evaluations in "
+                      f"parallel)", **info}
+
+
+def c2_summary(lbx, torch, args):
+    """The two-transmon CNOT gradient (LDS-resident path) with its per-state
+    loop speedup and CPU baseline, reported beside the headline."""
+    res = run_gradient_bench(lbx, torch, args.c2_steps, 3, 2, 0)
+    out = {"workload": WORKLOADS[2], "value": res["value"], "unit": "evals/s", "ms_per_eval": res["ms_per_step"],
+           "steps": args.c2_steps, "roofline": res["roofline"], "sweeps_per_step_mean": res["sweeps_per_step_mean"],
+           "G": res["G"]}
+    if not args.no_loop:
+        print("[bench] two-transmon per-state loop", file=sys.stderr, flush=True)
+        lb = run_loop_baseline(lbx, torch, args.loop_steps)
+        lb["speedup"] = res["value"] / lb["evals_per_s"]
+        out["per_state_loop"] = lb
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10, help="timed evaluations of the headline workload")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=HEADLINE, choices=[1, 2, 3, 4, 5],
+                    help="headline workload (default 5, the eight-qutrit ring)")
+    ap.add_argument("--window", "--sample-steps", type=int, default=-1, dest="window",
+                    help="time steps of the horizon evaluated per bench step (0: all; default 142 for "
+                         "workload 5, 500 for 3, all otherwise); the rate is scaled to the full horizon")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--c2-steps", type=int, default=20)
     ap.add_argument("--loop-steps", type=int, default=250)
-    ap.add_argument("--cpu-steps", type=int, default=800)
+    ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-apply", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
-                    help="workload: 2 (default, two-transmon CNOT) or 1, 3, 4, 5")
-    ap.add_argument("--sample-steps", type=int, default=0,
-                    help="time only the first S time steps of the workload and scale to the full "
-                         "horizon (for workloads whose single evaluation runs for minutes)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the launches whose HBM counters profiles/traffic.json records")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -460,41 +649,54 @@ def main():
     if args.traffic_probe:
         print(json.dumps(run_traffic_probe(lbx, torch)), flush=True)
         return
-    print("[bench] gradient evaluations", file=sys.stderr, flush=True)
-    res = run_gradient_bench(lbx, torch, args.steps, args.warmup, args.workload, args.sample_steps)
+    w = args.workload
+    window = DEFAULT_WINDOW.get(w, 0) if args.window < 0 else args.window
+    print(f"[bench] workload {w} gradient evaluations (window {window or 'all'})", file=sys.stderr, flush=True)
+    res = run_gradient_bench(lbx, torch, args.steps, args.warmup, w, window)
+    print(f"[bench] {res['value']:.4g} evals/s, {res['window_ms']:.1f} ms per bench step", file=sys.stderr,
+          flush=True)
     line = {
         "metric": "forward+adjoint gradient evals/sec; lindblad_apply HBM GB/s vs peak",
         "value": res["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": res["window_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "global_batch": res["states"],
-                   "parallelism": "single GPU"},
+        "config": {"workload": WORKLOADS[w], "global_batch": res["states"], "parallelism": "single GPU",
+                   "step": ("one gradient evaluation of the full-size system over a window of the horizon; "
+                            "value = evaluations of the whole horizon per second")
+                   if res["scale"] != 1 else "one gradient evaluation",
+                   "window_steps": round(WORKLOADS_NT[w] / res["scale"]), "horizon_steps": WORKLOADS_NT[w],
+                   "ckpt_every": res["ckpt_every"]},
         "sample": res["sample"],
+        "ms_per_eval": res["ms_per_step"],
         "roofline": res["roofline"],
         "detail": {"G": res["G"], "grad_max": res["grad_norm"],
                    "sweeps_per_step_mean": res["sweeps_per_step_mean"],
-                   "kernel_avg_ms": res["kernel_ms"], "kernel_ms_per_eval": res["kernel_total_ms"],
+                   "kernel_avg_ms": res["kernel_ms"], "kernel_ms_per_step": res["kernel_total_ms"],
                    "sweep_GBps_timed_region": res["sweep_GBps_timed_region"],
                    "autotune": res["autotune"]},
     }
-    if args.workload != 2:
-        args.no_apply = args.no_apply or args.workload != 5
-        args.no_loop = True
-        if args.workload == 5 and not args.no_cpu and res["apply_equivalents"]:
-            print("[bench] cpu baseline (oracle apply, extrapolated)", file=sys.stderr, flush=True)
-            line["cpu_baseline"] = run_cpu_apply_baseline(5, res["apply_equivalents"], res["scale"])
-        args.no_cpu = True
-    if not args.no_apply:
+    if w == 5 and not args.no_apply:
         print("[bench] lindblad_apply 8 qutrits", file=sys.stderr, flush=True)
         line["apply_roofline"] = run_apply_bench(lbx, torch, args.apply_reps)
-    if not args.no_loop:
+    if w != 2 and not args.no_c2:
+        print("[bench] two-transmon gradient", file=sys.stderr, flush=True)
+        line["c2_cnot"] = c2_summary(lbx, torch, args)
+    elif w == 2 and not args.no_loop:
         print("[bench] per-state loop baseline", file=sys.stderr, flush=True)
         lb = run_loop_baseline(lbx, torch, args.loop_steps)
         lb["speedup"] = res["value"] / lb["evals_per_s"]
         line["per_state_loop"] = lb
     if not args.no_cpu:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = run_cpu_baseline(args.cpu_steps)
+        if w == 5 and res["apply_equivalents"]:
+            print("[bench] cpu baseline (oracle applies, all processes at once)", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = run_cpu_apply_baseline(res["apply_equivalents"], res["scale"])
+        if w == 2 or "c2_cnot" in line:
+            print("[bench] cpu baseline (two-transmon oracle, one process per state)", file=sys.stderr, flush=True)
+            cb = run_cpu_baseline(args.cpu_steps)
+            if w == 2:
+                line["cpu_baseline"] = cb
+            else:
+                line["c2_cnot"]["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 

@@ -29,12 +29,17 @@ def _csv(path, rows):
 
 def test_traffic_summary_calibrates_against_the_copy(tmp_path, capsys):
     copy_bytes = 1024 * 1000
-    tile = "void lbx::tile_kernel<3, 8, 3, 3, false, 0, 256>(lbx::SysDev const*)"
+    tile = "void lbx::tile_kernel<3, 8, 3, 3, false, 256>(lbx::SysDev const*)"
+    sweep = "void lbx::sweep_tile_kernel<3, 8, 3, 3, true, 256>(lbx::StepArgs, int)"
     _csv(tmp_path / "f.csv", [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 500.0),
                               ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 2.0),
-                              (tile, "FETCH_SIZE", 3000.0), (tile, "FETCH_SIZE", 5000.0)])
+                              (tile, "FETCH_SIZE", 3000.0), (tile, "FETCH_SIZE", 5000.0),
+                              (sweep, "FETCH_SIZE", 6000.0), (sweep, "FETCH_SIZE", 2.0),
+                              (sweep, "FETCH_SIZE", 4000.0)])
     _csv(tmp_path / "w.csv", [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 1000.0),
-                              (tile, "WRITE_SIZE", 700.0), (tile, "WRITE_SIZE", 900.0)])
+                              (tile, "WRITE_SIZE", 700.0), (tile, "WRITE_SIZE", 900.0),
+                              (sweep, "WRITE_SIZE", 1500.0), (sweep, "WRITE_SIZE", 0.0),
+                              (sweep, "WRITE_SIZE", 500.0)])
     out = tmp_path / "traffic.json"
     bench.traffic_summary(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), copy_bytes, str(out))
     table = json.loads(out.read_text())
@@ -47,6 +52,12 @@ def test_traffic_summary_calibrates_against_the_copy(tmp_path, capsys):
     assert rec["dispatches"] == [2, 2]
     assert rec["source_sha"] == bench.source_sha(bench.APPLY_SOURCES)
     assert "apply_kernel_adjoint_ki33" not in table
+    # the stage sweep averages its executed launches only (the sweep kernel's
+    # name must not count as the apply kernel's either)
+    sw = table["stage_sweep_c5_ki33"]
+    assert sw["dispatches"] == [2, 2]
+    assert sw["fetch_bytes"] == pytest.approx(2.0 * 5000.0 * 1024)
+    assert sw["write_bytes"] == pytest.approx(1000.0 * 1024)
     # the lookup honours the source hash
     assert bench.measured_traffic("apply_kernel_forward_ki33", bench.APPLY_SOURCES, str(out)) == \
         pytest.approx(rec["bytes_per_launch"])
@@ -76,3 +87,31 @@ def test_cost_model_of_the_two_transmon_workload():
     assert grad == pytest.approx(62.0)
     ctl, jump = bench.neighbour_counts((3,))
     assert ctl == pytest.approx(4 * 2 / 3) and jump == pytest.approx(4 / 9)
+
+
+def test_window_checkpoints_follow_the_full_horizon():
+    from workloads import make_config
+    # eight qutrits: every system streams, so the full run's automatic
+    # interval ceil(sqrt(5000)) = 71 is made explicit for a window
+    assert bench.window_ckpt(make_config(5)) == 71
+    # five qutrits carry their own interval
+    assert bench.window_ckpt(make_config(4)) == 200
+    # the uneven batch mixes LDS-resident systems: automatic
+    assert bench.window_ckpt(make_config(3)) == 0
+
+
+def test_cpu_process_count_respects_share_and_memory():
+    info = {"affinity": 64, "mem_available": 200 << 30}
+    assert bench.cpu_procs(5, info) == 16
+    info = {"affinity": 64, "mem_available": 30 << 30}
+    assert bench.cpu_procs(5, info) == 2
+    info = {"affinity": 4, "mem_available": None}
+    assert bench.cpu_procs(2, info) == 4
+    h = bench.host_info()
+    assert h["nproc"] >= 1 and h["affinity"] >= 1
+
+
+def test_oracle_pool_runs_states_in_separate_processes():
+    # three two-transmon evaluations over two processes, 20 steps each
+    wall = bench.run_oracle_pool(("grad2", 20), [0, 1, 2], 2)
+    assert 0.0 < wall < 60.0
