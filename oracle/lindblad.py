@@ -298,13 +298,20 @@ def lindbladian_entries(sys, alpha, t, x, rows, cols, adjoint=False):
 # Implicit midpoint rule, App. A
 # ----------------------------------------------------------------------------
 
+# Bytes the GMRES Krylov basis may take: the restart length shrinks for very
+# large systems (it sets the solver's memory, not its converged result, which
+# the residual check below fixes).
+GMRES_BASIS_BYTES = 16 << 30
+
+
 def _gmres_solve(matvec, b, n):
     """Solve A x = b with GMRES plus one refinement pass (rtol ~1e-15)."""
     A = spla.LinearOperator((n, n), matvec=matvec, dtype=np.complex128)
-    x, info = spla.gmres(A, b, rtol=1e-14, atol=0.0, restart=80, maxiter=50)
+    restart = int(min(80, max(10, GMRES_BASIS_BYTES // (16 * n) - 1)))
+    x, info = spla.gmres(A, b, rtol=1e-14, atol=0.0, restart=restart, maxiter=50)
     r = b - matvec(x)
     if np.linalg.norm(r) > 0:
-        dx, info2 = spla.gmres(A, r, rtol=1e-10, atol=0.0, restart=80, maxiter=50)
+        dx, info2 = spla.gmres(A, r, rtol=1e-10, atol=0.0, restart=restart, maxiter=50)
         x = x + dx
     res = np.linalg.norm(b - matvec(x)) / max(np.linalg.norm(b), 1e-300)
     if res > 1e-13:
