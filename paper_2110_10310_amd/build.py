@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbx.so")
 SOURCES = ["api.hip", "kernels_stream.hip", "kernels_lds.hip", "kernels_lds_fast.hip", "kernels_tile.hip",
-           "kernels_step.hip", "noalloc.hip"]
+           "kernels_step.hip", "kernels_krylov.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for every HIP translation unit.

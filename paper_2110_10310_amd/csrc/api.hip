@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -92,7 +93,8 @@ int status_bits_code(int32_t s) {
   if (s & LB_STATUS_NONFINITE) return fail(LB_ENONFINITE, "an objective is not finite");
   if (s & LB_STATUS_THETA)
     return fail(LB_EUNSUPPORTED,
-                "a stage-solve contraction bound is >= 0.5 (step or control amplitude too large)");
+                "a stage-solve contraction bound is >= 0.5 (step or control amplitude too large); calls with a "
+                "workspace in LB_OPT_SYNC mode solve such steps with GMRES");
   if (s & LB_STATUS_NOCONV) return fail(LB_EUNSUPPORTED, "a stage solve did not converge within the sweep cap");
   if (s & LB_STATUS_RETRY)
     return fail(LB_EUNSUPPORTED, "a streamed step needed more stage sweeps than were launched; repeat the call "
@@ -374,6 +376,7 @@ struct Layout {
   size_t zhist = 0, gpart = 0;
   size_t q0 = 0, q1 = 0, z0 = 0, z1 = 0, zsf = 0, ringf = 0, zsa = 0, ringa = 0, zh = 0, qh0 = 0, qh1 = 0,
          seg = 0, st_gpart = 0, st_gfin = 0, slots = 0, kstep = 0;
+  size_t kry = 0, kpart = 0;  // Krylov fallback: vectors and reduction scratch
   size_t total = 0;
   TrajLayout T;
   int H = 0;
@@ -381,7 +384,10 @@ struct Layout {
   int gbatch = 1;     // steps whose partial rows are reduced by one launch
 };
 
-Layout layout(const lb_plan *p, const lbx_opts &o, int op, const BatchMeta &m, int ckpt_every) {
+// krylov: the layout of the Krylov fallback (no increment history; room for
+// the GMRES vectors of the streamed batch).
+Layout layout(const lb_plan *p, const lbx_opts &o, int op, const BatchMeta &m, int ckpt_every,
+              bool krylov = false) {
   Layout L;
   size_t cur = 0;
   auto take = [&](size_t bytes) {
@@ -392,7 +398,7 @@ Layout layout(const lb_plan *p, const lbx_opts &o, int op, const BatchMeta &m, i
   const int nsys = (int)p->sys.size();
   const size_t E = (size_t)m.st_entries * sizeof(double2);
   const bool st = !m.segs.empty();
-  L.H = st && op != LB_OP_IMR_STEP ? o.history : 0;
+  L.H = st && op != LB_OP_IMR_STEP && !krylov ? o.history : 0;
   L.status = take(sizeof(int32_t));
   L.ctab = take((size_t)p->ctab_total * sizeof(double2));
   L.ktab = take((size_t)nsys * p->NT * 2 * sizeof(int32_t));
@@ -405,6 +411,10 @@ Layout layout(const lb_plan *p, const lbx_opts &o, int op, const BatchMeta &m, i
   L.kstep = take((size_t)2 * nsys * sizeof(int32_t));
   L.z0 = take(st ? E : 0);
   L.z1 = take(st ? E : 0);
+  if (krylov && st) {
+    L.kry = take((size_t)KRY_VECTORS * E);
+    L.kpart = take(kry_part_bytes());
+  }
   L.T = traj_layout(p, m, ckpt_every);
   if (op == LB_OP_IMR_STEP) {
     L.total = cur;
@@ -609,8 +619,133 @@ struct PassHist {
 
 // One implicit-midpoint step of every streamed system, q -> out at step j:
 // the sweep launches of the stage solve (each runs only if the step needs it).
+// Restarted GMRES on the stage system of step j of the whole streamed batch
+// (App. A eq. linsystem_primal; eq. linsystem_adjoint when adj), right
+// preconditioned by W = (1 - h D)^{-1}, from y = q (z = W q, the start of the
+// splitting iteration).  Classical Gram-Schmidt twice per Arnoldi step;
+// complex Givens rotations on the host.  Ends when the true residual
+// ||q - A z|| is at most KRY_RTOL ||q|| (or, after KRY_RESTARTS cycles,
+// KRY_ACCEPT ||q||), then writes out = 2 z - q and zh = z like the last
+// sweep.  Synchronises the stream at every Arnoldi step.
+constexpr double KRY_RTOL = 1e-15;
+constexpr double KRY_ACCEPT = 1e-13;
+constexpr int KRY_RESTARTS = 60;
+
+int krylov_step(const StreamCtx &c, int j, bool adj, const double2 *q, double2 *out, double2 *zh, hipStream_t st) {
+  typedef std::complex<double> cd;
+  const lb_plan *p = c.p;
+  const BatchMeta &m = *c.m;
+  const Layout &L = *c.L;
+  const int64_t E = m.st_entries;
+  if (!L.kry) return fail(LB_EINVAL, "internal: Krylov step without its workspace");
+  double2 *V = (double2 *)(c.w + L.kry);
+  double2 *Y = V + (int64_t)(KRY_M + 1) * E;
+  double2 *U = V + (int64_t)(KRY_M + 2) * E;
+  double2 *part = (double2 *)(c.w + L.kpart);
+  double2 *dres = part + (size_t)1024 * KRY_MAXV;
+  const KryArgs A{p->d_sys, p->d_E, p->d_desc, (const double2 *)(c.w + L.ctab), m.d_segs, (int)m.segs.size(),
+                  m.st_blocks, j};
+  double2 hbuf[KRY_MAXV];
+  auto dots = [&](const double2 *Vb, int n, const double2 *x, cd *res) -> int {
+    if (int rc = launch_kry_dots(Vb, E, n, x, E, part, dres, st)) return rc;
+    LBX_HIP(hipMemcpyAsync(hbuf, dres, n * sizeof(double2), hipMemcpyDeviceToHost, st));
+    LBX_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) res[i] = cd(hbuf[i].x, hbuf[i].y);
+    return LB_OK;
+  };
+  auto norm = [&](const double2 *x, double *r) -> int {
+    cd v;
+    if (int rc = dots(x, 1, x, &v)) return rc;
+    *r = std::sqrt(std::max(0.0, v.real()));
+    return LB_OK;
+  };
+  // B x into y (q - B x when q is given)
+  auto bapply = [&](const double2 *x, const double2 *qq, double2 *y) -> int {
+    if (int rc = launch_kry_weight(A, adj, x, U, st)) return rc;
+    return launch_kry_apply(A, adj, U, qq, y, st);
+  };
+  auto axpy = [&](int n, const cd *cf, double s, double2 *x) -> int {
+    KryCoef k{};
+    k.n = n;
+    for (int i = 0; i < n; ++i) k.c[i] = make_double2(cf[i].real(), cf[i].imag());
+    return launch_kry_axpy(V, E, k, s, x, E, st);
+  };
+  int rc;
+  double qn;
+  if ((rc = norm(q, &qn))) return rc;
+  LBX_HIP(hipMemcpyAsync(Y, q, (size_t)E * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  for (int cyc = 0;; ++cyc) {
+    double beta;
+    if ((rc = bapply(Y, q, V)) || (rc = norm(V, &beta))) return rc;
+    if (beta <= KRY_RTOL * qn) break;
+    if (cyc == KRY_RESTARTS) {
+      if (beta <= KRY_ACCEPT * qn) break;
+      return fail(LB_EUNSUPPORTED, "step " + std::to_string(j) + ": the Krylov stage solve did not converge (" +
+                                       "relative residual " + std::to_string(beta / qn) + ")");
+    }
+    if ((rc = axpy(0, nullptr, 1.0 / beta, V))) return rc;
+    cd H[KRY_M + 1][KRY_M], sn[KRY_M], g[KRY_M + 1];
+    double cr[KRY_M];
+    for (int i = 0; i <= KRY_M; ++i) g[i] = 0.0;
+    g[0] = beta;
+    int kd = 0;
+    for (int k = 0; k < KRY_M; ++k) {
+      double2 *W = V + (int64_t)(k + 1) * E;
+      cd h1[KRY_MAXV], h2[KRY_MAXV];
+      if ((rc = bapply(V + (int64_t)k * E, nullptr, W))) return rc;
+      if ((rc = dots(V, k + 1, W, h1)) || (rc = axpy(k + 1, h1, 1.0, W))) return rc;
+      if ((rc = dots(V, k + 1, W, h2)) || (rc = axpy(k + 1, h2, 1.0, W))) return rc;
+      double hn;
+      if ((rc = norm(W, &hn))) return rc;
+      for (int i = 0; i <= k; ++i) H[i][k] = h1[i] + h2[i];
+      // earlier rotations, then the one that removes H[k+1][k] = hn
+      for (int i = 0; i < k; ++i) {
+        const cd x = H[i][k], y = H[i + 1][k];
+        H[i][k] = cr[i] * x + sn[i] * y;
+        H[i + 1][k] = -std::conj(sn[i]) * x + cr[i] * y;
+      }
+      const cd a = H[k][k];
+      const double ta = std::abs(a), r = std::hypot(ta, hn);
+      if (r == 0.0) {  // breakdown with a zero column: the space is exhausted
+        kd = k;
+        break;
+      }
+      if (ta == 0.0) {
+        cr[k] = 0.0;
+        sn[k] = 1.0;
+        H[k][k] = hn;
+      } else {
+        cr[k] = ta / r;
+        sn[k] = (a / ta) * hn / r;
+        H[k][k] = (a / ta) * r;
+      }
+      g[k + 1] = -std::conj(sn[k]) * g[k];
+      g[k] = cr[k] * g[k];
+      kd = k + 1;
+      if (hn > 0.0)
+        if ((rc = axpy(0, nullptr, 1.0 / hn, W))) return rc;
+      if (std::abs(g[k + 1]) <= KRY_RTOL * qn || hn == 0.0) break;
+    }
+    // y = R^{-1} g; Y += sum y_i V_i
+    cd yv[KRY_MAXV];
+    for (int i = kd - 1; i >= 0; --i) {
+      cd sacc = g[i];
+      for (int l = i + 1; l < kd; ++l) sacc -= H[i][l] * yv[l];
+      yv[i] = sacc / H[i][i];
+    }
+    for (int i = 0; i < kd; ++i) yv[i] = -yv[i];
+    if (kd > 0)
+      if ((rc = axpy(kd, yv, 1.0, Y))) return rc;
+  }
+  return launch_kry_finish(A, adj, Y, q, out, zh, st);
+}
+
 int stream_step(const StreamCtx &c, int j, bool adj, const double2 *q, double2 *out, PassHist &ph, double2 *zh,
                 hipStream_t st) {
+  if (c.kst && (*c.kst)[j] < 0) {  // Krylov fallback step
+    ph.n++;
+    return krylov_step(c, j, adj, q, out, zh, st);
+  }
   StepArgs A = c.base();
   A.j = j;
   A.q = q;
@@ -642,9 +777,11 @@ int stream_step(const StreamCtx &c, int j, bool adj, const double2 *q, double2 *
 
 // A-priori sweep counts from q of every step (the largest over the streamed
 // systems), read on the host: the counts of a call repeated after
-// LB_STATUS_RETRY.  Synchronises the stream.
+// LB_STATUS_RETRY.  With `krylov` a step whose contraction bound is >= 0.5
+// for any streamed system gets -1 (solved by krylov_step); otherwise such a
+// step is an error.  Synchronises the stream.
 int apriori_counts(const lb_plan *p, const BatchMeta &m, const int32_t *d_ktab, std::vector<int32_t> &kst,
-                   hipStream_t st) {
+                   hipStream_t st, bool krylov = false) {
   const size_t n = p->sys.size() * (size_t)p->NT * 2;
   std::vector<int32_t> k(n);
   LBX_HIP(hipMemcpyAsync(k.data(), d_ktab, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -653,11 +790,15 @@ int apriori_counts(const lb_plan *p, const BatchMeta &m, const int32_t *d_ktab, 
   for (const auto &sg : m.segs)
     for (int j = 0; j < p->NT; ++j) {
       const int kj = k[((size_t)sg.sys * p->NT + j) * 2 + 1];
-      if (kj < 1)
-        return fail(LB_EUNSUPPORTED, "system " + std::to_string(sg.sys) + " step " + std::to_string(j) +
-                                         ": the stage-solve contraction bound is >= 0.5 (step or control "
-                                         "amplitude too large)");
-      kst[j] = std::max(kst[j], kj);
+      if (kj < 1) {
+        if (!krylov)
+          return fail(LB_EUNSUPPORTED, "system " + std::to_string(sg.sys) + " step " + std::to_string(j) +
+                                           ": the stage-solve contraction bound is >= 0.5 (step or control "
+                                           "amplitude too large)");
+        kst[j] = -1;
+      } else if (kst[j] >= 0) {
+        kst[j] = std::max(kst[j], kj);
+      }
     }
   return LB_OK;
 }
@@ -739,25 +880,52 @@ int call_end(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layo
   return LB_OK;
 }
 
-// Runs attempt(kst) (kst NULL: device-side counts).  In LB_OPT_SYNC mode a
-// step that needed more sweeps than were launched makes the call run once
-// more with the a-priori counts of every step; the result is the status.
-template <class Attempt>
-int run_call(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w, hipStream_t st,
-             Attempt attempt) {
+// A call's batch metadata and workspace layout: the usual ones, or those of
+// the Krylov fallback (every system streamed, GMRES vectors, no history).
+struct CallPlan {
+  BatchMeta *m = nullptr;
+  Layout L;
+};
+
+// Runs attempt(o, plan, kst, bits) (kst NULL: device-side counts).  In
+// LB_OPT_SYNC mode:
+// * a step whose stage-solve contraction bound is >= 0.5 (LB_STATUS_THETA)
+//   makes the call run once more in the Krylov fallback: fallback(&plan)
+//   gives its metadata and layout, steps with the bound below 0.5 run their
+//   a-priori sweep counts and the others restarted GMRES;
+// * a step that needed more sweeps than were launched (LB_STATUS_RETRY)
+//   makes the call run once more with the a-priori counts of every step.
+// The result is the status of the last run.
+template <class Attempt, class Fallback>
+int run_call(const lb_plan *p, const lbx_opts &o, const CallPlan &cp, size_t ws_bytes, char *w, hipStream_t st,
+             Attempt attempt, Fallback fallback) {
   int32_t bits = 0;
-  int rc = attempt(nullptr, &bits);
+  int rc = attempt(o, cp, nullptr, &bits);
   if (rc || !o.sync) return rc;
-  if ((bits & LB_STATUS_RETRY) && !(bits & (LB_STATUS_THETA | LB_STATUS_NONFINITE))) {
+  if (bits & LB_STATUS_THETA) {
+    CallPlan fp;
+    if ((rc = fallback(&fp))) return rc;
+    if (ws_bytes < fp.L.total)
+      return fail(LB_ENOMEM, "workspace too small for the Krylov fallback of this call (size it with "
+                             "lb_workspace_bytes)");
     std::vector<int32_t> kst;
-    if ((rc = apriori_counts(p, m, (const int32_t *)(w + L.ktab), kst, st))) return rc;
-    if ((rc = attempt(&kst, &bits))) return rc;
+    // the tables of the first run (same offsets in both layouts)
+    if ((rc = apriori_counts(p, *fp.m, (const int32_t *)(w + cp.L.ktab), kst, st, true))) return rc;
+    lbx_opts of = o;
+    of.graph_steps = 0;  // the Krylov steps synchronise
+    bits = 0;
+    if ((rc = attempt(of, fp, &kst, &bits))) return rc;
+    return status_code(bits);
+  }
+  if ((bits & LB_STATUS_RETRY) && !(bits & LB_STATUS_NONFINITE)) {
+    std::vector<int32_t> kst;
+    if ((rc = apriori_counts(p, *cp.m, (const int32_t *)(w + cp.L.ktab), kst, st))) return rc;
+    bits = 0;
+    if ((rc = attempt(o, cp, &kst, &bits))) return rc;
   }
   return status_code(bits);
 }
 
-// Forward pass of every system: LDS-resident items keep every state in the
-// trajectory (when traj is not NULL), streamed systems keep checkpoints.
 int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w,
                 const double *alpha, const double2 *rho0, double2 *rhoT, char *traj, bool prof,
                 const std::vector<int32_t> *kst, hipStream_t st) {
@@ -1133,7 +1301,12 @@ extern "C" int lb_workspace_bytes(const lb_plan *p, int32_t op, const int32_t *b
   // imr_step always streams; only the trajectory-keeping operations honour ckpt_every.
   const bool small = op != LB_OP_IMR_STEP && streams_small(ckpt_every);
   if (int rc = build_batch(p, o, batch_per_sys, small, &m, op == LB_OP_IMR_STEP ? 2 : -1)) return rc;
-  *bytes = layout(p, o, op, *m, ckpt_every).total;
+  const int ck = op == LB_OP_IMR_STEP ? 1 : ckpt_every;
+  *bytes = layout(p, o, op, *m, ck).total;
+  // room for the Krylov fallback (every system streamed)
+  BatchMeta *mf;
+  if (int rc = build_batch(p, o, batch_per_sys, op != LB_OP_IMR_STEP, &mf, 2)) return rc;
+  *bytes = std::max(*bytes, layout(p, o, op, *mf, ck, true).total);
   return LB_OK;
 }
 
@@ -1146,6 +1319,10 @@ extern "C" int lb_trajectory_bytes(const lb_plan *p, const int32_t *batch_per_sy
   BatchMeta *m;
   if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &m)) return rc;
   *bytes = traj_layout(p, *m, ckpt_every).total;
+  // the layout of a trajectory written by the Krylov fallback
+  BatchMeta *mf;
+  if (int rc = build_batch(p, o, batch_per_sys, true, &mf, 2)) return rc;
+  *bytes = std::max(*bytes, traj_layout(p, *mf, ckpt_every).total);
   return LB_OK;
 }
 
@@ -1203,16 +1380,19 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
   hipStream_t st = (hipStream_t)stream;
   std::vector<int32_t> batch(nsys, 0);
   batch[sys] = B;
-  BatchMeta *m;
-  int rc = build_batch(p, o, batch.data(), false, &m, 2);
+  CallPlan cp;
+  int rc = build_batch(p, o, batch.data(), false, &cp.m, 2);
   if (rc) return rc;
-  const Layout L = layout(p, o, LB_OP_IMR_STEP, *m, 1);
-  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  cp.L = layout(p, o, LB_OP_IMR_STEP, *cp.m, 1);
+  if (ws_bytes < cp.L.total) return fail(LB_ENOMEM, "workspace too small");
   char *w = (char *)ws;
   const bool prof = o.profile;
-  double2 *ctab = (double2 *)(w + L.ctab);
   const double *abase = alpha - p->sys[sys].alpha_off;
-  auto attempt = [&](const std::vector<int32_t> *kst, int32_t *bits) -> int {
+  auto attempt = [&](const lbx_opts &oo, const CallPlan &c, const std::vector<int32_t> *kst, int32_t *bits) -> int {
+    const lbx_opts &o = oo;
+    const Layout &L = c.L;
+    BatchMeta *m = c.m;
+    double2 *ctab = (double2 *)(w + L.ctab);
     int rc = call_begin(p, L, w, prof, st);
     if (!rc)
       rc = launch_control_table(p, sys, 1, abase, ctab, 0, (int32_t *)(w + L.ktab), (double2 *)(w + L.ttab), o.tol,
@@ -1225,7 +1405,12 @@ extern "C" int imr_step(const lb_plan *p, int32_t sys, int32_t j, const double *
     if (rc) return rc;
     return call_end(p, o, *m, L, w, prof, st, bits);
   };
-  return run_call(p, o, *m, L, w, st, attempt);
+  auto fallback = [&](CallPlan *f) -> int {
+    f->m = cp.m;
+    f->L = layout(p, o, LB_OP_IMR_STEP, *cp.m, 1, true);
+    return LB_OK;
+  };
+  return run_call(p, o, cp, ws_bytes, w, st, attempt, fallback);
 }
 
 extern "C" int forward_solve(const lb_plan *p, const double *alpha, const void *rho0, void *rhoT,
@@ -1235,23 +1420,30 @@ extern "C" int forward_solve(const lb_plan *p, const double *alpha, const void *
   if (!alpha || !rho0 || !rhoT || !batch_per_sys || !ws) return fail(LB_EINVAL, "NULL argument");
   if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
   const lbx_opts o = snapshot(p);
-  BatchMeta *m;
+  CallPlan cp;
   const bool small = traj && streams_small(ckpt_every);
-  if (int rc = build_batch(p, o, batch_per_sys, small, &m)) return rc;
-  if (m->total_entries == 0) return LB_OK;
-  const Layout L = layout(p, o, LB_OP_FORWARD, *m, traj ? ckpt_every : 1);
-  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  if (int rc = build_batch(p, o, batch_per_sys, small, &cp.m)) return rc;
+  if (cp.m->total_entries == 0) return LB_OK;
+  const int ck = traj ? ckpt_every : 1;
+  cp.L = layout(p, o, LB_OP_FORWARD, *cp.m, ck);
+  if (ws_bytes < cp.L.total) return fail(LB_ENOMEM, "workspace too small");
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   const bool prof = o.profile;
-  auto attempt = [&](const std::vector<int32_t> *kst, int32_t *bits) -> int {
-    int rc = call_begin(p, L, w, prof, st);
+  auto attempt = [&](const lbx_opts &oo, const CallPlan &c, const std::vector<int32_t> *kst, int32_t *bits) -> int {
+    int rc = call_begin(p, c.L, w, prof, st);
     if (!rc)
-      rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, (double2 *)rhoT, (char *)traj, prof, kst, st);
+      rc = run_forward(p, oo, *c.m, c.L, w, alpha, (const double2 *)rho0, (double2 *)rhoT, (char *)traj, prof, kst,
+                       st);
     if (rc) return rc;
-    return call_end(p, o, *m, L, w, prof, st, bits);
+    return call_end(p, oo, *c.m, c.L, w, prof, st, bits);
   };
-  return run_call(p, o, *m, L, w, st, attempt);
+  auto fallback = [&](CallPlan *f) -> int {
+    if (int rc = build_batch(p, o, batch_per_sys, true, &f->m, 2)) return rc;
+    f->L = layout(p, o, LB_OP_FORWARD, *f->m, ck, true);
+    return LB_OK;
+  };
+  return run_call(p, o, cp, ws_bytes, w, st, attempt, fallback);
 }
 
 extern "C" int objective(const lb_plan *p, int32_t kind, const void *rhoT, const void *rhotar, const double *beta,
@@ -1288,26 +1480,34 @@ extern "C" int adjoint_backward(const lb_plan *p, int32_t kind, const double *al
   if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
   if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
   const lbx_opts o = snapshot(p);
-  BatchMeta *m;
-  if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &m)) return rc;
-  const Layout L = layout(p, o, LB_OP_BACKWARD, *m, ckpt_every);
-  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  CallPlan cp;
+  if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &cp.m)) return rc;
+  cp.L = layout(p, o, LB_OP_BACKWARD, *cp.m, ckpt_every);
+  if (ws_bytes < cp.L.total) return fail(LB_ENOMEM, "workspace too small");
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   const bool prof = o.profile;
-  auto attempt = [&](const std::vector<int32_t> *kst, int32_t *bits) -> int {
+  auto attempt = [&](const lbx_opts &oo, const CallPlan &c, const std::vector<int32_t> *kst, int32_t *bits) -> int {
+    const Layout &L = c.L;
     int rc = call_begin(p, L, w, prof, st);
     // The controls (and their tables) are rebuilt for this call.
     if (!rc)
       rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, (double2 *)(w + L.ctab), 0,
-                                (int32_t *)(w + L.ktab), (double2 *)(w + L.ttab), o.tol, st);
+                                (int32_t *)(w + L.ktab), (double2 *)(w + L.ttab), oo.tol, st);
     if (!rc)
-      rc = run_backward(p, o, *m, L, w, kind, alpha, (const char *)traj, (const double2 *)rhotar, beta, gamma2,
+      rc = run_backward(p, oo, *c.m, L, w, kind, alpha, (const char *)traj, (const double2 *)rhotar, beta, gamma2,
                         gscale, grad, prof, kst, st);
     if (rc) return rc;
-    return call_end(p, o, *m, L, w, prof, st, bits);
+    return call_end(p, oo, *c.m, L, w, prof, st, bits);
   };
-  return run_call(p, o, *m, L, w, st, attempt);
+  // A trajectory that forward_solve wrote in its Krylov fallback has the
+  // fallback's layout; this call meets the same bound and falls back too.
+  auto fallback = [&](CallPlan *f) -> int {
+    if (int rc = build_batch(p, o, batch_per_sys, true, &f->m, 2)) return rc;
+    f->L = layout(p, o, LB_OP_BACKWARD, *f->m, ckpt_every, true);
+    return LB_OK;
+  };
+  return run_call(p, o, cp, ws_bytes, w, st, attempt, fallback);
 }
 
 extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *alpha, const void *rho0,
@@ -1321,17 +1521,20 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
   if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
   if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
   const lbx_opts o = snapshot(p);
-  BatchMeta *m;
-  if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &m)) return rc;
-  const Layout L = layout(p, o, LB_OP_GRADIENT, *m, ckpt_every);
-  if (ws_bytes < L.total) return fail(LB_ENOMEM, "workspace too small");
+  CallPlan cp;
+  if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &cp.m)) return rc;
+  cp.L = layout(p, o, LB_OP_GRADIENT, *cp.m, ckpt_every);
+  if (ws_bytes < cp.L.total) return fail(LB_ENOMEM, "workspace too small");
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
-  char *traj = w + L.traj;
   const bool prof = o.profile;
-  // rho(T) goes to the caller's buffer, or to the workspace.
-  double2 *rhoT = rhoT_out ? (double2 *)rhoT_out : (double2 *)(w + L.rhoT);
-  auto attempt = [&](const std::vector<int32_t> *kst, int32_t *bits) -> int {
+  auto attempt = [&](const lbx_opts &oo, const CallPlan &c, const std::vector<int32_t> *kst, int32_t *bits) -> int {
+    const lbx_opts &o = oo;
+    const Layout &L = c.L;
+    BatchMeta *m = c.m;
+    char *traj = w + L.traj;
+    // rho(T) goes to the caller's buffer, or to the workspace.
+    double2 *rhoT = rhoT_out ? (double2 *)rhoT_out : (double2 *)(w + L.rhoT);
     int rc = call_begin(p, L, w, prof, st);
     if (!rc) rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, rhoT, traj, prof, kst, st);
     if (!rc)
@@ -1344,7 +1547,12 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
     if (rc) return rc;
     return call_end(p, o, *m, L, w, prof, st, bits);
   };
-  return run_call(p, o, *m, L, w, st, attempt);
+  auto fallback = [&](CallPlan *f) -> int {
+    if (int rc = build_batch(p, o, batch_per_sys, true, &f->m, 2)) return rc;
+    f->L = layout(p, o, LB_OP_GRADIENT, *f->m, ckpt_every, true);
+    return LB_OK;
+  };
+  return run_call(p, o, cp, ws_bytes, w, st, attempt, fallback);
 }
 
 extern "C" int lb_profile_read(const lb_plan *p, int32_t kernel, int64_t *launches, double *total_ms, int32_t reset) {

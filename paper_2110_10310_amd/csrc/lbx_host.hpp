@@ -182,6 +182,40 @@ int launch_sweep(const lb_plan *p, StepArgs &A, int kk, bool adj, int tile_sys, 
 // Clears the maxima slots of both parities of nsys systems.
 int launch_slots_clear(unsigned long long *slots, int nsys, hipStream_t st);
 
+// ---- Krylov stage solve of the streamed batch (steps with theta >= 0.5) ----
+constexpr int KRY_M = 10;             // restart length of GMRES
+constexpr int KRY_MAXV = KRY_M + 1;   // Krylov vectors of one cycle
+constexpr int KRY_VECTORS = KRY_M + 3;  // basis, solution and one work vector
+struct KryArgs {
+  const SysDev *sysv;
+  const double *Etab;
+  const uint64_t *desc;
+  const double2 *ctab;  // controls at the systems' offsets
+  const StreamSeg *segs;
+  int nseg;
+  int64_t nblk;
+  int j;  // step
+};
+struct KryCoef {
+  int n;
+  double2 c[KRY_MAXV];
+};
+// u = W x (W = (1 - h D)^{-1}, conjugated for the adjoint).
+int launch_kry_weight(const KryArgs &A, bool adj, const double2 *x, double2 *u, hipStream_t st);
+// y = u - h M u (M^+ for the adjoint), or q minus that when q is not NULL.
+int launch_kry_apply(const KryArgs &A, bool adj, const double2 *u, const double2 *q, double2 *y, hipStream_t st);
+// Device scratch of launch_kry_dots.
+size_t kry_part_bytes();
+// out[i] = <V_i, x> for i < n (V_i at V + i*stride), E entries.
+int launch_kry_dots(const double2 *V, int64_t stride, int n, const double2 *x, int64_t E, double2 *part,
+                    double2 *out, hipStream_t st);
+// x = s x - sum_i c_i V_i.
+int launch_kry_axpy(const double2 *V, int64_t stride, const KryCoef &c, double s, double2 *x, int64_t E,
+                    hipStream_t st);
+// z = W y, out = 2 z - q, zh = z (zh may be NULL).
+int launch_kry_finish(const KryArgs &A, bool adj, const double2 *y, const double2 *q, double2 *out, double2 *zh,
+                      hipStream_t st);
+
 // ---- launchers (each returns LB_OK or an error code) ----
 
 // Zeroes `bytes` (a multiple of 4) with a kernel.
