@@ -46,6 +46,12 @@
  * their work at the end and return that status as their code; with it off
  * they return as soon as the work is enqueued and lb_status() reads the
  * status later.  lindblad_apply and control_table never synchronise.
+ * Stage systems whose splitting iteration does not contract (a step with
+ * bound theta_j >= 0.5: a large step or control amplitude) are solved with
+ * restarted GMRES, as App. A solves every stage system: with LB_OPT_SYNC on
+ * a call that meets such a step runs once more with every system streamed,
+ * solving those steps with GMRES (a slower path that synchronises at every
+ * Krylov step); with it off, lb_status() reports LB_EUNSUPPORTED.
  * Options are copied when a call starts; concurrent calls on one plan (from
  * several threads or streams) need separate workspaces.
  *
@@ -163,20 +169,23 @@ int lb_plan_set_option(lb_plan *plan, int32_t option, double value);
  * small enough for the LDS-resident kernels; 1 keeps every state; c > 1
  * keeps every c-th state of every system (systems that would be
  * LDS-resident are streamed then, since those kernels keep every state).
- * The workspace begins with the call's status word (see lb_status). */
+ * The workspace begins with the call's status word (see lb_status).  The
+ * size covers the GMRES fallback of the call (every system streamed). */
 int lb_workspace_bytes(const lb_plan *plan, int32_t op, const int32_t *batch_per_sys,
                        int32_t ckpt_every, size_t *bytes);
 
 /* Bytes of the trajectory buffer that forward_solve fills and
- * adjoint_backward reads, for the batch and ckpt_every (as above). */
+ * adjoint_backward reads, for the batch and ckpt_every (as above), in the
+ * normal layout or that of the GMRES fallback (the larger of the two). */
 int lb_trajectory_bytes(const lb_plan *plan, const int32_t *batch_per_sys, int32_t ckpt_every,
                         size_t *bytes);
 
 /* Waits for `stream` and returns the status that the last call using the
  * workspace `ws` (DEVICE) raised on the device: LB_OK, LB_ENONFINITE (an
  * objective is not finite) or LB_EUNSUPPORTED (a step's stage-solve
- * contraction bound is >= 0.5, a stage solve hit its sweep cap, or a
- * streamed step needed more sweeps than were launched).  With ws NULL: the
+ * contraction bound is >= 0.5 in a call that could not fall back to GMRES,
+ * a stage solve hit its sweep cap, or a streamed step needed more sweeps
+ * than were launched).  With ws NULL: the
  * status of the last imr_step_noalloc call on the current device. */
 int lb_status(const lb_plan *plan, const void *ws, void *stream);
 
@@ -200,7 +209,7 @@ int lb_profile_work(const lb_plan *plan, int32_t kernel, int64_t *entry_sweeps);
  * iteration of the implicit-midpoint solve (App. A) contracts with a factor
  * theta_j that is known before the step, and the count is the number of
  * sweeps after which the contraction bound reaches LB_OPT_SOLVE_TOL.  A count
- * of -1 marks a step with theta_j >= 0.5, which every entry point rejects.
+ * of -1 marks a step with theta_j >= 0.5, solved with GMRES (see Streams).
  * The streaming kernels and the generic LDS-resident kernels run exactly
  * these counts; the specialised LDS-resident kernels start from an
  * extrapolation of the previous stage increments and stop on an
