@@ -96,7 +96,9 @@ extern "C" {
                               0: generic streaming kernels */
 #define LB_OPT_TILE_KI 4   /* block shape of the block-tiled kernels, 10*KR + KC with KR
                               (KC) row (column) digits inside a block; 0 (default): the
-                              shape listed first for the system */
+                              shape listed first for the system.  100 + KA (KA = 1..Q-1):
+                              the two-pass sweeps and apply, pass A over the KA least
+                              significant subsystems and pass B over the others */
 #define LB_OPT_GRAPH 5     /* > 0: streamed time loops are captured as HIP graphs of this
                               many steps and replayed (one graph launch per chunk);
                               0 (default): kernels are launched directly */

@@ -386,6 +386,13 @@ struct Layout {
 
 // krylov: the layout of the Krylov fallback (no increment history; room for
 // the GMRES vectors of the streamed batch).
+// Block shape of the gradient integrands of the tiled streamed system (the
+// two-pass sweeps use the system's first block shape), or 0: generic kernel.
+int grad_tile_k(const lb_plan *p, const BatchMeta &m) {
+  if (m.tile_sys < 0) return 0;
+  return m.tile_k >= LB_SPLIT_BASE ? tile_ki(p, m.tile_sys, 0) : m.tile_k;
+}
+
 Layout layout(const lb_plan *p, const lbx_opts &o, int op, const BatchMeta &m, int ckpt_every,
               bool krylov = false) {
   Layout L;
@@ -445,7 +452,7 @@ Layout layout(const lb_plan *p, const lbx_opts &o, int op, const BatchMeta &m, i
   L.qh1 = take(st ? E : 0);
   L.seg = take(st ? (size_t)std::max(0, L.T.c - 1) * E : 0);
   L.grows = std::max<int64_t>(
-      1, std::max<int64_t>(m.st_blocks, m.tile_sys >= 0 ? tile_grad_rows(p, m.tile_sys, m.tile_B, m.tile_k) : 0));
+      1, std::max<int64_t>(m.st_blocks, grad_tile_k(p, m) > 0 ? tile_grad_rows(p, m.tile_sys, m.tile_B, grad_tile_k(p, m)) : 0));
   // Up to a checkpoint interval of steps, within 256 MB of partial rows.
   const size_t row_bytes = (size_t)L.grows * 2 * QMAX * sizeof(double);
   L.gbatch = (int)std::max<int64_t>(1, std::min<int64_t>(L.T.c, (int64_t)((256u << 20) / row_bytes)));
@@ -1018,6 +1025,7 @@ int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const 
     int pend = 0, jtop = 0;
     int64_t rows = 0;
     const int nseg = (int)m.segs.size();
+    const int gk = grad_tile_k(p, m);
     if ((rc = launch_terminal(p, kind, m.d_segs, nseg, m.st_blocks, ck + (size_t)(L.T.nck - 1) * E, rhotar, beta,
                               m.d_seg_state0, gscale, qh[0], st)))
       return rc;
@@ -1054,9 +1062,8 @@ int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const 
           double *gp = sgp + (size_t)pend * gstride;
           {
             ProfScope ps(p, prof, LB_KERNEL_STREAM_GRAD, ast, m.st_entries);
-            rc = m.tile_sys >= 0
-                     ? launch_tile_grad(p, m.tile_sys, m.tile_B, m.tile_k, zh, slot(j), slot(j + 1), gp, &rows, ast)
-                     : launch_stream_grad(p, m.d_segs, nseg, m.st_blocks, zh, slot(j), slot(j + 1), gp, ast);
+            rc = gk > 0 ? launch_tile_grad(p, m.tile_sys, m.tile_B, gk, zh, slot(j), slot(j + 1), gp, &rows, ast)
+                        : launch_stream_grad(p, m.d_segs, nseg, m.st_blocks, zh, slot(j), slot(j + 1), gp, ast);
             if (rc) return rc;
           }
           if (++pend == L.gbatch || j == cb) {
@@ -1254,7 +1261,8 @@ extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
     return LB_OK;
   }
   if (option == LB_OPT_TILE_KI) {
-    if (value < 0 || value > 99 || value != (int)value) return fail(LB_EINVAL, "LB_OPT_TILE_KI must be 0..99");
+    if (value < 0 || value > LB_SPLIT_BASE + LB_LIMIT_QMAX || value != (int)value)
+      return fail(LB_EINVAL, "LB_OPT_TILE_KI must be 0..99 (block shape) or 101..111 (two-pass split)");
     o.tile_ki = (int)value;
     return LB_OK;
   }
@@ -1660,6 +1668,12 @@ extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch
     const int sys = m->segs[0].sys;
     for (int ki : {44, 43, 34, 42, 33, 66, 55, 32, 23})
       if (tile_ki(p, sys, ki) == ki) cand.push_back({1, ki});
+    // two-pass splits with at least 9 rows and columns on both sides
+    for (int ka = 1; ka < p->sys[sys].Q; ++ka) {
+      SplitGeo g;
+      if (split_geo(p, sys, LB_SPLIT_BASE + ka, &g) && g.NA >= 9 && p->sys[sys].N / g.NA >= 9)
+        cand.push_back({1, LB_SPLIT_BASE + ka});
+    }
   }
   const int reps = m->st_entries > (1 << 22) ? 4 : 20;
   float best = 1e30f;

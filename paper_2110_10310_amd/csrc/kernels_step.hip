@@ -159,7 +159,7 @@ __device__ __forceinline__ void sweep_entry(const StepArgs &A, SweepOut &so, int
 }
 
 // The iterate sweep kk reads: the start for kk = 0, then the output of kk - 1.
-__device__ __forceinline__ const double2 *sweep_input(const StepArgs &A, int kk) {
+__host__ __device__ __forceinline__ const double2 *sweep_input(const StepArgs &A, int kk) {
   if (kk == 0) return A.zstart ? A.zstart : A.q;
   return (kk & 1) ? A.z0 : A.z1;
 }
@@ -321,6 +321,179 @@ int launch_slots_clear(unsigned long long *slots, int nsys, hipStream_t st) {
 }
 
 // ----------------------------------------------------------------------------
+// Two-pass sweep and apply of one system (a state too large for the caches).
+//
+// The off-diagonal part is a sum over subsystems.  Pass A forms the terms of
+// the subsystems q0..Q-1 (the least significant digits, level product NA)
+// and pass B adds those of 0..q0-1 and finishes the entry.  Each pass works
+// on sets of entries that contain all of its neighbours:
+// * pass A: an NA x NA block of the state (the high row and column digits
+//   fixed; rows and columns contiguous);
+// * pass B: the entries with fixed low row digits and fixed low column
+//   digits, except the SP lowest column values, which stay as contiguous
+//   runs for coalescing (NB x NB x SP entries, NB = N / NA).
+// Each workgroup takes 256 entries of one set and the sets are dealt to the
+// XCDs in contiguous bands, so a set's neighbours are read from the L2 its
+// own loads fill.  Pass A writes its partial sum to the output buffer of the
+// sweep (or to y), where pass B reads it back entry by entry.
+// ----------------------------------------------------------------------------
+struct SplitPass {
+  const SysDev *sysv;
+  const uint64_t *desc;
+  int sys, B, q0;
+  int64_t NA, SP;
+};
+
+// Unit u of pass A (XCD band mapping applied by the caller) and thread tid:
+// the entry, or false past the set's end.
+__device__ __forceinline__ bool split_a_entry(const SplitPass &P, const SysDev &S, int64_t u, int tid, int64_t &b,
+                                              int64_t &i, int64_t &j) {
+  const int64_t NA = P.NA, NB = S.N / NA;
+  const int64_t parts = (NA * NA + 255) / 256;
+  const int64_t t = u / parts, f = (u - t * parts) * 256 + tid;
+  if (f >= NA * NA) return false;
+  b = t / (NB * NB);
+  const int64_t rem = t - b * NB * NB;
+  const int64_t hr = rem / NB, hc = rem - (rem / NB) * NB;
+  const int64_t ar = f / NA, ac = f - (f / NA) * NA;
+  i = hr * NA + ar;
+  j = hc * NA + ac;
+  return true;
+}
+
+__device__ __forceinline__ bool split_b_entry(const SplitPass &P, const SysDev &S, int64_t u, int tid, int64_t &b,
+                                              int64_t &i, int64_t &j) {
+  const int64_t NA = P.NA, NB = S.N / NA, SP = P.SP, NCB = NA / SP;
+  const int64_t setsz = NB * NB * SP;
+  const int64_t parts = (setsz + 255) / 256;
+  const int64_t set = u / parts, f = (u - set * parts) * 256 + tid;
+  if (f >= setsz) return false;
+  b = set / (NA * NCB);
+  const int64_t rem = set - b * NA * NCB;
+  const int64_t rlo = rem / NCB, cb = rem - (rem / NCB) * NCB;
+  const int64_t sp = f % SP, g = f / SP;
+  const int64_t bc = g % NB, br = g / NB;
+  i = br * NA + rlo;
+  j = bc * NA + cb * SP + sp;
+  return true;
+}
+
+__host__ __device__ inline int64_t split_units(int64_t N, int64_t NA, int64_t SP, int B, bool passA) {
+  const int64_t NB = N / NA;
+  if (passA) return (int64_t)B * NB * NB * ((NA * NA + 255) / 256);
+  return (int64_t)B * NA * (NA / SP) * ((NB * NB * SP + 255) / 256);
+}
+
+__device__ __forceinline__ int64_t split_band(int64_t units) {
+  const int64_t per = (units + 7) / 8;
+  return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+// Pass A: acc[e] = sum over q0 <= q < Q of the off-diagonal terms of x (M or
+// M^+).  Controls: dtab[q] when given (a sweep: the step's row of the
+// control table), else d_q(t) from alpha.  kstep: a sweep's count (launches
+// at or past it return at once), or NULL.
+template <bool ADJ>
+__global__ __launch_bounds__(256) void split_a_kernel(SplitPass P, const double2 *__restrict__ dtab,
+                                                      const double *__restrict__ alpha,
+                                                      const double *__restrict__ carrier, double t,
+                                                      const int32_t *__restrict__ kstep, int kk,
+                                                      const double2 *__restrict__ x, double2 *__restrict__ acc) {
+  if (kstep && kk > 0 && kk >= *kstep) return;  // uniform per launch
+  __shared__ double sq[SQRT_TABLE];
+  __shared__ double2 dq[QMAX];
+  const SysDev &S = P.sysv[P.sys];
+  const int64_t units = split_units(S.N, P.NA, P.SP, P.B, true);
+  const int64_t u = split_band(units);
+  if (u >= units) return;  // uniform per workgroup
+  const int tid = threadIdx.x;
+  if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
+  if (tid < S.Q) dq[tid] = dtab ? dtab[tid] : control_value(S, alpha, carrier + S.carrier_off, tid, t);
+  __syncthreads();
+  int64_t b, i, j;
+  if (!split_a_entry(P, S, u, tid, b, i, j)) return;
+  const uint64_t di = P.desc[S.tab_off + i], dj = P.desc[S.tab_off + j];
+  const double2 *xs = x + b * S.N2;
+  const int64_t r = i * S.N + j;
+  acc[b * S.N2 + r] =
+      offdiag_range<ADJ>(S, di, dj, r, dq, sq, [&](int64_t idx) { return xs[idx]; }, P.q0, S.Q);
+}
+
+// Pass B of lindblad_apply: y = acc + (terms of q < q0) + D x.
+template <bool ADJ>
+__global__ __launch_bounds__(256) void split_b_apply_kernel(SplitPass P, const double *__restrict__ Etab,
+                                                            const double *__restrict__ alpha,
+                                                            const double *__restrict__ carrier, double t,
+                                                            const double2 *__restrict__ x, double2 *__restrict__ y) {
+  __shared__ double sq[SQRT_TABLE];
+  __shared__ double2 dq[QMAX];
+  const SysDev &S = P.sysv[P.sys];
+  const int64_t units = split_units(S.N, P.NA, P.SP, P.B, false);
+  const int64_t u = split_band(units);
+  if (u >= units) return;
+  const int tid = threadIdx.x;
+  if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
+  if (tid < S.Q) dq[tid] = control_value(S, alpha, carrier + S.carrier_off, tid, t);
+  __syncthreads();
+  int64_t b, i, j;
+  if (!split_b_entry(P, S, u, tid, b, i, j)) return;
+  const uint64_t di = P.desc[S.tab_off + i], dj = P.desc[S.tab_off + j];
+  const double2 *xs = x + b * S.N2;
+  const int64_t r = i * S.N + j, e = b * S.N2 + r;
+  const double2 acc = cadd(y[e], offdiag_range<ADJ>(S, di, dj, r, dq, sq, [&](int64_t idx) { return xs[idx]; },
+                                                    0, P.q0));
+  const double gam = diag_rate(S, di, dj);
+  const double dE = Etab[S.tab_off + i] - Etab[S.tab_off + j];
+  y[e] = cadd(acc, cmul(diag_coef(gam, dE, ADJ), xs[r]));
+}
+
+// Pass B of stage sweep kk: the partial sum of pass A is in the sweep's
+// output buffer (so.zo); the entry is finished like the other sweep kernels.
+template <bool ADJ>
+__global__ __launch_bounds__(256) void split_b_sweep_kernel(StepArgs A, int kk) {
+  __shared__ double sq[SQRT_TABLE];
+  __shared__ double2 dq[QMAX];
+  __shared__ double red[2][4];
+  const SysDev &S = A.sysv[A.sys];
+  int K = 2;
+  if (kk > 0) {
+    K = step_sweeps_of(A, A.sys);
+    if (kk >= K) return;  // uniform per launch
+  }
+  const SplitPass P{A.sysv, A.desc, A.sys, A.B, A.split_q, A.split_na, A.split_sp};
+  const int64_t units = split_units(S.N, P.NA, P.SP, P.B, false);
+  const int64_t u = split_band(units);
+  if (u >= units) return;  // uniform per workgroup
+  const int tid = threadIdx.x;
+  if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
+  if (tid < S.Q) dq[tid] = A.ctab[S.ctab_off + (int64_t)A.j * S.Q + tid - A.cshift];
+  __syncthreads();
+  SweepOut so;
+  so.first = kk == 0;
+  so.last = kk > 0 && kk == K - 1;
+  so.zo = (kk & 1) ? A.z1 : A.z0;
+  const double2 *zin = sweep_input(A, kk);
+  int64_t b, i, j;
+  if (split_b_entry(P, S, u, tid, b, i, j)) {
+    const uint64_t di = A.desc[S.tab_off + i], dj = A.desc[S.tab_off + j];
+    const double2 *zs = zin + b * S.N2;
+    const int64_t r = i * S.N + j, e = b * S.N2 + r;
+    const double2 acc = cadd(so.zo[e], offdiag_range<ADJ>(S, di, dj, r, dq, sq,
+                                                          [&](int64_t idx) { return zs[idx]; }, 0, P.q0));
+    sweep_entry<ADJ>(A, so, e, S.h, diag_rate(S, di, dj), A.Etab[S.tab_off + i] - A.Etab[S.tab_off + j], acc,
+                     zs[r]);
+  }
+  if (so.first) {
+    block_max2<256>(so.e1, so.qm, red);
+    if (tid == 0) {
+      unsigned long long *sl = slot_base(A, A.par, A.sys);
+      atomicMax(&sl[blockIdx.x % LB_STEP_SLOTS], dbits(so.e1));
+      atomicMax(&sl[LB_STEP_SLOTS + blockIdx.x % LB_STEP_SLOTS], dbits(so.qm));
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Launchers
 // ----------------------------------------------------------------------------
 namespace {
@@ -346,7 +519,38 @@ int sweep_tile_launch(const lb_plan *p, StepArgs &A, int kk, bool adj, hipStream
 
 namespace {
 
+int split_sweep_launch(const lb_plan *p, StepArgs &A, int kk, bool adj, const SplitGeo &g, hipStream_t st) {
+  const SysDev &S = p->sys[A.sys];
+  A.split_q = g.q0;
+  A.split_na = g.NA;
+  A.split_sp = g.SP;
+  const SplitPass P{A.sysv, A.desc, A.sys, A.B, g.q0, g.NA, g.SP};
+  const double2 *dtab = A.ctab + (S.ctab_off + (int64_t)A.j * S.Q - A.cshift);
+  const int32_t *kst = A.kstep + (int64_t)A.par * A.nsys + A.sys;
+  double2 *acc = (kk & 1) ? A.z1 : A.z0;
+  const double2 *zin = sweep_input(A, kk);
+  const int64_t ua = split_units(S.N, g.NA, g.SP, A.B, true), ub = split_units(S.N, g.NA, g.SP, A.B, false);
+  const dim3 ga((unsigned)(((ua + 7) / 8) * 8)), gb((unsigned)(((ub + 7) / 8) * 8));
+  if (adj) {
+    hipLaunchKernelGGL(split_a_kernel<true>, ga, dim3(256), 0, st, P, dtab, nullptr, nullptr, 0.0, kst, kk, zin,
+                       acc);
+    hipLaunchKernelGGL(split_b_sweep_kernel<true>, gb, dim3(256), 0, st, A, kk);
+  } else {
+    hipLaunchKernelGGL(split_a_kernel<false>, ga, dim3(256), 0, st, P, dtab, nullptr, nullptr, 0.0, kst, kk, zin,
+                       acc);
+    hipLaunchKernelGGL(split_b_sweep_kernel<false>, gb, dim3(256), 0, st, A, kk);
+  }
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
 int sweep_only(const lb_plan *p, StepArgs &A, int kk, bool adj, int tile_sys, int tile_k, hipStream_t st) {
+  if (tile_sys >= 0 && tile_k >= LB_SPLIT_BASE) {
+    SplitGeo g;
+    if (!split_geo(p, tile_sys, tile_k, &g)) return fail(LB_EUNSUPPORTED, "no two-pass split for this system");
+    A.sys = tile_sys;
+    return split_sweep_launch(p, A, kk, adj, g, st);
+  }
   if (tile_sys >= 0) {
     const SysDev &S = p->sys[tile_sys];
     const int nl = S.nlev[0];
@@ -367,6 +571,40 @@ int sweep_only(const lb_plan *p, StepArgs &A, int kk, bool adj, int tile_sys, in
 }
 
 }  // namespace
+
+bool split_geo(const lb_plan *p, int sys, int k, SplitGeo *g) {
+  if (k < LB_SPLIT_BASE) return false;
+  const SysDev &S = p->sys[sys];
+  const int ka = k - LB_SPLIT_BASE;
+  if (ka < 1 || ka >= S.Q) return false;
+  g->q0 = S.Q - ka;
+  g->NA = 1;
+  for (int q = g->q0; q < S.Q; ++q) g->NA *= S.nlev[q];
+  // spectator columns: the lowest column digits up to at least 8 values
+  g->SP = 1;
+  for (int q = S.Q - 1; q >= g->q0 && g->SP < 8; --q) g->SP *= S.nlev[q];
+  return g->NA > 1 && S.N / g->NA > 1;
+}
+
+int launch_split_apply(const lb_plan *p, int sys, int B, bool adj, double t, const double *alpha,
+                       const double2 *x, double2 *y, const SplitGeo &g, hipStream_t st) {
+  if (B == 0) return LB_OK;
+  const SysDev &S = p->sys[sys];
+  const SplitPass P{p->d_sys, p->d_desc, sys, B, g.q0, g.NA, g.SP};
+  const int64_t ua = split_units(S.N, g.NA, g.SP, B, true), ub = split_units(S.N, g.NA, g.SP, B, false);
+  const dim3 ga((unsigned)(((ua + 7) / 8) * 8)), gb((unsigned)(((ub + 7) / 8) * 8));
+  if (adj) {
+    hipLaunchKernelGGL(split_a_kernel<true>, ga, dim3(256), 0, st, P, nullptr, alpha, p->d_carrier, t, nullptr, 0,
+                       x, y);
+    hipLaunchKernelGGL(split_b_apply_kernel<true>, gb, dim3(256), 0, st, P, p->d_E, alpha, p->d_carrier, t, x, y);
+  } else {
+    hipLaunchKernelGGL(split_a_kernel<false>, ga, dim3(256), 0, st, P, nullptr, alpha, p->d_carrier, t, nullptr, 0,
+                       x, y);
+    hipLaunchKernelGGL(split_b_apply_kernel<false>, gb, dim3(256), 0, st, P, p->d_E, alpha, p->d_carrier, t, x, y);
+  }
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
 
 int launch_sweep(const lb_plan *p, StepArgs &A, int kk, bool adj, int tile_sys, int tile_k, hipStream_t st) {
   if (A.H > HMAX) return fail(LB_EINVAL, "increment history longer than the kernels keep");

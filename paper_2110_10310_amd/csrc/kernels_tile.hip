@@ -472,6 +472,10 @@ int launch_split(const lb_plan *p, int sys, int B, int mode, bool adj, const dou
 // LB_OPT_TILE_KI option selects another instantiated shape (10*KR + KC).
 int tile_ki(const lb_plan *p, int sys, int ki_opt) {
   const SysDev &S = p->sys[sys];
+  if (ki_opt >= LB_SPLIT_BASE) {  // two-pass sweep and apply (any levels)
+    SplitGeo g;
+    return split_geo(p, sys, ki_opt, &g) ? ki_opt : 0;
+  }
   const int nl = S.nlev[0];
   for (int q = 1; q < S.Q; ++q)
     if (S.nlev[q] != nl) return 0;
@@ -523,6 +527,7 @@ int launch_tile_grad(const lb_plan *p, int sys, int B, int k, const double2 *zh,
                      const double2 *q1, double *gpart, int64_t *rows, hipStream_t st) {
   *rows = 0;
   if (B == 0) return LB_OK;
+  if (k >= LB_SPLIT_BASE) k = tile_ki(p, sys, 0);  // the two-pass sweeps keep the block-tiled integrands
   const SysDev &S = p->sys[sys];
   const int nl = S.nlev[0];
 #define X(A, Bq, R, C, T) \
@@ -534,6 +539,7 @@ int launch_tile_grad(const lb_plan *p, int sys, int B, int k, const double2 *zh,
 
 int64_t tile_grad_rows(const lb_plan *p, int sys, int B, int k) {
   const SysDev &S = p->sys[sys];
+  if (k >= LB_SPLIT_BASE) k = tile_ki(p, sys, 0);
   if (!k) return 0;
   int tr = 1, tc = 1;
   for (int i = 0; i < k / 10; ++i) tr *= S.nlev[0];
@@ -544,6 +550,10 @@ int64_t tile_grad_rows(const lb_plan *p, int sys, int B, int k) {
 int launch_tile_apply(const lb_plan *p, int sys, int B, bool adj, const double *alpha, double t, const double2 *x,
                       double2 *y, int tile_opt, int ki_opt, hipStream_t st) {
   if (B == 0) return LB_OK;
+  if (ki_opt >= LB_SPLIT_BASE) {
+    SplitGeo g;
+    if (split_geo(p, sys, ki_opt, &g)) return launch_split_apply(p, sys, B, adj, t, alpha, x, y, g, st);
+  }
   if (tile_opt == 2 && split_kl(p, sys))
     return launch_split(p, sys, B, 0, adj, alpha, t, nullptr, 0, x, nullptr, y, nullptr, st);
   const SysDev &S = p->sys[sys];

@@ -92,14 +92,16 @@ __device__ __forceinline__ double2 stage_weight(double h, double gam, double dE,
 //                        V = sqrt(n) x_{i-e,j} - sqrt(m+1) x_{i,j+e};
 // the adjoint (+i [H_c, .]) flips the sign.  Decay jump, forward:
 // sqrt((n+1)(m+1))/T1 x_{i+e,j+e}; adjoint: sqrt(n m)/T1 x_{i-e,j-e}.
+// offdiag_range: the terms of subsystems q0 <= q < q1 only (the off-diagonal
+// part is a sum over subsystems, so disjoint ranges add up to offdiag).
 template <bool ADJ, class Load>
-__device__ __forceinline__ double2 offdiag(const SysDev &S, uint64_t di, uint64_t dj, int64_t r,
-                                           const double2 *dq, const double *sq, Load ld) {
+__device__ __forceinline__ double2 offdiag_range(const SysDev &S, uint64_t di, uint64_t dj, int64_t r,
+                                                 const double2 *dq, const double *sq, Load ld, int q0, int q1) {
   double2 acc = make_double2(0.0, 0.0);
   const int64_t N = S.N;
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) {
-    if (q < S.Q) {
+    if (q >= q0 && q < q1) {
       const int n = digit(di, q), m = digit(dj, q);
       const int nl = S.nlev[q];
       const int64_t s1 = S.stride[q];
@@ -134,6 +136,12 @@ __device__ __forceinline__ double2 offdiag(const SysDev &S, uint64_t di, uint64_
     }
   }
   return acc;
+}
+
+template <bool ADJ, class Load>
+__device__ __forceinline__ double2 offdiag(const SysDev &S, uint64_t di, uint64_t dj, int64_t r,
+                                           const double2 *dq, const double *sq, Load ld) {
+  return offdiag_range<ADJ>(S, di, dj, r, dq, sq, ld, 0, S.Q);
 }
 
 // Gradient integrands of one entry for subsystem q (App. B eq.

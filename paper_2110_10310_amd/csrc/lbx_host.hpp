@@ -166,7 +166,26 @@ struct StepArgs {
   const StreamSeg *segs;    // generic: segments
   int nseg;
   int64_t nblk;             // generic: units (STREAM_BLOCK entries each)
+  // two-pass sweep (tile_k >= LB_SPLIT_BASE): pass A takes subsystems
+  // split_q..Q-1 (products of levels split_na), pass B the others
+  int split_q;
+  int64_t split_na, split_sp;
 };
+
+// Block shapes at or above this code select the two-pass sweep and apply of
+// one system, split after (code - LB_SPLIT_BASE) least significant subsystems.
+constexpr int LB_SPLIT_BASE = 100;
+struct SplitGeo {
+  int q0;       // pass A: subsystems q0..Q-1 (the least significant digits)
+  int64_t NA;   // product of their levels
+  int64_t SP;   // spectator columns of a pass-B set (lowest column digits; divides NA)
+};
+// The split of system sys for code k (false when k is not a valid split).
+bool split_geo(const lb_plan *p, int sys, int k, SplitGeo *g);
+// lindblad_apply of B states with the two-pass kernels; y holds the partial
+// sum between the passes.
+int launch_split_apply(const lb_plan *p, int sys, int B, bool adj, double t, const double *alpha,
+                       const double2 *x, double2 *y, const SplitGeo &g, hipStream_t st);
 
 // A copy of the plan's options (taken when a call starts).
 lbx_opts plan_options(const lb_plan *p);
