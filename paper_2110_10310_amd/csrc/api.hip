@@ -933,6 +933,55 @@ int run_call(const lb_plan *p, const lbx_opts &o, const CallPlan &cp, size_t ws_
   return status_code(bits);
 }
 
+// Work of one call spread over the plan's side streams: each side stream it
+// uses first waits for what `st` holds at begin(), and `st` waits for all of
+// them at join() (also on the way out of an error).
+struct Fork {
+  const lb_plan *p;
+  hipStream_t st;
+  bool on;
+  hipEvent_t start = nullptr;
+  bool used[4] = {};
+  Fork(const lb_plan *p_, hipStream_t s, bool want) : p(p_), st(s), on(want && p_->naux > 0) {}
+  int begin() {
+    if (!on) return LB_OK;
+    LBX_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    LBX_HIP(hipEventRecord(start, st));
+    return LB_OK;
+  }
+  // The stream of item k.
+  int stream(int k, hipStream_t *out) {
+    if (!on) {
+      *out = st;
+      return LB_OK;
+    }
+    const int i = k % p->naux;
+    if (!used[i]) {
+      LBX_HIP(hipStreamWaitEvent(p->aux[i], start, 0));
+      used[i] = true;
+    }
+    *out = p->aux[i];
+    return LB_OK;
+  }
+  int join() {
+    if (!on) return LB_OK;
+    on = false;
+    int rc = LB_OK;
+    for (int i = 0; i < p->naux; ++i)
+      if (used[i]) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r == hipSuccess) r = hipEventRecord(e, p->aux[i]);
+        if (r == hipSuccess) r = hipStreamWaitEvent(st, e, 0);
+        (void)hipEventDestroy(e);
+        if (r != hipSuccess && rc == LB_OK) rc = hip_fail(r, "side-stream join");
+      }
+    (void)hipEventDestroy(start);
+    return rc;
+  }
+  ~Fork() { (void)join(); }
+};
+
 int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w,
                 const double *alpha, const double2 *rho0, double2 *rhoT, char *traj, bool prof,
                 const std::vector<int32_t> *kst, hipStream_t st) {
@@ -942,19 +991,27 @@ int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const L
   int32_t *status = (int32_t *)(w + L.status);
   int rc;
   if ((rc = launch_control_table(p, 0, (int)p->sys.size(), alpha, ctab, 0, ktab, ttab, o.tol, st))) return rc;
-  // LDS-resident systems: one persistent launch per kernel class.
+  // LDS-resident systems: one persistent launch per kernel class, each on a
+  // side stream of its own beside the streamed systems.
   double2 *hist = traj ? (double2 *)(traj + L.T.hist) : nullptr;
   int64_t *slots = prof ? (int64_t *)(w + L.sweeps) : nullptr;
-  for (const auto &c : m.classes) {
-    ProfScope ps(p, prof, LB_KERNEL_LDS_FORWARD, st);
+  Fork fk(p, st, m.classes.size() > 1 || (!m.classes.empty() && !m.segs.empty()));
+  if ((rc = fk.begin())) return rc;
+  for (size_t ci = 0; ci < m.classes.size(); ++ci) {
+    const auto &c = m.classes[ci];
+    hipStream_t cs;
+    if ((rc = fk.stream((int)ci, &cs))) return rc;
+    ProfScope ps(p, prof, LB_KERNEL_LDS_FORWARD, cs);
     rc = c.qc > 0 ? launch_lds_forward_fast(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, ctab, ttab,
-                                            o.tol, rho0, rhoT, hist, slots ? slots + c.i0 : nullptr, status, st)
+                                            o.tol, rho0, rhoT, hist, slots ? slots + c.i0 : nullptr, status, cs)
                   : launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab, rho0, rhoT,
-                                       hist, slots ? slots + c.i0 : nullptr, status, st);
+                                       hist, slots ? slots + c.i0 : nullptr, status, cs);
     if (rc) return rc;
   }
-  if ((rc = lds_profile_work(p, m, LB_KERNEL_LDS_FORWARD, slots, st))) return rc;
-  if (m.segs.empty()) return LB_OK;
+  if (m.segs.empty()) {
+    if ((rc = fk.join())) return rc;
+    return lds_profile_work(p, m, LB_KERNEL_LDS_FORWARD, slots, st);
+  }
   // Streamed systems: the sweeps of every step over all of them.
   StreamCtx sc{p, &o, &m, &L, w, prof, kst};
   double2 *q0 = (double2 *)(w + L.q0), *q1 = (double2 *)(w + L.q1);
@@ -972,6 +1029,7 @@ int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const L
     return r;
   };
   if ((rc = stream_forward(sc, 0, NT, start, slot, st))) return rc;
+  if ((rc = fk.join()) || (rc = lds_profile_work(p, m, LB_KERNEL_LDS_FORWARD, slots, st))) return rc;
   return copy_segments(m, last_out, false, rhoT, st);
 }
 
@@ -987,30 +1045,39 @@ int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const 
   int32_t *status = (int32_t *)(w + L.status);
   double *gstep = (double *)(w + L.gstep);
   if ((rc = launch_fill_zero(gstep, (size_t)2 * p->ctab_total * sizeof(double), st))) return rc;
-  // LDS-resident adjoint.
+  // LDS-resident adjoint: each kernel class on a side stream of its own beside
+  // the streamed systems; its gradient rows are reduced after the join.
+  LdsItem *items = (LdsItem *)(w + L.items);
+  double *gpart = (double *)(w + L.gpart);
+  int64_t *slots = prof ? (int64_t *)(w + L.sweeps) : nullptr;
+  Fork fk(p, st, m.classes.size() > 1 || (!m.classes.empty() && !m.segs.empty()));
   if (!m.items.empty()) {
     const double2 *hist = (const double2 *)(traj + L.T.hist);
-    LdsItem *items = (LdsItem *)(w + L.items);
     LBX_HIP(hipMemcpyAsync(items, m.d_items, m.items.size() * sizeof(LdsItem), hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(item_weights_kernel, dim3(((int)m.items.size() + 127) / 128), dim3(128), 0, st, items,
                        (int)m.items.size(), beta, m.d_sys_state0, gscale);
     LBX_HIP(hipGetLastError());
-    double *gpart = (double *)(w + L.gpart);
-    int64_t *slots = prof ? (int64_t *)(w + L.sweeps) : nullptr;
-    for (const auto &c : m.classes) {
-      ProfScope ps(p, prof, LB_KERNEL_LDS_ADJOINT, st);
+    if ((rc = fk.begin())) return rc;
+    for (size_t ci = 0; ci < m.classes.size(); ++ci) {
+      const auto &c = m.classes[ci];
+      hipStream_t cs;
+      if ((rc = fk.stream((int)ci, &cs))) return rc;
+      ProfScope ps(p, prof, LB_KERNEL_LDS_ADJOINT, cs);
       rc = c.qc > 0 ? launch_lds_adjoint_fast(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, kind, ctab, ttab,
                                               o.tol, rhotar, hist, (double2 *)(w + L.zhist), gpart,
-                                              slots ? slots + c.i0 : nullptr, status, st)
+                                              slots ? slots + c.i0 : nullptr, status, cs)
                     : launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab, ktab, rhotar,
-                                         hist, gpart, slots ? slots + c.i0 : nullptr, status, st);
+                                         hist, gpart, slots ? slots + c.i0 : nullptr, status, cs);
       if (rc) return rc;
     }
-    if ((rc = lds_profile_work(p, m, LB_KERNEL_LDS_ADJOINT, slots, st))) return rc;
-    if ((rc = launch_lds_grad_reduce(p, m.d_lds_item_range, (int)m.lds_sys.size(), m.d_lds_sys, items, gpart,
-                                     gstep, st)))
-      return rc;
   }
+  auto lds_tail = [&]() -> int {
+    if (m.items.empty()) return LB_OK;
+    if (int r = fk.join()) return r;
+    if (int r = lds_profile_work(p, m, LB_KERNEL_LDS_ADJOINT, slots, st)) return r;
+    return launch_lds_grad_reduce(p, m.d_lds_item_range, (int)m.lds_sys.size(), m.d_lds_sys, items, gpart, gstep,
+                                  st);
+  };
   // Streamed adjoint with checkpoint recomputation.
   if (!m.segs.empty()) {
     StreamCtx sc{p, &o, &m, &L, w, prof, kst};
@@ -1078,6 +1145,7 @@ int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const 
       }
     }
   }
+  if ((rc = lds_tail())) return rc;
   return launch_grad_contract(p, gstep, alpha, gamma2, gscale, grad, st);
 }
 
@@ -1210,6 +1278,13 @@ extern "C" int lb_plan_create(const lb_system_desc *desc, int32_t nsys, lb_plan 
       (e = hipMemcpy(p->d_desc, dg.data(), dg.size() * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->d_carrier, car.data(), car.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemcpy(plan tables)"));
+  for (auto &a : p->aux) {
+    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess) {
+      a = nullptr;
+      break;
+    }
+    p->naux++;
+  }
   *out = p.release();
   return LB_OK;
 }
@@ -1234,6 +1309,7 @@ extern "C" void lb_plan_destroy(lb_plan *p) {
     (void)hipEventDestroy(e.stop);
   }
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  for (int i = 0; i < p->naux; ++i) (void)hipStreamDestroy(p->aux[i]);
   delete p;
 }
 

@@ -49,6 +49,10 @@ struct lb_plan {
   mutable int64_t prof_work[LB_KERNEL_COUNT] = {};  // entries x sweeps (x steps for STREAM_GRAD)
   mutable std::vector<lbx_prof_pending> prof_pending;
   mutable std::vector<hipEvent_t> ev_pool;  // recycled profiling events
+  // side streams (default priority) on which a call runs its LDS-resident
+  // kernel classes beside the streamed systems
+  hipStream_t aux[4] = {};
+  int naux = 0;
 };
 
 namespace lbx {
