@@ -45,6 +45,7 @@ LB_KERNEL_LDS_FORWARD = 0
 LB_KERNEL_LDS_ADJOINT = 1
 LB_KERNEL_SWEEP = 2
 LB_KERNEL_STREAM_GRAD = 3
+LB_KERNEL_COUNT = 4
 
 # Every function the header declares, with its ctypes signature.
 _i32 = C.c_int32

@@ -314,8 +314,11 @@ def objective(plan: Plan, kind, rhoT: torch.Tensor, rhotar: torch.Tensor, beta: 
 
 def adjoint_gradient(plan: Plan, kind, alpha: torch.Tensor, rho0: torch.Tensor,
                      rhotar: torch.Tensor, beta: torch.Tensor, batch: Sequence[int],
-                     gamma2: float = 0.0, ckpt_every: int = 1, want_rhoT: bool = False):
-    """(G per system, dG/dalpha, rho(T) or None)."""
+                     gamma2: float = 0.0, ckpt_every: int = 1, want_rhoT: bool = False,
+                     workspace: torch.Tensor | None = None):
+    """(G per system, dG/dalpha, rho(T) or None).  `workspace` (uint8, at
+    least Plan.workspace_bytes(LB_OP_GRADIENT, batch, ckpt_every)) replaces
+    the plan's cached one: calls that may overlap need their own."""
     b = plan.batch_array(batch)
     _need(alpha, "alpha", torch.float64, int(plan.alpha_off[-1]))
     _states(plan, rho0, "rho0", batch)
@@ -324,7 +327,12 @@ def adjoint_gradient(plan: Plan, kind, alpha: torch.Tensor, rho0: torch.Tensor,
     G = torch.empty(len(plan.systems), dtype=torch.float64, device="cuda")
     grad = torch.empty_like(alpha)
     rhoT = torch.empty_like(rho0) if want_rhoT else None
-    ws = plan.workspace(nat.LB_OP_GRADIENT, batch, ckpt_every)
+    if workspace is None:
+        ws = plan.workspace(nat.LB_OP_GRADIENT, batch, ckpt_every)
+    else:
+        ws = _need(workspace, "workspace", torch.uint8)
+        if ws.numel() < plan.workspace_bytes(nat.LB_OP_GRADIENT, batch, ckpt_every):
+            raise ValueError("workspace is smaller than Plan.workspace_bytes")
     check(lib.adjoint_gradient(plan.handle, KIND[kind], _vp(alpha), _vp(rho0), _vp(rhotar),
                                _vp(beta), b.ctypes.data_as(nat._ip), float(gamma2), int(ckpt_every),
                                _vp(G), _vp(grad), _vp(rhoT) if rhoT is not None else None,
