@@ -76,7 +76,7 @@ def _one_blas_thread(fn):
 
 __all__ = [
     "TWO_PI", "KIND_FROB", "KIND_TR", "DENSE_MAX_N2",
-    "lowering", "embed", "system_hamiltonian", "bspline2", "spline_basis",
+    "lowering", "embed", "system_hamiltonian", "coupling_hamiltonian", "bspline2", "spline_basis",
     "controls", "control_hamiltonian", "hamiltonian", "collapse_operators",
     "vec", "unvec", "superoperator", "lindbladian", "lindbladian_adjoint",
     "lindbladian_entries", "imr_forward", "merit", "objective",
@@ -111,7 +111,8 @@ def embed(op, q: int, nlev, sparse: bool = False):
 
 
 def system_hamiltonian(sys, sparse: bool = False):
-    """H_sys of Sec. II in rad/ns (cross-Kerr coupling; no Jaynes-Cummings).
+    """Time-independent part of H_sys of Sec. II in rad/ns (the
+    Jaynes-Cummings coupling is ``coupling_hamiltonian``).
 
     H_sys = sum_q (omega_q - omega_q^rot) a_q^+ a_q - xi_q/2 a_q^+ a_q^+ a_q a_q
             - sum_{p>q} xi_pq a_p^+ a_p a_q^+ a_q
@@ -133,6 +134,34 @@ def system_hamiltonian(sys, sparse: bool = False):
                 ap, adp = ops[p]
                 aq, adq = ops[q]
                 H = H - TWO_PI * xi * (adp @ ap @ adq @ aq)
+    return H
+
+
+def coupling_hamiltonian(sys, t, sparse: bool = False):
+    """Jaynes-Cummings coupling of H_sys (Sec. II) at time t, rad/ns:
+
+        sum_{p>q} g_pq ( e^{+i (w_p^rot - w_q^rot) t} a_p^+ a_q
+                         + e^{-i (w_p^rot - w_q^rot) t} a_p a_q^+ ),
+
+    the general form with unequal rotation frequencies, whose phases
+    multiply a_p^+ a_q and a_p a_q^+ respectively.  Zero when the system has
+    no coupling (sys.jc None); missing rotation frequencies are all equal.
+    """
+    N = sys.N
+    H = sp.csr_matrix((N, N), dtype=np.complex128) if sparse else np.zeros((N, N), dtype=np.complex128)
+    g = getattr(sys, "jc", None)
+    if g is None:
+        return H
+    rot = getattr(sys, "rotfreq", None)
+    rot = np.zeros(sys.Q) if rot is None else np.asarray(rot, dtype=np.float64)
+    for p in range(sys.Q):
+        ap = embed(lowering(sys.nlev[p]), p, sys.nlev, sparse)
+        for q in range(p):
+            if g[p, q] == 0.0:
+                continue
+            aq = embed(lowering(sys.nlev[q]), q, sys.nlev, sparse)
+            ph = np.exp(1j * TWO_PI * (rot[p] - rot[q]) * t)
+            H = H + TWO_PI * g[p, q] * (ph * (ap.T @ aq) + np.conj(ph) * (ap @ aq.T))
     return H
 
 
@@ -180,8 +209,9 @@ def control_hamiltonian(sys, d, sparse: bool = False):
 
 
 def hamiltonian(sys, alpha, t, sparse: bool = False):
-    """H(t) = H_sys + H_c(t)."""
-    return system_hamiltonian(sys, sparse) + control_hamiltonian(sys, controls(sys, alpha, t), sparse)
+    """H(t) = H_sys(t) + H_c(t) (the Jaynes-Cummings part of H_sys may depend on t)."""
+    return (system_hamiltonian(sys, sparse) + coupling_hamiltonian(sys, t, sparse)
+            + control_hamiltonian(sys, controls(sys, alpha, t), sparse))
 
 
 def collapse_operators(sys, sparse: bool = False):
@@ -238,7 +268,7 @@ def lindbladian(sys, alpha, t, rho, ops=None):
     ``ops`` = (H_sys, collapse list) may be passed to avoid rebuilding them.
     """
     Hs, Ls = ops if ops is not None else (system_hamiltonian(sys, True), collapse_operators(sys, True))
-    H = Hs + control_hamiltonian(sys, controls(sys, alpha, t), True)
+    H = Hs + coupling_hamiltonian(sys, t, True) + control_hamiltonian(sys, controls(sys, alpha, t), True)
     out = -1j * (H @ rho - (H.T @ rho.T).T)
     for L in Ls:
         Ld = L.conj().T
@@ -253,7 +283,7 @@ def lindbladian_adjoint(sys, alpha, t, X, ops=None):
     i [H, X] + sum_L L^+ X L - 1/2 (L^+ L X + X L^+ L).
     """
     Hs, Ls = ops if ops is not None else (system_hamiltonian(sys, True), collapse_operators(sys, True))
-    H = Hs + control_hamiltonian(sys, controls(sys, alpha, t), True)
+    H = Hs + coupling_hamiltonian(sys, t, True) + control_hamiltonian(sys, controls(sys, alpha, t), True)
     out = 1j * (H @ X - (H.T @ X.T).T)
     for L in Ls:
         Ld = L.conj().T
@@ -269,7 +299,8 @@ def lindbladian_entries(sys, alpha, t, x, rows, cols, adjoint=False):
     of entries of a very large state can be checked one by one.
     """
     Hs = system_hamiltonian(sys, True)
-    H = sp.csr_matrix(Hs + control_hamiltonian(sys, controls(sys, alpha, t), True))
+    H = sp.csr_matrix(Hs + coupling_hamiltonian(sys, t, True)
+                      + control_hamiltonian(sys, controls(sys, alpha, t), True))
     Ls = [sp.csr_matrix(L) for L in collapse_operators(sys, True)]
     sgn = 1j if adjoint else -1j
     out = np.empty(len(rows), dtype=np.complex128)

@@ -237,9 +237,10 @@ def test_one_step_is_cayley_map():
     assert np.max(np.abs(oracle.vec(out) - ref)) < 1e-14 * np.max(np.abs(ref))
 
 
-def test_dense_and_operator_forms_agree_and_adjoint_identity():
+@pytest.mark.parametrize("jc", [0.0, 0.03])
+def test_dense_and_operator_forms_agree_and_adjoint_identity(jc):
     rng = np.random.default_rng(7)
-    s = random_system(rng, (3, 2, 2), NT=4, T=1.0)
+    s = random_system(rng, (3, 2, 2), NT=4, T=1.0, jc=jc)
     alpha = random_alpha(rng, s, amp=0.05)
     N = s.N
     X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
@@ -262,15 +263,98 @@ def test_dense_and_operator_forms_agree_and_adjoint_identity():
     assert np.max(np.abs(ent - adj[rows, cols])) < 1e-13
 
 
-def test_lindbladian_trace_zero_and_hermiticity_preserving():
+@pytest.mark.parametrize("jc", [0.0, 0.03])
+def test_lindbladian_trace_zero_and_hermiticity_preserving(jc):
     rng = np.random.default_rng(8)
-    s = random_system(rng, (3, 3), NT=4, T=1.0)
+    s = random_system(rng, (3, 3), NT=4, T=1.0, jc=jc)
     alpha = random_alpha(rng, s, amp=0.05)
     X = rng.standard_normal((9, 9)) + 1j * rng.standard_normal((9, 9))
     Hm = X + X.conj().T
     out = oracle.lindbladian(s, alpha, 0.2, Hm)
     assert abs(np.trace(out)) < 1e-12
     assert np.max(np.abs(out - out.conj().T)) < 1e-12
+
+
+# ------------------------------------------------------------ Jaynes-Cummings coupling
+
+def mk_jc(nlev, g, *, rot=None, det=None, T, NT):
+    """Closed system with one coupling g_10 (subsystem 1 > subsystem 0)."""
+    import dataclasses
+    Q = len(nlev)
+    jc = np.zeros((Q, Q))
+    jc[1, 0] = g
+    return dataclasses.replace(mk(nlev, det=det, T=T, NT=NT), jc=jc,
+                               rotfreq=None if rot is None else np.asarray(rot, float))
+
+
+def test_jaynes_cummings_single_excitation_closed_form():
+    # Two qubits, one excitation, equal rotation frequencies: H = G (|10><01|
+    # + |01><10|) on the span of |10> (index 2) and |01> (index 1), G = 2 pi g.
+    # One implicit-midpoint step is the Cayley map, so after j steps
+    # psi = cos(phi_j)|10> - i sin(phi_j)|01>, phi_j = j atan(G dt).
+    g = 0.013
+    s = mk_jc((2, 2), g, T=10.0, NT=100)
+    _, st = oracle.imr_forward(s, np.zeros((2, 5, 1, 2)), proj(4, 2)[None], keep_states=True)
+    for j in (1, 37, 100):
+        ph = j * np.arctan(2 * np.pi * g * s.dt)
+        r = st[j][0]
+        assert abs(r[2, 2] - np.cos(ph) ** 2) < 1e-14
+        assert abs(r[1, 1] - np.sin(ph) ** 2) < 1e-14
+        assert abs(r[2, 1] - 1j * np.sin(ph) * np.cos(ph)) < 1e-14
+        assert abs(r[1, 2] + 1j * np.sin(ph) * np.cos(ph)) < 1e-14
+        assert abs(r[0, 0]) + abs(r[3, 3]) < 1e-15
+
+
+def test_jaynes_cummings_two_excitations_closed_form():
+    # Two qutrits from |1,1> (index 4): the coupling mixes |2,0>, |1,1>, |0,2>
+    # with weights sqrt(2) (a^+|1> = sqrt2|2>), eigenvalues 0 and +-2G, so
+    # P_11 = cos^2(j atan(2 G dt)) and P_20 = P_02 = sin^2(j atan(2 G dt)) / 2.
+    g = 0.011
+    s = mk_jc((3, 3), g, T=8.0, NT=80)
+    _, st = oracle.imr_forward(s, np.zeros((2, 5, 1, 2)), proj(9, 4)[None], keep_states=True)
+    for j in (1, 20, 80):
+        th = j * np.arctan(2 * 2 * np.pi * g * s.dt)
+        r = st[j][0]
+        assert abs(r[4, 4] - np.cos(th) ** 2) < 1e-14
+        assert abs(r[6, 6] - 0.5 * np.sin(th) ** 2) < 1e-14
+        assert abs(r[2, 2] - 0.5 * np.sin(th) ** 2) < 1e-14
+
+
+def test_jaynes_cummings_rotating_frame_covariance():
+    # Sec. II: in a frame rotating at w_q^rot the detunings become
+    # w_q - w_q^rot and the coupling picks up exp(+-i (w_p^rot - w_q^rot) t).
+    # The lab-frame state U rho_rot U^+ (U = exp(-i sum_q w_q^rot n_q t)) must
+    # equal the rotating-frame one up to the O(dt^2) error of the method; a
+    # coupling phase of the wrong sign misses by O(1) (about 0.5 here).
+    om = [0.05, -0.03]
+    rng = np.random.default_rng(4)
+    psi = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    psi /= np.linalg.norm(psi)
+    rho0 = np.outer(psi, psi.conj())[None]
+    a = np.zeros((2, 5, 1, 2))
+    lab = oracle.imr_forward(mk_jc((2, 3), 0.02, det=om, T=20.0, NT=4000), a, rho0)[0]
+    rot = oracle.imr_forward(mk_jc((2, 3), 0.02, rot=om, T=20.0, NT=4000), a, rho0)[0]
+    theta = np.array([2 * np.pi * (om[0] * (i // 3) + om[1] * (i % 3)) * 20.0 for i in range(6)])
+    pred = np.exp(1j * theta)[:, None] * lab * np.exp(-1j * theta)[None, :]
+    assert np.max(np.abs(pred - rot)) < 2e-5
+
+
+def test_jaynes_cummings_gradient_against_central_differences():
+    rng = np.random.default_rng(19)
+    s = random_system(rng, (2, 3), NT=8, T=0.8, jc=0.05)
+    alpha = random_alpha(rng, s, amp=0.05)
+    rho0 = np.stack([proj(6, 1), proj(6, 4)])
+    tar = np.stack([proj(6, 3), proj(6, 2)])
+    beta = np.array([1.0, 0.7])
+    _, g = oracle.value_and_gradient(s, alpha, rho0, tar, beta, 0)
+    h = 1e-6
+    for k in [(0, 1, 0, 0), (1, 2, 1, 1), (1, 4, 0, 1)]:
+        ap, am = alpha.copy(), alpha.copy()
+        ap[k] += h
+        am[k] -= h
+        fd = (oracle.value_and_gradient(s, ap, rho0, tar, beta, 0)[0]
+              - oracle.value_and_gradient(s, am, rho0, tar, beta, 0)[0]) / (2 * h)
+        assert abs(fd - g[k]) < 1e-7 * max(1.0, np.max(np.abs(g)))
 
 
 # ------------------------------------------------------------ objective pins

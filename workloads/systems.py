@@ -12,7 +12,7 @@ changes every fixture derived from it.
 from __future__ import annotations
 
 from dataclasses import dataclass, replace
-from typing import List, Sequence
+from typing import Optional, List, Sequence
 
 import numpy as np
 
@@ -40,6 +40,8 @@ class System:
     carriers: np.ndarray   # [Q,Nf] carrier frequencies Omega/2pi [GHz]
     T: float               # horizon [ns]
     NT: int                # implicit-midpoint steps
+    jc: Optional[np.ndarray] = None       # [Q,Q] g_pq/2pi, entries p>q used [GHz] (Jaynes-Cummings)
+    rotfreq: Optional[np.ndarray] = None  # [Q] omega_q^rot/2pi [GHz] (None: all equal)
 
     @property
     def Q(self) -> int:
@@ -179,13 +181,17 @@ def _pm_uniform(rng, lo, hi, size):
 def random_system(rng: np.random.Generator, nlev: Sequence[int], *, NT: int = 40,
                   T: float = 4.0, Ns: int = 5, Nf: int = 2,
                   strong_dissipation: bool = True,
-                  some_terms_off: bool = True) -> System:
+                  some_terms_off: bool = True, jc: float = 0.0) -> System:
     """A random system for parity and property tests.
 
     With ``strong_dissipation`` the decay and dephasing times are a few tens
     of ns so that every term of the Lindbladian contributes visibly over a
     short horizon.  With ``some_terms_off`` roughly one in four T1/T2 values
-    is switched off (inf).
+    is switched off (inf).  With ``jc`` > 0 every pair p > q gets a
+    Jaynes-Cummings coupling g_pq/2pi uniform in +-[jc/2, jc] GHz (one in
+    four switched off) and the subsystems rotation frequencies uniform in
+    [-0.2, 0.2] GHz.  These draws come after all the others, so a system
+    drawn with jc = 0 is the same as before.
     """
     Q = len(nlev)
     detuning = rng.uniform(-0.3, 0.3, size=Q)
@@ -207,9 +213,17 @@ def random_system(rng: np.random.Generator, nlev: Sequence[int], *, NT: int = 40
         T2 = np.where(off2, np.inf, T2)
     carriers = rng.uniform(-0.05, 0.05, size=(Q, Nf))
     carriers[:, 0] = 0.0
+    g = rot = None
+    if jc > 0.0:
+        g = np.zeros((Q, Q))
+        for p in range(Q):
+            for q in range(p):
+                mag = rng.uniform(0.5 * jc, jc) * rng.choice([-1.0, 1.0])
+                g[p, q] = 0.0 if rng.uniform() < 0.25 else mag
+        rot = rng.uniform(-0.2, 0.2, size=Q)
     return System(nlev=tuple(int(n) for n in nlev), detuning=detuning,
                   selfkerr=selfkerr, crosskerr=ck, T1=T1, T2=T2, Ns=Ns,
-                  carriers=carriers, T=float(T), NT=int(NT))
+                  carriers=carriers, T=float(T), NT=int(NT), jc=g, rotfreq=rot)
 
 
 def _uniform_qudits(Q, n, *, crosskerr, T=100.0, NT=5000, Ns=10, Nf=1):
