@@ -146,6 +146,11 @@ typedef struct {
   const double *carrier;    /* [Q*Nf] Omega_q^f/2pi [GHz] */
   double T;                 /* horizon [ns], > 0 */
   int32_t NT;               /* implicit-midpoint steps, >= 1; dt = T/NT */
+  const double *jc;         /* [Q*Q] row-major or NULL: entry [p*Q+q] with p>q is the
+                               Jaynes-Cummings coupling g_pq/2pi [GHz] (Sec. II) */
+  const double *rotfreq;    /* [Q] omega_q^rot/2pi [GHz] or NULL (all equal): the coupling
+                               of p > q carries exp(+-i (omega_p^rot - omega_q^rot) t) on
+                               a_p^+ a_q and a_p a_q^+ */
 } lb_system_desc;
 
 typedef struct lb_plan lb_plan;

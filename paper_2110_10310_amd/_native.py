@@ -58,7 +58,7 @@ class SystemDesc(C.Structure):
     _fields_ = [
         ("Q", _i32), ("nlev", _ip), ("detuning", _dp), ("selfkerr", _dp),
         ("crosskerr", _dp), ("T1", _dp), ("T2", _dp), ("Ns", _i32), ("Nf", _i32),
-        ("carrier", _dp), ("T", C.c_double), ("NT", _i32),
+        ("carrier", _dp), ("T", C.c_double), ("NT", _i32), ("jc", _dp), ("rotfreq", _dp),
     ]
 
 

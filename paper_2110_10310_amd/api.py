@@ -73,6 +73,13 @@ class Plan:
             d.Nf = int(np.asarray(s.carriers).shape[1])
             d.T = float(s.T)
             d.NT = int(s.NT)
+            jc, rot = getattr(s, "jc", None), getattr(s, "rotfreq", None)
+            if jc is not None:
+                arrs["jc"] = np.ascontiguousarray(np.asarray(jc, dtype=np.float64).reshape(Q * Q))
+                d.jc = arrs["jc"].ctypes.data_as(nat._dp)
+            if rot is not None:
+                arrs["rotfreq"] = np.ascontiguousarray(rot, dtype=np.float64)
+                d.rotfreq = arrs["rotfreq"].ctypes.data_as(nat._dp)
         handle = C.c_void_p()
         check(lib.lb_plan_create(descs, n, C.byref(handle)), "lb_plan_create")
         self.handle = handle

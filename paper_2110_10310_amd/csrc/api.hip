@@ -245,7 +245,8 @@ int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool 
     if (m->path[s] == 1) {
       int blk, ept;
       lds_shape(p->sys[s].N2, &blk, &ept);
-      const int qc = lds_fast_ok(blk, ept, p->sys[s].Q) ? p->sys[s].Q : 0;
+      // the specialised kernels have no coupling terms
+      const int qc = lds_fast_ok(blk, ept, p->sys[s].Q) && p->sys[s].njc == 0 ? p->sys[s].Q : 0;
       cls[std::make_tuple(blk, ept, qc)].push_back(s);
     }
   for (auto &kv : cls) {
@@ -1220,6 +1221,35 @@ extern "C" int lb_plan_create(const lb_system_desc *desc, int32_t nsys, lb_plan 
       S.csum[q] = cs;
       theta_jump += S.g1[q] * (nl - 1);
       gmax += S.g1[q] * (nl - 1) + 0.5 * S.g2[q] * (nl - 1) * (nl - 1);
+    }
+    // Jaynes-Cummings pairs (Sec. II), p > q, with their share of the
+    // contraction bound: a pair's row and column terms each sum to at most
+    // |g| max over digits of (sqrt(n_p) sqrt(n_q+1) + sqrt(n_p+1) sqrt(n_q)).
+    S.njc = 0;
+    if (d.jc) {
+      for (int pp = 0; pp < d.Q; ++pp)
+        for (int qq = 0; qq < pp; ++qq) {
+          const double g = d.jc[pp * d.Q + qq];
+          if (!std::isfinite(g)) return fail(LB_EINVAL, who + "non-finite Jaynes-Cummings coupling");
+          if (g == 0.0) continue;
+          const double dr = d.rotfreq ? d.rotfreq[pp] - d.rotfreq[qq] : 0.0;
+          if (!std::isfinite(dr)) return fail(LB_EINVAL, who + "non-finite rotation frequency");
+          const int k = S.njc++;
+          S.jp[k] = (int8_t)pp;
+          S.jq[k] = (int8_t)qq;
+          S.jg[k] = TWO_PI * g;
+          S.jd[k] = TWO_PI * dr;
+          const int lp = d.nlev[pp], lq = d.nlev[qq];
+          double rmax = 0.0;
+          for (int np = 0; np < lp; ++np)
+            for (int nq = 0; nq < lq; ++nq) {
+              double v = 0.0;
+              if (np > 0 && nq + 1 < lq) v += std::sqrt((double)np * (nq + 1));
+              if (np + 1 < lp && nq > 0) v += std::sqrt((double)(np + 1) * nq);
+              rmax = std::max(rmax, v);
+            }
+          theta_jump += 2.0 * std::fabs(S.jg[k]) * rmax;
+        }
     }
     S.theta_jump = S.h * theta_jump;
     // Energies of H_sys (Sec. II), rad/ns, and digit tables.

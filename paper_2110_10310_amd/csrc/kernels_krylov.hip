@@ -73,17 +73,19 @@ __global__ __launch_bounds__(STREAM_BLOCK) void kry_apply_kernel(KryArgs A, cons
                                                                  double2 *__restrict__ y) {
   __shared__ double sq[SQRT_TABLE];
   __shared__ double2 dq[QMAX];
+  __shared__ double2 jq[JCMAX];
   const int tid = threadIdx.x;
   const StreamSeg &sg0 = A.segs[kry_seg(A.segs, A.nseg, blockIdx.x)];
   const SysDev &S0 = A.sysv[sg0.sys];
   if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
   if (tid < S0.Q) dq[tid] = A.ctab[S0.ctab_off + (int64_t)A.j * S0.Q + tid];
+  if (tid < S0.njc) jq[tid] = jc_coef(S0, tid, ((double)A.j + 0.5) * S0.dt);
   __syncthreads();
   const SysDev *S;
   KryEntry k;
   if (!kry_entry(A, S, k)) return;
   const double2 *us = u + k.base;
-  const double2 acc = offdiag<ADJ>(*S, k.di, k.dj, k.r, dq, sq, [&](int64_t idx) { return us[idx]; });
+  const double2 acc = offdiag_all<ADJ>(*S, k.di, k.dj, k.r, dq, jq, sq, [&](int64_t idx) { return us[idx]; });
   const double2 own = us[k.r];
   const double2 Mu = cadd(acc, cmul(diag_coef(k.gam, k.dE, ADJ), own));
   const double2 Au = csub(own, cscale(S->h, Mu));

@@ -32,6 +32,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
   extern __shared__ double2 zbuf[];  // two stage buffers of N^2 entries
   __shared__ double sq[SQRT_TABLE];
   __shared__ double2 dsh[2][QMAX];
+  __shared__ double2 jsh[2][JCMAX];
   const LdsItem it = items[blockIdx.x];
   const SysDev &S = sysv[it.sys];
   const int tid = threadIdx.x;
@@ -81,6 +82,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
       if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qv[k], cmul(wv[k], hdq[k]));
     }
     if (tid < S.Q) dsh[j & 1][tid] = ctab[S.ctab_off + (int64_t)j * S.Q + tid];
+    if (tid < S.njc) jsh[j & 1][tid] = jc_coef(S, tid, ((double)j + 0.5) * S.dt);
     __syncthreads();
     const int K = a_priori_sweeps(ktab[((int64_t)it.sys * NT + j) * 2 + 0], status);
     nsw += K;
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(BLOCK) void lds_forward_kernel(
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         if (ok[k]) {
-          const double2 acc = offdiag<false>(S, di[k], dj[k], ee[k], dsh[j & 1], sq,
+          const double2 acc = offdiag_all<false>(S, di[k], dj[k], ee[k], dsh[j & 1], jsh[j & 1], sq,
                                              [&](int64_t idx) { return src[idx]; });
           dn[k] = cmul(wv[k], cadd(hdq[k], cscale(h, acc)));
         }
@@ -127,6 +129,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
   extern __shared__ double2 zbuf[];
   __shared__ double sq[SQRT_TABLE];
   __shared__ double2 dsh[2][QMAX];
+  __shared__ double2 jsh[2][JCMAX];
   constexpr int WAVES = BLOCK / 64;
   const LdsItem it = items[blockIdx.x];
   const SysDev &S = sysv[it.sys];
@@ -176,6 +179,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
       if (ok[k]) (cb ? zb1 : zb0)[ee[k]] = cadd(qh[k], cmul(wv[k], hdq[k]));
     }
     if (tid < Q) dsh[j & 1][tid] = ctab[S.ctab_off + (int64_t)j * Q + tid];
+    if (tid < S.njc) jsh[j & 1][tid] = jc_coef(S, tid, ((double)j + 0.5) * S.dt);
     // Forward state q^j, consumed after the sweeps so that its load overlaps them.
     double2 qj[EPT];
 #pragma unroll
@@ -188,7 +192,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         if (ok[k]) {
-          const double2 acc = offdiag<true>(S, di[k], dj[k], ee[k], dsh[j & 1], sq,
+          const double2 acc = offdiag_all<true>(S, di[k], dj[k], ee[k], dsh[j & 1], jsh[j & 1], sq,
                                             [&](int64_t idx) { return src[idx]; });
           dn[k] = cmul(wv[k], cadd(hdq[k], cscale(h, acc)));
         }

@@ -230,6 +230,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_generic_kernel(StepArgs A,
   constexpr int BLOCK = STREAM_BLOCK;
   __shared__ double sq[SQRT_TABLE];
   __shared__ double2 dq[QMAX];
+  __shared__ double2 jq[JCMAX];
   __shared__ double red[2][BLOCK / 64];
   const int tid = threadIdx.x;
   const int64_t u = blockIdx.x;
@@ -243,6 +244,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_generic_kernel(StepArgs A,
   }
   if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
   if (tid < S.Q) dq[tid] = A.ctab[S.ctab_off + (int64_t)A.j * S.Q + tid - A.cshift];
+  if (tid < S.njc) jq[tid] = jc_coef(S, tid, ((double)A.j + 0.5) * S.dt);
   __syncthreads();
   SweepOut so;
   so.first = kk == 0;
@@ -257,7 +259,8 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_generic_kernel(StepArgs A,
     const int jj = (int)(r - (int64_t)i * S.N);
     const uint64_t di = A.desc[S.tab_off + i], dj = A.desc[S.tab_off + jj];
     const int64_t base = sg.off + b * S.N2;
-    const double2 acc = offdiag<ADJ>(S, di, dj, r, dq, sq, [&](int64_t idx) { return zin[base + idx]; });
+    const double2 acc =
+        offdiag_all<ADJ>(S, di, dj, r, dq, jq, sq, [&](int64_t idx) { return zin[base + idx]; });
     sweep_entry<ADJ>(A, so, base + r, S.h, diag_rate(S, di, dj), A.Etab[S.tab_off + i] - A.Etab[S.tab_off + jj],
                      acc, zin[base + r]);
   }
@@ -576,7 +579,7 @@ bool split_geo(const lb_plan *p, int sys, int k, SplitGeo *g) {
   if (k < LB_SPLIT_BASE) return false;
   const SysDev &S = p->sys[sys];
   const int ka = k - LB_SPLIT_BASE;
-  if (ka < 1 || ka >= S.Q) return false;
+  if (ka < 1 || ka >= S.Q || S.njc > 0) return false;
   g->q0 = S.Q - ka;
   g->NA = 1;
   for (int q = g->q0; q < S.Q; ++q) g->NA *= S.nlev[q];

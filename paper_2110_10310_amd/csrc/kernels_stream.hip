@@ -99,10 +99,12 @@ __global__ __launch_bounds__(STREAM_BLOCK) void apply_kernel(
     int64_t total) {
   __shared__ double sq[SQRT_TABLE];
   __shared__ double2 dq[QMAX];
+  __shared__ double2 jq[JCMAX];
   const SysDev &S = sysv[sys];
   const int tid = threadIdx.x;
   if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
   if (tid < S.Q) dq[tid] = control_value(S, alpha, carrier + S.carrier_off, tid, t);
+  if (tid < S.njc) jq[tid] = jc_coef(S, tid, t);
   __syncthreads();
   const int64_t g = (int64_t)blockIdx.x * STREAM_BLOCK + tid;
   if (g >= total) return;
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void apply_kernel(
   const double gam = diag_rate(S, di, dj);
   const double dE = Etab[S.tab_off + i] - Etab[S.tab_off + jj];
   const double2 *xs = x + b * S.N2;
-  const double2 acc = offdiag<ADJ>(S, di, dj, r, dq, sq, [&](int64_t idx) { return xs[idx]; });
+  const double2 acc = offdiag_all<ADJ>(S, di, dj, r, dq, jq, sq, [&](int64_t idx) { return xs[idx]; });
   y[g] = cadd(acc, cmul(diag_coef(gam, dE, ADJ), xs[r]));
 }
 

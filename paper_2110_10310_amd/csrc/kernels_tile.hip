@@ -437,6 +437,7 @@ static int pass_run(const lb_plan *p, int sys, int B, int mode, bool adj, const 
 
 int split_kl(const lb_plan *p, int sys) {
   const SysDev &S = p->sys[sys];
+  if (S.njc > 0) return 0;
   const int nl = S.nlev[0];
   for (int q = 1; q < S.Q; ++q)
     if (S.nlev[q] != nl) return 0;
@@ -472,6 +473,7 @@ int launch_split(const lb_plan *p, int sys, int B, int mode, bool adj, const dou
 // LB_OPT_TILE_KI option selects another instantiated shape (10*KR + KC).
 int tile_ki(const lb_plan *p, int sys, int ki_opt) {
   const SysDev &S = p->sys[sys];
+  if (S.njc > 0) return 0;  // the coupling runs on the generic kernels
   if (ki_opt >= LB_SPLIT_BASE) {  // two-pass sweep and apply (any levels)
     SplitGeo g;
     return split_geo(p, sys, ki_opt, &g) ? ki_opt : 0;

@@ -22,6 +22,7 @@ constexpr int QMAX = LB_LIMIT_QMAX;
 constexpr int DIGIT_BITS = 5;
 constexpr int SQRT_TABLE = 33;  // sqrt(k) for k = 0..32
 constexpr double TWO_PI = 6.283185307179586476925286766559;
+constexpr int JCMAX = QMAX * (QMAX - 1) / 2;  // Jaynes-Cummings pairs p > q
 
 // Per-system constants.  One array of these lives in device memory per plan.
 struct SysDev {
@@ -34,12 +35,17 @@ struct SysDev {
   double csum[QMAX];     // max over n of sqrt(n)[n>0] + sqrt(n+1)[n+1<nlev]
   double T, dt, h;       // h = dt/2
   double dtau;           // B-spline knot spacing T/(Ns-2)
-  double theta_jump;     // h * sum_q (nlev_q - 1)/T1_q
+  double theta_jump;     // h * sum_q (nlev_q - 1)/T1_q, plus the coupling bound
   double hDmax;          // h * max_ij |D_ij|
   int64_t tab_off;       // first row of this system in the energy/digit tables
   int64_t carrier_off;   // first entry in the carrier table ([Q][Nf])
   int64_t alpha_off;     // first entry in a concatenated alpha
   int64_t ctab_off;      // first entry in the control table ([NT][Q] complex)
+  // Jaynes-Cummings coupling (Sec. II): pair k couples subsystems jp[k] > jq[k]
+  // with g = jg[k] (rad/ns) and phase rate jd[k] = w_p^rot - w_q^rot (rad/ns).
+  int32_t njc;
+  int8_t jp[JCMAX], jq[JCMAX];
+  double jg[JCMAX], jd[JCMAX];
 };
 
 __device__ __forceinline__ int digit(uint64_t packed, int q) {
@@ -142,6 +148,55 @@ template <bool ADJ, class Load>
 __device__ __forceinline__ double2 offdiag(const SysDev &S, uint64_t di, uint64_t dj, int64_t r,
                                            const double2 *dq, const double *sq, Load ld) {
   return offdiag_range<ADJ>(S, di, dj, r, dq, sq, ld, 0, S.Q);
+}
+
+// Coefficient c_k = g e^{i Delta t} of Jaynes-Cummings pair k at time t.
+__device__ __forceinline__ double2 jc_coef(const SysDev &S, int k, double t) {
+  double sn, cs;
+  sincos(S.jd[k] * t, &sn, &cs);
+  return make_double2(S.jg[k] * cs, S.jg[k] * sn);
+}
+
+// The Jaynes-Cummings part of O x at entry r = i*N + j (Sec. II coupling
+// sum_{p>q} c a_p^+ a_q + c* a_p a_q^+, c = jq[k]; forward: -i [H, x]):
+//   -i [ c sqrt(n_p) sqrt(n_q+1) x_{i-e_p+e_q, j} + c* sqrt(n_p+1) sqrt(n_q) x_{i+e_p-e_q, j}
+//        - c sqrt(m_p+1) sqrt(m_q) x_{i, j+e_p-e_q} - c* sqrt(m_p) sqrt(m_q+1) x_{i, j-e_p+e_q} ]
+// (n, m: digits of i, j); the adjoint (+i [H, x]) flips the sign.
+template <bool ADJ, class Load>
+__device__ __forceinline__ double2 jc_terms(const SysDev &S, uint64_t di, uint64_t dj, int64_t r,
+                                            const double2 *jq, const double *sq, Load ld) {
+  double2 acc = make_double2(0.0, 0.0);
+  const int64_t N = S.N;
+  for (int k = 0; k < S.njc; ++k) {
+    const int p = S.jp[k], q = S.jq[k];
+    const int np = digit(di, p), nq = digit(di, q), mp = digit(dj, p), mq = digit(dj, q);
+    const int lp = S.nlev[p], lq = S.nlev[q];
+    const int64_t sp = S.stride[p], sqs = S.stride[q];
+    const double2 c = jq[k];
+    const double2 cc = make_double2(c.x, -c.y);
+    // row part
+    const bool r1 = np > 0 && nq + 1 < lq, r2 = np + 1 < lp && nq > 0;
+    const double w1 = r1 ? sq[np] * sq[nq + 1] : 0.0, w2 = r2 ? sq[np + 1] * sq[nq] : 0.0;
+    const double2 x1 = ld(r1 ? r + (sqs - sp) * N : r), x2 = ld(r2 ? r + (sp - sqs) * N : r);
+    // column part
+    const bool c1 = mp + 1 < lp && mq > 0, c2 = mp > 0 && mq + 1 < lq;
+    const double v1 = c1 ? sq[mp + 1] * sq[mq] : 0.0, v2 = c2 ? sq[mp] * sq[mq + 1] : 0.0;
+    const double2 y1 = ld(c1 ? r + (sp - sqs) : r), y2 = ld(c2 ? r + (sqs - sp) : r);
+    const double2 u = csub(cadd(cscale(w1, cmul(c, x1)), cscale(w2, cmul(cc, x2))),
+                           cadd(cscale(v1, cmul(c, y1)), cscale(v2, cmul(cc, y2))));
+    // -i u (forward), +i u (adjoint)
+    acc = ADJ ? cadd(acc, make_double2(-u.y, u.x)) : cadd(acc, make_double2(u.y, -u.x));
+  }
+  return acc;
+}
+
+// offdiag plus the coupling (jq may be NULL when the system has none).
+template <bool ADJ, class Load>
+__device__ __forceinline__ double2 offdiag_all(const SysDev &S, uint64_t di, uint64_t dj, int64_t r,
+                                               const double2 *dq, const double2 *jq, const double *sq, Load ld) {
+  double2 acc = offdiag<ADJ>(S, di, dj, r, dq, sq, ld);
+  if (S.njc > 0) acc = cadd(acc, jc_terms<ADJ>(S, di, dj, r, jq, sq, ld));
+  return acc;
 }
 
 // Gradient integrands of one entry for subsystem q (App. B eq.
