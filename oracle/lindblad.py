@@ -55,6 +55,7 @@ from threadpoolctl import threadpool_limits
 TWO_PI = 2.0 * np.pi
 KIND_FROB = 0
 KIND_TR = 1
+KIND_NM = 2
 
 # Dense superoperators are built while N^2 stays at or below this size;
 # above it the oracle works on density matrices with sparse operators.
@@ -75,7 +76,7 @@ def _one_blas_thread(fn):
     return wrapped
 
 __all__ = [
-    "TWO_PI", "KIND_FROB", "KIND_TR", "DENSE_MAX_N2",
+    "TWO_PI", "KIND_FROB", "KIND_TR", "KIND_NM", "DENSE_MAX_N2",
     "lowering", "embed", "system_hamiltonian", "coupling_hamiltonian", "bspline2", "spline_basis",
     "controls", "control_hamiltonian", "hamiltonian", "collapse_operators",
     "vec", "unvec", "superoperator", "lindbladian", "lindbladian_adjoint",
@@ -397,11 +398,15 @@ def imr_forward(sys, alpha, rho0, keep_states: bool = False, nsteps=None):
 # ----------------------------------------------------------------------------
 
 def merit(kind: int, rho, rhotar) -> float:
-    """J_Frob = 1/2 ||rho_tar - rho||_F^2;  J_Tr = 1 - Re Tr(rho_tar^+ rho)."""
+    """J_Frob = 1/2 ||rho_tar - rho||_F^2;  J_Tr = 1 - Re Tr(rho_tar^+ rho);
+    J_Nm = Tr(N_m rho), eq. (Jmeasure), with the observable N_m passed as
+    rhotar (real diagonal, so the trace is Re Tr(N_m^+ rho))."""
     if kind == KIND_FROB:
         return 0.5 * float(np.sum(np.abs(rhotar - rho) ** 2))
     if kind == KIND_TR:
         return 1.0 - float(np.real(np.trace(rhotar.conj().T @ rho)))
+    if kind == KIND_NM:
+        return float(np.real(np.trace(rhotar.conj().T @ rho)))
     raise ValueError(kind)
 
 
@@ -428,6 +433,8 @@ def terminal_adjoint(kind, rhoT, rhotar, beta):
         return w * (rhoT - rhotar)
     if kind == KIND_TR:
         return -w * rhotar
+    if kind == KIND_NM:
+        return w * rhotar
     raise ValueError(kind)
 
 

@@ -11,7 +11,8 @@ import scipy.interpolate as si
 import scipy.linalg as sla
 
 import oracle
-from workloads import System, basis_density_matrices, random_system, random_alpha
+from workloads import (System, basis_density_matrices, ensemble_state, gate_initial_states, observable_nm,
+                       random_alpha, random_pure_states, random_system)
 
 
 def mk(nlev, *, det=None, sk=None, ck=None, T1=None, T2=None, Ns=5, car=None, T=4.0, NT=40):
@@ -475,3 +476,67 @@ def test_operator_form_path_matches_dense_path(monkeypatch):
     assert np.max(np.abs(ro - rd)) < 1e-13
     assert Go == pytest.approx(Gd, rel=1e-12)
     assert np.max(np.abs(go - gd)) < 1e-11 * np.max(np.abs(gd))
+
+
+# ------------------------------------------------------------ J_Nm, ensemble and gate states
+
+def test_jnm_vanishes_only_at_its_target():
+    # Sec. III-B: J_Nm(rho) >= 0, and = 0 iff rho = |m><m|.
+    N, m = 6, 2
+    O = observable_nm(N, m)
+    assert abs(oracle.merit(oracle.KIND_NM, proj(N, m), O)) < 1e-15
+    rng = np.random.default_rng(31)
+    for r in random_pure_states(rng, N, 20):
+        assert oracle.merit(oracle.KIND_NM, r, O) > 1e-3
+    # the expected distance |l - m| of a basis state
+    for l in range(N):
+        assert abs(oracle.merit(oracle.KIND_NM, proj(N, l), O) - abs(l - m)) < 1e-15
+
+
+def test_ensemble_state_replaces_the_basis():
+    # Sec. III-B: the evolution is linear in rho(0) and J_Nm is linear in
+    # rho(T), so the ensemble state rho_s = (1/N^2) sum B^kj with M = 1 gives the
+    # objective and gradient of the N^2 basis matrices with M = N^2.
+    rng = np.random.default_rng(32)
+    s = random_system(rng, (2, 2), NT=10, T=1.0)
+    alpha = random_alpha(rng, s, amp=0.05)
+    N = s.N
+    O = observable_nm(N, 0)
+    basis = basis_density_matrices(N)
+    G1, g1 = oracle.value_and_gradient(s, alpha, ensemble_state(N)[None], O[None], np.ones(1), oracle.KIND_NM)
+    Gb, gb = oracle.value_and_gradient(s, alpha, basis, np.repeat(O[None], N * N, axis=0), np.ones(N * N),
+                                       oracle.KIND_NM)
+    assert abs(G1 - Gb) < 1e-14 * abs(Gb)
+    assert np.max(np.abs(g1 - gb)) < 1e-13 * np.max(np.abs(gb))
+
+
+def test_jnm_gradient_against_central_differences():
+    rng = np.random.default_rng(33)
+    s = random_system(rng, (2, 3), NT=8, T=0.8)
+    alpha = random_alpha(rng, s, amp=0.05)
+    N = s.N
+    rho0 = random_pure_states(rng, N, 2)
+    O = np.stack([observable_nm(N, 0), observable_nm(N, 4)])
+    beta = np.array([1.0, 0.6])
+    _, g = oracle.value_and_gradient(s, alpha, rho0, O, beta, oracle.KIND_NM)
+    h = 1e-6
+    for k in [(0, 1, 0, 0), (1, 3, 1, 1), (0, 4, 1, 0)]:
+        ap, am = alpha.copy(), alpha.copy()
+        ap[k] += h
+        am[k] -= h
+        fd = (oracle.value_and_gradient(s, ap, rho0, O, beta, oracle.KIND_NM)[0]
+              - oracle.value_and_gradient(s, am, rho0, O, beta, oracle.KIND_NM)[0]) / (2 * h)
+        assert abs(fd - g[k]) < 1e-7 * max(1.0, np.max(np.abs(g)))
+
+
+def test_gate_initial_states():
+    # Sec. III-C: rho_1 diagonal with distinct non-negative weights, rho_2 the
+    # pure uniform superposition, rho_3 = I/N; all density matrices.
+    N = 5
+    r1, r2, r3 = gate_initial_states(N)
+    d = np.real(np.diag(r1))
+    assert np.allclose(r1, np.diag(d)) and (d >= 0).all() and len(set(np.round(d, 14))) == N
+    assert abs(np.trace(r2 @ r2) - 1) < 1e-14 and np.allclose(r2 @ np.ones(N), np.ones(N))
+    assert np.allclose(r3, np.eye(N) / N)
+    for r in (r1, r2, r3):
+        assert abs(np.trace(r) - 1) < 1e-14 and np.allclose(r, r.conj().T)

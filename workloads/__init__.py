@@ -18,5 +18,10 @@ from .systems import (  # noqa: F401
     essential_embedding,
     cnot_essential,
     truncate_steps,
+    with_random_states,
+    observable_nm,
+    ensemble_state,
+    gate_initial_states,
+    gate_weights,
     n_alpha,
 )

@@ -121,6 +121,34 @@ def basis_density_matrices(n: int) -> np.ndarray:
     return out
 
 
+def observable_nm(N: int, m: int) -> np.ndarray:
+    """The observable N_m of J_Nm (Sec. III): diagonal, lambda_l = |l - m|."""
+    return np.diag(np.abs(np.arange(N) - m).astype(np.float64)).astype(np.complex128)
+
+
+def ensemble_state(N: int) -> np.ndarray:
+    """rho_s(0) = (1/N^2) sum_kj B^kj (Sec. III-B), from the basis matrices."""
+    return basis_density_matrices(N).sum(axis=0) / (N * N)
+
+
+def gate_initial_states(N: int) -> np.ndarray:
+    """The three initial states of gate optimisation (Sec. III-C): rho_1
+    diagonal with distinct weights lambda_j = 2 (N - j) / (N (N + 1)) (any
+    distinct non-negative values qualify; these sum to one), rho_2 the pure
+    uniform superposition, rho_3 = I / N."""
+    lam = 2.0 * (N - np.arange(N)) / (N * (N + 1))
+    psi = np.full(N, 1.0 / np.sqrt(N))
+    return np.stack([np.diag(lam), np.outer(psi, psi), np.eye(N) / N]).astype(np.complex128)
+
+
+def gate_weights(rho0: np.ndarray, first: float = 20.0) -> np.ndarray:
+    """beta_i = {first, 1, 1} / Tr(rho_i(0)^2): the emphasis on the first state
+    and the purity scaling suggested for J_Tr (Sec. III-C)."""
+    w = np.ones(rho0.shape[0])
+    w[0] = first
+    return w / np.real(np.einsum("bij,bji->b", rho0, rho0))
+
+
 def essential_embedding(nlev: Sequence[int], ness: Sequence[int]) -> np.ndarray:
     """Full-space basis index of every essential-level basis index.
 
@@ -325,6 +353,19 @@ def make_config(index: int) -> Problem:
     """The five named workloads, 1-based, each from its own seed."""
     rng = np.random.Generator(np.random.PCG64(CONFIG_SEED_BASE + index))
     return _MAKERS[index](rng)
+
+
+def with_random_states(prob: Problem, extra: int, seed: int) -> Problem:
+    """The same systems and controls with `extra` seeded random pure initial
+    states and targets (weight 1) appended to every system's batch."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho0, tar, beta = [], [], []
+    for k, s in enumerate(prob.systems):
+        rho0.append(np.concatenate([prob.rho0[k], random_pure_states(rng, s.N, extra)]))
+        tar.append(np.concatenate([prob.rhotar[k], random_pure_states(rng, s.N, extra)]))
+        beta.append(np.concatenate([prob.beta[k], np.ones(extra)]))
+    return Problem(prob.name + f"_plus{extra}", prob.systems, prob.alpha, rho0, tar, beta, prob.kind,
+                   prob.gamma2, prob.ckpt_every)
 
 
 def truncate_steps(prob: Problem, NT: int) -> Problem:
