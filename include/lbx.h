@@ -78,6 +78,8 @@ extern "C" {
 
 #define LB_J_FROB 0  /* J = 1/2 ||rho_tar - rho||_F^2            (Sec. III, eq. Jmeasure) */
 #define LB_J_TR 1    /* J = 1 - Re Tr(rho_tar^+ rho)              (Sec. III, eq. Jmeasure) */
+#define LB_J_NM 2    /* J = Re Tr(O^+ rho) = Tr(N_m rho) with the observable O = N_m
+                        (diagonal |l - m|) passed in place of rho_tar (Sec. III, eq. Jmeasure) */
 
 /* Workspace queries (lb_workspace_bytes). */
 #define LB_OP_IMR_STEP 0

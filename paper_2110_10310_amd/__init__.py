@@ -17,3 +17,4 @@ from .api import (  # noqa: F401
     LindbladObjective,
     lindblad_objective,
 )
+from .optim import optimize  # noqa: F401

@@ -21,6 +21,7 @@ LB_ENONFINITE = -5
 
 LB_J_FROB = 0
 LB_J_TR = 1
+LB_J_NM = 2
 
 LB_OP_IMR_STEP = 0
 LB_OP_FORWARD = 1

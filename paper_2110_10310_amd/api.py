@@ -17,7 +17,8 @@ import torch
 from . import _native as nat
 from ._native import check, lib
 
-KIND = {"frob": nat.LB_J_FROB, "tr": nat.LB_J_TR, 0: nat.LB_J_FROB, 1: nat.LB_J_TR}
+KIND = {"frob": nat.LB_J_FROB, "tr": nat.LB_J_TR, "nm": nat.LB_J_NM, 0: nat.LB_J_FROB, 1: nat.LB_J_TR,
+        2: nat.LB_J_NM}
 PATHS = {"auto": 0, "lds": 1, "stream": 2}
 
 

@@ -1564,7 +1564,7 @@ extern "C" int objective(const lb_plan *p, int32_t kind, const void *rhoT, const
                          const int32_t *batch_per_sys, double gamma2, const double *alpha, double *G, double *J,
                          void *ws, size_t ws_bytes, void *stream) {
   if (int rc = check_plan(p)) return rc;
-  if (kind != LB_J_FROB && kind != LB_J_TR) return fail(LB_EINVAL, "unknown merit functional");
+  if (kind != LB_J_FROB && kind != LB_J_TR && kind != LB_J_NM) return fail(LB_EINVAL, "unknown merit functional");
   if (!rhoT || !rhotar || !beta || !batch_per_sys || !alpha || !G || !ws) return fail(LB_EINVAL, "NULL argument");
   if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
   const lbx_opts o = snapshot(p);
@@ -1589,7 +1589,7 @@ extern "C" int adjoint_backward(const lb_plan *p, int32_t kind, const double *al
                                 const int32_t *batch_per_sys, double gamma2, const double *gscale, double *grad,
                                 void *ws, size_t ws_bytes, void *stream) {
   if (int rc = check_plan(p)) return rc;
-  if (kind != LB_J_FROB && kind != LB_J_TR) return fail(LB_EINVAL, "unknown merit functional");
+  if (kind != LB_J_FROB && kind != LB_J_TR && kind != LB_J_NM) return fail(LB_EINVAL, "unknown merit functional");
   if (!alpha || !traj || !rhotar || !beta || !batch_per_sys || !grad || !ws) return fail(LB_EINVAL, "NULL argument");
   if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
   if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
@@ -1629,7 +1629,7 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
                                 int32_t ckpt_every, double *G, double *grad, void *rhoT_out, void *ws, size_t ws_bytes,
                                 void *stream) {
   if (int rc = check_plan(p)) return rc;
-  if (kind != LB_J_FROB && kind != LB_J_TR) return fail(LB_EINVAL, "unknown merit functional");
+  if (kind != LB_J_FROB && kind != LB_J_TR && kind != LB_J_NM) return fail(LB_EINVAL, "unknown merit functional");
   if (!alpha || !rho0 || !rhotar || !beta || !batch_per_sys || !G || !grad || !ws)
     return fail(LB_EINVAL, "NULL argument");
   if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");

@@ -162,7 +162,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
     // Terminal condition (App. B): qh = (beta/M) dJ/d(conj q) at q = rho(T).
     qn[k] = ok[k] ? hist[(int64_t)NT * N2 + ee[k]] : make_double2(0.0, 0.0);
     const double2 t = ok[k] ? rhotar[it.off + ee[k]] : make_double2(0.0, 0.0);
-    qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qn[k], t)) : cscale(-it.wterm, t);
+    qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qn[k], t)) : cscale(kind == LB_J_NM ? it.wterm : -it.wterm, t);
     dn[k] = make_double2(0.0, 0.0);
   }
   // Two LDS stage buffers; selected by value (not through a pointer array)

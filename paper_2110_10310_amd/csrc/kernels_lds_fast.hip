@@ -439,7 +439,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_fast_kernel(
     // Terminal condition (App. B): qh = (beta/M) dJ/d(conj q) at q = rho(T).
     const double2 qT = ok[k] ? hist[(int64_t)NT * N2 + ee[k]] : make_double2(0.0, 0.0);
     const double2 t = ok[k] ? rhotar[it.off + ee[k]] : make_double2(0.0, 0.0);
-    qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qT, t)) : cscale(-it.wterm, t);
+    qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qT, t)) : cscale(kind == LB_J_NM ? it.wterm : -it.wterm, t);
     dn[k] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i < HL; ++i) dh[k][i] = make_double2(0.0, 0.0);

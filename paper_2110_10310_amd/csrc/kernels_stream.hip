@@ -286,7 +286,7 @@ int launch_stream_grad_finalize(const lb_plan *p, const StreamSeg *d_segs, int n
 // Adjoint terminal condition (App. B): qh = (beta_i/M) dJ/d(conj q), times
 // the weight gscale[s] of the system's objective when gscale is given (the
 // incoming gradient of a backward pass; the adjoint is linear in it).
-//   J_Frob: rho(T) - rho_tar;   J_Tr: -rho_tar.
+//   J_Frob: rho(T) - rho_tar;   J_Tr: -rho_tar;   J_Nm: the observable N_m.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(STREAM_BLOCK) void terminal_kernel(
     const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg, int kind,
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(STREAM_BLOCK) void terminal_kernel(
   const double wgt = beta[seg_state0[sseg] + b] / (double)sg.nstates * (gscale ? gscale[sg.sys] : 1.0);
   const int64_t e = sg.off + local;
   const double2 t = rhotar[sg.boff + local];
-  qh[e] = kind == LB_J_FROB ? cscale(wgt, csub(rhoT[e], t)) : cscale(-wgt, t);
+  qh[e] = kind == LB_J_FROB ? cscale(wgt, csub(rhoT[e], t)) : cscale(kind == LB_J_NM ? wgt : -wgt, t);
 }
 
 int launch_terminal(const lb_plan *p, int kind, const StreamSeg *d_segs, int nseg, int64_t nblk,
@@ -362,7 +362,7 @@ __global__ void objective_final_kernel(const SysDev *__restrict__ sysv, int nsys
   for (int st = st0; st < st1; ++st) {
     double v = 0.0;
     for (int k = 0; k < OBJ_PARTS; ++k) v += partial[(int64_t)st * OBJ_PARTS + k];
-    const double Jst = kind == LB_J_FROB ? 0.5 * v : 1.0 - v;
+    const double Jst = kind == LB_J_FROB ? 0.5 * v : kind == LB_J_TR ? 1.0 - v : v;
     if (J) J[st] = Jst;
     acc += beta[st] * Jst;
   }

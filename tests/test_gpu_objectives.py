@@ -1,0 +1,101 @@
+"""The rest of the objective family and the optimiser on the GPU:
+J_Nm (Sec. III, eq. Jmeasure) with the ensemble state, the three gate
+initial states with purity-scaled weights (Sec. III-C), both against the
+oracle, and L-BFGS (Sec. III) driving the adjoint gradient on small
+synthetic problems (qualitative convergence)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from workloads import (  # noqa: E402
+    System, cnot_essential, ensemble_state, gate_initial_states, gate_weights, observable_nm, random_alpha,
+    random_system,
+)
+
+from _gpu import dev, rel_state_err, say  # noqa: E402
+
+STATE_TOL = 1e-12
+GRAD_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def lbx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_10310_amd as lbx
+    return lbx
+
+
+def _compare(lbx, s, alpha, rho0, tar, beta, kind, path):
+    B = rho0.shape[0]
+    plan = lbx.Plan([s], path=path)
+    G, grad, rhoT = lbx.adjoint_gradient(plan, kind, dev(alpha.reshape(-1)), dev(rho0), dev(tar), dev(beta), [B],
+                                         0.0, 0, want_rhoT=True)
+    Gr, gr, rT = oracle.value_and_gradient(s, alpha, rho0, tar, beta, kind, return_final=True)
+    assert rel_state_err([rhoT.cpu().numpy().reshape(B, s.N, s.N)], [rT]) < STATE_TOL
+    assert abs(G.item() - Gr) <= 1e-12 * abs(Gr)
+    assert np.max(np.abs(grad.cpu().numpy().reshape(gr.shape) - gr)) <= GRAD_TOL * np.max(np.abs(gr))
+
+
+@pytest.mark.parametrize("nlev,path", [((2, 2, 3), "auto"), ((2, 2, 3), "stream"), ((3, 3), "lds")])
+def test_jnm_with_the_ensemble_state(lbx, nlev, path):
+    rng = np.random.default_rng(700 + sum(nlev))
+    s = random_system(rng, nlev, NT=16, T=1.6, Ns=5, Nf=2)
+    alpha = random_alpha(rng, s, amp=0.03)
+    N = s.N
+    say("J_Nm ensemble", nlev, path)
+    _compare(lbx, s, alpha, ensemble_state(N)[None], observable_nm(N, 0)[None], np.ones(1), 2, path)
+
+
+def test_gate_initial_states_with_purity_weights(lbx):
+    rng = np.random.default_rng(710)
+    s = random_system(rng, (2, 2), NT=16, T=1.6, Ns=5, Nf=2, jc=0.03)
+    alpha = random_alpha(rng, s, amp=0.03)
+    V = cnot_essential()
+    rho0 = gate_initial_states(4)
+    tar = np.stack([V @ r @ V.conj().T for r in rho0])
+    beta = gate_weights(rho0)
+    for kind in (0, 1):
+        say("gate states", kind)
+        _compare(lbx, s, alpha, rho0, tar, beta, kind, "auto")
+
+
+def _qubit(T, NT, Ns=8):
+    return System(nlev=(2,), detuning=np.zeros(1), selfkerr=np.zeros(1), crosskerr=np.zeros((1, 1)),
+                  T1=np.full(1, 1.0e5), T2=np.full(1, 8.0e4), Ns=Ns, carriers=np.zeros((1, 1)), T=T, NT=NT)
+
+
+def test_lbfgs_flips_a_qubit(lbx):
+    s = _qubit(10.0, 200)
+    rng = np.random.default_rng(720)
+    alpha0 = random_alpha(rng, s, amp=0.005).reshape(-1)
+    r0 = np.zeros((1, 2, 2), complex)
+    r0[0, 0, 0] = 1
+    tar = np.zeros((1, 2, 2), complex)
+    tar[0, 1, 1] = 1
+    plan = lbx.Plan([s])
+    say("lbfgs qubit flip")
+    alpha, hist = lbx.optimize(plan, 0, dev(alpha0), dev(r0), dev(tar), dev(np.ones(1)), [1], max_iter=60)
+    assert hist[0] > 0.5 and min(hist) < 1e-4, (hist[0], min(hist))
+    # the returned controls reach the target state on the oracle too
+    G = oracle.value_and_gradient(s, alpha.cpu().numpy().reshape(s.Q, s.Ns, 1, 2), r0, tar, np.ones(1), 0)[0]
+    assert G < 1e-4
+
+
+def test_lbfgs_reduces_a_two_qubit_gate_objective(lbx):
+    rng = np.random.default_rng(730)
+    s = random_system(rng, (2, 2), NT=200, T=20.0, Ns=8, Nf=1, strong_dissipation=False, some_terms_off=False,
+                      jc=0.01)
+    alpha0 = random_alpha(rng, s, amp=0.005).reshape(-1)
+    V = cnot_essential()
+    rho0 = gate_initial_states(4)
+    tar = np.stack([V @ r @ V.conj().T for r in rho0])
+    beta = gate_weights(rho0)
+    plan = lbx.Plan([s])
+    say("lbfgs two-qubit gate")
+    _, hist = lbx.optimize(plan, 0, dev(alpha0), dev(rho0), dev(tar), dev(beta), [3], max_iter=40)
+    assert min(hist) < 0.5 * hist[0], (hist[0], min(hist))
