@@ -32,6 +32,12 @@ Readings of passages that are silent or garbled (listed in the design doc too):
   conjugate-Wirtinger gradient of the merit functional).
 * The terminal condition is (beta_i / M) dJ/d(conj q) with M the number of
   initial states of the system.
+* Running penalty (gamma1 term of eq. optimproblem): averaged over the
+  initial states with the same 1/M as the final-time term, without the
+  weights beta_i, and integrated by the left rectangle rule on the time grid,
+  dt sum_{j=0}^{NT-1} beta(t_j) J(q^j), t_j = j dt; the adjoint source at step
+  j is then gamma1 dt beta(t_j) (1/M) dJ/d(conj q^j) (the source term of App.
+  B, with the rectangle weight dt).
 
 Parity pins (tests/test_oracle_pins.py): discrete and continuum T1 decay,
 dephasing rate and phase, the T1 cascade, closed two-level Rabi oscillation
@@ -42,7 +48,9 @@ operators, IMR against the matrix exponential (second order), the Cayley form
 of one IMR step, the J_Frob/J_Tr identity, basis-matrix purity, B-spline
 partition of unity and agreement with scipy's B-spline basis, dense against
 operator form, the adjoint dot-product identity, and the gradient against
-central finite differences and a Taylor remainder test.
+central finite differences and a Taylor remainder test.  The running penalty
+against the closed-form integral of a decaying qubit (its left-rectangle
+error term included), and its gradient against central differences.
 """
 from __future__ import annotations
 
@@ -81,7 +89,7 @@ __all__ = [
     "controls", "control_hamiltonian", "hamiltonian", "collapse_operators",
     "vec", "unvec", "superoperator", "lindbladian", "lindbladian_adjoint",
     "lindbladian_entries", "imr_forward", "merit", "objective",
-    "terminal_adjoint", "value_and_gradient", "fidelity",
+    "terminal_adjoint", "value_and_gradient", "fidelity", "penalty_weight", "running_penalty",
 ]
 
 
@@ -425,6 +433,26 @@ def objective(kind, rhoT, rhotar, beta, gamma2, alpha) -> float:
     return J / Mst + 0.5 * gamma2 * float(np.sum(np.asarray(alpha) ** 2))
 
 
+def penalty_weight(sys, a: float, t):
+    """beta(t) = (1/a) exp(-((t - T)/a)^2), the weight of the running penalty
+    in Sec. III (a > 0, in ns)."""
+    return np.exp(-(((np.asarray(t, dtype=np.float64) - sys.T) / a) ** 2)) / a
+
+
+def running_penalty(sys, kind, states, rhotar, gamma1, a) -> float:
+    """gamma1 (1/M) sum_i dt sum_{j=0}^{NT-1} beta(t_j) J(rho_tar_i, q_i^j):
+    the gamma1 term of eq. (optimproblem) by the left rectangle rule.
+    states: the list of q^j [M, N, N], j = 0..NT."""
+    if gamma1 == 0.0:
+        return 0.0
+    Mst = rhotar.shape[0]
+    tot = 0.0
+    for j in range(sys.NT):
+        w = sys.dt * float(penalty_weight(sys, a, j * sys.dt))
+        tot += w * sum(merit(kind, states[j][i], rhotar[i]) for i in range(Mst))
+    return gamma1 * tot / Mst
+
+
 def terminal_adjoint(kind, rhoT, rhotar, beta):
     """qhat^{NT} = (beta_i/M) dJ/d(conj q), App. B terminal condition."""
     Mst = rhoT.shape[0]
@@ -456,13 +484,17 @@ def _dcontrol_dalpha(sys, t):
 
 
 @_one_blas_thread
-def value_and_gradient(sys, alpha, rho0, rhotar, beta, kind, gamma2=0.0, return_final=False):
+def value_and_gradient(sys, alpha, rho0, rhotar, beta, kind, gamma2=0.0, return_final=False, gamma1=0.0,
+                       penalty_a=1.0):
     """Objective G and its exact discrete gradient, App. B.
 
     Backward for j = NT-1..0 with M = M(t_j + dt/2):
         (I - dt/2 M^+) zhat^j = qhat^{j+1}
         grad += dt Re <zhat^j, (dM/dalpha) z^j>
-        qhat^j = qhat^{j+1} + dt M^+ zhat^j
+        qhat^j = qhat^{j+1} + dt M^+ zhat^j + (source of the running penalty)
+    The source is gamma1 dt beta(t_j) (1/M) dJ/d(conj q^j), i.e. the terminal
+    condition's formula with gamma1 dt beta(t_j) in place of beta_i
+    (``penalty_a`` is the width a of beta(t)).
     with z^j from (linsystem_primal).  M depends on alpha only through the
     control Hamiltonian, which is linear in d_q and conj(d_q):
         dM/dalpha_k = c_k Sa_q + conj(c_k) Sad_q,
@@ -474,7 +506,13 @@ def value_and_gradient(sys, alpha, rho0, rhotar, beta, kind, gamma2=0.0, return_
     dt = sys.dt
     rhoT, states = imr_forward(sys, alpha, rho0, keep_states=True)
     G = objective(kind, rhoT, rhotar, beta, gamma2, alpha)
+    G += running_penalty(sys, kind, states, rhotar, gamma1, penalty_a)
     qhat = terminal_adjoint(kind, rhoT, rhotar, beta)
+    Mst = rhotar.shape[0]
+
+    def source(j):
+        w = gamma1 * sys.dt * float(penalty_weight(sys, penalty_a, j * dt))
+        return terminal_adjoint(kind, states[j], rhotar, np.full(Mst, w))
     grad = np.zeros_like(np.asarray(alpha, dtype=np.float64))
     avec = [embed(lowering(sys.nlev[q]), q, sys.nlev) for q in range(sys.Q)]
     if _dense_mode(sys):
@@ -495,6 +533,8 @@ def value_and_gradient(sys, alpha, rho0, rhotar, beta, kind, gamma2=0.0, return_
                 v = np.sum(Zh.conj() * (Sad[q] @ Z))
                 grad[q] += dt * np.real(c[q] * u + np.conj(c[q]) * v)
             Qh = Qh + dt * (M.conj().T @ Zh)
+            if gamma1 != 0.0:
+                Qh = Qh + np.stack([vec(r) for r in source(j)], axis=1)
     else:
         ops = (system_hamiltonian(sys, True), collapse_operators(sys, True))
         aS = [embed(lowering(sys.nlev[q]), q, sys.nlev, True) for q in range(sys.Q)]
@@ -515,5 +555,7 @@ def value_and_gradient(sys, alpha, rho0, rhotar, beta, kind, gamma2=0.0, return_
                     v = np.sum(zh.conj() * Sadz)
                     grad[q] += dt * np.real(c[q] * u + np.conj(c[q]) * v)
                 qhat[b] = qhat[b] + dt * unvec(MHv(vec(zh)), N)
+            if gamma1 != 0.0:
+                qhat = qhat + source(j)
     grad = grad + gamma2 * np.asarray(alpha)
     return (G, grad, rhoT) if return_final else (G, grad)

@@ -540,3 +540,64 @@ def test_gate_initial_states():
     assert np.allclose(r3, np.eye(N) / N)
     for r in (r1, r2, r3):
         assert abs(np.trace(r) - 1) < 1e-14 and np.allclose(r, r.conj().T)
+
+
+# ------------------------------------------------------------ running penalty
+
+def _decay_penalty_integral(T, T1, a):
+    """int_0^T (1/a) exp(-((t-T)/a)^2) exp(-t/T1) dt by completing the square."""
+    from scipy.special import erf
+    c = a * a / (2 * T1)
+    return 0.5 * np.sqrt(np.pi) * np.exp(a * a / (4 * T1 * T1) - T / T1) * (erf(c / a) + erf((T - c) / a))
+
+
+def test_running_penalty_matches_the_integral_for_a_decaying_qubit():
+    # J_Nm with m = 0 on a decaying qubit is rho_11(t) = exp(-t/T1) in the
+    # continuum.  The left rectangle sum differs from the integral by
+    # -(dt/2)(f(T) - f(0)) + O(dt^2) (Euler-Maclaurin): with that term added
+    # the error falls fourfold per halving of dt.  A right rectangle sum, a
+    # missing dt or a wrong weight fails this.
+    T, T1, a, g1 = 5.0, 7.0, 1.3, 0.8
+    I = _decay_penalty_integral(T, T1, a)
+    f = lambda t: np.exp(-(((t - T) / a) ** 2)) / a * np.exp(-t / T1)
+    O = observable_nm(2, 0)[None]
+    errs = []
+    for NT in (40, 80, 160):
+        s = mk((2,), T1=[T1], T=T, NT=NT)
+        alpha = np.zeros((1, s.Ns, 1, 2))
+        _, states = oracle.imr_forward(s, alpha, proj(2, 1)[None], keep_states=True)
+        P = oracle.running_penalty(s, oracle.KIND_NM, states, O, g1, a)
+        G, _ = oracle.value_and_gradient(s, alpha, proj(2, 1)[None], O, np.zeros(1), oracle.KIND_NM, gamma1=g1,
+                                         penalty_a=a)
+        assert G == pytest.approx(P, rel=1e-14)  # beta = 0 leaves only the penalty
+        errs.append(abs(P / g1 + 0.5 * s.dt * (f(T) - f(0.0)) - I))
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+    assert errs[-1] < 3e-5 * I
+
+
+@pytest.mark.parametrize("kind", [oracle.KIND_FROB, oracle.KIND_TR, oracle.KIND_NM])
+def test_running_penalty_gradient_against_central_differences(kind):
+    rng = np.random.default_rng(40 + kind)
+    s = random_system(rng, (2, 3), NT=14, T=2.0, Ns=4, Nf=2)
+    alpha = random_alpha(rng, s, amp=0.05)
+    from workloads import random_pure_states
+    rho0 = random_pure_states(rng, s.N, 3)
+    tar = random_pure_states(rng, s.N, 3) if kind != oracle.KIND_NM else np.repeat(observable_nm(s.N, 1)[None], 3, 0)
+    beta = rng.uniform(0.5, 2.0, 3)
+    kw = dict(gamma1=0.7, penalty_a=0.6)
+    G, g = oracle.value_and_gradient(s, alpha, rho0, tar, beta, kind, 0.1, **kw)
+    G0, g0 = oracle.value_and_gradient(s, alpha, rho0, tar, beta, kind, 0.1)
+    assert abs(G - G0) > 1e-3 * abs(G0) and np.max(np.abs(g - g0)) > 1e-3 * np.max(np.abs(g0))
+
+    def Gof(al):
+        return oracle.value_and_gradient(s, al, rho0, tar, beta, kind, 0.1, **kw)[0]
+
+    h = 1e-6
+    fd = np.zeros_like(alpha)
+    for idx in np.ndindex(alpha.shape):
+        ap = alpha.copy()
+        am = alpha.copy()
+        ap[idx] += h
+        am[idx] -= h
+        fd[idx] = (Gof(ap) - Gof(am)) / (2 * h)
+    assert np.max(np.abs(g - fd)) < 1e-7 * np.max(np.abs(g))
