@@ -274,7 +274,9 @@ int forward_solve(const lb_plan *plan, const double *alpha, const void *rho0, vo
                   size_t ws_bytes, void *stream);
 
 /* G_s = (1/M_s) sum_i beta_i J(rho_tar_i, rho_i(T)) + gamma2/2 ||alpha_s||^2 for
- * every system s (Sec. III eq. optimproblem with gamma1 = 0), M_s = batch_per_sys[s].
+ * every system s (Sec. III eq. optimproblem with gamma1 = 0: the running
+ * penalty needs the whole trajectory, adjoint_gradient computes it),
+ * M_s = batch_per_sys[s].
  * rhoT, rhotar: DEVICE batched states; beta: DEVICE [total states];
  * alpha: DEVICE; G: DEVICE [nsys]; J: DEVICE [total states] or NULL, receives
  * each J_i (unweighted).  ws: DEVICE, lb_workspace_bytes(LB_OP_FORWARD).
@@ -303,13 +305,22 @@ int adjoint_backward(const lb_plan *plan, int32_t kind, const double *alpha, con
  * (beta_i/M) dJ/d(conj q), adjoint implicit-midpoint sweep backwards with
  * recomputation between checkpoints, and the gradient reduction
  * dG/dalpha = sum_j dt Re <zh^j, dM/dalpha z^j> + gamma2 alpha.
+ * gamma1 != 0 adds the running penalty of Sec. III eq. optimproblem,
+ *   gamma1 (1/M_s) sum_i dt sum_{j=0}^{NT-1} beta(t_j) J(rho_tar_i, q_i^j),
+ *   beta(t) = exp(-((t - T)/a)^2) / a,  a = penalty_a > 0 [ns],
+ * the time integral taken by the left rectangle rule on the step grid and
+ * averaged over the initial states without the weights beta_i; the adjoint
+ * then carries its source term gamma1 dt beta(t_j) (1/M) dJ/d(conj q^j)
+ * (App. B).  With it, LDS-resident systems run on the generic LDS kernels.
  * G: DEVICE [nsys]; grad: DEVICE like alpha; rhoT: DEVICE batched states or
  * NULL.  ws: DEVICE, lb_workspace_bytes(LB_OP_GRADIENT, ckpt_every) bytes.
- * The status (LB_OPT_SYNC) is LB_ENONFINITE when a G is not finite. */
+ * Errors: LB_EINVAL for a non-finite gamma1 or gamma2, or (gamma1 != 0) a
+ * penalty_a that is not positive and finite.  The status (LB_OPT_SYNC) is
+ * LB_ENONFINITE when a G is not finite. */
 int adjoint_gradient(const lb_plan *plan, int32_t kind, const double *alpha, const void *rho0,
                      const void *rhotar, const double *beta, const int32_t *batch_per_sys,
-                     double gamma2, int32_t ckpt_every, double *G, double *grad, void *rhoT,
-                     void *ws, size_t ws_bytes, void *stream);
+                     double gamma2, double gamma1, double penalty_a, int32_t ckpt_every, double *G,
+                     double *grad, void *rhoT, void *ws, size_t ws_bytes, void *stream);
 
 /* Autotuner for the streamed systems of batch_per_sys (HOST): times a few
  * implicit-midpoint steps of the generic step kernel and of every

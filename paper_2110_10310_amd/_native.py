@@ -75,8 +75,8 @@ SIGNATURES = {
     "forward_solve": (C.c_int, [_p, _p, _p, _p, _ip, _p, _i32, _p, C.c_size_t, _p]),
     "objective": (C.c_int, [_p, _i32, _p, _p, _p, _ip, C.c_double, _p, _p, _p, _p,
                             C.c_size_t, _p]),
-    "adjoint_gradient": (C.c_int, [_p, _i32, _p, _p, _p, _p, _ip, C.c_double, _i32, _p, _p,
-                                   _p, _p, C.c_size_t, _p]),
+    "adjoint_gradient": (C.c_int, [_p, _i32, _p, _p, _p, _p, _ip, C.c_double, C.c_double, C.c_double, _i32,
+                                   _p, _p, _p, _p, C.c_size_t, _p]),
     "adjoint_backward": (C.c_int, [_p, _i32, _p, _p, _i32, _p, _p, _ip, C.c_double, _p, _p,
                                    _p, C.c_size_t, _p]),
     "lb_trajectory_bytes": (C.c_int, [_p, _ip, _i32, C.POINTER(C.c_size_t)]),

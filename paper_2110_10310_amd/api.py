@@ -323,10 +323,11 @@ def objective(plan: Plan, kind, rhoT: torch.Tensor, rhotar: torch.Tensor, beta: 
 def adjoint_gradient(plan: Plan, kind, alpha: torch.Tensor, rho0: torch.Tensor,
                      rhotar: torch.Tensor, beta: torch.Tensor, batch: Sequence[int],
                      gamma2: float = 0.0, ckpt_every: int = 1, want_rhoT: bool = False,
-                     workspace: torch.Tensor | None = None):
+                     workspace: torch.Tensor | None = None, gamma1: float = 0.0, penalty_a: float = 1.0):
     """(G per system, dG/dalpha, rho(T) or None).  `workspace` (uint8, at
     least Plan.workspace_bytes(LB_OP_GRADIENT, batch, ckpt_every)) replaces
-    the plan's cached one: calls that may overlap need their own."""
+    the plan's cached one: calls that may overlap need their own.  `gamma1`
+    and `penalty_a` add the running penalty (weight gamma1, width a in ns)."""
     b = plan.batch_array(batch)
     _need(alpha, "alpha", torch.float64, int(plan.alpha_off[-1]))
     _states(plan, rho0, "rho0", batch)
@@ -342,8 +343,9 @@ def adjoint_gradient(plan: Plan, kind, alpha: torch.Tensor, rho0: torch.Tensor,
         if ws.numel() < plan.workspace_bytes(nat.LB_OP_GRADIENT, batch, ckpt_every):
             raise ValueError("workspace is smaller than Plan.workspace_bytes")
     check(lib.adjoint_gradient(plan.handle, KIND[kind], _vp(alpha), _vp(rho0), _vp(rhotar),
-                               _vp(beta), b.ctypes.data_as(nat._ip), float(gamma2), int(ckpt_every),
-                               _vp(G), _vp(grad), _vp(rhoT) if rhoT is not None else None,
+                               _vp(beta), b.ctypes.data_as(nat._ip), float(gamma2), float(gamma1),
+                               float(penalty_a), int(ckpt_every), _vp(G), _vp(grad),
+                               _vp(rhoT) if rhoT is not None else None,
                                _vp(ws), ws.numel(), _stream()), "adjoint_gradient")
     return G, grad, rhoT
 
@@ -371,18 +373,28 @@ def adjoint_backward(plan: Plan, kind, alpha: torch.Tensor, traj: torch.Tensor, 
 class LindbladObjective(torch.autograd.Function):
     """G(alpha) per system; backward runs the discrete adjoint (App. B).
 
-    forward(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2, ckpt_every).
-    The forward pass integrates every state (forward_solve) and forms G
-    (objective); when alpha requires a gradient it keeps the forward
-    trajectory (checkpoints every ckpt_every steps, see lb_workspace_bytes)
-    for the backward pass.  The backward pass runs the adjoint sweep from that
-    trajectory with the incoming gradient of G as the weights of the terminal
-    conditions (adjoint_backward).
+    forward(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2, ckpt_every,
+    gamma1, penalty_a).  The forward pass integrates every state
+    (forward_solve) and forms G (objective); when alpha requires a gradient it
+    keeps the forward trajectory (checkpoints every ckpt_every steps, see
+    lb_workspace_bytes) for the backward pass.  The backward pass runs the
+    adjoint sweep from that trajectory with the incoming gradient of G as the
+    weights of the terminal conditions (adjoint_backward).  With a running
+    penalty (gamma1 != 0) G needs every state of the trajectory: the forward
+    pass then runs adjoint_gradient, and the backward pass scales its
+    gradient by the incoming one.
     """
 
     @staticmethod
-    def forward(ctx, alpha, plan, kind, rho0, rhotar, beta, batch, gamma2=0.0, ckpt_every=0):
+    def forward(ctx, alpha, plan, kind, rho0, rhotar, beta, batch, gamma2=0.0, ckpt_every=0, gamma1=0.0,
+                penalty_a=1.0):
         alpha = alpha.detach().contiguous()
+        if gamma1 != 0.0:
+            G, grad, _ = adjoint_gradient(plan, kind, alpha, rho0, rhotar, beta, batch, gamma2, ckpt_every,
+                                          gamma1=gamma1, penalty_a=penalty_a)
+            ctx.grads, ctx.alpha_off = grad, plan.alpha_off
+            return G
+        ctx.grads = None
         traj = plan.trajectory(batch, ckpt_every) if ctx.needs_input_grad[0] else None
         rhoT = forward_solve(plan, alpha, rho0, batch, traj=traj, ckpt_every=ckpt_every)
         G, _ = objective(plan, kind, rhoT, rhotar, beta, batch, gamma2, alpha)
@@ -393,12 +405,22 @@ class LindbladObjective(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gG):
-        alpha, traj, rhotar, beta = ctx.saved_tensors
         gscale = gG.detach().to(torch.float64).contiguous()
+        nones = (None,) * 10
+        if ctx.grads is not None:
+            # one gradient per system, each over that system's own coefficients
+            g = ctx.grads.clone()
+            off = ctx.alpha_off
+            for s in range(len(off) - 1):
+                g[int(off[s]):int(off[s + 1])] *= gscale[s]
+            return (g,) + nones
+        alpha, traj, rhotar, beta = ctx.saved_tensors
         grad = adjoint_backward(ctx.plan, ctx.kind, alpha, traj, ctx.ckpt_every, rhotar, beta, ctx.batch,
                                 ctx.gamma2, gscale)
-        return grad, None, None, None, None, None, None, None, None
+        return (grad,) + nones
 
 
-def lindblad_objective(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2=0.0, ckpt_every=0):
-    return LindbladObjective.apply(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2, ckpt_every)
+def lindblad_objective(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2=0.0, ckpt_every=0, gamma1=0.0,
+                       penalty_a=1.0):
+    return LindbladObjective.apply(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2, ckpt_every, gamma1,
+                                   penalty_a)

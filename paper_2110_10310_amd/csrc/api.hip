@@ -147,6 +147,9 @@ struct BatchMeta {
   int32_t *d_state_sys = nullptr;
   int64_t *d_state_off = nullptr;
   int32_t *d_sys_state0 = nullptr;
+  // running penalty: per system {first stream block, blocks, first LDS item, items}
+  std::vector<int64_t> pen_rng;
+  int64_t *d_pen_rng = nullptr;
 };
 
 struct PlanExtra {
@@ -195,8 +198,10 @@ int ckpt_count(int NT, int c) { return (NT - 1) / c + 2; }
 bool streams_small(int ckpt_every) { return ckpt_every > 1; }
 
 // path_override: -1 uses the option LB_OPT_PATH.
+// generic_lds: every LDS-resident system on the generic kernels (the
+// specialised ones have no running-penalty source).
 int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool stream_small,
-                BatchMeta **out, int path_override = -1) {
+                BatchMeta **out, int path_override = -1, bool generic_lds = false) {
   const int nsys = (int)p->sys.size();
   const int path = path_override >= 0 ? path_override : o.path;
   std::vector<int32_t> key(batch, batch + nsys);
@@ -206,6 +211,7 @@ int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool 
   key.push_back(o.tile);
   key.push_back(o.tile_ki);
   key.push_back(stream_small ? 1 : 0);
+  key.push_back(generic_lds ? 1 : 0);
   PlanExtra *ex = extra_of(p);
   std::lock_guard<std::mutex> g(ex->mu);
   auto it = ex->batches.find(key);
@@ -246,7 +252,7 @@ int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool 
       int blk, ept;
       lds_shape(p->sys[s].N2, &blk, &ept);
       // the specialised kernels have no coupling terms
-      const int qc = lds_fast_ok(blk, ept, p->sys[s].Q) && p->sys[s].njc == 0 ? p->sys[s].Q : 0;
+      const int qc = !generic_lds && lds_fast_ok(blk, ept, p->sys[s].Q) && p->sys[s].njc == 0 ? p->sys[s].Q : 0;
       cls[std::make_tuple(blk, ept, qc)].push_back(s);
     }
   for (auto &kv : cls) {
@@ -300,6 +306,17 @@ int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool 
       m->tile_k = k;
     }
   }
+  // Running-penalty ranges of every system.
+  m->pen_rng.assign((size_t)4 * nsys, 0);
+  for (const auto &sg : m->segs) {
+    m->pen_rng[4 * sg.sys] = sg.blk0;
+    m->pen_rng[4 * sg.sys + 1] = (sg.count + STREAM_BLOCK - 1) / STREAM_BLOCK;
+  }
+  for (size_t k = 0; k < m->lds_sys.size(); ++k) {
+    const int s = m->lds_sys[k];
+    m->pen_rng[4 * s + 2] = m->lds_item_range[k];
+    m->pen_rng[4 * s + 3] = m->lds_item_range[k + 1] - m->lds_item_range[k];
+  }
   // Per-state tables for the objective.
   std::vector<int32_t> state_sys(std::max(1, st));
   std::vector<int64_t> state_off(std::max(1, st));
@@ -315,7 +332,7 @@ int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool 
                  align256(std::max<size_t>(1, m->segs.size()) * sizeof(StreamSeg)) +
                  align256(std::max<size_t>(1, m->seg_state0.size()) * 4) +
                  align256(state_sys.size() * 4) + align256(state_off.size() * 8) +
-                 align256(m->sys_state0.size() * 4);
+                 align256(m->sys_state0.size() * 4) + align256(m->pen_rng.size() * 8);
   LBX_HIP(hipMalloc(&m->dmem, bytes));
   char *cur = (char *)m->dmem;
   m->d_items = carve<LdsItem>(cur, std::max<size_t>(1, m->items.size()));
@@ -326,6 +343,7 @@ int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool 
   m->d_state_sys = carve<int32_t>(cur, state_sys.size());
   m->d_state_off = carve<int64_t>(cur, state_off.size());
   m->d_sys_state0 = carve<int32_t>(cur, m->sys_state0.size());
+  m->d_pen_rng = carve<int64_t>(cur, m->pen_rng.size());
   if (!m->items.empty())
     LBX_HIP(hipMemcpy(m->d_items, m->items.data(), m->items.size() * sizeof(LdsItem), hipMemcpyHostToDevice));
   if (!m->lds_sys.empty())
@@ -339,6 +357,7 @@ int build_batch(const lb_plan *p, const lbx_opts &o, const int32_t *batch, bool 
   LBX_HIP(hipMemcpy(m->d_state_sys, state_sys.data(), state_sys.size() * 4, hipMemcpyHostToDevice));
   LBX_HIP(hipMemcpy(m->d_state_off, state_off.data(), state_off.size() * 8, hipMemcpyHostToDevice));
   LBX_HIP(hipMemcpy(m->d_sys_state0, m->sys_state0.data(), m->sys_state0.size() * 4, hipMemcpyHostToDevice));
+  LBX_HIP(hipMemcpy(m->d_pen_rng, m->pen_rng.data(), m->pen_rng.size() * 8, hipMemcpyHostToDevice));
   *out = m.get();
   ex->batches[key] = std::move(m);
   return LB_OK;
@@ -378,6 +397,7 @@ struct Layout {
   size_t q0 = 0, q1 = 0, z0 = 0, z1 = 0, zsf = 0, ringf = 0, zsa = 0, ringa = 0, zh = 0, qh0 = 0, qh1 = 0,
          seg = 0, st_gpart = 0, st_gfin = 0, slots = 0, kstep = 0;
   size_t kry = 0, kpart = 0;  // Krylov fallback: vectors and reduction scratch
+  size_t ptab = 0, pacc = 0, ppart = 0, pen = 0;  // LB_OP_GRADIENT: running penalty
   size_t total = 0;
   TrajLayout T;
   int H = 0;
@@ -440,6 +460,10 @@ Layout layout(const lb_plan *p, const lbx_opts &o, int op, const BatchMeta &m, i
   if (op == LB_OP_GRADIENT) {
     L.traj = take(L.T.total);
     L.rhoT = take((size_t)m.total_entries * sizeof(double2));
+    L.ptab = take((size_t)nsys * p->NT * sizeof(double));
+    L.pacc = take((size_t)m.st_blocks * sizeof(double));
+    L.ppart = take(m.items.size() * PEN_PARTS * sizeof(double));
+    L.pen = take((size_t)nsys * sizeof(double));
   }
   L.gstep = take((size_t)2 * p->ctab_total * sizeof(double));
   bool fast = false;
@@ -477,7 +501,9 @@ __global__ void item_weights_kernel(LdsItem *items, int n, const double *beta, c
   if (k >= n) return;
   LdsItem &it = items[k];
   const int M = sys_state0[it.sys + 1] - sys_state0[it.sys];
-  it.wterm = beta[sys_state0[it.sys] + it.b] / (double)M * (gscale ? gscale[it.sys] : 1.0);
+  const double gs = gscale ? gscale[it.sys] : 1.0;
+  it.wterm = beta[sys_state0[it.sys] + it.b] / (double)M * gs;
+  it.wpen = gs / (double)M;
 }
 
 int copy_segments(const BatchMeta &m, const double2 *src, bool src_batched, double2 *dst, hipStream_t st) {
@@ -811,10 +837,16 @@ int apriori_counts(const lb_plan *p, const BatchMeta &m, const int32_t *d_ktab, 
   return LB_OK;
 }
 
+struct NoHook {
+  int operator()(int, const double2 *, hipStream_t) const { return LB_OK; }
+};
+
 // Streamed forward steps j0..j1-1.  slot(j) returns the buffer that receives
-// q^j (j > j0); q^{j0} is `qstart`.  Each call starts a fresh history.
-template <class Slot>
-int stream_forward(const StreamCtx &c, int j0, int j1, const double2 *qstart, Slot slot, hipStream_t user) {
+// q^j (j > j0); q^{j0} is `qstart`.  hook(j, q^j, stream) runs before step j.
+// Each call starts a fresh history.
+template <class Slot, class Hook = NoHook>
+int stream_forward(const StreamCtx &c, int j0, int j1, const double2 *qstart, Slot slot, hipStream_t user,
+                   Hook hook = Hook()) {
   GraphRun gr(*c.o, user);
   if (int rc = gr.init()) return rc;
   const hipStream_t st = gr.stream();
@@ -828,6 +860,7 @@ int stream_forward(const StreamCtx &c, int j0, int j1, const double2 *qstart, Sl
     const int c1 = std::min(j1, c0 + chunk);
     if (int rc = gr.begin()) return rc;
     for (int j = c0; j < c1; ++j) {
+      if (int rc = hook(j, cur, st)) return rc;
       double2 *out = slot(j + 1);
       if (int rc = stream_step(c, j, false, cur, out, ph, nullptr, st)) return rc;
       cur = out;
@@ -983,9 +1016,18 @@ struct Fork {
   ~Fork() { (void)join(); }
 };
 
+// Running penalty of one gradient call (null when gamma1 = 0): the merit
+// functional, its target, the weight table and the accumulators.
+struct Penalty {
+  int kind;
+  const double2 *rhotar;
+  const double *ptab;
+  double *acc, *part;
+};
+
 int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w,
                 const double *alpha, const double2 *rho0, double2 *rhoT, char *traj, bool prof,
-                const std::vector<int32_t> *kst, hipStream_t st) {
+                const std::vector<int32_t> *kst, hipStream_t st, const Penalty *pen = nullptr) {
   double2 *ctab = (double2 *)(w + L.ctab);
   int32_t *ktab = (int32_t *)(w + L.ktab);
   double2 *ttab = (double2 *)(w + L.ttab);
@@ -1008,6 +1050,12 @@ int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const L
                   : launch_lds_forward(p, m.d_items + c.i0, c.i1 - c.i0, c.block, c.ept, ctab, ktab, rho0, rhoT,
                                        hist, slots ? slots + c.i0 : nullptr, status, cs);
     if (rc) return rc;
+    if (pen) {
+      if (!hist) return fail(LB_EINVAL, "internal: running penalty without a state history");
+      if ((rc = launch_penalty_lds(p, pen->kind, m.d_items + c.i0, c.i1 - c.i0, hist, pen->rhotar, pen->ptab,
+                                   pen->part + (size_t)c.i0 * PEN_PARTS, cs)))
+        return rc;
+    }
   }
   if (m.segs.empty()) {
     if ((rc = fk.join())) return rc;
@@ -1029,7 +1077,14 @@ int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const L
     last_out = r;
     return r;
   };
-  if ((rc = stream_forward(sc, 0, NT, start, slot, st))) return rc;
+  const int nseg = (int)m.segs.size();
+  auto hook = [&](int j, const double2 *q, hipStream_t s) -> int {
+    return pen ? launch_penalty_accum(p, pen->kind, m.d_segs, nseg, m.st_blocks, j, q, pen->rhotar, pen->ptab,
+                                      pen->acc, s)
+               : LB_OK;
+  };
+  if (pen && (rc = launch_fill_zero(pen->acc, (size_t)m.st_blocks * sizeof(double), st))) return rc;
+  if ((rc = stream_forward(sc, 0, NT, start, slot, st, hook))) return rc;
   if ((rc = fk.join()) || (rc = lds_profile_work(p, m, LB_KERNEL_LDS_FORWARD, slots, st))) return rc;
   return copy_segments(m, last_out, false, rhoT, st);
 }
@@ -1038,7 +1093,7 @@ int run_forward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const L
 int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const Layout &L, char *w, int kind,
                  const double *alpha, const char *traj, const double2 *rhotar, const double *beta, double gamma2,
                  const double *gscale, double *grad, bool prof, const std::vector<int32_t> *kst,
-                 hipStream_t st) {
+                 hipStream_t st, const Penalty *pen = nullptr) {
   int rc;
   double2 *ctab = (double2 *)(w + L.ctab);
   int32_t *ktab = (int32_t *)(w + L.ktab);
@@ -1064,11 +1119,13 @@ int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const 
       hipStream_t cs;
       if ((rc = fk.stream((int)ci, &cs))) return rc;
       ProfScope ps(p, prof, LB_KERNEL_LDS_ADJOINT, cs);
+      if (pen && c.qc > 0) return fail(LB_EINVAL, "internal: running penalty on the specialised LDS kernels");
       rc = c.qc > 0 ? launch_lds_adjoint_fast(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, c.qc, kind, ctab, ttab,
                                               o.tol, rhotar, hist, (double2 *)(w + L.zhist), gpart,
                                               slots ? slots + c.i0 : nullptr, status, cs)
                     : launch_lds_adjoint(p, items + c.i0, c.i1 - c.i0, c.block, c.ept, kind, ctab, ktab, rhotar,
-                                         hist, gpart, slots ? slots + c.i0 : nullptr, status, cs);
+                                         hist, pen ? pen->ptab : nullptr, gpart, slots ? slots + c.i0 : nullptr,
+                                         status, cs);
       if (rc) return rc;
     }
   }
@@ -1140,6 +1197,12 @@ int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const 
               return rc;
             pend = 0;
           }
+          // Source of the running penalty at q^j (App. B); none at j = 0,
+          // where it would not reach the gradient.
+          if (pen && j > 0)
+            if ((rc = launch_penalty_source(p, pen->kind, m.d_segs, nseg, m.st_blocks, j, slot(j), pen->rhotar,
+                                            pen->ptab, gscale, qh[cur ^ 1], ast)))
+              return rc;
           cur ^= 1;
         }
         if ((rc = gr.end())) return rc;
@@ -1417,6 +1480,12 @@ extern "C" int lb_workspace_bytes(const lb_plan *p, int32_t op, const int32_t *b
   if (int rc = build_batch(p, o, batch_per_sys, small, &m, op == LB_OP_IMR_STEP ? 2 : -1)) return rc;
   const int ck = op == LB_OP_IMR_STEP ? 1 : ckpt_every;
   *bytes = layout(p, o, op, *m, ck).total;
+  // room for the generic LDS kernels of a call with a running penalty
+  if (op == LB_OP_GRADIENT) {
+    BatchMeta *mg;
+    if (int rc = build_batch(p, o, batch_per_sys, small, &mg, -1, true)) return rc;
+    *bytes = std::max(*bytes, layout(p, o, op, *mg, ck).total);
+  }
   // room for the Krylov fallback (every system streamed)
   BatchMeta *mf;
   if (int rc = build_batch(p, o, batch_per_sys, op != LB_OP_IMR_STEP, &mf, 2)) return rc;
@@ -1577,7 +1646,7 @@ extern "C" int objective(const lb_plan *p, int32_t kind, const void *rhoT, const
   int32_t *status = (int32_t *)(w + L.status);
   if (int rc = launch_fill_zero(status, 4, st)) return rc;
   if (int rc = launch_objective(p, kind, (const double2 *)rhoT, (const double2 *)rhotar, beta, m->d_state_sys,
-                                m->d_state_off, m->d_sys_state0, m->total_states, gamma2, alpha,
+                                m->d_state_off, m->d_sys_state0, m->total_states, gamma2, alpha, nullptr,
                                 (double *)(w + L.objpart), J, G, status, st))
     return rc;
   if (o.sync) return status_code(status, st);
@@ -1626,17 +1695,21 @@ extern "C" int adjoint_backward(const lb_plan *p, int32_t kind, const double *al
 
 extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *alpha, const void *rho0,
                                 const void *rhotar, const double *beta, const int32_t *batch_per_sys, double gamma2,
-                                int32_t ckpt_every, double *G, double *grad, void *rhoT_out, void *ws, size_t ws_bytes,
-                                void *stream) {
+                                double gamma1, double penalty_a, int32_t ckpt_every, double *G, double *grad,
+                                void *rhoT_out, void *ws, size_t ws_bytes, void *stream) {
   if (int rc = check_plan(p)) return rc;
   if (kind != LB_J_FROB && kind != LB_J_TR && kind != LB_J_NM) return fail(LB_EINVAL, "unknown merit functional");
   if (!alpha || !rho0 || !rhotar || !beta || !batch_per_sys || !G || !grad || !ws)
     return fail(LB_EINVAL, "NULL argument");
   if (ckpt_every < 0) return fail(LB_EINVAL, "ckpt_every must be >= 0");
   if (!std::isfinite(gamma2)) return fail(LB_EINVAL, "gamma2 must be finite");
+  if (!std::isfinite(gamma1)) return fail(LB_EINVAL, "gamma1 must be finite");
+  const bool penal = gamma1 != 0.0;
+  if (penal && !(penalty_a > 0.0 && std::isfinite(penalty_a)))
+    return fail(LB_EINVAL, "penalty_a must be positive and finite");
   const lbx_opts o = snapshot(p);
   CallPlan cp;
-  if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &cp.m)) return rc;
+  if (int rc = build_batch(p, o, batch_per_sys, streams_small(ckpt_every), &cp.m, -1, penal)) return rc;
   cp.L = layout(p, o, LB_OP_GRADIENT, *cp.m, ckpt_every);
   if (ws_bytes < cp.L.total) return fail(LB_ENOMEM, "workspace too small");
   hipStream_t st = (hipStream_t)stream;
@@ -1649,15 +1722,22 @@ extern "C" int adjoint_gradient(const lb_plan *p, int32_t kind, const double *al
     char *traj = w + L.traj;
     // rho(T) goes to the caller's buffer, or to the workspace.
     double2 *rhoT = rhoT_out ? (double2 *)rhoT_out : (double2 *)(w + L.rhoT);
+    const Penalty pn{kind, (const double2 *)rhotar, (const double *)(w + L.ptab), (double *)(w + L.pacc),
+                     (double *)(w + L.ppart)};
+    const Penalty *pen = penal ? &pn : nullptr;
+    double *penv = penal ? (double *)(w + L.pen) : nullptr;
     int rc = call_begin(p, L, w, prof, st);
-    if (!rc) rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, rhoT, traj, prof, kst, st);
+    if (!rc && pen) rc = launch_penalty_table(p, gamma1, penalty_a, (double *)(w + L.ptab), st);
+    if (!rc) rc = run_forward(p, o, *m, L, w, alpha, (const double2 *)rho0, rhoT, traj, prof, kst, st, pen);
+    if (!rc && pen)
+      rc = launch_penalty_final(p, kind, m->d_pen_rng, pn.acc, pn.part, pn.ptab, m->d_sys_state0, penv, st);
     if (!rc)
       rc = launch_objective(p, kind, rhoT, (const double2 *)rhotar, beta, m->d_state_sys, m->d_state_off,
-                            m->d_sys_state0, m->total_states, gamma2, alpha, (double *)(w + L.objpart), nullptr, G,
-                            (int32_t *)(w + L.status), st);
+                            m->d_sys_state0, m->total_states, gamma2, alpha, penv, (double *)(w + L.objpart),
+                            nullptr, G, (int32_t *)(w + L.status), st);
     if (!rc)
       rc = run_backward(p, o, *m, L, w, kind, alpha, traj, (const double2 *)rhotar, beta, gamma2, nullptr, grad,
-                        prof, kst, st);
+                        prof, kst, st, pen);
     if (rc) return rc;
     return call_end(p, o, *m, L, w, prof, st, bits);
   };

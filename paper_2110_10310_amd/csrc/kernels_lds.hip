@@ -124,7 +124,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
     const SysDev *__restrict__ sysv, const LdsItem *__restrict__ items,
     const double *__restrict__ Etab, const uint64_t *__restrict__ desc,
     const double2 *__restrict__ ctab, const int32_t *__restrict__ ktab, int NT, int kind,
-    const double2 *__restrict__ rhotar, const double2 *__restrict__ states,
+    const double2 *__restrict__ rhotar, const double2 *__restrict__ states, const double *__restrict__ ptab,
     double *__restrict__ gpart, int64_t *__restrict__ sweeps, int32_t *__restrict__ status) {
   extern __shared__ double2 zbuf[];
   __shared__ double sq[SQRT_TABLE];
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
   const int Q = S.Q;
   if (tid < SQRT_TABLE) sq[tid] = sqrt((double)tid);
 
-  double2 qh[EPT], wv[EPT], hd[EPT], dn[EPT], qn[EPT];
+  double2 qh[EPT], wv[EPT], hd[EPT], dn[EPT], qn[EPT], tg[EPT];
   uint64_t di[EPT], dj[EPT];
   int ee[EPT];
   bool ok[EPT];
@@ -162,6 +162,7 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
     // Terminal condition (App. B): qh = (beta/M) dJ/d(conj q) at q = rho(T).
     qn[k] = ok[k] ? hist[(int64_t)NT * N2 + ee[k]] : make_double2(0.0, 0.0);
     const double2 t = ok[k] ? rhotar[it.off + ee[k]] : make_double2(0.0, 0.0);
+    tg[k] = t;
     qh[k] = kind == LB_J_FROB ? cscale(it.wterm, csub(qn[k], t)) : cscale(kind == LB_J_NM ? it.wterm : -it.wterm, t);
     dn[k] = make_double2(0.0, 0.0);
   }
@@ -230,10 +231,16 @@ __global__ __launch_bounds__(BLOCK) void lds_adjoint_kernel(
         dstp[1] = gq;
       }
     }
-    // qh^j = qh^{j+1} + dt M^+ zh = qh^{j+1} + 2 delta.
+    // qh^j = qh^{j+1} + dt M^+ zh = qh^{j+1} + 2 delta, plus the source of the
+    // running penalty (App. B), w dJ/d(conj q^j) with w = gamma1 dt beta(t_j) / M
+    // (it has no effect on the gradient at j = 0).
+    const double wp = (ptab && j > 0) ? it.wpen * ptab[(int64_t)it.sys * NT + j] : 0.0;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       qh[k] = cadd(qh[k], cscale(2.0, dn[k]));
+      if (wp != 0.0)
+        qh[k] = cadd(qh[k], cscale(wp, kind == LB_J_FROB ? csub(qj[k], tg[k])
+                                                          : (kind == LB_J_NM ? tg[k] : cscale(-1.0, tg[k]))));
       qn[k] = qj[k];
     }
     // The next step writes its first iterate into (cb ? zb1 : zb0): the last sweep's
@@ -270,13 +277,13 @@ static int launch_fwd_t(const lb_plan *p, const LdsItem *d_items, int nitems, si
 template <int BLOCK, int EPT>
 static int launch_adj_t(const lb_plan *p, const LdsItem *d_items, int nitems, size_t shmem,
                         int kind, const double2 *ctab, const int32_t *ktab,
-                        const double2 *rhotar, const double2 *states, double *gpart,
+                        const double2 *rhotar, const double2 *states, const double *ptab, double *gpart,
                         int64_t *sweeps, int32_t *status, hipStream_t st) {
   auto kern = lds_adjoint_kernel<BLOCK, EPT>;
   LBX_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shmem));
   hipLaunchKernelGGL(kern, dim3(nitems), dim3(BLOCK), shmem, st, p->d_sys, d_items, p->d_E,
-                     p->d_desc, ctab, ktab, p->NT, kind, rhotar, states, gpart, sweeps, status);
+                     p->d_desc, ctab, ktab, p->NT, kind, rhotar, states, ptab, gpart, sweeps, status);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }
@@ -298,12 +305,12 @@ int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int
 
 int launch_lds_adjoint(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                        int kind, const double2 *ctab, const int32_t *ktab, const double2 *rhotar,
-                       const double2 *states, double *gpart, int64_t *sweeps, int32_t *status,
-                       hipStream_t st) {
+                       const double2 *states, const double *ptab, double *gpart, int64_t *sweeps,
+                       int32_t *status, hipStream_t st) {
   if (nitems == 0) return LB_OK;
   const size_t sh = lds_bytes(block, ept);
 #define LBX_ADJ(Bk, Ep) \
-  if (block == Bk && ept == Ep) return launch_adj_t<Bk, Ep>(p, d_items, nitems, sh, kind, ctab, ktab, rhotar, states, gpart, sweeps, status, st);
+  if (block == Bk && ept == Ep) return launch_adj_t<Bk, Ep>(p, d_items, nitems, sh, kind, ctab, ktab, rhotar, states, ptab, gpart, sweeps, status, st);
   LBX_ADJ(64, 1) LBX_ADJ(128, 1) LBX_ADJ(256, 1) LBX_ADJ(512, 1) LBX_ADJ(1024, 1)
   LBX_ADJ(1024, 2) LBX_ADJ(1024, 4)
 #undef LBX_ADJ

@@ -352,8 +352,9 @@ __global__ void objective_final_kernel(const SysDev *__restrict__ sysv, int nsys
                                        const double *__restrict__ partial,
                                        const double *__restrict__ beta,
                                        const int32_t *__restrict__ sys_state0, double gamma2,
-                                       const double *__restrict__ alpha, double *__restrict__ J,
-                                       double *__restrict__ G, int32_t *__restrict__ status) {
+                                       const double *__restrict__ alpha, const double *__restrict__ pen,
+                                       double *__restrict__ J, double *__restrict__ G,
+                                       int32_t *__restrict__ status) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsys) return;
   const SysDev &S = sysv[s];
@@ -372,7 +373,7 @@ __global__ void objective_final_kernel(const SysDev *__restrict__ sysv, int nsys
     reg += a * a;
   }
   const int M = st1 - st0;
-  const double g = (M > 0 ? acc / (double)M : 0.0) + 0.5 * gamma2 * reg;
+  const double g = (M > 0 ? acc / (double)M : 0.0) + 0.5 * gamma2 * reg + (pen ? pen[s] : 0.0);
   if (G) G[s] = g;
   if (status && M > 0 && !isfinite(g)) atomicOr(status, LB_STATUS_NONFINITE);
 }
@@ -380,7 +381,8 @@ __global__ void objective_final_kernel(const SysDev *__restrict__ sysv, int nsys
 int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const double2 *rhotar,
                      const double *beta, const int32_t *d_state_sys, const int64_t *d_state_off,
                      const int32_t *d_sys_state0, int nstates, double gamma2, const double *alpha,
-                     double *partial, double *J, double *G, int32_t *status, hipStream_t st) {
+                     const double *pen, double *partial, double *J, double *G, int32_t *status,
+                     hipStream_t st) {
   if (nstates > 0) {
     hipLaunchKernelGGL(objective_partial_kernel, dim3(OBJ_PARTS, nstates), dim3(256), 0, st,
                        p->d_sys, kind, rhoT, rhotar, d_state_sys, d_state_off, partial);
@@ -388,7 +390,168 @@ int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const doub
   }
   const int nsys = (int)p->sys.size();
   hipLaunchKernelGGL(objective_final_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, p->d_sys, nsys,
-                     kind, partial, beta, d_sys_state0, gamma2, alpha, J, G, status);
+                     kind, partial, beta, d_sys_state0, gamma2, alpha, pen, J, G, status);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Running penalty (Sec. III eq. optimproblem, gamma1 term) by the left
+// rectangle rule: gamma1 (1/M) sum_i dt sum_{j<NT} beta(t_j) J(q_i^j), and
+// its adjoint source gamma1 dt beta(t_j) (1/M) dJ/d(conj q^j) (App. B).  The
+// sums are deterministic: every stream block owns one accumulator across the
+// steps, every LDS-resident state a fixed set of chunk partials.
+// ----------------------------------------------------------------------------
+__global__ void penalty_table_kernel(const SysDev *__restrict__ sysv, int nsys, int NT, double gamma1, double a,
+                                     double *__restrict__ ptab) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)nsys * NT) return;
+  const SysDev &S = sysv[k / NT];
+  const int j = (int)(k % NT);
+  const double u = ((double)j * S.dt - S.T) / a;
+  ptab[k] = gamma1 * S.dt * (exp(-(u * u)) / a);
+}
+
+int launch_penalty_table(const lb_plan *p, double gamma1, double a, double *ptab, hipStream_t st) {
+  const int64_t n = (int64_t)p->sys.size() * p->NT;
+  hipLaunchKernelGGL(penalty_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p->d_sys,
+                     (int)p->sys.size(), p->NT, gamma1, a, ptab);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+// Merit value of one entry: |q - t|^2 / 2 (J_Frob) or Re conj(t) q.
+__device__ __forceinline__ double penalty_value(int kind, double2 q, double2 t) {
+  if (kind == LB_J_FROB) {
+    const double dx = q.x - t.x, dy = q.y - t.y;
+    return 0.5 * (dx * dx + dy * dy);
+  }
+  return t.x * q.x + t.y * q.y;
+}
+
+// Sum over a 256-thread block, in a fixed order; valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double *red) {
+  v = wave_sum<64>(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(STREAM_BLOCK) void penalty_accum_kernel(
+    const SysDev *__restrict__ sysv, const StreamSeg *__restrict__ segs, int nseg, int kind, int NT, int j,
+    const double2 *__restrict__ q, const double2 *__restrict__ rhotar, const double *__restrict__ ptab,
+    double *__restrict__ acc) {
+  static_assert(STREAM_BLOCK == 256, "block_sum256 assumes 256 threads");
+  __shared__ int sseg;
+  __shared__ double red[4];
+  if (threadIdx.x == 0) sseg = find_segment(segs, nseg, blockIdx.x);
+  __syncthreads();
+  const StreamSeg &sg = segs[sseg];
+  const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + threadIdx.x;
+  const double v = local < sg.count ? penalty_value(kind, q[sg.off + local], rhotar[sg.boff + local]) : 0.0;
+  const double b = block_sum256(v, red);
+  if (threadIdx.x == 0) acc[blockIdx.x] += ptab[(int64_t)sg.sys * NT + j] * b;
+}
+
+int launch_penalty_accum(const lb_plan *p, int kind, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
+                         const double2 *q, const double2 *rhotar, const double *ptab, double *acc,
+                         hipStream_t st) {
+  if (nblk == 0) return LB_OK;
+  hipLaunchKernelGGL(penalty_accum_kernel, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st, p->d_sys, d_segs,
+                     nseg, kind, p->NT, j, q, rhotar, ptab, acc);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+__global__ __launch_bounds__(256) void penalty_lds_kernel(const SysDev *__restrict__ sysv,
+                                                          const LdsItem *__restrict__ items, int kind, int NT,
+                                                          const double2 *__restrict__ hist,
+                                                          const double2 *__restrict__ rhotar,
+                                                          const double *__restrict__ ptab,
+                                                          double *__restrict__ part) {
+  __shared__ double red[4];
+  const LdsItem it = items[blockIdx.x];
+  const SysDev &S = sysv[it.sys];
+  const int per = (NT + PEN_PARTS - 1) / PEN_PARTS;
+  const int j0 = (int)blockIdx.y * per, j1 = min(NT, j0 + per);
+  double v = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const double2 *qj = hist + it.st_off + (int64_t)j * S.N2;
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < S.N2; e += 256) s += penalty_value(kind, qj[e], rhotar[it.off + e]);
+    v += ptab[(int64_t)it.sys * NT + j] * s;
+  }
+  const double b = block_sum256(v, red);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.x * PEN_PARTS + blockIdx.y] = b;
+}
+
+int launch_penalty_lds(const lb_plan *p, int kind, const LdsItem *d_items, int nitems, const double2 *hist,
+                       const double2 *rhotar, const double *ptab, double *part, hipStream_t st) {
+  if (nitems == 0) return LB_OK;
+  hipLaunchKernelGGL(penalty_lds_kernel, dim3((unsigned)nitems, PEN_PARTS), dim3(256), 0, st, p->d_sys, d_items,
+                     kind, p->NT, hist, rhotar, ptab, part);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+__global__ __launch_bounds__(256) void penalty_final_kernel(int kind, int NT, const int64_t *__restrict__ rng,
+                                                            const double *__restrict__ acc,
+                                                            const double *__restrict__ part,
+                                                            const double *__restrict__ ptab,
+                                                            const int32_t *__restrict__ sys_state0,
+                                                            double *__restrict__ pen) {
+  __shared__ double red[4];
+  const int s = blockIdx.x;
+  const int64_t b0 = rng[4 * s], nb = rng[4 * s + 1], i0 = rng[4 * s + 2], ni = rng[4 * s + 3];
+  double v = 0.0;
+  for (int64_t k = threadIdx.x; k < nb; k += 256) v += acc[b0 + k];
+  for (int64_t k = threadIdx.x; k < ni * PEN_PARTS; k += 256) v += part[i0 * PEN_PARTS + k];
+  const double tot = block_sum256(v, red);
+  double w = 0.0;
+  if (kind == LB_J_TR)
+    for (int j = threadIdx.x; j < NT; j += 256) w += ptab[(int64_t)s * NT + j];
+  const double wsum = block_sum256(w, red);
+  if (threadIdx.x == 0) {
+    const int M = sys_state0[s + 1] - sys_state0[s];
+    // J_Tr = 1 - sum v: the constant integrates to sum_j ptab (times M / M).
+    pen[s] = M == 0 ? 0.0 : (kind == LB_J_TR ? wsum - tot / (double)M : tot / (double)M);
+  }
+}
+
+int launch_penalty_final(const lb_plan *p, int kind, const int64_t *d_rng, const double *acc,
+                         const double *part, const double *ptab, const int32_t *d_sys_state0, double *pen,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(penalty_final_kernel, dim3((unsigned)p->sys.size()), dim3(256), 0, st, kind, p->NT, d_rng,
+                     acc, part, ptab, d_sys_state0, pen);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
+__global__ __launch_bounds__(STREAM_BLOCK) void penalty_source_kernel(
+    const StreamSeg *__restrict__ segs, int nseg, int kind, int NT, int j, const double2 *__restrict__ q,
+    const double2 *__restrict__ rhotar, const double *__restrict__ ptab, const double *__restrict__ gscale,
+    double2 *__restrict__ qh) {
+  __shared__ int sseg;
+  if (threadIdx.x == 0) sseg = find_segment(segs, nseg, blockIdx.x);
+  __syncthreads();
+  const StreamSeg &sg = segs[sseg];
+  const int64_t local = ((int64_t)blockIdx.x - sg.blk0) * STREAM_BLOCK + threadIdx.x;
+  if (local >= sg.count) return;
+  const double w = ptab[(int64_t)sg.sys * NT + j] / (double)sg.nstates * (gscale ? gscale[sg.sys] : 1.0);
+  const int64_t e = sg.off + local;
+  const double2 t = rhotar[sg.boff + local];
+  const double2 d = kind == LB_J_FROB ? csub(q[e], t) : (kind == LB_J_NM ? t : cscale(-1.0, t));
+  qh[e] = cadd(qh[e], cscale(w, d));
+}
+
+int launch_penalty_source(const lb_plan *p, int kind, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
+                          const double2 *q, const double2 *rhotar, const double *ptab, const double *gscale,
+                          double2 *qh, hipStream_t st) {
+  if (nblk == 0) return LB_OK;
+  hipLaunchKernelGGL(penalty_source_kernel, dim3((unsigned)nblk), dim3(STREAM_BLOCK), 0, st, d_segs, nseg, kind,
+                     p->NT, j, q, rhotar, ptab, gscale, qh);
   LBX_HIP(hipGetLastError());
   return LB_OK;
 }

@@ -67,6 +67,7 @@ struct LdsItem {
   double wterm;       // beta_b / M_s (terminal condition weight)
   int32_t parts;      // gradient partial sums per step written by this item's block
   int32_t pad;
+  double wpen;        // 1 / M_s (running-penalty source weight, times the table entry)
 };
 
 // Segment of the streaming kernels: all states of one system.
@@ -274,21 +275,53 @@ int launch_lds_forward(const lb_plan *p, const LdsItem *d_items, int nitems, int
                        const double2 *ctab, const int32_t *ktab, const double2 *rho0,
                        double2 *rhoT, double2 *states, int64_t *sweeps, int32_t *status, hipStream_t st);
 
+// ptab (nullable): the running-penalty table of launch_penalty_table; the
+// adjoint then adds the source term of every step j >= 1.
 int launch_lds_adjoint(const lb_plan *p, const LdsItem *d_items, int nitems, int block, int ept,
                        int kind, const double2 *ctab, const int32_t *ktab, const double2 *rhotar,
-                       const double2 *states, double *gpart, int64_t *sweeps, int32_t *status,
-                       hipStream_t st);
+                       const double2 *states, const double *ptab, double *gpart, int64_t *sweeps,
+                       int32_t *status, hipStream_t st);
 
 int launch_lds_grad_reduce(const lb_plan *p, const int32_t *d_item_range, int nsys_lds,
                            const int32_t *d_sys_ids, const LdsItem *d_items, const double *gpart,
                            double *gstep, hipStream_t st);
 
 // G (nullable) and J (nullable) per system / state; status (nullable)
-// receives LB_STATUS_NONFINITE when a G is not finite.
+// receives LB_STATUS_NONFINITE when a G is not finite.  pen (nullable,
+// DEVICE [nsys]) is added to G: the running penalty.
 int launch_objective(const lb_plan *p, int kind, const double2 *rhoT, const double2 *rhotar,
                      const double *beta, const int32_t *d_state_sys, const int64_t *d_state_off,
                      const int32_t *d_sys_state0, int nstates, double gamma2, const double *alpha,
-                     double *partial, double *J, double *G, int32_t *status, hipStream_t st);
+                     const double *pen, double *partial, double *J, double *G, int32_t *status,
+                     hipStream_t st);
+
+// Running penalty (Sec. III eq. optimproblem, gamma1 term), integrated by
+// the left rectangle rule on the time grid.
+//   ptab[s][j] = gamma1 dt_s beta_s(j dt_s), beta(t) = exp(-((t - T)/a)^2) / a,
+// for every system s and step j < NT.  Per merit functional the value of
+// one entry is v = |q - t|^2 / 2 (J_Frob) or Re conj(t) q (J_Tr, J_Nm), and
+//   pen_s = (1/M_s) sum_i sum_j ptab[s][j] J(q_i^j),  J_Tr = 1 - sum v.
+constexpr int PEN_PARTS = 32;  // partial sums per LDS-resident state
+int launch_penalty_table(const lb_plan *p, double gamma1, double a, double *ptab, hipStream_t st);
+// acc[b] += ptab[sys][j] * (sum of v over the entries of stream block b), q
+// holding q^j of the streamed states (compact layout).
+int launch_penalty_accum(const lb_plan *p, int kind, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
+                         const double2 *q, const double2 *rhotar, const double *ptab, double *acc,
+                         hipStream_t st);
+// part[item][c] = sum over the steps of chunk c of ptab[sys][j] * (sum of v
+// over q^j), from the state history of each LDS-resident item.
+int launch_penalty_lds(const lb_plan *p, int kind, const LdsItem *d_items, int nitems, const double2 *hist,
+                       const double2 *rhotar, const double *ptab, double *part, hipStream_t st);
+// pen[s] from the accumulators; rng[s] = {first stream block, blocks, first
+// LDS item, items} of system s.
+int launch_penalty_final(const lb_plan *p, int kind, const int64_t *d_rng, const double *acc,
+                         const double *part, const double *ptab, const int32_t *d_sys_state0, double *pen,
+                         hipStream_t st);
+// Adjoint source of step j on the streamed states:
+//   qh += ptab[sys][j] gscale[sys] / M (dJ/d(conj q) at q = q^j).
+int launch_penalty_source(const lb_plan *p, int kind, const StreamSeg *d_segs, int nseg, int64_t nblk, int j,
+                          const double2 *q, const double2 *rhotar, const double *ptab, const double *gscale,
+                          double2 *qh, hipStream_t st);
 
 // Terminal condition of the streamed states; gscale (nullable, DEVICE
 // [nsys]) weights each system's objective.

@@ -19,8 +19,10 @@ from .api import Plan, lindblad_objective
 def optimize(plan: Plan, kind, alpha0: torch.Tensor, rho0: torch.Tensor, rhotar: torch.Tensor,
              beta: torch.Tensor, batch: Sequence[int], gamma2: float = 0.0, ckpt_every: int = 0,
              max_iter: int = 100, tolerance_grad: float = 1e-9, tolerance_change: float = 1e-14,
-             history_size: int = 20, callback: Callable[[int, float], None] | None = None):
-    """Minimise sum_s G_s(alpha) from alpha0.
+             history_size: int = 20, callback: Callable[[int, float], None] | None = None,
+             gamma1: float = 0.0, penalty_a: float = 1.0):
+    """Minimise sum_s G_s(alpha) from alpha0 (with the running penalty when
+    gamma1 != 0).
 
     Returns (alpha, history) where history lists the objective of every
     evaluation (line-search trials included).  `callback(k, G)` is called
@@ -34,7 +36,8 @@ def optimize(plan: Plan, kind, alpha0: torch.Tensor, rho0: torch.Tensor, rhotar:
 
     def closure():
         opt.zero_grad()
-        G = lindblad_objective(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2, ckpt_every).sum()
+        G = lindblad_objective(alpha, plan, kind, rho0, rhotar, beta, batch, gamma2, ckpt_every, gamma1,
+                               penalty_a).sum()
         G.backward()
         history.append(float(G.detach()))
         if callback is not None:

@@ -50,7 +50,7 @@ def test_invalid_arguments_rejected_before_device_calls(built_lib):
     b = (C.c_int32 * 1)(1)
     assert lib.lb_workspace_bytes(None, 0, b, 1, C.byref(size)) == nat.LB_EINVAL
     assert lib.lindblad_apply(None, 0, 0.0, None, None, None, 1, 0, None) == nat.LB_EINVAL
-    assert lib.adjoint_gradient(None, 0, None, None, None, None, None, 0.0, 1, None, None, None,
+    assert lib.adjoint_gradient(None, 0, None, None, None, None, None, 0.0, 0.0, 1.0, 1, None, None, None,
                                 None, 0, None) == nat.LB_EINVAL
     assert lib.lb_plan_set_option(None, 0, 0.0) == nat.LB_EINVAL
     assert lib.imr_step_noalloc(None, 0, 0, None, None, None, 1, 0, None) == nat.LB_EINVAL

@@ -1,0 +1,143 @@
+"""Running penalty (Sec. III eq. optimproblem, gamma1 term; its adjoint source
+term in App. B) on the GPU against the oracle: every merit functional on the
+LDS-resident and streamed paths, checkpoint recomputation, a batch mixing
+both paths, the block-tiled streamed system, the GMRES fallback, and the
+autograd objective.  Tolerances as in the other parity tests: 1e-12 for
+objectives and states, 1e-10 of the gradient's max-norm."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from workloads import observable_nm, random_alpha, random_pure_states, random_system  # noqa: E402
+
+from _gpu import dev, flat_alpha, flat_states, rel_state_err, say, split_states  # noqa: E402
+
+STATE_TOL = 1e-12
+GRAD_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def lbx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_10310_amd as lbx
+    return lbx
+
+
+def _targets(rng, s, B, kind):
+    if kind == oracle.KIND_NM:
+        return np.repeat(observable_nm(s.N, 1)[None], B, axis=0)
+    return random_pure_states(rng, s.N, B)
+
+
+def _case(lbx, systems, alphas, rng, path, B, kind, gamma1, a, ckpt=0, gamma2=0.0):
+    batch = [B] * len(systems)
+    rho0 = [random_pure_states(rng, s.N, B) for s in systems]
+    tar = [_targets(rng, s, B, kind) for s in systems]
+    beta = rng.uniform(0.5, 2, B * len(systems))
+    plan = lbx.Plan(systems, path=path)
+    G, grad, rhoT = lbx.adjoint_gradient(plan, kind, dev(flat_alpha(alphas)), dev(flat_states(rho0)),
+                                         dev(flat_states(tar)), dev(beta), batch, gamma2, ckpt, want_rhoT=True,
+                                         gamma1=gamma1, penalty_a=a)
+    G, grad = G.cpu().numpy(), grad.cpu().numpy()
+    got = split_states(rhoT.cpu().numpy(), systems, batch)
+    off = 0
+    for k, s in enumerate(systems):
+        Gr, gr, rT = oracle.value_and_gradient(s, alphas[k], rho0[k], tar[k], beta[k * B:(k + 1) * B], kind, gamma2,
+                                               return_final=True, gamma1=gamma1, penalty_a=a)
+        G0 = oracle.value_and_gradient(s, alphas[k], rho0[k], tar[k], beta[k * B:(k + 1) * B], kind, gamma2)[0]
+        assert abs(Gr - G0) > 1e-6 * abs(G0)  # the penalty is not negligible in this case
+        assert rel_state_err([got[k]], [rT]) < STATE_TOL
+        assert abs(G[k] - Gr) <= 1e-12 * abs(Gr), (k, G[k], Gr)
+        gk = grad[off:off + alphas[k].size].reshape(gr.shape)
+        assert np.max(np.abs(gk - gr)) <= GRAD_TOL * np.max(np.abs(gr)), (k, np.max(np.abs(gk - gr)))
+        off += alphas[k].size
+
+
+def _sys(seed, nlev, NT=14, T=1.4, jc=0.0, amp=0.03):
+    rng = np.random.default_rng(seed)
+    s = random_system(rng, nlev, NT=NT, T=T, Ns=5, Nf=2, jc=jc)
+    return s, random_alpha(rng, s, amp=amp), rng
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("path", ["lds", "stream"])
+def test_penalty_matches_oracle(lbx, kind, path):
+    s, alpha, rng = _sys(800 + kind, (2, 3))
+    say("penalty", kind, path)
+    _case(lbx, [s], [alpha], rng, path, 3, kind, gamma1=0.9, a=0.5)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_penalty_with_checkpoint_recomputation(lbx, kind):
+    # ckpt_every 4 streams every system and recomputes the states between
+    # checkpoints, where the adjoint reads q^j for the source
+    s, alpha, rng = _sys(810 + kind, (3, 3), NT=13, T=1.3)
+    say("penalty ckpt", kind)
+    _case(lbx, [s], [alpha], rng, "auto", 2, kind, gamma1=1.3, a=0.4, ckpt=4, gamma2=0.2)
+
+
+def test_penalty_on_a_mixed_batch(lbx):
+    # generic LDS kernels (which would otherwise be the specialised ones)
+    # beside the streamed systems; a coupled system among them
+    rng = np.random.default_rng(820)
+    systems, alphas = [], []
+    for nlev, jc in [((2, 2), 0.0), ((2, 3), 0.02), ((4, 4), 0.0), ((3,) * 5, 0.0)]:
+        s = random_system(rng, nlev, NT=8, T=0.8, Ns=4, Nf=2, jc=jc)
+        systems.append(s)
+        alphas.append(random_alpha(rng, s, amp=0.03))
+    say("penalty mixed batch")
+    _case(lbx, systems, alphas, rng, "auto", 1, 0, gamma1=0.6, a=0.3)
+
+
+def test_penalty_on_the_block_tiled_system(lbx):
+    s, alpha, rng = _sys(830, (3, 3, 3, 3), NT=6, T=0.6)
+    say("penalty tiled")
+    _case(lbx, [s], [alpha], rng, "auto", 1, 1, gamma1=2.0, a=0.25)
+
+
+def test_penalty_in_the_gmres_fallback(lbx):
+    s, alpha, rng = _sys(840, (3, 3), NT=8, T=1.6, jc=0.6, amp=0.02)
+    plan = lbx.Plan([s])
+    assert (lbx.sweep_counts(plan, dev(alpha.reshape(-1)))[0, :, 1] < 1).all()
+    say("penalty krylov")
+    _case(lbx, [s], [alpha], rng, "auto", 2, 0, gamma1=0.8, a=0.6)
+
+
+def test_penalty_autograd_scales_each_system(lbx):
+    rng = np.random.default_rng(850)
+    systems = [random_system(rng, n, NT=10, T=1.0, Ns=4, Nf=2) for n in ((2, 2), (2, 3))]
+    alphas = [random_alpha(rng, s, amp=0.03) for s in systems]
+    r0 = [random_pure_states(rng, s.N, 2) for s in systems]
+    tg = [random_pure_states(rng, s.N, 2) for s in systems]
+    rho0, tar = flat_states(r0), flat_states(tg)
+    beta = dev(rng.uniform(0.5, 2, 4))
+    plan = lbx.Plan(systems)
+    a = dev(flat_alpha(alphas)).requires_grad_(True)
+    w = dev(np.array([0.7, -1.9]))
+    say("penalty autograd")
+    G = lbx.lindblad_objective(a, plan, 0, dev(rho0), dev(tar), beta, [2, 2], 0.1, 0, 0.5, 0.4)
+    (G * w).sum().backward()
+    off = plan.alpha_off
+    ref = np.zeros(a.numel())
+    for k, s in enumerate(systems):
+        p1 = lbx.Plan([s])
+        Gk, gk, _ = lbx.adjoint_gradient(p1, 0, dev(alphas[k].reshape(-1)), dev(r0[k]), dev(tg[k]),
+                                         beta[2 * k:2 * k + 2].contiguous(), [2], 0.1, 0, gamma1=0.5,
+                                         penalty_a=0.4)
+        assert abs(G[k].item() - Gk.item()) <= 1e-14 * abs(Gk.item())
+        ref[int(off[k]):int(off[k + 1])] = w[k].item() * gk.cpu().numpy()
+    assert np.max(np.abs(a.grad.cpu().numpy() - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def test_penalty_width_is_validated(lbx):
+    s, alpha, rng = _sys(860, (2, 2), NT=4, T=0.4)
+    r = dev(random_pure_states(rng, s.N, 1))
+    say("penalty validation")
+    with pytest.raises(Exception, match="penalty_a"):
+        lbx.adjoint_gradient(lbx.Plan([s]), 0, dev(alpha.reshape(-1)), r, r, dev(np.ones(1)), [1], 0.0, 0,
+                             gamma1=1.0, penalty_a=0.0)
