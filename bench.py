@@ -232,8 +232,15 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=HEADLINE, window=0):
         achieved = by / avg_s / 1e9
         ki = tuned.get("tile_ki", 0)
         tiled = tuned.get("tile", 0) == 1 and ki > 0 and len(p.systems) == 1
-        roof = {"kernel": (f"sweep_tile_kernel<3, 8, {ki // 10}, {ki % 10}, forward|adjoint, {TILE_KIS.get(ki)}>"
-                           if tiled else "sweep_generic_kernel<forward|adjoint>"),
+        s0 = p.systems[0]
+        if tiled and ki >= 100:
+            kname = "split_a_kernel + split_b_sweep_kernel<forward|adjoint>"
+        elif tiled:
+            kname = (f"sweep_tile_kernel<{s0.nlev[0]}, {s0.Q}, {ki // 10}, {ki % 10}, forward|adjoint, "
+                     f"{TILE_KIS.get(ki, 256) if s0.Q == 8 else 256}>")
+        else:
+            kname = "sweep_generic_kernel<forward|adjoint>"
+        roof = {"kernel": kname,
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(f"stage_sweep_c{workload}_ki{ki}", APPLY_SOURCES + STEP_SOURCES)
