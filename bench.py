@@ -6,16 +6,16 @@ entries per state, 689 MB), one state |0..0>, J_Frob to |1..1>, 20
 B-splines per control, T = 100 ns, 5000 implicit-midpoint steps, forward
 pass plus discrete-adjoint gradient with checkpoints every ceil(sqrt(5000))
 = 71 steps recomputed in the adjoint.  One bench step is one gradient
-evaluation of that system at full size over a window of the horizon (default
-142 steps = two checkpoint segments of 71, the segment structure of the full
-run): control table, forward pass with checkpoints, objective, adjoint with
-recomputation and gradient contraction.  `value` is c5 gradient evaluations
-per second derived from it (time per window x 5000 / 142); `--window 5000`
-times the whole horizon.  Inputs are seeded and synthetic and already
-resident in GPU memory when the timed region starts.
+evaluation of that system over its whole horizon: control table, forward
+pass with checkpoints, objective, adjoint with recomputation and gradient
+contraction (about 90 s).  Inputs are seeded and synthetic and already
+resident in GPU memory when the timed region starts.  `--window W` times W
+steps instead, with the horizon shortened to W dt: the B-spline controls
+then vary faster per step than in the workload (more stage sweeps per step),
+so such a line is a quick look, not the workload's rate.
 
 Printed as one JSON line:
-  value          c5 gradient evaluations per second (scaled from the window),
+  value          c5 gradient evaluations per second,
   roofline       the dominant kernel: the block-tiled stage sweep, 48
                  algorithmic bytes per entry and executed sweep (read the
                  iterate and q, write the next iterate) over the HIP-event
@@ -127,7 +127,7 @@ WORKLOADS = {
 
 HEADLINE = 5
 WORKLOADS_NT = {1: 2000, 2: 10000, 3: 5000, 4: 20000, 5: 5000}
-DEFAULT_WINDOW = {5: 142, 3: 500}   # time-step windows of the workloads whose evaluation runs for minutes
+DEFAULT_STEPS = {1: 20, 2: 20, 3: 1, 4: 3, 5: 1}   # timed evaluations (about a minute or less)
 
 
 LDS_MAX_N2 = 4096   # systems up to this N^2 run LDS-resident (every state kept, no recomputation)
@@ -165,15 +165,18 @@ def run_gradient_bench(lbx, torch, steps, warmup, workload=HEADLINE, window=0):
     batch = p.batch
     plan = lbx.Plan(p.systems)
     tuned = plan.autotune(alpha, batch)
-    for _ in range(warmup):
+    for k in range(warmup):
         lbx.adjoint_gradient(plan, p.kind, alpha, rho0, tar, beta, batch, p.gamma2, ckpt)
+        print(f"[bench] warm-up evaluation {k + 1} of {warmup} done", file=sys.stderr, flush=True)
     plan.profile(True)
     for k in range(4):
         plan.profile_read(k, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         G, grad, _ = lbx.adjoint_gradient(plan, p.kind, alpha, rho0, tar, beta, batch, p.gamma2, ckpt)
+        if steps <= 5:  # evaluations of a minute or more: name each one
+            print(f"[bench] evaluation {k + 1} of {steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = {k: plan.profile_read(k) for k in range(4)}
@@ -613,13 +616,16 @@ def c2_summary(lbx, torch, args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed evaluations of the headline workload")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed evaluations of the headline workload (default 1 for workloads 3 and 5, 3 for 4, "
+                         "20 otherwise)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", type=int, default=HEADLINE, choices=[1, 2, 3, 4, 5],
                     help="headline workload (default 5, the eight-qutrit ring)")
-    ap.add_argument("--window", "--sample-steps", type=int, default=-1, dest="window",
-                    help="time steps of the horizon evaluated per bench step (0: all; default 142 for "
-                         "workload 5, 500 for 3, all otherwise); the rate is scaled to the full horizon")
+    ap.add_argument("--window", "--sample-steps", type=int, default=0, dest="window",
+                    help="time W steps with the horizon shortened to W dt (0, the default: the whole "
+                         "horizon); the rate is scaled to the full horizon, but the controls vary faster "
+                         "per step than in the workload")
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--c2-steps", type=int, default=20)
     ap.add_argument("--loop-steps", type=int, default=250)
@@ -657,7 +663,9 @@ def main():
         print(json.dumps(run_traffic_probe(lbx, torch)), flush=True)
         return
     w = args.workload
-    window = DEFAULT_WINDOW.get(w, 0) if args.window < 0 else args.window
+    if args.steps is None:
+        args.steps = DEFAULT_STEPS[w]
+    window = args.window
     print(f"[bench] workload {w} gradient evaluations (window {window or 'all'})", file=sys.stderr, flush=True)
     res = run_gradient_bench(lbx, torch, args.steps, args.warmup, w, window)
     print(f"[bench] {res['value']:.4g} evals/s, {res['window_ms']:.1f} ms per bench step", file=sys.stderr,
@@ -668,9 +676,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": res["window_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": WORKLOADS[w], "global_batch": res["states"], "parallelism": "single GPU",
-                   "step": ("one gradient evaluation of the full-size system over a window of the horizon; "
-                            "value = evaluations of the whole horizon per second")
-                   if res["scale"] != 1 else "one gradient evaluation",
+                   "step": ("one gradient evaluation of the full-size system over a shortened horizon "
+                            "(controls compressed into it); value scaled to the whole horizon")
+                   if res["scale"] != 1 else "one gradient evaluation of the whole horizon",
                    "window_steps": round(WORKLOADS_NT[w] / res["scale"]), "horizon_steps": WORKLOADS_NT[w],
                    "ckpt_every": res["ckpt_every"]},
         "sample": res["sample"],

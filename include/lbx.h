@@ -104,7 +104,7 @@ extern "C" {
 #define LB_OPT_GRAPH 5     /* > 0: streamed time loops are captured as HIP graphs of this
                               many steps and replayed (one graph launch per chunk);
                               0 (default): kernels are launched directly */
-#define LB_OPT_HISTORY 6   /* 0..4, default 4: converged stage increments of earlier steps
+#define LB_OPT_HISTORY 6   /* 0..6, default 5: converged stage increments of earlier steps
                               from which a streamed step extrapolates its first iterate
                               (order HISTORY-1 in the frame of the diagonal Cayley factor);
                               0 starts every stage solve from q */

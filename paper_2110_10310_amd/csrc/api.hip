@@ -1450,7 +1450,7 @@ extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
     return LB_OK;
   }
   if (option == LB_OPT_HISTORY) {
-    if (value < 0 || value > 4 || value != (int)value) return fail(LB_EINVAL, "LB_OPT_HISTORY must be 0..4");
+    if (value < 0 || value > 6 || value != (int)value) return fail(LB_EINVAL, "LB_OPT_HISTORY must be 0..6");
     o.history = (int)value;
     return LB_OK;
   }

@@ -106,7 +106,7 @@ __device__ __forceinline__ double2 cfma(double2 acc, double c, double2 r, double
 // Start of the next step from the history (see the file comment): dn is this
 // step's increment delta_n, R the diagonal Cayley factor, ring slot
 // (n - k) mod H holds delta_{n-k} for k = 1 .. m-1.
-constexpr int HMAX = 4;
+constexpr int HMAX = 6;
 
 __device__ __forceinline__ double2 next_start(double2 dn, double2 R, int m, int n, int H,
                                               const double2 *__restrict__ ring, int64_t stride, int64_t e) {

@@ -25,7 +25,7 @@ struct lbx_opts {
   int tile = 1;                          // LB_OPT_TILE
   int tile_ki = 0;                       // LB_OPT_TILE_KI (0: default block)
   int graph_steps = 0;                   // LB_OPT_GRAPH (0: launch directly)
-  int history = 4;                       // LB_OPT_HISTORY
+  int history = 5;                       // LB_OPT_HISTORY
   int sweeps = 0;                        // LB_OPT_SWEEPS (0: built-in)
   bool profile = false;                  // LB_OPT_PROFILE
   bool sync = true;                      // LB_OPT_SYNC

@@ -649,9 +649,9 @@ def test_streamed_steps_repeat_with_a_priori_counts(lbx):
     assert e.value.code == nat.LB_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("H", [0, 1, 2, 4])
+@pytest.mark.parametrize("H", [0, 1, 2, 4, 6])
 def test_streamed_history_lengths_match_oracle(lbx, H):
-    # The first iterate of a streamed step extrapolated from 0 to 4 earlier
+    # The first iterate of a streamed step extrapolated from 0 to 6 earlier
     # increments (in the diagonal Cayley frame): the converged steps agree
     # with the oracle whatever the start.
     shapes = [(3, 3), (2, 2, 2)]
