@@ -424,27 +424,38 @@ def traffic_summary(fetch_csv, write_csv, copy_bytes, out_path=None):
     print("\n".join(rows))
 
 
-def kernel_stats(db):
-    """Markdown table of the per-kernel summary in a rocprofv3 --stats database;
-    for the stage sweep kernels also the average over executed launches (a
-    launch after its step's solve has converged returns at once)."""
+def kernel_records(path):
+    """(kernel name, duration in ms) of every dispatch in a rocprofv3 kernel
+    trace: a results database, or the kernel_trace.csv of --output-format csv."""
+    if path.endswith(".csv"):
+        import csv
+        with open(path, newline="") as fh:
+            return [(r["Kernel_Name"], (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+                    for r in csv.DictReader(fh)]
     import sqlite3
-    con = sqlite3.connect(db)
-    # durations in the summary view are in microseconds
+    con = sqlite3.connect(path)
+    return [(n, (t1 - t0) / 1e6) for n, t0, t1 in con.execute("select name, start, end from kernels")]
+
+
+def kernel_stats(path):
+    """Markdown table of the per-kernel times in a rocprofv3 kernel trace; for
+    the stage sweep kernels also the average over executed launches (a launch
+    after its step's solve has converged returns at once)."""
+    recs = kernel_records(path)
+    tot = {}
+    for name, d in recs:
+        short = name.split("(")[0].replace("void ", "")
+        c, t = tot.get(short, (0, 0.0))
+        tot[short] = (c + 1, t + d)
+    grand = sum(t for _, t in tot.values()) or 1.0
     print("| kernel | calls | total ms | average ms | % |")
     print("|---|---|---|---|---|")
-    for name, calls, total, avg, pct in con.execute(
-            "select name, total_calls, total_duration, average, percentage from top_kernels limit 16"):
-        short = name.split("(")[0].replace("void ", "")
-        print(f"| `{short}` | {calls} | {total / 1e3:.3f} | {avg / 1e3:.4f} | {pct:.1f} |")
-    try:
-        rows = con.execute("select name, start, end from kernels").fetchall()
-    except sqlite3.Error:
-        return
+    for short, (c, t) in sorted(tot.items(), key=lambda kv: -kv[1][1])[:16]:
+        print(f"| `{short}` | {c} | {t:.3f} | {t / c:.4f} | {100 * t / grand:.1f} |")
     by = {}
-    for name, t0, t1 in rows:
+    for name, d in recs:
         if "sweep_tile_kernel" in name or "sweep_generic_kernel" in name:
-            by.setdefault(name.split("(")[0].replace("void ", ""), []).append((t1 - t0) / 1e6)
+            by.setdefault(name.split("(")[0].replace("void ", ""), []).append(d)
     if not by:
         return
     print()
@@ -638,8 +649,9 @@ def main():
                     help="run only the launches whose HBM counters profiles/traffic.json records")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs")
-    ap.add_argument("--kernel-stats", metavar="DB",
-                    help="print the per-kernel table of a rocprofv3 --stats results database")
+    ap.add_argument("--kernel-stats", metavar="TRACE",
+                    help="print the per-kernel table of a rocprofv3 kernel trace (results database or "
+                         "kernel_trace.csv)")
     args = ap.parse_args()
     if args.kernel_stats:
         kernel_stats(args.kernel_stats)

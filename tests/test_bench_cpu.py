@@ -66,17 +66,26 @@ def test_traffic_summary_calibrates_against_the_copy(tmp_path, capsys):
 
 
 def test_kernel_stats_table(tmp_path, capsys):
+    # the same table from a results database (kernels view, ns timestamps) and
+    # from a kernel_trace.csv; a launch below 5 % of the longest is "other"
+    rows = [("void lbx::sweep_tile_kernel<3, 8, 3, 4, false, 256>(int)", 0, 2_000_000),
+            ("void lbx::sweep_tile_kernel<3, 8, 3, 4, false, 256>(int)", 3_000_000, 5_000_000),
+            ("void lbx::sweep_tile_kernel<3, 8, 3, 4, false, 256>(int)", 6_000_000, 6_010_000),
+            ("void lbx::step_count_kernel(lbx::StepArgs)", 7_000_000, 7_005_000)]
     db = tmp_path / "r.db"
     con = sqlite3.connect(db)
-    con.execute("create table top_kernels (name text, total_calls int, total_duration real, "
-                "average real, percentage real)")
-    con.execute("insert into top_kernels values ('void lbx::sweep_kernel<false, true>(int)', 4, 2000.0, "
-                "500.0, 75.0)")
+    con.execute("create table kernels (name text, start int, end int)")
+    con.executemany("insert into kernels values (?, ?, ?)", rows)
     con.commit()
     con.close()
-    bench.kernel_stats(str(db))
-    out = capsys.readouterr().out
-    assert "| `lbx::sweep_kernel<false, true>` | 4 | 2.000 | 0.5000 | 75.0 |" in out
+    csvf = tmp_path / "kernel_trace.csv"
+    csvf.write_text("Kernel_Name,Start_Timestamp,End_Timestamp\n" +
+                    "".join(f'"{n}",{a},{b}\n' for n, a, b in rows))
+    for path in (db, csvf):
+        bench.kernel_stats(str(path))
+        out = capsys.readouterr().out
+        assert "| `lbx::sweep_tile_kernel<3, 8, 3, 4, false, 256>` | 3 | 4.010 | 1.3367 | 99.9 |" in out
+        assert "| `lbx::sweep_tile_kernel<3, 8, 3, 4, false, 256>` | 3 | 2 | 2.0000 | 0.0100 |" in out
 
 
 def test_cost_model_of_the_two_transmon_workload():
