@@ -16,9 +16,14 @@ Each target writes tests/golden/<name>.npz:
 * c4_chain_nt400    the five-qutrit chain (10 states) over its first 400
                     steps: G, dG/dalpha, sampled entries, traces and norms of
                     rho(T).  About two CPU-hours.
-* c5_ring_nt2       the eight-qutrit ring from |0..0> over its first 2 steps:
-                    G, dG/dalpha, sampled entries, trace and norm of rho(T).
-                    About half an hour and 20 GB of memory.
+* c5_ring_nt2       the eight-qutrit ring shortened to 2 steps (T = 2 dt, the
+                    controls' splines over that horizon), from |0..0> and from
+                    one seeded random pure state (random target):
+                    G, dG/dalpha, sampled entries, traces and norms of rho(T).
+                    About an hour and 20 GB of memory per state.  (From
+                    |0..0> alone the 2-step gradient is 2.6e-11, eleven orders
+                    below G, a sum of cancelling terms whose rounding floor in
+                    FP64 is about 1e-19; the random state makes it large.)
 
 The states of a workload are evaluated one per task over a process pool
 (default: the CPU count less two).
@@ -38,16 +43,25 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from workloads import make_config, truncate_steps  # noqa: E402
+from workloads import make_config, truncate_steps, with_random_states  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# (workload, steps kept, sampled entries per state, name)
+# (workload, steps kept, sampled entries per state, name, extra random states)
 TARGETS = {
-    "c3": (3, 20, 8, "c3_uneven_nt20"),
-    "c4": (4, 400, 64, "c4_chain_nt400"),
-    "c5": (5, 2, 512, "c5_ring_nt2"),
+    "c3": (3, 20, 8, "c3_uneven_nt20", 0),
+    "c4": (4, 400, 64, "c4_chain_nt400", 0),
+    "c5": (5, 2, 512, "c5_ring_nt2", 1),
 }
+EXTRA_SEED = 5150  # seed of the extra random states
+
+
+def problem(cfg, nt, extra):
+    """The truncated workload, with `extra` random states per system."""
+    p = make_config(cfg)
+    if extra:
+        p = with_random_states(p, extra, EXTRA_SEED)
+    return truncate_steps(p, nt)
 
 
 def make_c2():
@@ -65,8 +79,8 @@ def make_c2():
 def _one_state(args):
     """The oracle's G and gradient of one state of one system (weight beta_b,
     no regularisation) and its rho(T)."""
-    cfg, nt, k, b = args
-    p = truncate_steps(make_config(cfg), nt)
+    cfg, nt, extra, k, b = args
+    p = problem(cfg, nt, extra)
     s = p.systems[k]
     g, gr, rhoT = oracle.value_and_gradient(s, p.alpha[k], p.rho0[k][b:b + 1], p.rhotar[k][b:b + 1],
                                             p.beta[k][b:b + 1], p.kind, 0.0, return_final=True)
@@ -79,11 +93,11 @@ def make_truncated(key, procs):
     states' gradients plus gamma2 alpha: the states are evaluated one per
     task, over `procs` processes."""
     import multiprocessing as mp
-    cfg, nt, nsamp, name = TARGETS[key]
-    p = truncate_steps(make_config(cfg), nt)
-    tasks = [(cfg, nt, k, b) for k in range(len(p.systems)) for b in range(p.rho0[k].shape[0])]
+    cfg, nt, nsamp, name, extra = TARGETS[key]
+    p = problem(cfg, nt, extra)
+    tasks = [(cfg, nt, extra, k, b) for k in range(len(p.systems)) for b in range(p.rho0[k].shape[0])]
     # largest systems first, so the pool ends together
-    tasks.sort(key=lambda a: -p.systems[a[2]].N)
+    tasks.sort(key=lambda a: -p.systems[a[3]].N)
     t0 = time.time()
     res = {}
     with mp.get_context("spawn").Pool(procs) as pool:
@@ -113,7 +127,8 @@ def make_truncated(key, procs):
             fro.append(np.linalg.norm(rT))
     out = os.path.join(HERE, name + ".npz")
     np.savez_compressed(out, G=np.array(G), grad=np.concatenate(grads), NT=np.array(nt),
-                        config=np.array(cfg), samp_sys=np.array(si), samp_state=np.array(sb),
+                        config=np.array(cfg), extra=np.array(extra), extra_seed=np.array(EXTRA_SEED),
+                        samp_sys=np.array(si), samp_state=np.array(sb),
                         samp_row=np.concatenate(sr), samp_col=np.concatenate(sc),
                         samp_val=np.concatenate(sv), trace=np.array(tr), fro=np.array(fro))
     print(f"wrote {out}: {len(p.systems)} systems, |grad|max={np.abs(np.concatenate(grads)).max():.6e} "

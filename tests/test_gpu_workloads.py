@@ -4,7 +4,7 @@ linsystem_adjoint and the reduced gradient of App. A/B).
 * Stored oracle values (tests/golden/make_golden.py, oracle only): the whole
   uneven batch of 96 systems over its first 20 steps, the five-qutrit chain
   over 400 steps with checkpoints every 200, and the eight-qutrit ring over
-  2 steps.  G within 1e-12 relative, the gradient within 1e-10 of its
+  2 steps from |0..0> and from a seeded random pure state.  G within 1e-12 relative, the gradient within 1e-10 of its
   max-norm, sampled entries of rho(T) within 1e-12 of each state's
   Frobenius norm, traces and norms within 1e-12 relative.
 * The eight-qutrit ring's implicit-midpoint step (forward and adjoint) at
@@ -23,7 +23,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
-from workloads import make_config, random_alpha, random_pure_states, random_system, truncate_steps  # noqa: E402
+from workloads import (  # noqa: E402
+    make_config, random_alpha, random_pure_states, random_system, truncate_steps, with_random_states,
+)
 
 from _gpu import dev, flat_alpha, flat_states, rel_state_err, say, split_states  # noqa: E402
 
@@ -43,7 +45,10 @@ def lbx():
 def _check_against_golden(lbx, name, ckpt):
     gold = np.load(os.path.join(GOLDEN, name + ".npz"))
     cfg, nt = int(gold["config"]), int(gold["NT"])
-    p = truncate_steps(make_config(cfg), nt)
+    p = make_config(cfg)
+    if "extra" in gold.files and int(gold["extra"]) > 0:
+        p = with_random_states(p, int(gold["extra"]), int(gold["extra_seed"]))
+    p = truncate_steps(p, nt)
     plan = lbx.Plan(p.systems)
     alpha = dev(flat_alpha(p.alpha))
     say(name, "systems", len(p.systems), "steps", nt, "ckpt", ckpt)
