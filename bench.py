@@ -468,7 +468,10 @@ def kernel_stats(path):
         rest = [v for v in d if v < cut]
         print(f"| `{name}` | {len(d)} | {len(ex)} | {np.mean(ex):.4f} | "
               f"{np.mean(rest) if rest else 0.0:.4f} |")
-    allex = [v for d in by.values() for v in d if v >= 0.05 * max(d)]
+    allex = []
+    for d in by.values():
+        cut = 0.05 * max(d)
+        allex += [v for v in d if v >= cut]
     print(f"\nall executed stage sweep launches: {len(allex)}, average {np.mean(allex):.4f} ms")
 
 

@@ -18,7 +18,7 @@ What is computed, and where the paper defines it:
 * Discrete adjoint and reduced gradient: App. B, eqs. (linsystem_adjoint)
   and (reducedgradient).
 
-Readings of passages that are silent or garbled (listed in the design doc too):
+Readings of passages that are silent or garbled:
 
 * All frequencies enter as 2*pi times the GHz value; times are in ns.
   Control coefficients alpha are GHz values as well, so d_q carries 2*pi.
