@@ -110,6 +110,13 @@ extern "C" {
                               0 starts every stage solve from q */
 #define LB_OPT_SYNC 7      /* 1 (default): calls wait for their work and return the device
                               status; 0: calls return once enqueued (see lb_status) */
+#define LB_OPT_FUSE_GRAD 9 /* 1: the last sweep of a block-tiled adjoint step also forms the
+                              step's gradient integrands (App. B eq. reducedgradient) from the
+                              neighbour values it loads, with the stage vector one sweep
+                              before convergence (a difference within the stage solve's
+                              bound), where the block shape allows it without spilling;
+                              0 (default): a separate integrand kernel after the converged
+                              step (as fast or faster on the measured systems) */
 #define LB_OPT_SWEEPS 8    /* stage-solve sweeps launched per streamed step: 0 (default)
                               8 for steps started from a full history, 12 for the others;
                               2..64: that many for every step.  A step runs only the sweeps

@@ -37,6 +37,7 @@ LB_OPT_GRAPH = 5
 LB_OPT_HISTORY = 6
 LB_OPT_SYNC = 7
 LB_OPT_SWEEPS = 8
+LB_OPT_FUSE_GRAD = 9
 
 LB_NOALLOC_SCRATCH_BYTES = 67108864
 LB_NOALLOC_MAX_ENTRIES = 2064384

@@ -774,8 +774,11 @@ int krylov_step(const StreamCtx &c, int j, bool adj, const double2 *q, double2 *
   return launch_kry_finish(A, adj, Y, q, out, zh, st);
 }
 
+// gq0, gq1, gpart (block-tiled adjoint steps): the forward states q^j, q^{j+1}
+// and the partial-sum rows of the gradient integrands the last sweep forms.
 int stream_step(const StreamCtx &c, int j, bool adj, const double2 *q, double2 *out, PassHist &ph, double2 *zh,
-                hipStream_t st) {
+                hipStream_t st, const double2 *gq0 = nullptr, const double2 *gq1 = nullptr,
+                double *gpart = nullptr) {
   if (c.kst && (*c.kst)[j] < 0) {  // Krylov fallback step
     ph.n++;
     return krylov_step(c, j, adj, q, out, zh, st);
@@ -785,6 +788,9 @@ int stream_step(const StreamCtx &c, int j, bool adj, const double2 *q, double2 *
   A.q = q;
   A.out = out;
   A.zh = zh;
+  A.gq0 = gq0;
+  A.gq1 = gq1;
+  A.gpart = gpart;
   A.par = (int)(c.seq++ & 1);
   const int H = c.kst ? 0 : ph.H;
   A.H = H;
@@ -1151,6 +1157,8 @@ int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const 
     int64_t rows = 0;
     const int nseg = (int)m.segs.size();
     const int gk = grad_tile_k(p, m);
+    // the last sweep of a block-tiled adjoint step forms its gradient integrands
+    const bool fuse = o.fuse_grad && gk > 0 && m.tile_sys >= 0 && tile_grad_fusable(p, m.tile_sys, m.tile_k);
     if ((rc = launch_terminal(p, kind, m.d_segs, nseg, m.st_blocks, ck + (size_t)(L.T.nck - 1) * E, rhotar, beta,
                               m.d_seg_state0, gscale, qh[0], st)))
       return rc;
@@ -1178,14 +1186,19 @@ int run_backward(const lb_plan *p, const lbx_opts &o, const BatchMeta &m, const 
         const int cb = std::max(j0, ce - chunk);
         if ((rc = gr.begin())) return rc;
         for (int j = ce - 1; j >= cb; --j) {
-          // The last sweep also writes the stage vector zh = qh^{j+1} + delta
-          // = (qh^j + qh^{j+1})/2.
-          if ((rc = stream_step(sc, j, true, qh[cur], qh[cur ^ 1], ah, zh, ast))) return rc;
           // Partial rows of the pending steps go to successive slots and are
           // reduced together (every gbatch steps and at the end of a chunk).
           if (pend == 0) jtop = j;
           double *gp = sgp + (size_t)pend * gstride;
-          {
+          const bool fj = fuse && !(kst && (*kst)[j] < 0);  // not a Krylov step
+          if (fj) {
+            if ((rc = stream_step(sc, j, true, qh[cur], qh[cur ^ 1], ah, nullptr, ast, slot(j), slot(j + 1), gp)))
+              return rc;
+            rows = tile_grad_rows(p, m.tile_sys, m.tile_B, gk);
+          } else {
+            // The last sweep also writes the stage vector zh = qh^{j+1} + delta
+            // = (qh^j + qh^{j+1})/2.
+            if ((rc = stream_step(sc, j, true, qh[cur], qh[cur ^ 1], ah, zh, ast))) return rc;
             ProfScope ps(p, prof, LB_KERNEL_STREAM_GRAD, ast, m.st_entries);
             rc = gk > 0 ? launch_tile_grad(p, m.tile_sys, m.tile_B, gk, zh, slot(j), slot(j + 1), gp, &rows, ast)
                         : launch_stream_grad(p, m.d_segs, nseg, m.st_blocks, zh, slot(j), slot(j + 1), gp, ast);
@@ -1458,6 +1471,10 @@ extern "C" int lb_plan_set_option(lb_plan *p, int32_t option, double value) {
     if (value != 0 && (value < 2 || value > 64 || value != (int)value))
       return fail(LB_EINVAL, "LB_OPT_SWEEPS must be 0 or 2..64");
     o.sweeps = (int)value;
+    return LB_OK;
+  }
+  if (option == LB_OPT_FUSE_GRAD) {
+    o.fuse_grad = value != 0.0;
     return LB_OK;
   }
   if (option == LB_OPT_SYNC) {

@@ -181,6 +181,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_tile_kernel(StepArgs A, int kk) {
   if (kk > 0) {
     K = step_sweeps_of(A, A.sys);
     if (kk >= K) return;  // this step's solve is done (uniform per launch)
+    if (ADJ && A.gpart && kk == K - 1) return;  // sweep_tile_grad_kernel takes it
   }
   const int lane = threadIdx.x & 63;
   double2 dv = make_double2(0.0, 0.0);
@@ -207,6 +208,64 @@ __global__ __launch_bounds__(BLOCK) void sweep_tile_kernel(StepArgs A, int kk) {
       atomicMax(&sl[blockIdx.x % LB_STEP_SLOTS], dbits(so.e1));
       atomicMax(&sl[LB_STEP_SLOTS + blockIdx.x % LB_STEP_SLOTS], dbits(so.qm));
     }
+  }
+}
+
+// Last sweep of a block-tiled adjoint step together with the step's gradient
+// integrands (App. B eq. reducedgradient), which read the stage vector at the
+// neighbours the sweep loads anyway.  The stage vector of the integrands is
+// the sweep's input iterate (after K - 1 sweeps) instead of the converged one:
+// the two differ by at most the solve's bound one sweep earlier, about
+// tol / theta relative.  Runs only when kk is the step's last sweep (the plain
+// kernel skips that one), writes the step's update like any last sweep, and
+// one row of 2 Q partial sums per unit into A.gpart in a fixed order.
+template <int NL, int QC, int KR, int KC, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void sweep_tile_grad_kernel(StepArgs A, int kk) {
+  extern __shared__ double2 tileb[];
+  __shared__ double red[BLOCK / 64][2 * QC];
+  const int64_t per = (A.units + 7) / 8;
+  const int64_t lb = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (lb >= A.units) return;
+  const SysDev &S = A.sysv[A.sys];
+  const int K = step_sweeps_of(A, A.sys);
+  if (kk != K - 1) return;  // uniform per launch
+  const int lane = threadIdx.x & 63;
+  double2 dv = make_double2(0.0, 0.0);
+  if (lane < QC) dv = A.ctab[S.ctab_off + (int64_t)A.j * QC + lane - A.cshift];
+  double da[QC], db[QC];
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    da[q] = tile::lane_d(dv.x, q);
+    db[q] = tile::lane_d(dv.y, q);
+  }
+  SweepOut so;
+  so.first = false;
+  so.last = true;
+  so.zo = (kk & 1) ? A.z1 : A.z0;
+  tile::GradAcc<QC> ga;
+  ga.q0 = A.gq0;
+  ga.q1 = A.gq1;
+#pragma unroll
+  for (int q = 0; q < QC; ++q) ga.p[q] = ga.q[q] = 0.0;
+  const double h = S.h;
+  tile::tile_unit<NL, QC, KR, KC, true, BLOCK, true>(
+      S, lb, sweep_input(A, kk), tileb, da, db, A.Etab + S.tab_off, false,
+      [&](const tile::Entry &en) { sweep_entry<true>(A, so, en.e, h, en.gam, en.dE, en.acc, en.own); }, &ga);
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    const double a = wave_sum<64>(ga.p[q]), c = wave_sum<64>(ga.q[q]);
+    if (lane == 0) {
+      red[wv][2 * q] = a;
+      red[wv][2 * q + 1] = c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * QC) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) v += red[w][threadIdx.x];
+    A.gpart[lb * 2 * QMAX + threadIdx.x] = v;
   }
 }
 
@@ -515,6 +574,14 @@ int sweep_tile_launch(const lb_plan *p, StepArgs &A, int kk, bool adj, hipStream
   else
     hipLaunchKernelGGL((sweep_tile_kernel<NL, QC, KR, KC, false, BLOCK>), grid, dim3(BLOCK), shmem, st, A, kk);
   LBX_HIP(hipGetLastError());
+  if (adj && A.gpart && kk > 0) {  // the step's last sweep with its gradient integrands
+    // same blocks, twice the threads where a thread would hold more than 5 entries
+    constexpr int GB = (Sh::EPT > 5 && BLOCK < 512) ? 2 * BLOCK : BLOCK;
+    const void *g = (const void *)sweep_tile_grad_kernel<NL, QC, KR, KC, GB>;
+    LBX_HIP(hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * shmem)));
+    hipLaunchKernelGGL((sweep_tile_grad_kernel<NL, QC, KR, KC, GB>), grid, dim3(GB), 2 * shmem, st, A, kk);
+    LBX_HIP(hipGetLastError());
+  }
   return LB_OK;
 }
 
@@ -607,6 +674,34 @@ int launch_split_apply(const lb_plan *p, int sys, int B, bool adj, double t, con
   }
   LBX_HIP(hipGetLastError());
   return LB_OK;
+}
+
+namespace {
+
+// Whether the fused last adjoint sweep of this block shape keeps every value
+// in registers (no private memory): otherwise the separate integrand kernel
+// is faster.
+template <int NL, int QC, int KR, int KC, int BLOCK>
+bool tile_grad_fused_fits() {
+  using Sh = tile::Shape<NL, QC, KR, KC, BLOCK>;
+  constexpr int GB = (Sh::EPT > 5 && BLOCK < 512) ? 2 * BLOCK : BLOCK;
+  if (2 * Sh::lds_bytes() > (size_t)160 * 1024) return false;  // the block and the stage vector in LDS
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, (const void *)sweep_tile_grad_kernel<NL, QC, KR, KC, GB>) != hipSuccess) return false;
+  return fa.localSizeBytes == 0;
+}
+
+}  // namespace
+
+bool tile_grad_fusable(const lb_plan *p, int sys, int tile_k) {
+  if (sys < 0 || tile_k <= 0 || tile_k >= LB_SPLIT_BASE) return false;
+  const SysDev &S = p->sys[sys];
+  const int nl = S.nlev[0];
+#define X(NL_, Q_, R_, C_, T_) \
+  if (nl == NL_ && S.Q == Q_ && tile_k == 10 * R_ + C_) return tile_grad_fused_fits<NL_, Q_, R_, C_, T_>();
+  LBX_TILE_SHAPES(X)
+#undef X
+  return false;
 }
 
 int launch_sweep(const lb_plan *p, StepArgs &A, int kk, bool adj, int tile_sys, int tile_k, hipStream_t st) {

@@ -27,6 +27,7 @@ struct lbx_opts {
   int graph_steps = 0;                   // LB_OPT_GRAPH (0: launch directly)
   int history = 5;                       // LB_OPT_HISTORY
   int sweeps = 0;                        // LB_OPT_SWEEPS (0: built-in)
+  bool fuse_grad = false;                // LB_OPT_FUSE_GRAD
   bool profile = false;                  // LB_OPT_PROFILE
   bool sync = true;                      // LB_OPT_SYNC
   double tol = 1.1102230246251565e-16;   // LB_OPT_SOLVE_TOL (2^-53)
@@ -175,7 +176,16 @@ struct StepArgs {
   // split_q..Q-1 (products of levels split_na), pass B the others
   int split_q;
   int64_t split_na, split_sp;
+  // block-tiled adjoint step: when gpart is set, its last sweep also forms
+  // the step's gradient integrands from the forward states gq0 = q^j and
+  // gq1 = q^{j+1}, one row of 2 QMAX partial sums per unit
+  const double2 *gq0, *gq1;
+  double *gpart;
 };
+
+// Whether the last sweep of a block-tiled adjoint step of this system and
+// block shape can form the step's gradient integrands (StepArgs::gpart).
+bool tile_grad_fusable(const lb_plan *p, int sys, int tile_k);
 
 // Block shapes at or above this code select the two-pass sweep and apply of
 // one system, split after (code - LB_SPLIT_BASE) least significant subsystems.

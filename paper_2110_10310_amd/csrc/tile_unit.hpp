@@ -108,6 +108,21 @@ __host__ __device__ inline int64_t tile_units(int N, int TR, int TC, int B) {
   return (int64_t)B * (N / TR) * (N / TC);
 }
 
+// Gradient integrands of one adjoint step (App. B eq. reducedgradient) formed
+// alongside a unit: the unit's input x is the adjoint stage vector zh, z =
+// (q0 + q1)/2 is the forward stage vector at the unit's own entries, and for
+// every subsystem q the thread sums
+//   p[q] += w Im-type and q[q] += w Re-type products of x at the q-neighbours
+// with z, regrouped by neighbour (the terms of grad_term in lbx_device.hpp).
+template <int QC>
+struct GradAcc {
+  const double2 *q0, *q1;  // forward states q^j and q^{j+1} ([B][N][N])
+  double p[QC], q[QC];
+};
+
+__device__ __forceinline__ double gcross(double2 a, double2 z) { return a.x * z.y - a.y * z.x; }
+__device__ __forceinline__ double gdot(double2 a, double2 z) { return a.x * z.x + a.y * z.y; }
+
 // The data of one entry handed to the output functor.
 struct Entry {
   int64_t e;     // flat index of the entry in the batch ([B][N][N])
@@ -123,14 +138,19 @@ struct Entry {
 // (uniform); Es: energies of this system.  When `sync_first` the workgroup
 // waits before its LDS stores (a previous unit in the same workgroup may
 // still read the buffer).  out(const Entry &) is called once per entry of
-// the unit.
-template <int NL, int QC, int KR, int KC, bool ADJ, int BLOCK, class Out>
+// the unit.  With GRAD the unit also adds this thread's gradient integrands
+// with zin as the adjoint stage vector to *ga (the neighbour values the
+// stencil loads serve both); the forward stage vector of the unit is then
+// staged in LDS after the block (tile must hold 2 TT entries) and the
+// external directions are taken one at a time.
+template <int NL, int QC, int KR, int KC, bool ADJ, int BLOCK, bool GRAD = false, class Out>
 __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const double2 *__restrict__ zin,
                                           double2 *tile, const double (&da)[QC], const double (&db)[QC],
-                                          const double *__restrict__ Es, bool sync_first, Out &&out) {
+                                          const double *__restrict__ Es, bool sync_first, Out &&out,
+                                          GradAcc<QC> *ga = nullptr) {
   using Sh = Shape<NL, QC, KR, KC, BLOCK>;
   constexpr int ER = Sh::ER, EC = Sh::EC, TR = Sh::TR, TC = Sh::TC, TT = Sh::TT, EPT = Sh::EPT;
-  constexpr int ND = Sh::ND, G = Sh::G;
+  constexpr int ND = Sh::ND, G = GRAD ? 1 : Sh::G;
   constexpr bool TABLE = Sh::TABLE;
   const int N = S.N;
   const int NBR = N / TR, NBC = N / TC;
@@ -172,6 +192,21 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
     offs[k] = off_of(k);
     tv[k] = X[offs[k]];
   }
+  // forward stage vector at the own entries, staged in LDS with the block
+  double2 *const ztile = tile + TT;
+  double2 zl[GRAD ? EPT : 1];
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const double2 a = ga->q0[b * N2 + offs[k]], c = ga->q1[b * N2 + offs[k]];
+      zl[k] = make_double2(0.5 * (a.x + c.x), 0.5 * (a.y + c.y));
+    }
+  }
+  // forward stage vector of this thread's k-th entry (zero past the block's end)
+  auto zf = [&](int k) -> double2 {
+    const int f = tid + k * BLOCK;
+    return f < TT ? ztile[f] : make_double2(0.0, 0.0);
+  };
   // While the block loads, every wavefront builds its table of external
   // directions (blocks of 2 to 11 entries per thread): lane d takes slot
   // d (row digit d / 2, column digit (d - 2 ER) / 2, then jumps) and decides
@@ -180,6 +215,8 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
   bool ex = false;
   double2 cf = make_double2(0.0, 0.0);
   int64_t sh = 0;
+  double gwp = 0.0, gwq = 0.0;  // GRAD: weights of the direction's integrand terms
+  int gqi = 0;                  // GRAD: its subsystem
   if constexpr (TABLE) {
     if (lane < ND) {
       const int d = lane;
@@ -208,11 +245,21 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
         cf = plus ? ctl_coef<DIR_RP, ADJ>(a, bq, sqrt_small<NL>(n + 1))
                   : ctl_coef<DIR_RM, ADJ>(a, bq, sqrt_small<NL>(n));
         sh = plus ? st * N : -st * N;
+        // row shift +e: (w, -w) with w = sqrt(n+1); -e: (w, w) with w = sqrt(n)
+        const double w = plus ? sqrt_small<NL>(n + 1) : sqrt_small<NL>(n);
+        gwp = w;
+        gwq = plus ? -w : w;
+        gqi = q;
       } else if (kind == 1) {
         ex = plus ? m + 1 < NL : m > 0;
         cf = plus ? ctl_coef<DIR_CP, ADJ>(a, bq, sqrt_small<NL>(m + 1))
                   : ctl_coef<DIR_CM, ADJ>(a, bq, sqrt_small<NL>(m));
         sh = plus ? st : -st;
+        // column shift +e: (-w, -w) with w = sqrt(m+1); -e: (-w, w) with w = sqrt(m)
+        const double w = plus ? sqrt_small<NL>(m + 1) : sqrt_small<NL>(m);
+        gwp = -w;
+        gwq = plus ? -w : w;
+        gqi = q;
       } else {
         ex = !ADJ ? (n + 1 < NL && m + 1 < NL) : (n > 0 && m > 0);
         cf = make_double2(!ADJ ? g1 * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
@@ -227,6 +274,8 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
   for (int k = 0; k < EPT; ++k) {
     const int f = tid + k * BLOCK;
     if (f < TT) tile[f] = tv[k];
+    if constexpr (GRAD)
+      if (f < TT) ztile[f] = zl[k];
   }
   // External directions first (they do not read the LDS block), G at a time:
   // the existing slots are taken in order from the ballot mask, a missing
@@ -257,27 +306,68 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int k = 0; k < EPT; ++k) cmac(acc[k], cg[g], v[g][k]);
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const double wp = lane_d(gwp, dl[g]), wq = lane_d(gwq, dl[g]);
+          const int qg = __builtin_amdgcn_readlane(gqi, dl[g]);
+          double cp = 0.0, dp = 0.0;
+#pragma unroll
+          for (int k = 0; k < EPT; ++k) {
+            const double2 z = zf(k);
+            cp += gcross(v[g][k], z);
+            dp += gdot(v[g][k], z);
+          }
+#pragma unroll
+          for (int qq = 0; qq < QC; ++qq)
+            if (qq == qg) {  // uniform
+              ga->p[qq] += wp * cp;
+              ga->q[qq] += wq * dp;
+            }
+        }
+      }
     }
   } else {
     // One entry per thread, or the largest blocks: the directions one at a
     // time under uniform branches (measured faster there than the table).
-    auto direction = [&](double2 c, int64_t shift) {
+    // GRAD: the integrand weights (wp, wq) of subsystem q as in the table.
+    auto direction = [&](double2 c, int64_t shift, int q, double wp, double wq) {
+      double2 v[EPT];
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) cmac(acc[k], c, X[offs[k] + shift]);
+      for (int k = 0; k < EPT; ++k) v[k] = X[offs[k] + shift];
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) cmac(acc[k], c, v[k]);
+      if constexpr (GRAD) {
+        double cp = 0.0, dp = 0.0;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const double2 z = zf(k);
+          cp += gcross(v[k], z);
+          dp += gdot(v[k], z);
+        }
+        ga->p[q] += wp * cp;
+        ga->q[q] += wq * dp;
+      }
     };
 #pragma unroll
     for (int q = 0; q < ER; ++q) {
       const int n = ne[q];
       const int64_t sN = (int64_t)S.stride[q] * N;
-      if (n + 1 < NL) direction(ctl_coef<DIR_RP, ADJ>(da[q], db[q], sqrt_small<NL>(n + 1)), sN);
-      if (n > 0) direction(ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), -sN);
+      if (n + 1 < NL)
+        direction(ctl_coef<DIR_RP, ADJ>(da[q], db[q], sqrt_small<NL>(n + 1)), sN, q, sqrt_small<NL>(n + 1),
+                  -sqrt_small<NL>(n + 1));
+      if (n > 0) direction(ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), -sN, q, sqrt_small<NL>(n),
+                           sqrt_small<NL>(n));
     }
 #pragma unroll
     for (int q = 0; q < EC; ++q) {
       const int m = me[q];
       const int64_t s1 = S.stride[q];
-      if (m + 1 < NL) direction(ctl_coef<DIR_CP, ADJ>(da[q], db[q], sqrt_small<NL>(m + 1)), s1);
-      if (m > 0) direction(ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), -s1);
+      if (m + 1 < NL)
+        direction(ctl_coef<DIR_CP, ADJ>(da[q], db[q], sqrt_small<NL>(m + 1)), s1, q, -sqrt_small<NL>(m + 1),
+                  -sqrt_small<NL>(m + 1));
+      if (m > 0) direction(ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), -s1, q, -sqrt_small<NL>(m),
+                           sqrt_small<NL>(m));
     }
 #pragma unroll
     for (int q = 0; q < (ER < EC ? ER : EC); ++q) {
@@ -287,7 +377,7 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
         const double cj = !ADJ ? S.g1[q] * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
                                : S.g1[q] * sqrt_small<NL>(n) * sqrt_small<NL>(m);
         const int64_t sj = (int64_t)S.stride[q] * N + S.stride[q];
-        direction(make_double2(cj, 0.0), !ADJ ? sj : -sj);
+        direction(make_double2(cj, 0.0), !ADJ ? sj : -sj, q, 0.0, 0.0);
       }
     }
   }
@@ -329,14 +419,16 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
       // itself with a zero weight (no divergent branches).
       const bool rp = n + 1 < NL, rm = n > 0, cp = m + 1 < NL, cm = m > 0;
       if (q >= ER) {  // internal row digit: a row shift of st is st*TC entries in the block
-        cmac(ac, ctl_coef<DIR_RP, ADJ>(da[q], db[q], rp ? sqrt_small<NL>(n + 1) : 0.0),
-             tile[f + (rp ? st * TC : 0)]);
-        cmac(ac, ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), tile[f - (rm ? st * TC : 0)]);
+        const double2 vp = tile[f + (rp ? st * TC : 0)], vm = tile[f - (rm ? st * TC : 0)];
+        const double wp = rp ? sqrt_small<NL>(n + 1) : 0.0, wm = sqrt_small<NL>(n);
+        cmac(ac, ctl_coef<DIR_RP, ADJ>(da[q], db[q], wp), vp);
+        cmac(ac, ctl_coef<DIR_RM, ADJ>(da[q], db[q], wm), vm);
       }
       if (q >= EC) {
-        cmac(ac, ctl_coef<DIR_CP, ADJ>(da[q], db[q], cp ? sqrt_small<NL>(m + 1) : 0.0),
-             tile[f + (cp ? st : 0)]);
-        cmac(ac, ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), tile[f - (cm ? st : 0)]);
+        const double2 vp = tile[f + (cp ? st : 0)], vm = tile[f - (cm ? st : 0)];
+        const double wp = cp ? sqrt_small<NL>(m + 1) : 0.0, wm = sqrt_small<NL>(m);
+        cmac(ac, ctl_coef<DIR_CP, ADJ>(da[q], db[q], wp), vp);
+        cmac(ac, ctl_coef<DIR_CM, ADJ>(da[q], db[q], wm), vm);
       }
       const bool jr = !ADJ ? (rp && cp) : (rm && cm);
       const double cj = !jr ? 0.0
@@ -362,6 +454,39 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
     en.gam = gam;
     en.dE = Es[i] - Es[j];
     out(en);
+  }
+  // GRAD: the integrand terms of the internal digits, in a pass of their own
+  // over the LDS block (the stencil's registers are free by now).
+  if constexpr (GRAD) {
+#pragma unroll 1
+    for (int k = 0; k < EPT; ++k) {
+      const int f = tid + k * BLOCK;
+      if (f >= TT) continue;
+      const double2 z = ztile[f];
+      int ra = f / TC, rc = f - (f / TC) * TC;
+#pragma unroll
+      for (int q = QC - 1; q >= 0; --q) {
+        const int st = S.stride[q];
+        if (q >= ER) {
+          const int n = ra % NL;
+          ra /= NL;
+          const bool rp = n + 1 < NL, rm = n > 0;
+          const double2 vp = tile[f + (rp ? st * TC : 0)], vm = tile[f - (rm ? st * TC : 0)];
+          const double wp = rp ? sqrt_small<NL>(n + 1) : 0.0, wm = sqrt_small<NL>(n);
+          ga->p[q] += wp * gcross(vp, z) + wm * gcross(vm, z);
+          ga->q[q] += -wp * gdot(vp, z) + wm * gdot(vm, z);
+        }
+        if (q >= EC) {
+          const int m = rc % NL;
+          rc /= NL;
+          const bool cp = m + 1 < NL, cm = m > 0;
+          const double2 vp = tile[f + (cp ? st : 0)], vm = tile[f - (cm ? st : 0)];
+          const double wp = cp ? sqrt_small<NL>(m + 1) : 0.0, wm = sqrt_small<NL>(m);
+          ga->p[q] += -wp * gcross(vp, z) - wm * gcross(vm, z);
+          ga->q[q] += -wp * gdot(vp, z) + wm * gdot(vm, z);
+        }
+      }
+    }
   }
 }
 

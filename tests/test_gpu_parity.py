@@ -676,3 +676,62 @@ def test_streamed_history_lengths_match_oracle(lbx, H):
         assert np.max(np.abs(ga - gr)) <= GRAD_TOL * np.max(np.abs(gr))
         off_b += batch[k]
         off_a += alphas[k].size
+
+
+# ------------------------------------------------- gradient integrands in the last sweep
+
+@pytest.mark.parametrize("nlev,ki,fused", [((3,) * 5, 33, True), ((3,) * 5, 32, True), ((3,) * 5, 23, True),
+                                           ((3,) * 6, 43, True), ((3,) * 7, 33, True), ((3,) * 6, 0, False),
+                                           ((2,) * 9, 0, False)])
+def test_fused_gradient_integrands_match_the_separate_kernel(lbx, nlev, ki, fused):
+    # The last sweep of a block-tiled adjoint step forms the gradient
+    # integrands with the stage vector one sweep before convergence; the
+    # separate kernel uses the converged one.  Both agree with each other to
+    # the stage solve's bound and with the oracle to the parity tolerance.
+    # Block shapes whose fused kernel would not keep its values in registers
+    # (the 81 x 81 qutrit and 64 x 64 qubit blocks) keep the separate kernel.
+    systems, alphas, rho0, batch = _multi([(290 + len(nlev), nlev)], NT=5, B=(2,), T=0.25)
+    rng = np.random.default_rng(291)
+    tars = [random_pure_states(rng, systems[0].N, 2)]
+    beta = np.array([0.8, 1.3])
+    res = {}
+    for fuse in (1, 0):
+        plan = lbx.Plan(systems, path="stream")
+        plan.set_option(lbx._native.LB_OPT_TILE_KI, ki)
+        plan.set_option(lbx._native.LB_OPT_FUSE_GRAD, fuse)
+        plan.profile(True)
+        say("fused integrands", nlev, ki, fuse)
+        G, grad, _ = lbx.adjoint_gradient(plan, 0, dev(flat_alpha(alphas)), dev(flat_states(rho0)),
+                                          dev(flat_states(tars)), dev(beta), batch, 0.0, 2)
+        n_grad = plan.profile_read(lbx._native.LB_KERNEL_STREAM_GRAD)[0]
+        res[fuse] = (G.item(), grad.cpu().numpy(), n_grad)
+    assert res[0][2] > 0 and (res[1][2] == 0) == fused  # a fused run launches no integrand kernel
+    assert res[1][0] == res[0][0]
+    g1, g0 = res[1][1], res[0][1]
+    assert np.max(np.abs(g1 - g0)) <= 1e-12 * np.max(np.abs(g0))
+    if systems[0].N <= 729:  # (seven qutrits: the oracle's gradient takes over a quarter of an hour)
+        say("fused integrands oracle", nlev)
+        Gr, gr = oracle.value_and_gradient(systems[0], alphas[0], rho0[0], tars[0], beta, 0)
+        assert np.max(np.abs(g1.reshape(gr.shape) - gr)) <= GRAD_TOL * np.max(np.abs(gr))
+
+
+def test_fused_gradient_integrands_eight_qutrits(lbx):
+    # The eight-qutrit ring's block shape, three steps from a seeded random
+    # state: fused and separate integrands against each other.
+    from workloads import make_config, truncate_steps, with_random_states
+    p = truncate_steps(with_random_states(make_config(5), 1, 77), 3)
+    s = p.systems[0]
+    alpha = dev(p.alpha[0].reshape(-1))
+    r0, tar = dev(p.rho0[0][1:]), dev(p.rhotar[0][1:])
+    out = {}
+    for fuse in (1, 0):
+        plan = lbx.Plan([s])
+        plan.set_option(lbx._native.LB_OPT_TILE_KI, 34)
+        plan.set_option(lbx._native.LB_OPT_FUSE_GRAD, fuse)
+        say("fused integrands eight qutrits", fuse)
+        G, grad, _ = lbx.adjoint_gradient(plan, 0, alpha, r0, tar, dev(np.ones(1)), [1], 0.0, 1)
+        out[fuse] = (G.item(), grad.cpu().numpy())
+        del plan
+        torch.cuda.empty_cache()
+    assert out[1][0] == out[0][0]
+    assert np.max(np.abs(out[1][1] - out[0][1])) <= 1e-12 * np.max(np.abs(out[0][1]))
