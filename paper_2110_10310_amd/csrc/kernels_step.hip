@@ -9,9 +9,12 @@
 // max norm with a factor theta_j <= h sum_q (2 |d_q| c_q + (n_q - 1)/T1_q)
 // (control_table_kernel).  After a first sweep delta0 -> delta1 the error obeys
 //   |delta1 - delta*| <= theta/(1 - theta) |delta1 - delta0|,
-// and every further sweep multiplies the bound by theta; a step takes at
-// least two sweeps and otherwise the fewest that bring the bound below
-// tol * max|q|.  Sweep 0 folds its workgroup maxima of |delta1 - delta0| and
+// and every further sweep multiplies the bound by theta; a step takes the
+// fewest sweeps that bring the bound below tol * max|q|.  A step whose first
+// sweep suffices (its start was within the bound) is finished by
+// stage_finish_kernel, which writes the step's outputs from that sweep's
+// iterate without another pass over the neighbours.  Sweep 0 folds its
+// workgroup maxima of |delta1 - delta0| and
 // |q| into LB_STEP_SLOTS slots per system with atomic maxima (exact, so the
 // order does not matter); a one-wavefront count kernel reduces those slots
 // into the step's count K, and every workgroup of a later sweep reads K,
@@ -46,7 +49,7 @@ namespace lbx {
 namespace {
 
 // Total sweeps of a stage solve after a first sweep that changed the iterate
-// by e1 (max norm), with |q| <= qmax: at least two, at most kcap + 1.
+// by e1 (max norm), with |q| <= qmax: at least one, at most kcap + 1.
 __device__ __forceinline__ int stage_sweeps(double theta, double ratio, double e1, double qmax, double tol,
                                             int kcap) {
   double r = ratio * e1;
@@ -56,7 +59,7 @@ __device__ __forceinline__ int stage_sweeps(double theta, double ratio, double e
     r *= theta;
     ++k;
   }
-  return 1 + (k > 1 ? k : 1);
+  return 1 + k;
 }
 
 // Order-preserving bits of a non-negative double (NaN orders above every
@@ -131,6 +134,22 @@ struct SweepOut {
   double e1 = 0.0, qm = 0.0;
 };
 
+// What the last sweep of a step writes for entry e, from its increment dn:
+// q^{j+1} = q + 2 dn, the stage vector q + dn (adjoint), and the next step's
+// start and the increment history.
+template <bool ADJ>
+__device__ __forceinline__ void step_output(const StepArgs &A, int64_t e, double h, double2 D, double2 w, double2 qv,
+                                            double2 dn) {
+  const double2 qn = make_double2(qv.x + 2.0 * dn.x, qv.y + 2.0 * dn.y);
+  A.out[e] = qn;
+  if (ADJ && A.zh) A.zh[e] = cadd(qv, dn);
+  if (A.znext) {
+    const double2 R = cmul(make_double2(1.0 + h * D.x, h * D.y), w);
+    A.znext[e] = cadd(qn, next_start(dn, R, A.m, A.n, A.H, A.ring, A.ring_stride, e));
+    A.ring[(int64_t)(A.n % A.H) * A.ring_stride + e] = dn;
+  }
+}
+
 template <bool ADJ>
 __device__ __forceinline__ void sweep_entry(const StepArgs &A, SweepOut &so, int64_t e, double h, double gam,
                                             double dE, double2 acc, double2 own) {
@@ -148,14 +167,7 @@ __device__ __forceinline__ void sweep_entry(const StepArgs &A, SweepOut &so, int
     so.zo[e] = cadd(qv, dn);
     return;
   }
-  const double2 qn = make_double2(qv.x + 2.0 * dn.x, qv.y + 2.0 * dn.y);
-  A.out[e] = qn;
-  if (ADJ && A.zh) A.zh[e] = cadd(qv, dn);
-  if (A.znext) {
-    const double2 R = cmul(make_double2(1.0 + h * D.x, h * D.y), w);
-    A.znext[e] = cadd(qn, next_start(dn, R, A.m, A.n, A.H, A.ring, A.ring_stride, e));
-    A.ring[(int64_t)(A.n % A.H) * A.ring_stride + e] = dn;
-  }
+  step_output<ADJ>(A, e, h, D, w, qv, dn);
 }
 
 // The iterate sweep kk reads: the start for kk = 0, then the output of kk - 1.
@@ -334,6 +346,37 @@ __global__ __launch_bounds__(STREAM_BLOCK) void sweep_generic_kernel(StepArgs A,
   }
 }
 
+// The outputs of a step whose stage solve converged in its first sweep
+// (count 1), for every streamed system with that count: sweep 0 left
+// z = q + delta in z0, and this writes what a last sweep writes
+// (step_output) without another pass over the neighbours.  delta is
+// recovered as z - q, exact where |delta| << |q| and otherwise within one
+// rounding of z.
+// A bounded grid walks the STREAM_BLOCK-entry units, so that the launch costs
+// little when no system has count 1.
+template <bool ADJ>
+__global__ __launch_bounds__(STREAM_BLOCK) void stage_finish_kernel(StepArgs A) {
+  if (A.nseg == 1 && step_sweeps_of(A, A.segs[0].sys) != 1) return;  // one system: one test
+  for (int64_t u = blockIdx.x; u < A.nblk; u += gridDim.x) {
+    const StreamSeg &sg = A.segs[find_seg(A.segs, A.nseg, u)];
+    if (step_sweeps_of(A, sg.sys) != 1) continue;  // uniform per workgroup
+    const SysDev &S = A.sysv[sg.sys];
+    const int64_t local = (u - sg.blk0) * STREAM_BLOCK + threadIdx.x;
+    if (local >= sg.count) continue;
+    const int64_t b = local / S.N2;
+    const int64_t r = local - b * S.N2;
+    const int i = (int)(r / S.N);
+    const int jj = (int)(r - (int64_t)i * S.N);
+    const uint64_t di = A.desc[S.tab_off + i], dj = A.desc[S.tab_off + jj];
+    const double gam = diag_rate(S, di, dj);
+    const double dE = A.Etab[S.tab_off + i] - A.Etab[S.tab_off + jj];
+    const int64_t e = sg.off + local;
+    const double2 qv = A.q[e];
+    step_output<ADJ>(A, e, S.h, diag_coef(gam, dE, ADJ), stage_weight(S.h, gam, dE, ADJ), qv,
+                     csub(A.z0[e], qv));
+  }
+}
+
 // Sweep count of the current step of every streamed system, after sweep 0:
 // workgroup g takes segment g, reduces the system's slots (one per lane),
 // writes the count, raises status bits, adds the count to kout and clears
@@ -357,6 +400,7 @@ __global__ __launch_bounds__(64) void step_count_kernel(StepArgs A) {
   int bits = 0;
   if (!A.apriori) {
     K = stage_sweeps(tt.x, tt.y, e1, qm, A.tol, A.kcap);
+    if (A.gpart && K < 2) K = 2;  // the integrands are formed in a sweep after the first
     if (K > A.L) {
       bits |= LB_STATUS_RETRY;
       K = A.L;
@@ -706,6 +750,14 @@ bool tile_grad_fusable(const lb_plan *p, int sys, int tile_k) {
 
 int launch_sweep(const lb_plan *p, StepArgs &A, int kk, bool adj, int tile_sys, int tile_k, hipStream_t st) {
   if (A.H > HMAX) return fail(LB_EINVAL, "increment history longer than the kernels keep");
+  if (kk == 1 && !A.apriori && A.nblk > 0) {  // the steps whose first sweep sufficed
+    const dim3 grid((unsigned)std::min<int64_t>(A.nblk, 2048));
+    if (adj)
+      hipLaunchKernelGGL(stage_finish_kernel<true>, grid, dim3(STREAM_BLOCK), 0, st, A);
+    else
+      hipLaunchKernelGGL(stage_finish_kernel<false>, grid, dim3(STREAM_BLOCK), 0, st, A);
+    LBX_HIP(hipGetLastError());
+  }
   if (int rc = sweep_only(p, A, kk, adj, tile_sys, tile_k, st)) return rc;
   if (kk == 0 && A.nseg > 0) {
     hipLaunchKernelGGL(step_count_kernel, dim3((unsigned)A.nseg), dim3(64), 0, st, A);

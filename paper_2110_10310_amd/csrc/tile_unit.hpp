@@ -245,21 +245,25 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
         cf = plus ? ctl_coef<DIR_RP, ADJ>(a, bq, sqrt_small<NL>(n + 1))
                   : ctl_coef<DIR_RM, ADJ>(a, bq, sqrt_small<NL>(n));
         sh = plus ? st * N : -st * N;
-        // row shift +e: (w, -w) with w = sqrt(n+1); -e: (w, w) with w = sqrt(n)
-        const double w = plus ? sqrt_small<NL>(n + 1) : sqrt_small<NL>(n);
-        gwp = w;
-        gwq = plus ? -w : w;
-        gqi = q;
+        if constexpr (GRAD) {
+          // row shift +e: (w, -w) with w = sqrt(n+1); -e: (w, w) with w = sqrt(n)
+          const double w = plus ? sqrt_small<NL>(n + 1) : sqrt_small<NL>(n);
+          gwp = w;
+          gwq = plus ? -w : w;
+          gqi = q;
+        }
       } else if (kind == 1) {
         ex = plus ? m + 1 < NL : m > 0;
         cf = plus ? ctl_coef<DIR_CP, ADJ>(a, bq, sqrt_small<NL>(m + 1))
                   : ctl_coef<DIR_CM, ADJ>(a, bq, sqrt_small<NL>(m));
         sh = plus ? st : -st;
-        // column shift +e: (-w, -w) with w = sqrt(m+1); -e: (-w, w) with w = sqrt(m)
-        const double w = plus ? sqrt_small<NL>(m + 1) : sqrt_small<NL>(m);
-        gwp = -w;
-        gwq = plus ? -w : w;
-        gqi = q;
+        if constexpr (GRAD) {
+          // column shift +e: (-w, -w) with w = sqrt(m+1); -e: (-w, w) with w = sqrt(m)
+          const double w = plus ? sqrt_small<NL>(m + 1) : sqrt_small<NL>(m);
+          gwp = -w;
+          gwq = plus ? -w : w;
+          gqi = q;
+        }
       } else {
         ex = !ADJ ? (n + 1 < NL && m + 1 < NL) : (n > 0 && m > 0);
         cf = make_double2(!ADJ ? g1 * sqrt_small<NL>(n + 1) * sqrt_small<NL>(m + 1)
@@ -332,6 +336,11 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
     // time under uniform branches (measured faster there than the table).
     // GRAD: the integrand weights (wp, wq) of subsystem q as in the table.
     auto direction = [&](double2 c, int64_t shift, int q, double wp, double wq) {
+      if constexpr (!GRAD) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) cmac(acc[k], c, X[offs[k] + shift]);
+        return;
+      }
       double2 v[EPT];
 #pragma unroll
       for (int k = 0; k < EPT; ++k) v[k] = X[offs[k] + shift];
@@ -419,16 +428,14 @@ __device__ __forceinline__ void tile_unit(const SysDev &S, int64_t lb, const dou
       // itself with a zero weight (no divergent branches).
       const bool rp = n + 1 < NL, rm = n > 0, cp = m + 1 < NL, cm = m > 0;
       if (q >= ER) {  // internal row digit: a row shift of st is st*TC entries in the block
-        const double2 vp = tile[f + (rp ? st * TC : 0)], vm = tile[f - (rm ? st * TC : 0)];
-        const double wp = rp ? sqrt_small<NL>(n + 1) : 0.0, wm = sqrt_small<NL>(n);
-        cmac(ac, ctl_coef<DIR_RP, ADJ>(da[q], db[q], wp), vp);
-        cmac(ac, ctl_coef<DIR_RM, ADJ>(da[q], db[q], wm), vm);
+        cmac(ac, ctl_coef<DIR_RP, ADJ>(da[q], db[q], rp ? sqrt_small<NL>(n + 1) : 0.0),
+             tile[f + (rp ? st * TC : 0)]);
+        cmac(ac, ctl_coef<DIR_RM, ADJ>(da[q], db[q], sqrt_small<NL>(n)), tile[f - (rm ? st * TC : 0)]);
       }
       if (q >= EC) {
-        const double2 vp = tile[f + (cp ? st : 0)], vm = tile[f - (cm ? st : 0)];
-        const double wp = cp ? sqrt_small<NL>(m + 1) : 0.0, wm = sqrt_small<NL>(m);
-        cmac(ac, ctl_coef<DIR_CP, ADJ>(da[q], db[q], wp), vp);
-        cmac(ac, ctl_coef<DIR_CM, ADJ>(da[q], db[q], wm), vm);
+        cmac(ac, ctl_coef<DIR_CP, ADJ>(da[q], db[q], cp ? sqrt_small<NL>(m + 1) : 0.0),
+             tile[f + (cp ? st : 0)]);
+        cmac(ac, ctl_coef<DIR_CM, ADJ>(da[q], db[q], sqrt_small<NL>(m)), tile[f - (cm ? st : 0)]);
       }
       const bool jr = !ADJ ? (rp && cp) : (rm && cm);
       const double cj = !jr ? 0.0
