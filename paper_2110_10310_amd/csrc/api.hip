@@ -1863,7 +1863,9 @@ extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch
                                 (double2 *)(w + L.ttab), o.tol, st);
   if (rc) return rc;
   const size_t E = (size_t)m->st_entries * sizeof(double2);
-  if ((rc = launch_fill_zero(w + L.q0, E, st)) || (rc = launch_fill_zero(w + L.q1, E, st))) return rc;
+  if ((rc = launch_fill_trial((double2 *)(w + L.q0), m->st_entries, st)) ||
+      (rc = launch_fill_trial((double2 *)(w + L.q1), m->st_entries, st)))
+    return rc;
   if ((rc = launch_slots_clear((unsigned long long *)(w + L.slots), (int)p->sys.size(), st))) return rc;
   // Kernel family and block shape.
   std::vector<std::pair<int, int>> cand = {{0, 0}};
@@ -1878,7 +1880,7 @@ extern "C" int lb_autotune(lb_plan *p, const double *alpha, const int32_t *batch
         cand.push_back({1, LB_SPLIT_BASE + ka});
     }
   }
-  const int reps = m->st_entries > (1 << 22) ? 4 : 20;
+  const int reps = m->st_entries > (1 << 22) ? 6 : 20;
   float best = 1e30f;
   int bt = o.tile, bk = o.tile_ki;
   lbx_opts oc = o;

@@ -19,6 +19,30 @@ __global__ void fill_zero_kernel(uint32_t *__restrict__ p, int64_t n) {
     p[i] = 0u;
 }
 
+// A deterministic, non-zero trial state for the autotuner: entry k gets
+// 1e-2 (u, v) with u, v in [-1, 1) from a splitmix64 hash of k.  (Timing on
+// zeros runs faster than on a real trajectory and can reorder the kernels.)
+__device__ __forceinline__ double hash_unit(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void fill_trial_kernel(double2 *__restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_double2(1e-2 * hash_unit(2 * (uint64_t)i), 1e-2 * hash_unit(2 * (uint64_t)i + 1));
+}
+
+int launch_fill_trial(double2 *ptr, int64_t n, hipStream_t st) {
+  if (n == 0) return LB_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_trial_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ptr, n);
+  LBX_HIP(hipGetLastError());
+  return LB_OK;
+}
+
 int launch_fill_zero(void *ptr, size_t bytes, hipStream_t st) {
   const int64_t n = (int64_t)(bytes / 4);
   if (n == 0) return LB_OK;

@@ -254,6 +254,7 @@ int launch_kry_finish(const KryArgs &A, bool adj, const double2 *y, const double
 
 // Zeroes `bytes` (a multiple of 4) with a kernel.
 int launch_fill_zero(void *ptr, size_t bytes, hipStream_t st);
+int launch_fill_trial(double2 *ptr, int64_t n, hipStream_t st);
 
 // Control table of systems s0..s0+nsys-1; entry (s, j, q) goes to
 // ctab[ctab_off(s) - ctab_shift + j*Q + q].  ktab ([s][j][2] a-priori sweep
