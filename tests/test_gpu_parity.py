@@ -735,3 +735,41 @@ def test_fused_gradient_integrands_eight_qutrits(lbx):
         torch.cuda.empty_cache()
     assert out[1][0] == out[0][0]
     assert np.max(np.abs(out[1][1] - out[0][1])) <= 1e-12 * np.max(np.abs(out[0][1]))
+
+
+def test_one_sweep_steps_match_a_cold_start(lbx):
+    # A three-qutrit cut of the eight-qutrit ring over its real horizon from
+    # |0..0> (smooth controls, small contraction bound): with a history of 6
+    # many forward steps meet the bound after their first sweep and are
+    # finished by stage_finish_kernel; a cold start (no history) never is.
+    # Both solve the same stage systems to the same bound.
+    from dataclasses import replace
+    p = make_config(5)
+    s8 = p.systems[0]
+    Q = 3
+    s = replace(s8, nlev=s8.nlev[:Q], detuning=s8.detuning[:Q], selfkerr=s8.selfkerr[:Q],
+                crosskerr=s8.crosskerr[:Q, :Q], T1=s8.T1[:Q], T2=s8.T2[:Q], carriers=s8.carriers[:Q])
+    alpha = dev(np.ascontiguousarray(p.alpha[0].reshape(s8.Q, s8.Ns, s8.Nf, 2)[:Q]).reshape(-1))
+    N = s.N
+    r0 = np.zeros((1, N, N), complex)
+    r0[0, 0, 0] = 1
+    tar = np.zeros((1, N, N), complex)
+    tar[0, N - 1, N - 1] = 1
+    r0, tar, beta = dev(r0), dev(tar), dev(np.ones(1))
+    out = {}
+    for H in (6, 0):
+        plan = lbx.Plan([s], path="stream")
+        plan.set_option(lbx._native.LB_OPT_HISTORY, H)
+        plan.profile(True)
+        plan.profile_read(lbx._native.LB_KERNEL_SWEEP, reset=True)
+        say("one-sweep steps", H)
+        lbx.forward_solve(plan, alpha, r0, [1])
+        n, _ = plan.profile_read(lbx._native.LB_KERNEL_SWEEP)
+        sweeps = plan.profile_work(lbx._native.LB_KERNEL_SWEEP) / (N * N) / n
+        G, grad, rhoT = lbx.adjoint_gradient(plan, 0, alpha, r0, tar, beta, [1], 0.0, 0, want_rhoT=True)
+        out[H] = (G.item(), grad.cpu().numpy(), rhoT.cpu().numpy(), sweeps)
+    # forward sweeps per step: many steps took one sweep with the history
+    assert out[6][3] < 1.95 and out[0][3] > 2.5, (out[6][3], out[0][3])
+    assert rel_state_err([out[6][2]], [out[0][2]]) < STATE_TOL
+    assert abs(out[6][0] - out[0][0]) <= 1e-12 * abs(out[0][0])
+    assert np.max(np.abs(out[6][1] - out[0][1])) <= GRAD_TOL * np.max(np.abs(out[0][1]))
