@@ -91,6 +91,19 @@ def measured_traffic(key, files, traffic_file=None):
     return rec.get("bytes_per_launch")
 
 
+def with_traffic_rate(roof):
+    """Add the counter-measured HBM rate to a roofline object that holds a
+    `traffic` figure (bytes per launch from the rocprofv3 counters) and an
+    average launch duration: traffic_GBps and its fraction of the peak,
+    beside the algorithmic `achieved` (whose gap to it is the extra traffic
+    of the tiling)."""
+    if roof and roof.get("traffic") and roof.get("avg_launch_ms") and roof.get("unit") == "GB/s":
+        rate = roof["traffic"] / (roof["avg_launch_ms"] / 1e3) / 1e9
+        roof["traffic_GBps"] = rate
+        roof["traffic_frac"] = rate / roof["peak"]
+    return roof
+
+
 def neighbour_counts(nlev):
     """Mean number of existing control neighbours (row and column ladder
     shifts) and decay-jump neighbours per entry, summed over subsystems."""
@@ -698,7 +711,7 @@ def main():
                    "ckpt_every": res["ckpt_every"]},
         "sample": res["sample"],
         "ms_per_eval": res["ms_per_step"],
-        "roofline": res["roofline"],
+        "roofline": with_traffic_rate(res["roofline"]),
         "detail": {"G": res["G"], "grad_max": res["grad_norm"],
                    "sweeps_per_step_mean": res["sweeps_per_step_mean"],
                    "kernel_avg_ms": res["kernel_ms"], "kernel_ms_per_step": res["kernel_total_ms"],
@@ -707,7 +720,7 @@ def main():
     }
     if w == 5 and not args.no_apply:
         print("[bench] lindblad_apply 8 qutrits", file=sys.stderr, flush=True)
-        line["apply_roofline"] = run_apply_bench(lbx, torch, args.apply_reps)
+        line["apply_roofline"] = with_traffic_rate(run_apply_bench(lbx, torch, args.apply_reps))
     if w != 2 and not args.no_c2:
         print("[bench] two-transmon gradient", file=sys.stderr, flush=True)
         line["c2_cnot"] = c2_summary(lbx, torch, args)

@@ -124,3 +124,13 @@ def test_oracle_pool_runs_states_in_separate_processes():
     # three two-transmon evaluations over two processes, 20 steps each
     wall = bench.run_oracle_pool(("grad2", 20), [0, 1, 2], 2)
     assert 0.0 < wall < 60.0
+
+
+def test_traffic_rate_beside_the_algorithmic_rate():
+    roof = {"unit": "GB/s", "peak": 8000.0, "traffic": 4e9, "avg_launch_ms": 2.0, "achieved": 1000.0}
+    out = bench.with_traffic_rate(dict(roof))
+    assert out["traffic_GBps"] == pytest.approx(2000.0)
+    assert out["traffic_frac"] == pytest.approx(0.25)
+    # no counters (or another unit): unchanged
+    assert "traffic_GBps" not in bench.with_traffic_rate(dict(roof, traffic=None))
+    assert "traffic_GBps" not in bench.with_traffic_rate(dict(roof, unit="TFLOP/s"))
