@@ -141,3 +141,26 @@ def test_penalty_width_is_validated(lbx):
     with pytest.raises(Exception, match="penalty_a"):
         lbx.adjoint_gradient(lbx.Plan([s]), 0, dev(alpha.reshape(-1)), r, r, dev(np.ones(1)), [1], 0.0, 0,
                              gamma1=1.0, penalty_a=0.0)
+
+
+def test_penalty_with_jnm_on_the_block_tiled_system(lbx):
+    # J_Nm with the ensemble state (Sec. III-B) on five qutrits (block-tiled
+    # streamed kernels), with the running penalty: the terminal condition and
+    # every step's source are the observable N_m.
+    from workloads import ensemble_state
+    rng = np.random.default_rng(870)
+    s = random_system(rng, (3,) * 5, NT=6, T=0.6, Ns=4, Nf=2)
+    alpha = random_alpha(rng, s, amp=0.03)
+    r0 = ensemble_state(s.N)[None]
+    O = observable_nm(s.N, 2)[None]
+    beta = np.ones(1)
+    plan = lbx.Plan([s], path="stream")
+    say("penalty J_Nm tiled")
+    G, grad, rhoT = lbx.adjoint_gradient(plan, 2, dev(alpha.reshape(-1)), dev(r0), dev(O), dev(beta), [1], 0.0, 0,
+                                         want_rhoT=True, gamma1=1.5, penalty_a=0.3)
+    Gr, gr, rT = oracle.value_and_gradient(s, alpha, r0, O, beta, 2, 0.0, return_final=True, gamma1=1.5,
+                                           penalty_a=0.3)
+    assert rel_state_err([rhoT.cpu().numpy().reshape(1, s.N, s.N)], [rT]) < STATE_TOL
+    assert abs(G.item() - Gr) <= 1e-12 * abs(Gr)
+    g = grad.cpu().numpy().reshape(gr.shape)
+    assert np.max(np.abs(g - gr)) <= GRAD_TOL * np.max(np.abs(gr))
