@@ -118,3 +118,12 @@ def test_coupled_steps_beyond_the_splitting_bound(lbx):
     assert (k < 1).all()
     say("coupled krylov")
     _gradient_case(lbx, [s], [alpha], rng, "auto")
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_coupled_gradient_with_checkpoint_recomputation(lbx, kind):
+    # checkpoints every 3 steps: the coupled streamed forward states are
+    # recomputed between checkpoints in the adjoint
+    s, alpha, rng = _jc(690 + kind, (3, 2, 2), NT=11, T=1.1)
+    say("coupled gradient ckpt", kind)
+    _gradient_case(lbx, [s], [alpha], rng, "auto", B=2, kind=kind, ckpt=3)
