@@ -51,6 +51,23 @@ def test_noalloc_step_matches_workspace_step_twice(lbx, case, adjoint):
         assert rel_state_err(out.cpu().numpy(), ref.cpu().numpy()) < STATE_TOL
 
 
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_noalloc_step_with_coupling(lbx, adjoint):
+    # a Jaynes-Cummings coupled system (generic sweep kernel with the coupling
+    # terms and its contraction bound), two calls, the second smaller
+    rng = np.random.default_rng(4300)
+    s = random_system(rng, (3, 2, 2), NT=12, T=1.2, Ns=5, Nf=2, jc=0.04)
+    alpha = dev(random_alpha(rng, s, amp=0.02).reshape(-1))
+    plan = lbx.Plan([s])
+    for call, (B, j) in enumerate([(5, 3), (2, 8)]):
+        q = dev(_states(rng, B, s.N))
+        say("imr_step_noalloc coupled", adjoint, "call", call, "B", B)
+        out = torch.empty_like(q)
+        lbx.imr_step_noalloc(plan, 0, j, alpha, q, out, adjoint=adjoint)
+        ref = lbx.imr_step(plan, 0, j, alpha, q, adjoint=adjoint)
+        assert rel_state_err([out.cpu().numpy()], [ref.cpu().numpy()]) < STATE_TOL
+
+
 def test_noalloc_step_async_status(lbx):
     """With LB_OPT_SYNC off the call only enqueues; lb_status(plan, NULL)
     then reads the status of the last call on the device: clean with enough
