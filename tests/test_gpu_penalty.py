@@ -164,3 +164,26 @@ def test_penalty_with_jnm_on_the_block_tiled_system(lbx):
     assert abs(G.item() - Gr) <= 1e-12 * abs(Gr)
     g = grad.cpu().numpy().reshape(gr.shape)
     assert np.max(np.abs(g - gr)) <= GRAD_TOL * np.max(np.abs(gr))
+
+
+def test_penalty_with_an_empty_system(lbx):
+    # a system with no states in the batch gets G = 0 (no penalty, no
+    # terminal term) and leaves the other system's result unchanged
+    rng = np.random.default_rng(880)
+    systems = [random_system(rng, n, NT=8, T=0.8, Ns=4, Nf=2) for n in ((2, 3), (3, 3))]
+    alphas = [random_alpha(rng, s, amp=0.03) for s in systems]
+    r0 = random_pure_states(rng, systems[0].N, 2)
+    tar = random_pure_states(rng, systems[0].N, 2)
+    beta = rng.uniform(0.5, 2, 2)
+    a = dev(flat_alpha(alphas))
+    say("penalty empty system")
+    both = lbx.Plan(systems)
+    G, grad, _ = lbx.adjoint_gradient(both, 0, a, dev(r0), dev(tar), dev(beta), [2, 0], 0.0, 0, gamma1=0.7,
+                                      penalty_a=0.4)
+    one = lbx.Plan(systems[:1])
+    G1, g1, _ = lbx.adjoint_gradient(one, 0, dev(alphas[0].reshape(-1)), dev(r0), dev(tar), dev(beta), [2], 0.0, 0,
+                                     gamma1=0.7, penalty_a=0.4)
+    G, grad = G.cpu().numpy(), grad.cpu().numpy()
+    n0 = alphas[0].size
+    assert G[1] == 0.0 and np.all(grad[n0:] == 0.0)
+    assert G[0] == G1.item() and np.array_equal(grad[:n0], g1.cpu().numpy())
