@@ -99,3 +99,24 @@ def test_lbfgs_reduces_a_two_qubit_gate_objective(lbx):
     say("lbfgs two-qubit gate")
     _, hist = lbx.optimize(plan, 0, dev(alpha0), dev(rho0), dev(tar), dev(beta), [3], max_iter=40)
     assert min(hist) < 0.5 * hist[0], (hist[0], min(hist))
+
+
+def test_lbfgs_with_the_running_penalty(lbx):
+    # the running penalty makes each evaluation run the whole adjoint in the
+    # autograd forward pass; L-BFGS still lowers the penalised objective, and
+    # its history holds the penalised values (the oracle's G at the start)
+    s = _qubit(10.0, 200)
+    rng = np.random.default_rng(740)
+    alpha0 = random_alpha(rng, s, amp=0.005).reshape(-1)
+    r0 = np.zeros((1, 2, 2), complex)
+    r0[0, 0, 0] = 1
+    tar = np.zeros((1, 2, 2), complex)
+    tar[0, 1, 1] = 1
+    plan = lbx.Plan([s])
+    say("lbfgs with running penalty")
+    alpha, hist = lbx.optimize(plan, 0, dev(alpha0), dev(r0), dev(tar), dev(np.ones(1)), [1], max_iter=30,
+                               gamma1=0.5, penalty_a=2.0)
+    G0 = oracle.value_and_gradient(s, alpha0.reshape(s.Q, s.Ns, 1, 2), r0, tar, np.ones(1), 0, gamma1=0.5,
+                                   penalty_a=2.0)[0]
+    assert abs(hist[0] - G0) <= 1e-12 * abs(G0)
+    assert min(hist) < 0.5 * hist[0], (hist[0], min(hist))
